@@ -1,0 +1,197 @@
+/*
+ * hsp.h - C ABI of the MI355X two-grid sweeping preconditioner library.
+ *
+ * Method: C. C. Stolk, "An improved sweeping domain decomposition
+ * preconditioner for the Helmholtz equation" (arXiv 1412.0464).
+ *
+ * Problem (Sec. 1, Sec. 2.1): -Laplace u - k^2 u = f with k = omega / c on a
+ * rectangle, truncated by PML layers (d/dx -> alpha d/dx, alpha = 1/(1 +
+ * i sigma/omega), sigma = C dist^2, C = S c_pml / d^3) and homogeneous
+ * Dirichlet values outside.  Time factor exp(-i omega t): outgoing waves
+ * behave like exp(+i k r).
+ *
+ * Mesh (Sec. 2.2): N = n + 1 + 2 w cells per axis (n interior nodes, w
+ * outer-PML cells on each side), spacing h, unknowns at nodes 1..N-1.
+ * Vectors are dense arrays over the unknown nodes with the x axis (the
+ * sweep axis) slowest: index (i-1)*(N2-1) + (k-1) for node (i, k).
+ * Complex vectors are interleaved (re, im) pairs of double ("complex128").
+ *
+ * Memory and streams.  Every pointer named *_dev is a device pointer on the
+ * current HIP device.  The caller owns all of them, including the workspace
+ * passed to hsp_setup; the library never allocates device memory.  All work
+ * is enqueued on the HIP stream passed in (NULL = the default stream); a call
+ * blocks the host only where it must read a result (setup status, solve
+ * iterations).  A handle may be used from one host thread at a time.
+ *
+ * Errors.  Every function returns an hsp_status; 0 is success.  Nothing is
+ * thrown across the ABI.  hsp_last_error() returns a message for the last
+ * failure on the calling thread.
+ */
+#ifndef HSP_H
+#define HSP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HSP_OK = 0,
+  HSP_EINVAL = -1,     /* invalid argument: nothing was enqueued            */
+  HSP_ENOMEM = -2,     /* workspace smaller than hsp_workspace_size        */
+  HSP_ESINGULAR = -3,  /* zero or non-finite pivot in a slab factorization */
+  HSP_ENOCONV = -4,    /* maxit reached; the last iterate is returned      */
+  HSP_EDEVICE = -5     /* a HIP runtime call failed                        */
+} hsp_status;
+
+enum { HSP_SWEEP_X = 0, HSP_SWEEP_UD = 1 };
+enum { HSP_FP64 = 0, HSP_MIXED = 1 };
+
+typedef struct hsp_ctx* hsp_handle;
+
+/* Geometry of the fine mesh. */
+typedef struct hsp_grid {
+  int dim;          /* 2 (other values: HSP_EINVAL)                           */
+  int n[3];         /* interior nodes per axis, x first                       */
+  double h;         /* mesh spacing                                            */
+  int pml[3];       /* outer PML cells per side, per axis (>= 0)               */
+  double S_outer;   /* outer PML strength S; <= 0 selects 5 * pml[0]           */
+  double c_pml;     /* PML reference speed c_pml; <= 0 selects mean(c)        */
+} hsp_grid;
+
+/* Method parameters (Sec. 4 and 5). */
+typedef struct hsp_options {
+  int fine_stencil; /* 5: the 5-point PML finite differences of eq.
+                       define_pml_fd (the paper's fine level); 9: the
+                       finite-element 9-point form (App. A) with Table (a)
+                       coefficients at the fine 1/G                           */
+  int two_grid;     /* 0: the sweep acts on the fine operator itself;
+                       1: two-grid sweeping preconditioner (TGSP, Sec. 4): the
+                       sweep acts on the optimized 9-point FE operator of the
+                       PML-aware coarse mesh (App. A)                         */
+  int w_dd;         /* DD-PML layers added to each slab side (>= 1)           */
+  double S_dd;      /* DD-PML strength; <= 0 selects 5 * w_dd                  */
+  int nu;           /* omega-Jacobi pre- and post-smoothing steps             */
+  double omega_jac; /* Jacobi weight                                           */
+  int sweep;        /* HSP_SWEEP_X (SweepingPrecX) or HSP_SWEEP_UD            */
+  int precision;    /* HSP_FP64: everything complex128.  HSP_MIXED: smoother,
+                       slab factors and sweeps complex64; FGMRES, its
+                       residual and the restriction / prolongation complex128 */
+  int restart;      /* FGMRES restart length (sizes the workspace)            */
+} hsp_options;
+
+/* Fills *opt with: fine_stencil 5, two_grid 0, w_dd 4, S_dd 0 (= 5 w_dd),
+ * nu 3, omega_jac 0.8 (Sec. 5, Table 2), sweep X, precision FP64, restart 40. */
+hsp_status hsp_default_options(hsp_options* opt);
+
+/* Bytes of device workspace that hsp_setup needs for this geometry, slab
+ * count J and options (depends on sizes only, not on the medium).
+ * Errors: HSP_EINVAL for an invalid geometry / J / options (the same checks
+ * as hsp_setup except those that need the medium). */
+hsp_status hsp_workspace_size(const hsp_grid* grid, int J, const hsp_options* opt,
+                              size_t* bytes);
+
+/* Build the preconditioner for one medium and frequency (Sec. 2-4):
+ * PML profiles, coarse mesh and coarse optimized-FE coefficients (App. A),
+ * slab partition beta_j (outer-PML layers join the first and last cores, the
+ * interior layers are split evenly), slab operators with DD-PML and k
+ * continuation (Sec. 2.1 "subdomains"), and the LU factorization of all J
+ * slabs on the device.
+ *   c_dev      wave speed at all (N1-1)*(N2-1) unknown nodes, PML nodes
+ *              included, x slowest; read during the call only.
+ *   omega      angular frequency (> 0).
+ *   J          number of slabs (>= 1); every core must have >= 3 layers.
+ *   ws_dev     caller-owned device workspace of at least
+ *              hsp_workspace_size bytes, 256-byte aligned; it must stay
+ *              valid and untouched until hsp_destroy.
+ *   stream     hipStream_t or NULL.
+ *   out        receives the handle.
+ * Errors: HSP_EINVAL (bad geometry, options, non-positive or non-finite c or
+ * omega, cores thinner than 3 layers, DD-PML leaving the domain, odd interior
+ * cell count with two_grid), HSP_ENOMEM (workspace too small),
+ * HSP_ESINGULAR (a zero or non-finite pivot), HSP_EDEVICE.  Synchronises
+ * the stream (it reads the medium statistics and the pivot status). */
+hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, int J,
+                     const hsp_options* opt, void* ws_dev, size_t ws_bytes, void* stream,
+                     hsp_handle* out);
+
+/* Right-hand side of the discrete system (right side of eq. define_pml_fd,
+ * FE scaled): b = h^2 f / (alpha_1(x_i) alpha_2(y_k)).  f_dev, b_dev:
+ * complex128 vectors of the fine unknowns (may alias). */
+hsp_status hsp_rhs(hsp_handle hd, const void* f_dev, void* b_dev, void* stream);
+
+/* y = A x with the fine operator (eq. define_pml_fd times h^2, or the FE
+ * 9-point form), complex128.  x_dev and y_dev must not alias. */
+hsp_status hsp_apply_operator(hsp_handle hd, const void* x_dev, void* y_dev, void* stream);
+
+/* z = M r: one application of the preconditioner - the X (or UD) sweep of
+ * Table 3 on the fine level (two_grid = 0) or the two-grid cycle of Sec. 4
+ * with that sweep as coarse solver (two_grid = 1).  complex128 in and out,
+ * no aliasing.  M is a fixed linear map. */
+hsp_status hsp_apply_precond(hsp_handle hd, const void* r_dev, void* z_dev, void* stream);
+
+/* Solve A u = b for the FE-scaled right-hand side b (see hsp_rhs) with
+ * right-preconditioned FGMRES (x0 = 0, restart from options), stopping when
+ * ||b - A u||_2 <= tol ||b||_2 (Arnoldi estimate, then checked on the true
+ * residual).  conj_transpose = 1 solves A^H u = b instead (A is complex
+ * symmetric, so this is conj(A^{-1} conj(b))).  iters and relres (may be
+ * NULL) receive the iteration count and the true relative residual.
+ * Errors: HSP_ENOCONV when maxit is reached (u holds the last iterate). */
+hsp_status hsp_solve(hsp_handle hd, const void* b_dev, void* u_dev, double tol, int maxit,
+                     int conj_transpose, int* iters, double* relres, void* stream);
+
+/* Release the handle (host memory only; the caller frees the workspace). */
+hsp_status hsp_destroy(hsp_handle hd);
+
+/* Message for the last error on this thread (never NULL). */
+const char* hsp_last_error(void);
+
+/* ---- Component entry points, used to check each step against the
+ *      reference implementation.  Vectors are complex128. ---------------- */
+
+/* Sizes of the handle: fine unknowns per axis n_fine[2], coarse unknowns
+ * n_coarse[2] (zeros without two-grid), J, the largest slab thickness. */
+typedef struct hsp_info {
+  int n_fine[2];
+  int n_coarse[2];
+  int J;
+  int max_slab_layers;
+  int precision;
+  int two_grid;
+} hsp_info;
+hsp_status hsp_get_info(hsp_handle hd, hsp_info* info);
+
+/* Partition (host arrays supplied by the caller): beta[0..J] (Sec. 2.2) and
+ * the first / last global layer x0[j], x1[j] of slab j = 0..J-1. */
+hsp_status hsp_get_partition(hsp_handle hd, int* beta, int* x0, int* x1);
+
+/* y = A_level x for level 0 (fine) or 1 (coarse optimized FE operator,
+ * App. A, eq. define_H_FE), complex128, computed in the precision of that
+ * level's use inside the preconditioner converted to complex128. */
+hsp_status hsp_apply_level_operator(hsp_handle hd, int level, const void* x_dev,
+                                    void* y_dev, void* stream);
+
+/* r_c = P^T r_f (restriction, Sec. 4 "Using PML layers in the two-grid
+ * method"); e_f += P e_c (prolongation and correction).  complex128. */
+hsp_status hsp_restrict(hsp_handle hd, const void* rf_dev, void* rc_dev, void* stream);
+hsp_status hsp_prolong_add(hsp_handle hd, const void* ec_dev, void* xf_dev, void* stream);
+
+/* x = S^steps(0; r): omega-Jacobi smoothing on the fine operator from a zero
+ * start, x <- x + omega_jac D^{-1} (r - A x).  complex128. */
+hsp_status hsp_smooth(hsp_handle hd, const void* r_dev, void* x_dev, int steps, void* stream);
+
+/* u = P_X f (or P_UD f) on the level that carries the slabs (the coarse
+ * level with two-grid, the fine level otherwise), Table 3.  complex128. */
+hsp_status hsp_sweep(hsp_handle hd, const void* f_dev, void* u_dev, void* stream);
+
+/* x = (A^(j))^{-1} b for slab j (0-based) alone: b and x are complex128
+ * arrays over the slab's unknowns, layer-major (layer x0[j] first).  Uses
+ * the stored factors. */
+hsp_status hsp_slab_solve(hsp_handle hd, int j, const void* b_dev, void* x_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSP_H */

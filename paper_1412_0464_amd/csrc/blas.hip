@@ -1,0 +1,234 @@
+// Vector kernels: conversions, the fused Gram-Schmidt pieces of FGMRES
+// (multi-dot, multi-axpy, normalisation), right-hand-side scaling and the
+// per-node / per-cell medium preprocessing of the setup.
+#include <cmath>
+
+#include "internal.h"
+
+namespace hsp {
+
+namespace {
+
+template <class To, class Ti>
+__global__ void k_convert(const cx<Ti>* __restrict__ in, cx<To>* __restrict__ out, size_t n, int cj) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    cx<To> v = cvt<To>(in[i]);
+    if (cj) v.im = -v.im;
+    out[i] = v;
+  }
+}
+
+template <class T>
+__global__ void k_zero(cx<T>* v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = mk<T>(0, 0);
+}
+
+__device__ __forceinline__ cd block_sum(cd v, cd* sh) {
+  // 256 threads
+  const int t = threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) {
+    v.re += __shfl_down(v.re, off, 64);
+    v.im += __shfl_down(v.im, off, 64);
+  }
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  cd r = mk<double>(0, 0);
+  if (t == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  return r;
+}
+
+__global__ void __launch_bounds__(256) k_multidot(const cd* __restrict__ V, size_t ldv, const cd* __restrict__ w,
+                                                  size_t n, cd* __restrict__ partial, int m) {
+  __shared__ cd sh[4];
+  const int j = blockIdx.y;
+  const cd* v = V + (size_t)j * ldv;
+  cd acc = mk<double>(0, 0);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    cfma(acc, conj(v[i]), w[i]);
+  cd r = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * m + j] = r;
+}
+
+__global__ void __launch_bounds__(256) k_reduce_partials(const cd* __restrict__ partial, int nb, int m,
+                                                         cd* __restrict__ out) {
+  __shared__ cd sh[4];
+  const int j = blockIdx.x;
+  cd acc = mk<double>(0, 0);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[(size_t)b * m + j];
+  cd r = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[j] = r;
+}
+
+__global__ void __launch_bounds__(256) k_multiaxpy(const cd* __restrict__ V, size_t ldv, int m,
+                                                   const cd* __restrict__ h, cd* __restrict__ w, size_t n,
+                                                   int sub) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    cd acc = mk<double>(0, 0);
+    for (int j = 0; j < m; ++j) cfma(acc, h[j], V[(size_t)j * ldv + i]);
+    w[i] = sub ? (w[i] - acc) : (w[i] + acc);
+  }
+}
+
+__global__ void k_normalize(const cd* __restrict__ w, const cd* __restrict__ nrm2, cd* __restrict__ v, size_t n) {
+  const double s = 1.0 / sqrt(nrm2[0].re);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = s * w[i];
+}
+
+__global__ void k_scale_rhs(int n1, int n2, double h2, const cd* __restrict__ ixn, const cd* __restrict__ iyn,
+                            const cd* __restrict__ f, cd* __restrict__ b) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= n2) return;
+  const size_t id = (size_t)i * n2 + k;
+  b[id] = h2 * ((ixn[i + 1] * iyn[k + 1]) * f[id]);
+}
+
+__global__ void __launch_bounds__(1024) k_stats(const double* __restrict__ c, size_t n, double* __restrict__ out) {
+  __shared__ double s_sum[16], s_min[16], s_max[16], s_bad[16];
+  double sum = 0, mn = INFINITY, mx = -INFINITY, bad = 0;
+  for (size_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = c[i];
+    if (!(v > 0.0) || !isfinite(v)) {
+      bad += 1;
+      continue;
+    }
+    sum += v;
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sum += __shfl_down(sum, off, 64);
+    bad += __shfl_down(bad, off, 64);
+    mn = fmin(mn, __shfl_down(mn, off, 64));
+    mx = fmax(mx, __shfl_down(mx, off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_sum[w] = sum;
+    s_min[w] = mn;
+    s_max[w] = mx;
+    s_bad[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+      sum += s_sum[q];
+      mn = fmin(mn, s_min[q]);
+      mx = fmax(mx, s_max[q]);
+      bad += s_bad[q];
+    }
+    out[0] = sum;
+    out[1] = mn;
+    out[2] = mx;
+    out[3] = bad;
+  }
+}
+
+__global__ void k_k2_nodes(const double* __restrict__ c, size_t n, double om2, double* __restrict__ k2) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    k2[i] = om2 / (c[i] * c[i]);
+}
+
+__global__ void k_cell_average(const double* __restrict__ k2n, int n1, int n2, const int* __restrict__ x0,
+                               const double* __restrict__ wx, const int* __restrict__ y0,
+                               const double* __restrict__ wy, int nc2, double* __restrict__ k2c) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (q >= nc2) return;
+  double acc = 0;
+  for (int a = 0; a < 3; ++a) {
+    const double wa = wx[3 * p + a];
+    if (wa == 0.0) continue;
+    int gi = x0[p] + a;                       // node index 0..N1
+    gi = gi < 1 ? 1 : (gi > n1 ? n1 : gi);    // edge value for Dirichlet nodes
+    for (int b = 0; b < 3; ++b) {
+      const double wb = wy[3 * q + b];
+      if (wb == 0.0) continue;
+      int gk = y0[q] + b;
+      gk = gk < 1 ? 1 : (gk > n2 ? n2 : gk);
+      acc += wa * wb * k2n[(size_t)(gi - 1) * n2 + (gk - 1)];
+    }
+  }
+  k2c[(size_t)p * nc2 + q] = acc;
+}
+
+// Optimized finite-difference coefficients (App. A, Table (a)): 1/G_k and
+// c_1, c_2, c_3 at the support points 1/G_k = 0, 0.04, ..., 0.40.
+__constant__ double kOptTable2D[11][3] = {
+    {0.61953, 0.45295, 0.77363}, {0.63691, 0.47535, 0.87242}, {0.62988, 0.48633, 0.86400},
+    {0.62610, 0.48880, 0.84984}, {0.62289, 0.48759, 0.83017}, {0.62596, 0.47106, 0.80852},
+    {0.62213, 0.46478, 0.78215}, {0.61036, 0.47016, 0.74857}, {0.59107, 0.48468, 0.70553},
+    {0.56369, 0.50746, 0.65062}, {0.52412, 0.54163, 0.57676}};
+
+__global__ void k_cell_coefs(const double* __restrict__ k2c, size_t n, double h_nom, double* __restrict__ coef) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    // 1/G = h k / (2 pi), clamped to the table range
+    double g = h_nom * sqrt(k2c[i]) * (0.5 / M_PI);
+    g = fmin(fmax(g, 0.0), 0.40);
+    double s = g / 0.04;
+    int j = (int)floor(s);
+    if (j > 9) j = 9;
+    const double t = s - j;
+    for (int c = 0; c < 3; ++c) coef[3 * i + c] = (1.0 - t) * kOptTable2D[j][c] + t * kOptTable2D[j + 1][c];
+  }
+}
+
+inline int nblk(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b > 4096 ? 4096 : (b == 0 ? 1 : b));
+}
+
+}  // namespace
+
+template <class To, class Ti>
+void launch_convert(const cx<Ti>* in, cx<To>* out, size_t n, int conjugate, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<To, Ti>), dim3(nblk(n)), dim3(256), 0, s, in, out, n, conjugate);
+}
+template void launch_convert<float, double>(const cd*, cf*, size_t, int, hipStream_t);
+template void launch_convert<double, float>(const cf*, cd*, size_t, int, hipStream_t);
+template void launch_convert<double, double>(const cd*, cd*, size_t, int, hipStream_t);
+template void launch_convert<float, float>(const cf*, cf*, size_t, int, hipStream_t);
+
+template <class T>
+void launch_zero(cx<T>* v, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_zero<T>), dim3(nblk(n)), dim3(256), 0, s, v, n);
+}
+template void launch_zero<double>(cd*, size_t, hipStream_t);
+template void launch_zero<float>(cf*, size_t, hipStream_t);
+
+void launch_multidot(const cd* V, size_t ldv, int m, const cd* w, size_t n, cd* partial, int nblocks,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot, dim3(nblocks, m), dim3(256), 0, s, V, ldv, w, n, partial, m);
+}
+void launch_reduce_partials(const cd* partial, int nblocks, int m, cd* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(m), dim3(256), 0, s, partial, nblocks, m, out);
+}
+void launch_multiaxpy(const cd* V, size_t ldv, int m, const cd* h, cd* w, size_t n, int sub, hipStream_t s) {
+  hipLaunchKernelGGL(k_multiaxpy, dim3(nblk(n)), dim3(256), 0, s, V, ldv, m, h, w, n, sub);
+}
+void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize, dim3(nblk(n)), dim3(256), 0, s, w, nrm2, v, n);
+}
+void launch_scale_rhs_arrays(int n1, int n2, double h2, const cd* ixn, const cd* iyn, const cd* f, cd* b,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_rhs, dim3((n2 + 255) / 256, n1), dim3(256), 0, s, n1, n2, h2, ixn, iyn, f, b);
+}
+void launch_stats(const double* c, size_t n, double* out4, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, c, n, out4);
+}
+void launch_k2_nodes(const double* c, size_t n, double omega, double* k2, hipStream_t s) {
+  hipLaunchKernelGGL(k_k2_nodes, dim3(nblk(n)), dim3(256), 0, s, c, n, omega * omega, k2);
+}
+void launch_cell_average(const double* k2n, int n1, int n2, const int* x0, const double* wx, int nc1,
+                         const int* y0, const double* wy, int nc2, double* k2c, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_average, dim3((nc2 + 255) / 256, nc1), dim3(256), 0, s, k2n, n1, n2, x0, wx, y0, wy,
+                     nc2, k2c);
+}
+void launch_cell_coefs(const double* k2c, size_t ncell, double h_nom, double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_coefs, dim3(nblk(ncell)), dim3(256), 0, s, k2c, ncell, h_nom, coef);
+}
+
+}  // namespace hsp

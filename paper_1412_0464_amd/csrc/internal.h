@@ -1,0 +1,103 @@
+// Internal interfaces between the host orchestration (hsp_api.hip) and the
+// kernel translation units.  Not part of the public ABI.
+#pragma once
+
+#include "common.h"
+
+namespace hsp {
+
+constexpr int kMaxSlabLayers = 56;   // 2-D slab thickness limit (LDS sized)
+constexpr int kWave = 64;
+
+// ---- stencil kernels (stencil.hip) ---------------------------------------
+// y = A x                         (mode 0)
+// y = b - A x                     (mode 1)
+// y = x + w D^{-1} (b - A x)      (mode 2; x == nullptr means x = 0)
+// Tx/Tb/Ty are the storage types of x, b, y; Ta the arithmetic type.
+template <class Ta, class Tx, class Tb, class Ty>
+void launch_stencil(const LevelDev& L, int mode, const cx<Tx>* x, const cx<Tb>* b, cx<Ty>* y,
+                    double w, hipStream_t s);
+
+// ---- transfers (transfer.hip) ---------------------------------------------
+struct TransferDev {
+  int nf1, nf2, nc1, nc2;
+  const int* rx;      // [nc1][3] fine x unknown (0-based) per coarse x unknown, -1 = none
+  const double* rwx;  // [nc1][3] weights
+  const int* ry;
+  const double* rwy;
+  const int* px;      // [nf1][2] coarse x unknown (0-based) per fine x unknown, -1 = none
+  const double* pwx;  // [nf1][2]
+  const int* py;
+  const double* pwy;
+};
+template <class Tin, class Tout>
+void launch_restrict(const TransferDev& T, const cx<Tin>* rf, cx<Tout>* rc, hipStream_t s);
+template <class Tc, class Tf>
+void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipStream_t s);
+
+// ---- slab factorization and sweep stages (slab.hip) ------------------------
+struct SlabDev {
+  int x0;          // first global layer (1-based)
+  int nl;          // layers
+  LevelDev op;     // the slab operator A^(j)
+  size_t fac_off;  // element offset of this slab's factors
+};
+
+struct TaskDev {
+  int slab;                  // 0-based slab
+  int a, b;                  // f_d = J(j, a, b) f : global layers a+1..b
+  int at, bt;                // u += J(j, a~, b~)^T u_d
+  int t1, t2, t3, t4;        // transmission flags (in fwd, out fwd, in bwd, out bwd)
+  int bin_f, bin_b;          // buffer read by t1 / t3
+  int bout_f, bout_b;        // buffer written by t2 / t4
+  int beta_in, bt_in;        // beta_{j-1} (t1 layers) and beta~_j (t3 layers)
+  int beta_out, bt_out;      // beta_j (t2 layers) and beta~_{j-1} (t4 layers)
+  int src;                   // 0: read the sweep input f, 1: read the residual g
+  int mode;                  // 0: subdomain solve on level vectors, 1: slab-layout solve
+};
+
+// Factor storage per slab (elements of cx<T>): G [n2][nl][nl] (column major
+// blocks), E [n2][nl][nl], Acoup [n2][3][nl].
+inline size_t slab_factor_elems(int nl, int n2) {
+  return (size_t)n2 * nl * nl * 2 + (size_t)n2 * 3 * nl;
+}
+
+template <class T>
+void launch_factor(const SlabDev* slabs_dev, int nslabs, int nl_max, int n2, cx<T>* factors,
+                   cd* scratch, int* status, hipStream_t s);
+
+template <class T>
+void launch_stage(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev,
+                  const LevelDev& G, const cx<T>* f, const cx<T>* g, cx<T>* u, cx<T>* bufs,
+                  cx<T>* scratch, const cx<T>* factors, int nl_max, hipStream_t s);
+
+// ---- BLAS-1 and utilities (blas.hip) ---------------------------------------
+template <class To, class Ti>
+void launch_convert(const cx<Ti>* in, cx<To>* out, size_t n, int conjugate, hipStream_t s);
+template <class T>
+void launch_zero(cx<T>* v, size_t n, hipStream_t s);
+// partial[b*m + j] = sum over block b of conj(V_j) . w  (j < m), V_j = V + j*ldv
+void launch_multidot(const cd* V, size_t ldv, int m, const cd* w, size_t n, cd* partial,
+                     int nblocks, hipStream_t s);
+// out[j] = sum_b partial[b*m + j]   (+ out[j] if accumulate)
+void launch_reduce_partials(const cd* partial, int nblocks, int m, cd* out, hipStream_t s);
+// w -= sum_j h[j] V_j   (h on device)
+void launch_multiaxpy(const cd* V, size_t ldv, int m, const cd* h, cd* w, size_t n, int sub,
+                      hipStream_t s);
+// v = w / sqrt(re(nrm2[0]))
+void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t s);
+// b = h2 * f / (alpha_1(x_i) alpha_2(y_k)); ixn, iyn = 1/alpha at nodes 0..n+1
+void launch_scale_rhs_arrays(int n1, int n2, double h2, const cd* ixn, const cd* iyn, const cd* f, cd* b,
+                             hipStream_t s);
+// statistics of a real array: [sum, min, max, count of non-finite or <= 0]
+void launch_stats(const double* c, size_t n, double* out4, hipStream_t s);
+// per-node medium arrays
+void launch_k2_nodes(const double* c, size_t n, double omega, double* k2, hipStream_t s);
+// cell k2 = W1 (k2 nodes padded) W2^T with per-axis 3-tap weights
+void launch_cell_average(const double* k2n, int n1, int n2, const int* x0, const double* wx,
+                         int nc1, const int* y0, const double* wy, int nc2, double* k2c,
+                         hipStream_t s);
+void launch_cell_coefs(const double* k2c, size_t ncell, double h_nom, double* coef,
+                       hipStream_t s);
+
+}  // namespace hsp

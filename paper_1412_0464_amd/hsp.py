@@ -1,0 +1,275 @@
+"""Thin Python binding of the C ABI in include/hsp.h (argument marshalling only).
+
+Device memory comes from PyTorch: the workspace is a ``torch.uint8`` tensor on
+the GPU, vectors are contiguous ``torch.complex128`` tensors of shape
+(N1-1, N2-1) (x slowest), and every call is enqueued on the current torch
+stream.  All arithmetic runs in the HIP kernels of ``libhsp.so``; there is no
+CPU fallback: if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libhsp.so")
+_lib = None
+
+HSP_OK, HSP_EINVAL, HSP_ENOMEM, HSP_ESINGULAR, HSP_ENOCONV, HSP_EDEVICE = 0, -1, -2, -3, -4, -5
+SWEEP = {"x": 0, "ud": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+class HspError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"hsp status {status}: {message}")
+        self.status = status
+
+
+class HspGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+                ("pml", ctypes.c_int * 3), ("S_outer", ctypes.c_double), ("c_pml", ctypes.c_double)]
+
+
+class HspOptions(ctypes.Structure):
+    _fields_ = [("fine_stencil", ctypes.c_int), ("two_grid", ctypes.c_int), ("w_dd", ctypes.c_int),
+                ("S_dd", ctypes.c_double), ("nu", ctypes.c_int), ("omega_jac", ctypes.c_double),
+                ("sweep", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int)]
+
+
+class HspInfo(ctypes.Structure):
+    _fields_ = [("n_fine", ctypes.c_int * 2), ("n_coarse", ctypes.c_int * 2), ("J", ctypes.c_int),
+                ("max_slab_layers", ctypes.c_int), ("precision", ctypes.c_int), ("two_grid", ctypes.c_int)]
+
+
+EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", "hsp_apply_operator",
+           "hsp_apply_precond", "hsp_solve", "hsp_destroy", "hsp_last_error", "hsp_get_info",
+           "hsp_get_partition", "hsp_apply_level_operator", "hsp_restrict", "hsp_prolong_add",
+           "hsp_smooth", "hsp_sweep", "hsp_slab_solve"]
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load():
+    """Load libhsp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {_LIB_PATH} is missing "
+                           "(run `python -c 'import __graft_entry__ as g; g.build()'`)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "hsp_default_options": [ctypes.POINTER(HspOptions)],
+        "hsp_workspace_size": [ctypes.POINTER(HspGrid), I, ctypes.POINTER(HspOptions), ctypes.POINTER(S)],
+        "hsp_setup": [P, D, ctypes.POINTER(HspGrid), I, ctypes.POINTER(HspOptions), P, S, P,
+                      ctypes.POINTER(P)],
+        "hsp_rhs": [P, P, P, P],
+        "hsp_apply_operator": [P, P, P, P],
+        "hsp_apply_precond": [P, P, P, P],
+        "hsp_solve": [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D), P],
+        "hsp_destroy": [P],
+        "hsp_get_info": [P, ctypes.POINTER(HspInfo)],
+        "hsp_get_partition": [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
+        "hsp_apply_level_operator": [P, I, P, P, P],
+        "hsp_restrict": [P, P, P, P],
+        "hsp_prolong_add": [P, P, P, P],
+        "hsp_smooth": [P, P, P, I, P],
+        "hsp_sweep": [P, P, P, P],
+        "hsp_slab_solve": [P, I, P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.hsp_last_error.argtypes = []
+    lib.hsp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != HSP_OK:
+        raise HspError(st, load().hsp_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _vec(t, shape, name):
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def make_grid(n, h, pml, S_outer=0.0, c_pml=0.0):
+    g = HspGrid()
+    g.dim = 2
+    g.n[0], g.n[1], g.n[2] = int(n[0]), int(n[1]), 0
+    g.h = float(h)
+    g.pml[0], g.pml[1], g.pml[2] = int(pml[0]), int(pml[1]), 0
+    g.S_outer = float(S_outer)
+    g.c_pml = float(c_pml)
+    return g
+
+
+def make_options(**kw):
+    o = HspOptions()
+    _check(load().hsp_default_options(ctypes.byref(o)))
+    for k, v in kw.items():
+        if k == "sweep":
+            v = SWEEP[v] if isinstance(v, str) else v
+        if k == "precision":
+            v = PRECISION[v] if isinstance(v, str) else v
+        if k == "two_grid":
+            v = int(bool(v))
+        setattr(o, k, v)
+    return o
+
+
+def workspace_size(n, h, pml, J, **opts):
+    S = ctypes.c_size_t()
+    g = make_grid(n, h, pml)
+    o = make_options(**opts)
+    _check(load().hsp_workspace_size(ctypes.byref(g), int(J), ctypes.byref(o), ctypes.byref(S)))
+    return S.value
+
+
+class Helmholtz:
+    """One medium and frequency: hsp_setup on construction, hsp_destroy on close.
+
+    ``c``   contiguous float64 CUDA tensor of wave speeds at all unknown nodes
+            (PML nodes included), shape (N1-1, N2-1).
+    ``pml`` outer PML cells per side (int or pair); the interior node counts
+            follow from c.shape - 2*pml.
+    Options follow hsp_options (fine_stencil, two_grid, w_dd, S_dd, nu,
+    omega_jac, sweep 'x'/'ud', precision 'fp64'/'mixed', restart).
+    """
+
+    def __init__(self, c, omega, h, pml, J, S_outer=0.0, c_pml=0.0, **opts):
+        lib = load()
+        if not (c.is_cuda and c.dtype == torch.float64 and c.is_contiguous() and c.dim() == 2):
+            raise ValueError("c must be a contiguous 2-D float64 CUDA tensor")
+        pml = (pml, pml) if isinstance(pml, int) else tuple(pml)
+        n = (c.shape[0] - 2 * pml[0], c.shape[1] - 2 * pml[1])
+        self.shape = tuple(c.shape)
+        self.grid = make_grid(n, h, pml, S_outer, c_pml)
+        self.opts = make_options(**opts)
+        self.J = int(J)
+        S = ctypes.c_size_t()
+        _check(lib.hsp_workspace_size(ctypes.byref(self.grid), self.J, ctypes.byref(self.opts), ctypes.byref(S)))
+        self.ws = torch.empty(S.value, dtype=torch.uint8, device=c.device)
+        hd = ctypes.c_void_p()
+        _check(lib.hsp_setup(_ptr(c), float(omega), ctypes.byref(self.grid), self.J, ctypes.byref(self.opts),
+                             _ptr(self.ws), S.value, _stream(), ctypes.byref(hd)))
+        self.handle = hd
+        inf = HspInfo()
+        _check(lib.hsp_get_info(self.handle, ctypes.byref(inf)))
+        self.n_fine = tuple(inf.n_fine)
+        self.n_coarse = tuple(inf.n_coarse)
+        self.max_slab_layers = inf.max_slab_layers
+        self.two_grid = bool(inf.two_grid)
+        beta = (ctypes.c_int * (self.J + 1))()
+        x0 = (ctypes.c_int * self.J)()
+        x1 = (ctypes.c_int * self.J)()
+        _check(lib.hsp_get_partition(self.handle, beta, x0, x1))
+        self.beta, self.x0, self.x1 = list(beta), list(x0), list(x1)
+        self.dd_shape = self.n_coarse if self.two_grid else self.n_fine
+
+    # -- lifecycle ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            load().hsp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls ----------------------------------------------------------------
+    def _new(self, shape):
+        return torch.empty(shape, dtype=torch.complex128, device=self.ws.device)
+
+    def rhs(self, f):
+        _vec(f, self.n_fine, "f")
+        b = self._new(self.n_fine)
+        _check(load().hsp_rhs(self.handle, _ptr(f), _ptr(b), _stream()))
+        return b
+
+    def apply_operator(self, x):
+        _vec(x, self.n_fine, "x")
+        y = self._new(self.n_fine)
+        _check(load().hsp_apply_operator(self.handle, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def apply_level_operator(self, level, x):
+        shape = self.n_fine if level == 0 else self.n_coarse
+        _vec(x, shape, "x")
+        y = self._new(shape)
+        _check(load().hsp_apply_level_operator(self.handle, int(level), _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def apply_precond(self, r, out=None):
+        _vec(r, self.n_fine, "r")
+        z = self._new(self.n_fine) if out is None else _vec(out, self.n_fine, "out")
+        _check(load().hsp_apply_precond(self.handle, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def restrict(self, rf):
+        _vec(rf, self.n_fine, "rf")
+        rc = self._new(self.n_coarse)
+        _check(load().hsp_restrict(self.handle, _ptr(rf), _ptr(rc), _stream()))
+        return rc
+
+    def prolong_add(self, ec, xf):
+        _vec(ec, self.n_coarse, "ec")
+        _vec(xf, self.n_fine, "xf")
+        _check(load().hsp_prolong_add(self.handle, _ptr(ec), _ptr(xf), _stream()))
+        return xf
+
+    def smooth(self, r, steps):
+        _vec(r, self.n_fine, "r")
+        x = self._new(self.n_fine)
+        _check(load().hsp_smooth(self.handle, _ptr(r), _ptr(x), int(steps), _stream()))
+        return x
+
+    def sweep(self, f):
+        _vec(f, self.dd_shape, "f")
+        u = self._new(self.dd_shape)
+        _check(load().hsp_sweep(self.handle, _ptr(f), _ptr(u), _stream()))
+        return u
+
+    def slab_solve(self, j, b):
+        nl = self.x1[j] - self.x0[j] + 1
+        shape = (nl, self.dd_shape[1])
+        _vec(b, shape, "b")
+        x = self._new(shape)
+        _check(load().hsp_slab_solve(self.handle, int(j), _ptr(b), _ptr(x), _stream()))
+        return x
+
+    def solve(self, b, tol=1e-6, maxit=200, conj_transpose=False, out=None, raise_on_noconv=True):
+        """FGMRES on A u = b (b already FE scaled, see rhs).  Returns
+        (u, iterations, true relative residual)."""
+        _vec(b, self.n_fine, "b")
+        u = self._new(self.n_fine) if out is None else _vec(out, self.n_fine, "out")
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        st = load().hsp_solve(self.handle, _ptr(b), _ptr(u), float(tol), int(maxit), int(bool(conj_transpose)),
+                              ctypes.byref(it), ctypes.byref(rr), _stream())
+        if st == HSP_ENOCONV and not raise_on_noconv:
+            return u, it.value, rr.value
+        _check(st)
+        return u, it.value, rr.value

@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/hsp.h; host-side argument validation works without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1412_0464_amd import hsp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "hsp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsp_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hsp.load()
+    names = _declared()
+    assert "hsp_setup" in names and "hsp_solve" in names and "hsp_apply_precond" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(hsp.EXPORTS)
+
+
+def test_default_options():
+    o = hsp.make_options()
+    assert (o.fine_stencil, o.two_grid, o.w_dd, o.nu, o.sweep, o.precision) == (5, 0, 4, 3, 0, 0)
+    assert abs(o.omega_jac - 0.8) < 1e-15
+
+
+def _ws(n=(127, 127), h=1 / 128, pml=(10, 10), J=4, **kw):
+    return hsp.workspace_size(n, h, pml, J, **kw)
+
+
+def test_workspace_size_valid_configs():
+    assert _ws() > 0
+    assert _ws(two_grid=True, n=(255, 255), pml=(16, 16), J=8) > 0
+    assert _ws(precision="mixed") < _ws(precision="fp64")
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(J=0), "J"),
+    (dict(J=60), "thinner than 3"),                     # cores thinner than 3 layers
+    (dict(J=1), "slab thicker"),                        # 147 layers in one slab
+    (dict(w_dd=0), "w_dd"),
+    (dict(two_grid=True, n=(126, 127)), "even"),        # odd interior cell count
+    (dict(fine_stencil=7), "fine_stencil"),
+    (dict(h=-1.0), "h must"),
+    (dict(nu=-1), "nu"),
+    (dict(restart=0), "restart"),
+])
+def test_workspace_size_rejects_invalid(kw, msg):
+    with pytest.raises(hsp.HspError) as e:
+        _ws(**kw)
+    assert e.value.status == hsp.HSP_EINVAL
+    assert msg in str(e.value)
+
+
+def test_null_arguments_rejected_without_device():
+    lib = hsp.load()
+    assert lib.hsp_workspace_size(None, 4, None, None) == hsp.HSP_EINVAL
+    assert lib.hsp_apply_precond(None, None, None, None) == hsp.HSP_EINVAL
+    assert lib.hsp_solve(None, None, None, 1e-6, 10, 0, None, None, None) == hsp.HSP_EINVAL
+    out = ctypes.c_void_p()
+    g = hsp.make_grid((31, 31), 0.1, (4, 4))
+    o = hsp.make_options()
+    assert lib.hsp_setup(None, 1.0, ctypes.byref(g), 2, ctypes.byref(o), None, 0, None,
+                         ctypes.byref(out)) == hsp.HSP_EINVAL
+    assert b"null" in lib.hsp_last_error()
