@@ -295,6 +295,7 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
 struct Stage {
   int residual;
   int first, ntasks;
+  int nl;  // thickest slab among the stage's tasks
 };
 
 }  // namespace
@@ -372,8 +373,11 @@ void build_schedule(hsp_ctx* C) {
     return t;
   };
   auto push_stage = [&](std::vector<TaskDev> ts) {
-    Stage s{0, (int)T.size(), (int)ts.size()};
-    for (auto& t : ts) T.push_back(t);
+    Stage s{0, (int)T.size(), (int)ts.size(), 0};
+    for (auto& t : ts) {
+      T.push_back(t);
+      s.nl = std::max(s.nl, P.x1[t.slab] - P.x0[t.slab] + 1);
+    }
     if (s.ntasks > 0) S.push_back(s);
   };
   auto mark = [&](const TaskDev& t) {
@@ -386,7 +390,7 @@ void build_schedule(hsp_ctx* C) {
       push_stage({t});
       mark(t);
     }
-    S.push_back(Stage{1, 0, 0});
+    S.push_back(Stage{1, 0, 0, 0});
     for (int j = J; j >= 1; --j) {
       TaskDev t = bwd(j, 1, 0);
       push_stage({t});
@@ -415,7 +419,7 @@ void build_schedule(hsp_ctx* C) {
     t.bt_in = bt[jm];
     push_stage({t});
   }
-  S.push_back(Stage{1, 0, 0});
+  S.push_back(Stage{1, 0, 0, 0});
   written[0] = written[1] = false;
   {  // MidSolveOut: forward output -> buffer 1, backward output -> buffer 0
     TaskDev t = blank(jm);
@@ -454,7 +458,7 @@ void run_sweep(hsp_ctx* C, const cx<T>* f, cx<T>* u, hipStream_t s) {
       launch_stencil<T, T, T, T>(C->dd, 1, u, f, g, 0.0, s);
     } else {
       launch_stage<T>(C->tasks_dev + st.first, st.ntasks, C->slabs_dev, C->dd, f, g, u, C->at<T>(P.o_swB),
-                      C->at<T>(P.o_swscr), reinterpret_cast<const cx<T>*>(C->factors), P.nl_max, s);
+                      C->at<T>(P.o_swscr), reinterpret_cast<const cx<T>*>(C->factors), P.nl_max, st.nl, s);
     }
   }
 }
@@ -1013,14 +1017,14 @@ hsp_status hsp_slab_solve(hsp_handle C, int j, const void* b, void* x, void* str
     cd* uo = C->at<double>(P.o_swu);
     launch_convert<double, double>((const cd*)b, fin, n, 0, s);
     launch_stage<double>(td, 1, C->slabs_dev, C->dd, fin, fin, uo, C->at<double>(P.o_swB), C->at<double>(P.o_swscr),
-                         reinterpret_cast<const cd*>(C->factors), P.nl_max, s);
+                         reinterpret_cast<const cd*>(C->factors), P.nl_max, nl, s);
     launch_convert<double, double>(uo, (cd*)x, n, 0, s);
   } else {
     cf* fin = C->at<float>(P.o_swf);
     cf* uo = C->at<float>(P.o_swu);
     launch_convert<float, double>((const cd*)b, fin, n, 0, s);
     launch_stage<float>(td, 1, C->slabs_dev, C->dd, fin, fin, uo, C->at<float>(P.o_swB), C->at<float>(P.o_swscr),
-                        reinterpret_cast<const cf*>(C->factors), P.nl_max, s);
+                        reinterpret_cast<const cf*>(C->factors), P.nl_max, nl, s);
     launch_convert<double, float>(uo, (cd*)x, n, 0, s);
   }
   HIPCHK(hipGetLastError());

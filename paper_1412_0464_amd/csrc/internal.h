@@ -69,7 +69,7 @@ void launch_factor(const SlabDev* slabs_dev, int nslabs, int nl_max, int n2, cx<
 template <class T>
 void launch_stage(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev,
                   const LevelDev& G, const cx<T>* f, const cx<T>* g, cx<T>* u, cx<T>* bufs,
-                  cx<T>* scratch, const cx<T>* factors, int nl_max, hipStream_t s);
+                  cx<T>* scratch, const cx<T>* factors, int nl_max, int nl_launch, hipStream_t s);
 
 // ---- BLAS-1 and utilities (blas.hip) ---------------------------------------
 template <class To, class Ti>
