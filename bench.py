@@ -60,6 +60,9 @@ def source(cfg, shape):
 
 
 def gpu_run(cfg, c, f, precision, steps, warmup, tol, profile=False):
+    """Setup once, then time ``steps`` complete solves after ``warmup`` ones.
+    With ``profile`` the library brackets every kernel launch of each class
+    with HIP events on the solve's stream during the timed region."""
     import torch
     from paper_1412_0464_amd import Helmholtz
     dev = torch.device("cuda:0")
@@ -76,6 +79,10 @@ def gpu_run(cfg, c, f, precision, steps, warmup, tol, profile=False):
     for _ in range(warmup):
         hs.solve(b, tol=tol, maxit=200, out=u)
     torch.cuda.synchronize()
+    if profile:
+        hs.profile(True)
+        for cls in ("stage", "smooth", "coarse", "transfer", "krylov"):
+            hs.profile_read(cls)
     its = []
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -84,9 +91,33 @@ def gpu_run(cfg, c, f, precision, steps, warmup, tol, profile=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     res = dict(setup_s=setup_s, solve_s=dt / steps, iters=its[-1], relres=rr, total_iters=sum(its), time_s=dt)
+    if profile:
+        res["classes"] = {cls: hs.profile_read(cls) for cls in ("stage", "smooth", "coarse", "transfer", "krylov")}
+        hs.profile(False)
     res["u"] = u
     res["hs"] = hs
     return res
+
+
+def cpu_baseline(cfg, c, f, iters, tol):
+    """The CPU reference implementation (oracle), untuned, on a bounded
+    sample of the same workload: its full setup, then ``iters`` FGMRES
+    iterations of the same solve.  Single-threaded (SciPy sparse kernels and
+    SuperLU are; BLAS is pinned to one thread)."""
+    from threadpoolctl import threadpool_limits
+    from oracle.problem import Problem2D
+    dof = cfg["n"] ** 2
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        P = Problem2D(c, cfg["omega"], cfg["h"], cfg["w"], S_outer=cfg.get("S_outer"), c_pml=cfg.get("c_pml"),
+                      J=cfg["J"], w_dd=4, two_grid=cfg["two_grid"])
+        t1 = time.perf_counter()
+        _, it, hist, _ = P.solve(f, tol=tol, maxit=iters)
+        t2 = time.perf_counter()
+    return {"value": dof * it / (t2 - t1), "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"full setup ({t1 - t0:.1f} s) + {it} FGMRES iterations of the same solve "
+                      f"({t2 - t1:.1f} s); value = interior dof x iterations / iteration time",
+            "setup_s": t1 - t0, "s_per_iter": (t2 - t1) / max(it, 1)}
 
 
 def main():
@@ -98,7 +129,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -111,7 +142,7 @@ def main():
     dof = cfg["n"] ** 2
     print(f"[bench] {cfg['workload']}: {dof} interior dof, {c.size} unknowns", file=sys.stderr, flush=True)
 
-    mixed = gpu_run(cfg, c, f, "mixed", args.steps, args.warmup, args.tol)
+    mixed = gpu_run(cfg, c, f, "mixed", args.steps, args.warmup, args.tol, profile=True)
     print(f"[bench] mixed: setup {mixed['setup_s']:.3f} s, solve {mixed['solve_s'] * 1e3:.2f} ms, "
           f"{mixed['iters']} iters, relres {mixed['relres']:.2e}", file=sys.stderr, flush=True)
     value = dof * mixed["total_iters"] / mixed["time_s"]
@@ -124,6 +155,18 @@ def main():
                    "iterations": mixed["iters"], "relres": mixed["relres"],
                    "setup_s": mixed["setup_s"], "solve_s": mixed["solve_s"], "precision": "mixed"},
     }
+    # roofline of the dominant kernel class (the fused slab-solve stage):
+    # algorithmic bytes per launch / average event-timed launch duration
+    cls = mixed["classes"]
+    st_ms, st_n, st_bytes = cls["stage"]
+    per_launch_bytes = st_bytes / max(st_n, 1)
+    per_launch_s = st_ms * 1e-3 / max(st_n, 1)
+    achieved = per_launch_bytes / per_launch_s / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_stage (fused SubdomSolve stage)", "launches": st_n,
+                       "avg_launch_us": per_launch_s * 1e6, "alg_bytes_per_launch": per_launch_bytes}
+    out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
     if not args.no_fp64:
         fp = gpu_run(cfg, c, f, "fp64", args.steps, args.warmup, args.tol)
         print(f"[bench] fp64: setup {fp['setup_s']:.3f} s, solve {fp['solve_s'] * 1e3:.2f} ms, "
@@ -133,6 +176,9 @@ def main():
                        "setup_s": fp["setup_s"], "iterations": fp["iters"], "relres": fp["relres"],
                        "mixed_vs_fp64_rel_l2": float(np.linalg.norm(um - uf) / np.linalg.norm(uf)),
                        "speedup_mixed_over_fp64": fp["solve_s"] / mixed["solve_s"]}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, c, f, args.cpu_iters, args.tol)
     print(json.dumps(out))
 
 

@@ -190,6 +190,26 @@ hsp_status hsp_sweep(hsp_handle hd, const void* f_dev, void* u_dev, void* stream
  * the stored factors. */
 hsp_status hsp_slab_solve(hsp_handle hd, int j, const void* b_dev, void* x_dev, void* stream);
 
+/* ---- Timing (tracing aid).  When enabled, every kernel launch of the
+ *      classes below is bracketed by a pair of HIP events on the stream it
+ *      is launched on; hsp_profile_read synchronises on the last event and
+ *      returns the summed event time, the launch count and the algorithmic
+ *      bytes of those launches (what the method must move: factors, the
+ *      gathered right-hand side, the scattered solution and transmission
+ *      layers for a sweep stage; the vectors and coefficients read and the
+ *      vector written for a stencil or transfer), then resets the class. */
+enum {
+  HSP_PROF_STAGE = 0,     /* fused slab-solve stage kernels (sweeps)        */
+  HSP_PROF_SMOOTH = 1,    /* fine-level Jacobi / residual kernels (two-grid) */
+  HSP_PROF_COARSE = 2,    /* residual inside the sweep (DD level)           */
+  HSP_PROF_TRANSFER = 3,  /* restriction and prolongation                   */
+  HSP_PROF_KRYLOV = 4,    /* FGMRES matvec and Gram-Schmidt kernels         */
+  HSP_PROF_NCLASS = 5
+};
+hsp_status hsp_profile_enable(hsp_handle hd, int on);
+hsp_status hsp_profile_read(hsp_handle hd, int cls, double* total_ms, long long* launches,
+                            double* alg_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -295,7 +295,17 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
 struct Stage {
   int residual;
   int first, ntasks;
-  int nl;  // thickest slab among the stage's tasks
+  int nl;        // thickest slab among the stage's tasks
+  double bytes;  // algorithmic bytes per complex unit (times sizeof(T) at launch)
+};
+
+// Event-pair timing per kernel class.
+struct Prof {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[HSP_PROF_NCLASS];
+  size_t used[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
+  double bytes[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
+  long long n[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
 };
 
 }  // namespace
@@ -315,6 +325,14 @@ struct hsp_ctx {
   TaskDev* tasks_dev = nullptr;
   std::vector<TaskDev> tasks_host;
   void* factors = nullptr;
+  Prof prof;
+  ~hsp_ctx() {
+    for (int c = 0; c < HSP_PROF_NCLASS; ++c)
+      for (auto& e : prof.ev[c]) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+  }
   template <class T>
   cx<T>* at(size_t off) const {
     return reinterpret_cast<cx<T>*>(ws + off);
@@ -373,10 +391,16 @@ void build_schedule(hsp_ctx* C) {
     return t;
   };
   auto push_stage = [&](std::vector<TaskDev> ts) {
-    Stage s{0, (int)T.size(), (int)ts.size(), 0};
+    Stage s{0, (int)T.size(), (int)ts.size(), 0, 0.0};
+    const double n2 = P.dd_n2;
     for (auto& t : ts) {
       T.push_back(t);
-      s.nl = std::max(s.nl, P.x1[t.slab] - P.x0[t.slab] + 1);
+      const int nl = P.x1[t.slab] - P.x0[t.slab] + 1;
+      s.nl = std::max(s.nl, nl);
+      // factors G, E and the couplings; gathered rows; u read-modify-write;
+      // transmission layers in and out (complex units)
+      s.bytes += n2 * (2.0 * nl * nl + 3.0 * nl) + n2 * (t.b - t.a) + 2.0 * n2 * (t.bt - t.at) +
+                 2.0 * n2 * (t.t1 + t.t2 + t.t3 + t.t4);
     }
     if (s.ntasks > 0) S.push_back(s);
   };
@@ -390,7 +414,7 @@ void build_schedule(hsp_ctx* C) {
       push_stage({t});
       mark(t);
     }
-    S.push_back(Stage{1, 0, 0, 0});
+    S.push_back(Stage{1, 0, 0, 0, 0.0});
     for (int j = J; j >= 1; --j) {
       TaskDev t = bwd(j, 1, 0);
       push_stage({t});
@@ -419,7 +443,7 @@ void build_schedule(hsp_ctx* C) {
     t.bt_in = bt[jm];
     push_stage({t});
   }
-  S.push_back(Stage{1, 0, 0, 0});
+  S.push_back(Stage{1, 0, 0, 0, 0.0});
   written[0] = written[1] = false;
   {  // MidSolveOut: forward output -> buffer 1, backward output -> buffer 0
     TaskDev t = blank(jm);
@@ -447,6 +471,30 @@ void build_schedule(hsp_ctx* C) {
 // ---------------------------------------------------------------------------
 // Sweep, two-grid cycle and preconditioner
 // ---------------------------------------------------------------------------
+void prof_begin(hsp_ctx* C, int cls, hipStream_t s) {
+  Prof& P = C->prof;
+  if (!P.on) return;
+  if (P.used[cls] == P.ev[cls].size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return;
+    }
+    P.ev[cls].push_back({a, b});
+  }
+  (void)hipEventRecord(P.ev[cls][P.used[cls]].first, s);
+}
+
+void prof_end(hsp_ctx* C, int cls, hipStream_t s, double bytes) {
+  Prof& P = C->prof;
+  if (!P.on || P.used[cls] >= P.ev[cls].size()) return;
+  (void)hipEventRecord(P.ev[cls][P.used[cls]].second, s);
+  ++P.used[cls];
+  ++P.n[cls];
+  P.bytes[cls] += bytes;
+}
+
 template <class T>
 void run_sweep(hsp_ctx* C, const cx<T>* f, cx<T>* u, hipStream_t s) {
   const Plan& P = C->P;
@@ -455,10 +503,15 @@ void run_sweep(hsp_ctx* C, const cx<T>* f, cx<T>* u, hipStream_t s) {
   launch_zero<T>(u, nd, s);
   for (const Stage& st : C->stages) {
     if (st.residual) {
+      prof_begin(C, HSP_PROF_COARSE, s);
       launch_stencil<T, T, T, T>(C->dd, 1, u, f, g, 0.0, s);
+      // u, f read, g written, medium per node
+      prof_end(C, HSP_PROF_COARSE, s, (double)nd * (3.0 * sizeof(cx<T>) + 4.0 * sizeof(double)));
     } else {
+      prof_begin(C, HSP_PROF_STAGE, s);
       launch_stage<T>(C->tasks_dev + st.first, st.ntasks, C->slabs_dev, C->dd, f, g, u, C->at<T>(P.o_swB),
                       C->at<T>(P.o_swscr), reinterpret_cast<const cx<T>*>(C->factors), P.nl_max, st.nl, s);
+      prof_end(C, HSP_PROF_STAGE, s, st.bytes * sizeof(cx<T>));
     }
   }
 }
@@ -483,7 +536,11 @@ void run_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
   const int nu = C->opt.nu;
   cx<T>* xa = C->at<T>(P.o_tgx0);
   cx<T>* xb = C->at<T>(P.o_tgx1);
+  const size_t nc = (size_t)P.nc1 * P.nc2;
+  // bytes of one smoothing step: r, x read, x written, k^2 per node
+  const double jb = (double)nf * (sizeof(cd) + 2.0 * sizeof(cx<T>) + sizeof(double));
   // pre-smoothing from x = 0
+  prof_begin(C, HSP_PROF_SMOOTH, s);
   if (nu > 0) {
     launch_stencil<T, T, double, T>(C->fine, 2, (const cx<T>*)nullptr, r, xa, wj, s);
     for (int k = 1; k < nu; ++k) {
@@ -496,16 +553,22 @@ void run_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
   // coarse-grid correction: r_c = P^T (r - A x), e_c = P_X r_c, x += P e_c
   cd* res = C->at<double>(P.o_tgres);
   launch_stencil<double, T, double, double>(C->fine, 1, xa, r, res, 0.0, s);
+  prof_end(C, HSP_PROF_SMOOTH, s, nu * jb + (double)nf * (2.0 * sizeof(cd) + sizeof(cx<T>) + sizeof(double)));
   cx<T>* rc = C->at<T>(P.o_tgrc);
   cx<T>* ec = C->at<T>(P.o_tgec);
+  prof_begin(C, HSP_PROF_TRANSFER, s);
   launch_restrict<double, T>(C->tr, res, rc, s);
+  prof_end(C, HSP_PROF_TRANSFER, s, (double)nf * sizeof(cd) + (double)nc * sizeof(cx<T>));
   run_sweep<T>(C, rc, ec, s);
+  prof_begin(C, HSP_PROF_TRANSFER, s);
   launch_prolong_add<T, T>(C->tr, ec, xa, s);
+  prof_end(C, HSP_PROF_TRANSFER, s, (double)nc * sizeof(cx<T>) + 2.0 * nf * sizeof(cx<T>));
   // post-smoothing, the last step writes z in double
   if (nu == 0) {
     launch_convert<double, T>(xa, z, nf, 0, s);
     return;
   }
+  prof_begin(C, HSP_PROF_SMOOTH, s);
   for (int k = 0; k < nu; ++k) {
     if (k == nu - 1) {
       launch_stencil<T, T, double, double>(C->fine, 2, xa, r, z, wj, s);
@@ -514,6 +577,7 @@ void run_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
       std::swap(xa, xb);
     }
   }
+  prof_end(C, HSP_PROF_SMOOTH, s, nu * jb);
 }
 
 void precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
@@ -1032,6 +1096,33 @@ hsp_status hsp_slab_solve(hsp_handle C, int j, const void* b, void* x, void* str
   return HSP_OK;
 }
 
+hsp_status hsp_profile_enable(hsp_handle C, int on) {
+  if (!C) return fail(HSP_EINVAL, "null handle");
+  C->prof.on = on != 0;
+  return HSP_OK;
+}
+
+hsp_status hsp_profile_read(hsp_handle C, int cls, double* total_ms, long long* launches, double* alg_bytes) {
+  if (!C || cls < 0 || cls >= HSP_PROF_NCLASS) return fail(HSP_EINVAL, "bad handle or class");
+  Prof& P = C->prof;
+  double ms = 0;
+  if (P.used[cls] > 0) {
+    HIPCHK(hipEventSynchronize(P.ev[cls][P.used[cls] - 1].second));
+    for (size_t i = 0; i < P.used[cls]; ++i) {
+      float e = 0;
+      HIPCHK(hipEventElapsedTime(&e, P.ev[cls][i].first, P.ev[cls][i].second));
+      ms += e;
+    }
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = P.n[cls];
+  if (alg_bytes) *alg_bytes = P.bytes[cls];
+  P.used[cls] = 0;
+  P.n[cls] = 0;
+  P.bytes[cls] = 0;
+  return HSP_OK;
+}
+
 hsp_status hsp_apply_precond(hsp_handle C, const void* r, void* z, void* stream) {
   if (!C || !r || !z || r == z) return fail(HSP_EINVAL, "null or aliased argument");
   precond(C, (const cd*)r, (cd*)z, S_(stream));
@@ -1098,6 +1189,7 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
       cd* vk = V + (size_t)k * n;
       cd* zk = Z + (size_t)k * n;
       precond(C, vk, zk, s);
+      prof_begin(C, HSP_PROF_KRYLOV, s);
       launch_stencil<double, double, double, double>(A, 0, zk, (const cd*)nullptr, w, 0.0, s);
       // classical Gram-Schmidt, twice
       dotn(V, k + 1, w, hb);
@@ -1106,6 +1198,10 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
       launch_multiaxpy(V, n, k + 1, hb + (m + 1), w, n, 1, s);
       dotn(w, 1, w, hb + 2 * (m + 1));
       launch_normalize(w, hb + 2 * (m + 1), V + (size_t)(k + 1) * n, n, s);
+      // matvec (z, k^2 read, w written) + two Gram-Schmidt passes over k+1
+      // basis vectors + norm + normalisation, complex128 vectors
+      prof_end(C, HSP_PROF_KRYLOV, s, (double)n * (2.0 * sizeof(cd) + sizeof(double)) +
+                                          (double)n * sizeof(cd) * (4.0 * k + 13.0));
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(hh.data(), hb, hh.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));

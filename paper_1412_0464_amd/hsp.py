@@ -46,7 +46,8 @@ class HspInfo(ctypes.Structure):
 EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", "hsp_apply_operator",
            "hsp_apply_precond", "hsp_solve", "hsp_destroy", "hsp_last_error", "hsp_get_info",
            "hsp_get_partition", "hsp_apply_level_operator", "hsp_restrict", "hsp_prolong_add",
-           "hsp_smooth", "hsp_sweep", "hsp_slab_solve"]
+           "hsp_smooth", "hsp_sweep", "hsp_slab_solve", "hsp_profile_enable", "hsp_profile_read"]
+PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4}
 
 
 def library_path():
@@ -81,6 +82,8 @@ def load():
         "hsp_smooth": [P, P, P, I, P],
         "hsp_sweep": [P, P, P, P],
         "hsp_slab_solve": [P, I, P, P, P],
+        "hsp_profile_enable": [P, I],
+        "hsp_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -259,6 +262,20 @@ class Helmholtz:
         x = self._new(shape)
         _check(load().hsp_slab_solve(self.handle, int(j), _ptr(b), _ptr(x), _stream()))
         return x
+
+    def profile(self, on=True):
+        """Enable or disable per-kernel-class event timing (hsp_profile_enable)."""
+        _check(load().hsp_profile_enable(self.handle, int(bool(on))))
+
+    def profile_read(self, cls):
+        """(total event ms, launches, algorithmic bytes) of a kernel class since
+        the last read; resets the class (hsp_profile_read)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        by = ctypes.c_double()
+        c = PROF_CLASSES[cls] if isinstance(cls, str) else int(cls)
+        _check(load().hsp_profile_read(self.handle, c, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+        return ms.value, n.value, by.value
 
     def solve(self, b, tol=1e-6, maxit=200, conj_transpose=False, out=None, raise_on_noconv=True):
         """FGMRES on A u = b (b already FE scaled, see rhs).  Returns
