@@ -79,10 +79,14 @@ typedef struct hsp_options {
                        slab factors and sweeps complex64; FGMRES, its
                        residual and the restriction / prolongation complex128 */
   int restart;      /* FGMRES restart length (sizes the workspace)            */
+  int chunk;        /* blocks per chunk of the parallel slab substitutions
+                       (1..64); 0 selects about sqrt(2 n_t) for n_t tangential
+                       nodes.  Changes the evaluation order only.             */
 } hsp_options;
 
 /* Fills *opt with: fine_stencil 5, two_grid 0, w_dd 4, S_dd 0 (= 5 w_dd),
- * nu 3, omega_jac 0.8 (Sec. 5, Table 2), sweep X, precision FP64, restart 40. */
+ * nu 3, omega_jac 0.8 (Sec. 5, Table 2), sweep X, precision FP64, restart 40,
+ * chunk 0 (automatic). */
 hsp_status hsp_default_options(hsp_options* opt);
 
 /* Bytes of device workspace that hsp_setup needs for this geometry, slab

@@ -101,6 +101,7 @@ struct Plan {
   int fine_kind = 5;
   std::vector<int> beta, bt, x0, x1;
   int nl_max = 0;
+  int chunk = 0, nchunk = 0;              // parallel substitution: chunk length m, count P
   size_t tsize = 16;                      // bytes per preconditioner complex
   int m = 0;                              // FGMRES restart
   // workspace offsets
@@ -112,6 +113,7 @@ struct Plan {
   size_t o_swf, o_swg, o_swu, o_swB, o_swscr;
   size_t o_tgx0, o_tgx1, o_tgres, o_tgrc, o_tgec, o_cvin, o_cvout;
   size_t o_V, o_Z, o_w, o_part, o_hbuf, o_stats, o_bconj;
+  size_t o_red, o_ctr, o_setup, o_ttmp;  // chunk tips/heads, arrival counters, setup scratch (aliases V, Z)
   size_t n_slabA = 0, n_xmap = 0, n_fac = 0, n_tasks = 0;
   size_t total = 0;
 };
@@ -134,6 +136,7 @@ hsp_status validate(const hsp_grid* g, int J, const hsp_options* o) {
   if (o->sweep != HSP_SWEEP_X && o->sweep != HSP_SWEEP_UD) return fail(HSP_EINVAL, "bad sweep");
   if (o->precision != HSP_FP64 && o->precision != HSP_MIXED) return fail(HSP_EINVAL, "bad precision");
   if (!std::isfinite(o->omega_jac)) return fail(HSP_EINVAL, "bad omega_jac");
+  if (o->chunk < 0 || o->chunk > kMaxChunk) return fail(HSP_EINVAL, "chunk must be in 0..64");
   return HSP_OK;
 }
 
@@ -205,6 +208,14 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   }
   if (P.nl_max > kMaxSlabLayers)
     return fail(HSP_EINVAL, "slab thicker than " + std::to_string(kMaxSlabLayers) + " layers: use more slabs");
+  if (o->chunk > 0) {
+    P.chunk = o->chunk;
+  } else {
+    P.chunk = (int)std::ceil(std::sqrt(2.0 * P.dd_n2));
+    P.chunk = std::max(8, std::min(kMaxChunk, P.chunk));
+  }
+  P.chunk = std::min(P.chunk, P.dd_n2);
+  P.nchunk = (P.dd_n2 + P.chunk - 1) / P.chunk;
 
   // ---- workspace layout
   Carver c;
@@ -255,6 +266,8 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
     P.n_xmap += (size_t)(nl + 1);
     P.n_fac += slab_factor_elems(nl, P.dd_n2);
   }
+  P.o_red = c.take((size_t)2 * 2 * P.nchunk * P.nl_max * P.tsize);
+  P.o_ctr = c.take(64 * sizeof(int));
   P.o_slabs = c.take(J * sizeof(SlabDev));
   P.o_slabA = c.take(P.n_slabA * sizeof(cd));
   P.o_slabB = c.take(P.n_slabA * sizeof(cd));
@@ -280,9 +293,17 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   }
   P.o_cvin = c.take(std::max(nf, nd) * sizeof(cd));
   P.o_cvout = c.take(std::max(nf, nd) * sizeof(cd));
-  // FGMRES
-  P.o_V = c.take((size_t)(P.m + 1) * nf * sizeof(cd));
-  P.o_Z = c.take((size_t)P.m * nf * sizeof(cd));
+  // FGMRES basis V, Z; during setup the same region holds the FP64 slab
+  // factors and the temporaries of the transfer-matrix kernel
+  size_t setup_elems = 0;
+  for (int j = 0; j < J; ++j) setup_elems += slab_setup_elems(P.x1[j] - P.x0[j] + 1, P.dd_n2);
+  const size_t ttmp_elems = (size_t)J * P.nchunk * kTransferTmpElems;
+  const size_t vz_bytes = (size_t)(2 * P.m + 1) * nf * sizeof(cd);
+  const size_t setup_bytes = (setup_elems + ttmp_elems) * sizeof(cd) + 512;
+  P.o_V = c.take(std::max(vz_bytes, setup_bytes));
+  P.o_Z = P.o_V + (size_t)(P.m + 1) * nf * sizeof(cd);
+  P.o_setup = P.o_V;
+  P.o_ttmp = P.o_V + ((setup_elems * sizeof(cd) + 255) & ~(size_t)255);
   P.o_w = c.take(nf * sizeof(cd));
   P.o_bconj = c.take(nf * sizeof(cd));
   P.o_part = c.take((size_t)kPartBlocks * (P.m + 2) * sizeof(cd));
@@ -510,7 +531,8 @@ void run_sweep(hsp_ctx* C, const cx<T>* f, cx<T>* u, hipStream_t s) {
     } else {
       prof_begin(C, HSP_PROF_STAGE, s);
       launch_stage<T>(C->tasks_dev + st.first, st.ntasks, C->slabs_dev, C->dd, f, g, u, C->at<T>(P.o_swB),
-                      C->at<T>(P.o_swscr), reinterpret_cast<const cx<T>*>(C->factors), P.nl_max, st.nl, s);
+                      C->at<T>(P.o_swscr), reinterpret_cast<const cx<T>*>(C->factors), P.nl_max, st.nl, P.chunk,
+                      P.nchunk, C->at<T>(P.o_red), C->raw<int>(P.o_ctr), s);
       prof_end(C, HSP_PROF_STAGE, s, st.bytes * sizeof(cx<T>));
     }
   }
@@ -609,6 +631,7 @@ hsp_status hsp_default_options(hsp_options* o) {
   o->sweep = HSP_SWEEP_X;
   o->precision = HSP_FP64;
   o->restart = 40;
+  o->chunk = 0;
   return HSP_OK;
 }
 
@@ -866,7 +889,7 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
     const double Cdd = S_dd * C->c_pml / (d * d * d);
     std::vector<cd> SA(P.n_slabA, mk<double>(0, 0)), SB(P.n_slabA, mk<double>(0, 0));
     std::vector<int> XM(P.n_xmap, 0);
-    size_t oA = 0, oM = 0, oF = 0;
+    size_t oA = 0, oM = 0, oF = 0, oS = 0;
     C->slabs_host.resize(J);
     const int ncell = P.dd_n1 + 1;  // cells of the DD level along x
     for (int j = 1; j <= J; ++j) {
@@ -907,10 +930,12 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
       sd.op.xB = C->at<double>(P.o_slabB) + oA;
       sd.op.xmap = C->raw<int>(P.o_xmap) + oM;
       sd.fac_off = oF;
+      sd.scr_off = oS;
       C->slabs_host[j - 1] = sd;
       oA += nl + 2;
       oM += nl + 1;
       oF += slab_factor_elems(nl, P.dd_n2);
+      oS += slab_setup_elems(nl, P.dd_n2);
     }
     up(P.o_slabA, SA.data(), SA.size() * sizeof(cd));
     up(P.o_slabB, SB.data(), SB.size() * sizeof(cd));
@@ -926,15 +951,16 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
   for (hipError_t e : errs)
     if (e != hipSuccess) return cleanup(fail(HSP_EDEVICE, std::string("upload: ") + hipGetErrorString(e)));
 
-  // factorization of all slabs
+  // factorization of all slabs, then the chunk transfer matrices
   int* status = C->raw<int>(P.o_status);
   CHK(hipMemsetAsync(status, 0, sizeof(int), s));
+  CHK(hipMemsetAsync(C->raw<int>(P.o_ctr), 0, 64 * sizeof(int), s));
   if (P.tsize == sizeof(cf))
-    launch_factor<float>(C->slabs_dev, J, P.nl_max, P.dd_n2, reinterpret_cast<cf*>(C->factors),
-                         C->at<double>(P.o_facscr), status, s);
+    launch_factor<float>(C->slabs_dev, J, P.nl_max, P.dd_n2, P.chunk, P.nchunk, reinterpret_cast<cf*>(C->factors),
+                         C->at<double>(P.o_setup), C->at<double>(P.o_facscr), C->at<double>(P.o_ttmp), status, s);
   else
-    launch_factor<double>(C->slabs_dev, J, P.nl_max, P.dd_n2, reinterpret_cast<cd*>(C->factors),
-                          C->at<double>(P.o_facscr), status, s);
+    launch_factor<double>(C->slabs_dev, J, P.nl_max, P.dd_n2, P.chunk, P.nchunk, reinterpret_cast<cd*>(C->factors),
+                          C->at<double>(P.o_setup), C->at<double>(P.o_facscr), C->at<double>(P.o_ttmp), status, s);
   CHK(hipGetLastError());
   int hstat = 0;
   CHK(hipMemcpyAsync(&hstat, status, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1081,14 +1107,16 @@ hsp_status hsp_slab_solve(hsp_handle C, int j, const void* b, void* x, void* str
     cd* uo = C->at<double>(P.o_swu);
     launch_convert<double, double>((const cd*)b, fin, n, 0, s);
     launch_stage<double>(td, 1, C->slabs_dev, C->dd, fin, fin, uo, C->at<double>(P.o_swB), C->at<double>(P.o_swscr),
-                         reinterpret_cast<const cd*>(C->factors), P.nl_max, nl, s);
+                         reinterpret_cast<const cd*>(C->factors), P.nl_max, nl, P.chunk, P.nchunk,
+                         C->at<double>(P.o_red), C->raw<int>(P.o_ctr), s);
     launch_convert<double, double>(uo, (cd*)x, n, 0, s);
   } else {
     cf* fin = C->at<float>(P.o_swf);
     cf* uo = C->at<float>(P.o_swu);
     launch_convert<float, double>((const cd*)b, fin, n, 0, s);
     launch_stage<float>(td, 1, C->slabs_dev, C->dd, fin, fin, uo, C->at<float>(P.o_swB), C->at<float>(P.o_swscr),
-                        reinterpret_cast<const cf*>(C->factors), P.nl_max, nl, s);
+                        reinterpret_cast<const cf*>(C->factors), P.nl_max, nl, P.chunk, P.nchunk,
+                        C->at<float>(P.o_red), C->raw<int>(P.o_ctr), s);
     launch_convert<double, float>(uo, (cd*)x, n, 0, s);
   }
   HIPCHK(hipGetLastError());

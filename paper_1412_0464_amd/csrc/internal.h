@@ -7,6 +7,7 @@
 namespace hsp {
 
 constexpr int kMaxSlabLayers = 56;   // 2-D slab thickness limit (LDS sized)
+constexpr int kMaxChunk = 64;        // longest chunk of the parallel substitutions
 constexpr int kWave = 64;
 
 // ---- stencil kernels (stencil.hip) ---------------------------------------
@@ -41,6 +42,7 @@ struct SlabDev {
   int nl;          // layers
   LevelDev op;     // the slab operator A^(j)
   size_t fac_off;  // element offset of this slab's factors
+  size_t scr_off;  // element offset (complex double) of its setup scratch
 };
 
 struct TaskDev {
@@ -56,20 +58,29 @@ struct TaskDev {
   int mode;                  // 0: subdomain solve on level vectors, 1: slab-layout solve
 };
 
-// Factor storage per slab (elements of cx<T>): G [n2][nl][nl] (column major
-// blocks), E [n2][nl][nl], Acoup [n2][3][nl].
-inline size_t slab_factor_elems(int nl, int n2) {
-  return (size_t)n2 * nl * nl * 2 + (size_t)n2 * 3 * nl;
+// Factor storage per slab (elements of cx<T>), column-major nl x nl blocks:
+// G_t, M_t = -G_t A_t, E_t, the chunk transfer matrices Y_t and X_t, each
+// [n2][nl][nl].
+inline size_t slab_factor_elems(int nl, int n2) { return (size_t)5 * n2 * nl * nl; }
+// Setup scratch per slab (complex double): G_t, E_t and the couplings A_t.
+inline size_t slab_setup_elems(int nl, int n2) {
+  return (size_t)2 * n2 * nl * nl + (size_t)3 * n2 * nl;
 }
+// Temporaries of the transfer-matrix kernel per (chunk, slab), complex double.
+constexpr size_t kTransferTmpElems = (size_t)3 * kMaxSlabLayers * kMaxSlabLayers;
 
 template <class T>
-void launch_factor(const SlabDev* slabs_dev, int nslabs, int nl_max, int n2, cx<T>* factors,
-                   cd* scratch, int* status, hipStream_t s);
+void launch_factor(const SlabDev* slabs_dev, int nslabs, int nl_max, int n2, int m, int P,
+                   cx<T>* factors, cd* setup, cd* scratchE, cd* tmp, int* status, hipStream_t s);
 
+// One SubdomSolve stage (ntasks slabs at once), as three launches over
+// (P chunks) x (ntasks).  red: per task 2 P nl_max complex (chunk tips and
+// heads); counters: 2 ints per task, zero between launches.
 template <class T>
 void launch_stage(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev,
                   const LevelDev& G, const cx<T>* f, const cx<T>* g, cx<T>* u, cx<T>* bufs,
-                  cx<T>* scratch, const cx<T>* factors, int nl_max, int nl_launch, hipStream_t s);
+                  cx<T>* scratch, const cx<T>* factors, int nl_max, int nl_launch, int m, int P,
+                  cx<T>* red, int* counters, hipStream_t s);
 
 // ---- BLAS-1 and utilities (blas.hip) ---------------------------------------
 template <class To, class Ti>

@@ -35,7 +35,8 @@ class HspGrid(ctypes.Structure):
 class HspOptions(ctypes.Structure):
     _fields_ = [("fine_stencil", ctypes.c_int), ("two_grid", ctypes.c_int), ("w_dd", ctypes.c_int),
                 ("S_dd", ctypes.c_double), ("nu", ctypes.c_int), ("omega_jac", ctypes.c_double),
-                ("sweep", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("sweep", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
+                ("chunk", ctypes.c_int)]
 
 
 class HspInfo(ctypes.Structure):
@@ -157,7 +158,7 @@ class Helmholtz:
     ``pml`` outer PML cells per side (int or pair); the interior node counts
             follow from c.shape - 2*pml.
     Options follow hsp_options (fine_stencil, two_grid, w_dd, S_dd, nu,
-    omega_jac, sweep 'x'/'ud', precision 'fp64'/'mixed', restart).
+    omega_jac, sweep 'x'/'ud', precision 'fp64'/'mixed', restart, chunk).
     """
 
     def __init__(self, c, omega, h, pml, J, S_outer=0.0, c_pml=0.0, **opts):

@@ -38,17 +38,18 @@ CASES = {
 }
 
 
-def _build(name, precision="fp64", J=None):
+def _build(name, precision="fp64", J=None, chunk=0):
     n1, n2, w, J0, fine, tg, sweep, ppw = CASES[name]
     J = J0 if J is None else J
     c = extend_into_pml(layered_medium_2d(n1, n2, 1412046, n_layers=7, corr_len=6.0), w)
     h = 0.02
     om = 2 * np.pi * 1.5 / (ppw * h)
-    print(f"[case {name} precision={precision} J={J} shape={c.shape}]", flush=True)
+    print(f"[case {name} precision={precision} J={J} chunk={chunk} shape={c.shape}]", flush=True)
     ref = Problem2D(c, om, h, w, S_outer=5.0 * w, J=J, w_dd=4, fine=fine, two_grid=tg, sweep=sweep)
     from paper_1412_0464_amd import Helmholtz
     hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, J, S_outer=5.0 * w,
-                   fine_stencil=5 if fine == "fd5" else 9, two_grid=tg, sweep=sweep, precision=precision)
+                   fine_stencil=5 if fine == "fd5" else 9, two_grid=tg, sweep=sweep, precision=precision,
+                   chunk=chunk)
     return c, ref, hs
 
 
@@ -136,6 +137,21 @@ def test_sweep_fp64(name):
     u = hs.sweep(_t(f)).cpu().numpy()
     uo = (ref.dd.apply_x if CASES[name][6] == "x" else ref.dd.apply_ud)(f)
     assert _relerr(u, uo) < 1e-10
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 13, 64])
+def test_sweep_chunk_geometry(chunk):
+    """The parallel substitutions give the same sweep for any chunk length:
+    one block per chunk, ragged last chunks, and a single chunk."""
+    c, ref, hs = _build("fd5_1lvl_x", chunk=chunk)
+    f = _rand(hs.dd_shape, 22)
+    u = hs.sweep(_t(f)).cpu().numpy()
+    assert _relerr(u, ref.dd.apply_x(f)) < 1e-10
+    for j in range(hs.J):
+        nl = hs.x1[j] - hs.x0[j] + 1
+        b = _rand((nl, hs.dd_shape[1]), 40 + j)
+        x = hs.slab_solve(j, _t(b)).cpu().numpy()
+        assert _relerr(x, ref.dd.lu[j].solve(b.ravel())) < 1e-10
 
 
 def test_sweep_mixed():
