@@ -194,6 +194,19 @@ hsp_status hsp_sweep(hsp_handle hd, const void* f_dev, void* u_dev, void* stream
  * the stored factors. */
 hsp_status hsp_slab_solve(hsp_handle hd, int j, const void* b_dev, void* x_dev, void* stream);
 
+/* Adjoint-state gradient of a data misfit with respect to the squared
+ * slowness m = 1/c^2 at the fine unknown nodes.  With A u = b, A^H lam = r
+ * (r = R^T of the misfit gradient, solved with hsp_solve(conj_transpose=1))
+ * and the FE-scaled 5-point operator, whose only m-dependence is the
+ * diagonal term -h^2 omega^2 m / (alpha_1 alpha_2) of eq. define_pml_fd:
+ *   g_dev[i] += h^2 omega^2 Re( conj(lam_i) u_i / (alpha_1 alpha_2)_i ).
+ * u_dev, lam_dev: complex128 fine vectors; g_dev: double fine array,
+ * accumulated in place.  Requires fine_stencil = 5 and an explicit c_pml in
+ * the grid (with c_pml = mean(c) the PML itself would depend on m).
+ * Errors: HSP_EINVAL otherwise. */
+hsp_status hsp_gradient_accumulate(hsp_handle hd, const void* u_dev, const void* lam_dev, double* g_dev,
+                                   void* stream);
+
 /* ---- Timing (tracing aid).  When enabled, every kernel launch of the
  *      classes below is bracketed by a pair of HIP events on the stream it
  *      is launched on; hsp_profile_read synchronises on the last event and

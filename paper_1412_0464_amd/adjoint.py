@@ -1,0 +1,62 @@
+"""Receiver-data misfit and its gradient with respect to the squared slowness
+m = 1/c^2, as a ``torch.autograd.Function`` over the GPU library.
+
+forward(m) solves A(m) u_s = b_s for every source with FGMRES and the
+preconditioner of the handle (hsp_solve) and returns the predicted data
+d_s = u_s[receivers] (complex, shape (n_sources, n_receivers)).
+backward(g_d) solves the adjoint systems A^H lam_s = R^T g_d,s with the same
+handle (hsp_solve with conj_transpose = 1, A being complex symmetric) and
+accumulates dL/dm = h^2 omega^2 sum_s Re(conj(lam_s) u_s / (alpha_1 alpha_2))
+in a device kernel (hsp_gradient_accumulate).  ``g_d`` is torch's
+conjugate-Wirtinger gradient of a real loss (for L = 1/2 ||d - d_obs||^2 it
+is d - d_obs).
+
+Selecting receiver values and placing the adjoint sources are index
+operations on device tensors; all arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from .hsp import Helmholtz
+
+
+class HelmholtzMisfit(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, m, sources, receivers, omega, h, pml, J, c_pml, tol, opts):
+        if not (c_pml and c_pml > 0):
+            raise ValueError("an explicit c_pml > 0 is required (with mean(c) the PML would depend on m)")
+        opts = dict(opts or {})
+        opts.setdefault("fine_stencil", 5)
+        c = torch.rsqrt(m.detach()).contiguous()
+        hs = Helmholtz(c, omega, h, pml, J, c_pml=c_pml, **opts)
+        us, ds = [], []
+        for s in range(sources.shape[0]):
+            b = hs.rhs(sources[s].contiguous())
+            u, it, rr = hs.solve(b, tol=tol, maxit=500)
+            us.append(u)
+            ds.append(u.reshape(-1)[receivers])
+        ctx.hs = hs
+        ctx.tol = tol
+        ctx.receivers = receivers
+        ctx.save_for_backward(*us)
+        return torch.stack(ds)
+
+    @staticmethod
+    def backward(ctx, grad_d):
+        hs = ctx.hs
+        us = ctx.saved_tensors
+        g = torch.zeros(hs.n_fine, dtype=torch.float64, device=grad_d.device)
+        for s, u in enumerate(us):
+            rt = torch.zeros(hs.n_fine, dtype=torch.complex128, device=grad_d.device)
+            rt.view(-1)[ctx.receivers] = grad_d[s].to(torch.complex128)
+            lam, it, rr = hs.solve(rt, tol=ctx.tol, maxit=500, conj_transpose=True)
+            hs.gradient_accumulate(u, lam, g)
+        return g, None, None, None, None, None, None, None, None, None
+
+
+def misfit(m, sources, receivers, d_obs, omega, h, pml, J, c_pml, tol=1e-8, **opts):
+    """L = 1/2 sum_s ||d_s(m) - d_obs_s||^2, differentiable in m."""
+    d = HelmholtzMisfit.apply(m, sources, receivers, omega, h, pml, J, c_pml, tol, opts)
+    r = d - d_obs
+    return 0.5 * (r.real ** 2 + r.imag ** 2).sum()

@@ -176,6 +176,16 @@ __global__ void k_cell_coefs(const double* __restrict__ k2c, size_t n, double h_
   }
 }
 
+__global__ void k_grad_m(int n1, int n2, double scale, const cd* __restrict__ ixn, const cd* __restrict__ iyn,
+                         const cd* __restrict__ u, const cd* __restrict__ lam, double* __restrict__ g) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= n2) return;
+  const size_t id = (size_t)i * n2 + k;
+  const cd w = conj(lam[id]) * (u[id] * (ixn[i + 1] * iyn[k + 1]));
+  g[id] += scale * w.re;
+}
+
 inline int nblk(size_t n) {
   size_t b = (n + 255) / 256;
   return (int)(b > 4096 ? 4096 : (b == 0 ? 1 : b));
@@ -215,6 +225,10 @@ void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t 
 void launch_scale_rhs_arrays(int n1, int n2, double h2, const cd* ixn, const cd* iyn, const cd* f, cd* b,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_scale_rhs, dim3((n2 + 255) / 256, n1), dim3(256), 0, s, n1, n2, h2, ixn, iyn, f, b);
+}
+void launch_grad_m(int n1, int n2, double scale, const cd* ixn, const cd* iyn, const cd* u, const cd* lam, double* g,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_m, dim3((n2 + 255) / 256, n1), dim3(256), 0, s, n1, n2, scale, ixn, iyn, u, lam, g);
 }
 void launch_stats(const double* c, size_t n, double* out4, hipStream_t s) {
   hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, c, n, out4);

@@ -1124,6 +1124,16 @@ hsp_status hsp_slab_solve(hsp_handle C, int j, const void* b, void* x, void* str
   return HSP_OK;
 }
 
+hsp_status hsp_gradient_accumulate(hsp_handle C, const void* u, const void* lam, double* g, void* stream) {
+  if (!C || !u || !lam || !g) return fail(HSP_EINVAL, "null argument");
+  if (C->opt.fine_stencil != 5) return fail(HSP_EINVAL, "the gradient is implemented for the 5-point fine operator");
+  if (!(C->grid.c_pml > 0)) return fail(HSP_EINVAL, "the gradient needs an explicit c_pml (not mean(c))");
+  launch_grad_m(C->P.nf1, C->P.nf2, C->h * C->h * C->omega * C->omega, C->at<double>(C->P.o_ixn),
+                C->at<double>(C->P.o_iyn), (const cd*)u, (const cd*)lam, g, S_(stream));
+  HIPCHK(hipGetLastError());
+  return HSP_OK;
+}
+
 hsp_status hsp_profile_enable(hsp_handle C, int on) {
   if (!C) return fail(HSP_EINVAL, "null handle");
   C->prof.on = on != 0;

@@ -100,6 +100,9 @@ void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t 
 // b = h2 * f / (alpha_1(x_i) alpha_2(y_k)); ixn, iyn = 1/alpha at nodes 0..n+1
 void launch_scale_rhs_arrays(int n1, int n2, double h2, const cd* ixn, const cd* iyn, const cd* f, cd* b,
                              hipStream_t s);
+// g += scale * Re(conj(lam) u / (alpha_1 alpha_2)) on the fine unknowns
+void launch_grad_m(int n1, int n2, double scale, const cd* ixn, const cd* iyn, const cd* u, const cd* lam, double* g,
+                   hipStream_t s);
 // statistics of a real array: [sum, min, max, count of non-finite or <= 0]
 void launch_stats(const double* c, size_t n, double* out4, hipStream_t s);
 // per-node medium arrays

@@ -47,7 +47,8 @@ class HspInfo(ctypes.Structure):
 EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", "hsp_apply_operator",
            "hsp_apply_precond", "hsp_solve", "hsp_destroy", "hsp_last_error", "hsp_get_info",
            "hsp_get_partition", "hsp_apply_level_operator", "hsp_restrict", "hsp_prolong_add",
-           "hsp_smooth", "hsp_sweep", "hsp_slab_solve", "hsp_profile_enable", "hsp_profile_read"]
+           "hsp_smooth", "hsp_sweep", "hsp_slab_solve", "hsp_profile_enable", "hsp_profile_read",
+           "hsp_gradient_accumulate"]
 PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4}
 
 
@@ -84,6 +85,7 @@ def load():
         "hsp_sweep": [P, P, P, P],
         "hsp_slab_solve": [P, I, P, P, P],
         "hsp_profile_enable": [P, I],
+        "hsp_gradient_accumulate": [P, P, P, P, P],
         "hsp_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D)],
     }
     for name, args in sig.items():
@@ -263,6 +265,15 @@ class Helmholtz:
         x = self._new(shape)
         _check(load().hsp_slab_solve(self.handle, int(j), _ptr(b), _ptr(x), _stream()))
         return x
+
+    def gradient_accumulate(self, u, lam, g):
+        """g += h^2 omega^2 Re(conj(lam) u / (alpha_1 alpha_2)) (hsp_gradient_accumulate)."""
+        _vec(u, self.n_fine, "u")
+        _vec(lam, self.n_fine, "lam")
+        if not (g.is_cuda and g.dtype == torch.float64 and g.is_contiguous() and tuple(g.shape) == self.n_fine):
+            raise ValueError("g must be a contiguous float64 CUDA tensor of the fine shape")
+        _check(load().hsp_gradient_accumulate(self.handle, _ptr(u), _ptr(lam), _ptr(g), _stream()))
+        return g
 
     def profile(self, on=True):
         """Enable or disable per-kernel-class event timing (hsp_profile_enable)."""

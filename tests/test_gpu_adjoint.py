@@ -1,0 +1,97 @@
+"""GPU adjoint gradient (torch.autograd.Function over the library) against
+the oracle's adjoint and against central finite differences."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import adjoint as ADJ  # noqa: E402
+from synth.media import layered_medium_2d, extend_into_pml, gaussian_anomaly, point_source  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")]
+C_PML = 3.0
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def config5(n=511, w=12, ns=16, seed=1412050):
+    """Layered medium n x n + w PML; true model with one +5 % Gaussian anomaly
+    (25 cells at full size); sources and receivers on the first interior row."""
+    cb = layered_medium_2d(n, n, seed)
+    sig = 25.0 * n / 511
+    ct = cb * gaussian_anomaly(cb.shape, ((n - 1) / 2, (n - 1) / 2), sig, 0.05)
+    cb, ct = extend_into_pml(cb, w), extend_into_pml(ct, w)
+    h = 0.01
+    om = 2 * np.pi * 1.5 / (8 * h)
+    shape = cb.shape
+    xs = [w + int((k + 0.5) * n / ns) for k in range(ns)]
+    src = np.array([point_source(shape, (x, w), h) for x in xs])
+    rec = np.array([i * shape[1] + w for i in range(w, w + n)])
+    return 1 / cb ** 2, 1 / ct ** 2, om, h, w, src, rec
+
+
+def _gpu_misfit(m, src, rec, d_obs, om, h, w, J, tol, **opts):
+    from paper_1412_0464_amd.adjoint import misfit
+    dev = _dev()
+    mt = torch.tensor(m, device=dev, requires_grad=True)
+    L = misfit(mt, torch.tensor(src, dtype=torch.complex128, device=dev), torch.tensor(rec, device=dev),
+               torch.tensor(d_obs, device=dev), om, h, w, J, C_PML, tol=tol, **opts)
+    L.backward()
+    return L.item(), mt.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("two_grid,J", [(False, 3), (True, 4)])
+def test_gradient_matches_oracle_small(two_grid, J):
+    m, mt, om, h, w, src, rec = config5(n=63, w=8, ns=4)
+    print(f"[adjoint small two_grid={two_grid} J={J}]", flush=True)
+    d_obs = ADJ.predicted_data(mt, om, h, w, 5.0 * w, C_PML, src, rec)
+    Lo, go, _ = ADJ.misfit_gradient(m, om, h, w, 5.0 * w, C_PML, src, rec, d_obs)
+    L, g = _gpu_misfit(m, src, rec, d_obs, om, h, w, J, 1e-11, two_grid=two_grid, S_outer=5.0 * w)
+    assert abs(L - Lo) <= 1e-8 * Lo
+    assert np.linalg.norm(g - go) <= 1e-6 * np.linalg.norm(go)
+
+
+def test_gradient_central_differences_small():
+    m, mt, om, h, w, src, rec = config5(n=47, w=6, ns=3)
+    d_obs = ADJ.predicted_data(mt, om, h, w, 5.0 * w, C_PML, src, rec)
+    L, g = _gpu_misfit(m, src, rec, d_obs, om, h, w, 3, 1e-12, S_outer=5.0 * w)
+    rng = np.random.default_rng(5)
+    for c in rng.choice(m.size, size=8, replace=False):
+        vals = []
+        for sgn in (1, -1):
+            mp = m.copy().ravel()
+            mp[c] += sgn * 1e-6
+            vals.append(_gpu_misfit(mp.reshape(m.shape), src, rec, d_obs, om, h, w, 3, 1e-12, S_outer=5.0 * w)[0])
+        fd = (vals[0] - vals[1]) / 2e-6
+        assert abs(fd - g.ravel()[c]) <= 1e-5 * np.abs(g).max()
+
+
+def test_config5_full_size():
+    """511^2 + 12 PML, 16 sources, 511 receivers, two-grid J = 16: the GPU
+    gradient against the oracle's adjoint (direct solves) and against central
+    differences (step 1e-6) at 32 random cells."""
+    m, mt, om, h, w, src, rec = config5()
+    print("[adjoint config5 511^2 + 12 PML, 16 sources, 511 receivers, TGSP J=16]", flush=True)
+    d_obs = ADJ.predicted_data(mt, om, h, w, 5.0 * w, C_PML, src, rec)
+    Lo, go, _ = ADJ.misfit_gradient(m, om, h, w, 5.0 * w, C_PML, src, rec, d_obs)
+    L, g = _gpu_misfit(m, src, rec, d_obs, om, h, w, 16, 1e-10, two_grid=True, S_outer=5.0 * w)
+    assert abs(L - Lo) <= 1e-7 * Lo
+    assert np.linalg.norm(g - go) <= 1e-5 * np.linalg.norm(go)
+    rng = np.random.default_rng(1412)
+    cells = rng.choice(m.size, size=32, replace=False)
+    errs = []
+    for c in cells:
+        vals = []
+        for sgn in (1, -1):
+            mp = m.copy().ravel()
+            mp[c] += sgn * 1e-6
+            vals.append(_gpu_misfit(mp.reshape(m.shape), src, rec, d_obs, om, h, w, 16, 1e-11, two_grid=True,
+                                    S_outer=5.0 * w)[0])
+        fd = (vals[0] - vals[1]) / 2e-6
+        errs.append(abs(fd - g.ravel()[c]))
+    print(f"[adjoint config5] max |fd - adj| / max|g| = {max(errs) / np.abs(g).max():.2e}", flush=True)
+    assert max(errs) <= 1e-4 * np.abs(g).max()

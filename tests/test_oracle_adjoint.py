@@ -1,0 +1,62 @@
+"""Pins of the oracle's adjoint gradient (P15): central finite differences
+with direct solves, and torch autograd through a dense complex solve."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as ADJ
+from synth.media import layered_medium_2d, extend_into_pml, gaussian_anomaly, point_source
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")
+
+
+def _case(n=23, w=5, ns=3):
+    cb = layered_medium_2d(n, n, 31, n_layers=5, corr_len=4.0)
+    ct = cb * gaussian_anomaly(cb.shape, (n / 2, n / 2), 3.0, 0.05)
+    cb, ct = extend_into_pml(cb, w), extend_into_pml(ct, w)
+    h = 0.02
+    om = 2 * np.pi * 1.5 / (8 * h)
+    shape = cb.shape
+    xs = [w + (k + 1) * n // (ns + 1) for k in range(ns)]
+    src = np.array([point_source(shape, (x, w), h) for x in xs])
+    rec = np.array([i * shape[1] + w for i in range(w, w + n)])
+    d_obs = ADJ.predicted_data(1 / ct ** 2, om, h, w, 5.0 * w, 2.5, src, rec)
+    return 1 / cb ** 2, om, h, w, src, rec, d_obs
+
+
+def test_adjoint_gradient_matches_central_differences():
+    m, om, h, w, src, rec, d_obs = _case()
+    L, g, _ = ADJ.misfit_gradient(m, om, h, w, 5.0 * w, 2.5, src, rec, d_obs)
+    assert L > 0
+    rng = np.random.default_rng(7)
+    cells = rng.integers(0, m.size, size=8)
+    dm = 1e-6
+    for c in cells:
+        mp, mm = m.copy().ravel(), m.copy().ravel()
+        mp[c] += dm
+        mm[c] -= dm
+        Lp = ADJ.misfit_gradient(mp.reshape(m.shape), om, h, w, 5.0 * w, 2.5, src, rec, d_obs)[0]
+        Lm = ADJ.misfit_gradient(mm.reshape(m.shape), om, h, w, 5.0 * w, 2.5, src, rec, d_obs)[0]
+        fd = (Lp - Lm) / (2 * dm)
+        assert abs(fd - g.ravel()[c]) <= 1e-5 * np.abs(g).max(), (c, fd, g.ravel()[c])
+
+
+def test_adjoint_gradient_matches_torch_autograd():
+    """A(m) = A(0) + diag(-h^2 omega^2 m / (alpha_1 alpha_2)) built densely in
+    torch; autograd of the misfit through torch.linalg.solve."""
+    m, om, h, w, src, rec, d_obs = _case(n=15, w=4, ns=2)
+    A0, scale, dscale = ADJ.operator(np.zeros_like(m), om, h, w, 5.0 * w, 2.5)
+    A0 = torch.tensor(A0.toarray())
+    dsc = torch.tensor(dscale.ravel())
+    mt = torch.tensor(m.ravel(), requires_grad=True)
+    A = A0 - torch.diag(dsc * mt)
+    L = 0
+    for s in range(src.shape[0]):
+        b = torch.tensor((scale * src[s]).ravel())
+        u = torch.linalg.solve(A, b)
+        r = u[torch.tensor(rec)] - torch.tensor(d_obs[s])
+        L = L + 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+    L.backward()
+    Lo, go, _ = ADJ.misfit_gradient(m, om, h, w, 5.0 * w, 2.5, src, rec, d_obs)
+    assert abs(L.item() - Lo) <= 1e-10 * Lo
+    assert np.abs(mt.grad.numpy() - go.ravel()).max() <= 1e-9 * np.abs(go).max()
