@@ -155,7 +155,8 @@ def main():
                    "iterations": mixed["iters"], "relres": mixed["relres"],
                    "setup_s": mixed["setup_s"], "solve_s": mixed["solve_s"], "precision": "mixed"},
     }
-    # roofline of the dominant kernel class (the fused slab-solve stage):
+    # roofline of the dominant kernel class (the SubdomSolve stage, three
+    # dependent launches timed as one):
     # algorithmic bytes per launch / average event-timed launch duration
     cls = mixed["classes"]
     st_ms, st_n, st_bytes = cls["stage"]
@@ -164,7 +165,7 @@ def main():
     achieved = per_launch_bytes / per_launch_s / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                       "kernel": "k_stage (fused SubdomSolve stage)", "launches": st_n,
+                       "kernel": "SubdomSolve stage (k_stage_fwd + k_stage_mid + k_stage_bwd)", "launches": st_n,
                        "avg_launch_us": per_launch_s * 1e6, "alg_bytes_per_launch": per_launch_bytes}
     out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
     if not args.no_fp64:
