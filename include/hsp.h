@@ -207,6 +207,53 @@ hsp_status hsp_slab_solve(hsp_handle hd, int j, const void* b_dev, void* x_dev, 
 hsp_status hsp_gradient_accumulate(hsp_handle hd, const void* u_dev, const void* lam_dev, double* g_dev,
                                    void* stream);
 
+/* ---- Batched right-hand sides.  Many sources (or adjoint sources) of one
+ *      medium and frequency share the setup: the slab factors serve every
+ *      right-hand side, which is the multi-RHS pipelining of Sec. 4.  A
+ *      batch is nrhs contiguous complex128 fine vectors, right-hand side j
+ *      at offset j * (N1-1)(N2-1).  Every sweep stage is one set of three
+ *      launches over (slab task, tangential chunk, tile of right-hand
+ *      sides).  These calls need a second caller-owned device workspace,
+ *      256-byte aligned, of hsp_batch_workspace_size bytes; it holds the
+ *      per-right-hand-side vectors, the FGMRES bases and the slab scratch,
+ *      and may be reused between calls.  tile selects the number of right-
+ *      hand sides per work item (1, 2, 4 or 8; 0 = the tile found by
+ *      hsp_tune_batch for this batch size, else a size heuristic); it
+ *      changes the evaluation order only. ------------------------------- */
+
+/* Bytes of batch workspace for up to nrhs right-hand sides (>= 1) and FGMRES
+ * restart length restart (>= 1). */
+hsp_status hsp_batch_workspace_size(hsp_handle hd, int nrhs, int restart, size_t* bytes);
+
+/* z_j = M r_j for j < nrhs (the preconditioner of hsp_apply_precond applied
+ * to every column).  r_dev, z_dev: nrhs complex128 fine vectors, no aliasing;
+ * nrhs = 0 does nothing.  ws sized for (nrhs, restart >= 1).
+ * Errors: HSP_EINVAL (bad tile, null or aliased pointers), HSP_ENOMEM. */
+hsp_status hsp_apply_precond_batch(hsp_handle hd, int nrhs, const void* r_dev, void* z_dev, int tile,
+                                   void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Times one batched preconditioner application for every tile and keeps the
+ * fastest for batches of nrhs right-hand sides (used when tile = 0).  Writes
+ * into the batch workspace (sized for nrhs, restart).  tile_out and ms_out
+ * (may be NULL) receive the tile and its time per application.
+ * Synchronises the stream. */
+hsp_status hsp_tune_batch(hsp_handle hd, int nrhs, int restart, void* ws_dev, size_t ws_bytes, int* tile_out,
+                          double* ms_out, void* stream);
+
+/* Solve A u_j = b_j (or A^H u_j = b_j) for j < nrhs with one right-
+ * preconditioned FGMRES process per right-hand side (x0 = 0, restart
+ * length restart), all advanced together; each stops at its own test
+ * ||b_j - A u_j||_2 <= tol ||b_j||_2 and leaves the batch, so later
+ * iterations work on the remaining ones only.  b_j = 0 gives u_j = 0 with 0
+ * iterations.  iters[nrhs] and relres[nrhs] (host arrays, may be NULL)
+ * receive the iteration counts and true relative residuals.  One host
+ * synchronisation per iteration.
+ * Errors: HSP_EINVAL, HSP_ENOMEM, HSP_ENOCONV (some right-hand side reached
+ * maxit; all u_j hold their last iterates). */
+hsp_status hsp_solve_batch(hsp_handle hd, int nrhs, const void* b_dev, void* u_dev, double tol, int maxit,
+                           int restart, int conj_transpose, int tile, void* ws_dev, size_t ws_bytes,
+                           int* iters, double* relres, void* stream);
+
 /* ---- Timing (tracing aid).  When enabled, every kernel launch of the
  *      classes below is bracketed by a pair of HIP events on the stream it
  *      is launched on; hsp_profile_read synchronises on the last event and

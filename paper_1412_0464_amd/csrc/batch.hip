@@ -1,0 +1,401 @@
+// Batched SubdomSolve stages: the slab solves of one sweep stage applied to
+// many right-hand sides at once (the multi-RHS pipelining of Sec. 4, where
+// the factors of a slab are shared by every source).
+//
+// Work items are (task of the stage, chunk of the tangential axis, tile of
+// RB right-hand sides); every launch covers all of them, so one stage is
+// three launches whatever the number of right-hand sides.  Within a tile the
+// block substitutions act on nl x RB blocks:
+//   forward   y_t = G_t (f_t - A_t y_{t-1})         (A_t: coupling to t-1),
+//   backward  x_t = y_t - E_t x_{t+1},
+// chunked exactly as in the single right-hand-side kernels (chunk-local chains
+// from zero, a chain over the chunk ends through the transfer matrices Y and
+// X, and a fix-up of every block).  The factor blocks of a chunk are read
+// once per tile; the tiles of one chunk are placed on the same XCD so that
+// they share its L2.
+//
+// Scratch per (task, tile) slot: y [n2][RB][nl] (right-hand side, then the
+// solution), chunk tips and heads [2][P][RB][nl], two arrival counters.
+#include "internal.h"
+#include "sweep_dev.h"
+
+namespace hsp {
+
+namespace {
+
+// Thread layout of a 256-thread workgroup for slabs of up to NB layers.
+// Product phase: thread (l, g), l = tid % NB, owns row l and the CW columns
+// [g CW, (g+1) CW) of a block.  Reduction phase: thread (l, g) owns row l of
+// the right-hand sides g, g + NG, ... (RC of them).
+template <int NB, int RB>
+struct BLay {
+  static constexpr int NT = 256;
+  static constexpr int NG = NT / NB;
+  static constexpr int CW = NB / NG;
+  static constexpr int RC = (RB + NG - 1) / NG;
+};
+
+template <class T>
+__device__ __forceinline__ cx<T> shfl_up1(cx<T> v, int width) {
+  return mk<T>(__shfl_up(v.re, 1, width), __shfl_up(v.im, 1, width));
+}
+template <class T>
+__device__ __forceinline__ cx<T> shfl_down1(cx<T> v, int width) {
+  return mk<T>(__shfl_down(v.re, 1, width), __shfl_down(v.im, 1, width));
+}
+
+// Block chain over the RB columns of a tile, by the whole workgroup.  Step k
+// (k = 0..count-1) uses the index r = first + dir k:
+//   GD = false:  Z_k = B_k + sigma Mat_r Z_{k-1}
+//   GD = true:   Z_k = Mat_r (B_k - Cpl_r Z_{k-1})
+// with Z_{-1} = 0, Mat_r the column-major nl x nl block at mat + r mstride
+// and Cpl_r the tridiagonal coupling (Cpl Z)[l] = sum_a cpl[r][a][l] Z[l+a-1].
+// B_k is read from, and Z_k written to, rows[(r RB + c) nl + l].  The matrix
+// slices (and B, couplings) of the next D steps are held in a register ring;
+// loads are unconditional from clamped addresses.  LDS: q [NB][RB] holds the
+// product input, ps [NG][RB][NB] the partial products.
+template <class T, int NB, int RB, int D, bool GD>
+__device__ __forceinline__ void bchain(const cx<T>* __restrict__ mat, long mstride, const cx<T>* __restrict__ cpl,
+                                       cx<T>* rows, int first, int dir, int count, int nl, T sigma, cx<T>* q,
+                                       cx<T>* ps) {
+  using LY = BLay<NB, RB>;
+  constexpr int NG = LY::NG, CW = LY::CW, RC = LY::RC;
+  if (count <= 0) return;
+  const int tid = threadIdx.x;
+  const int l = tid % NB, g = tid / NB;
+  const bool act = l < nl;
+  const int lc = act ? l : nl - 1;
+  cx<T> rm[D][CW];
+  cx<T> rb[D][RC];
+  cx<T> ra[D][3];
+  // Ring slot d of step kk holds Mat_{r_kk} and what the reduction of step kk
+  // needs: GD: B and couplings of step kk+1 (the next input); else B_kk.
+#define BCH_FETCH(kk, d)                                                                         \
+  {                                                                                              \
+    const int kc = (kk) < count ? (kk) : count - 1;                                              \
+    const cx<T>* Mk = mat + (long)(first + dir * kc) * mstride;                                  \
+    _Pragma("unroll") for (int cc = 0; cc < CW; ++cc) {                                          \
+      const int j = g * CW + cc;                                                                 \
+      const int jc = j < nl ? j : nl - 1;                                                        \
+      rm[d][cc] = sel(act && j < nl, Mk[(size_t)jc * nl + lc]);                                  \
+    }                                                                                            \
+    const int kb = GD ? ((kk) + 1 < count ? (kk) + 1 : count - 1) : kc;                          \
+    const int rbi = first + dir * kb;                                                            \
+    _Pragma("unroll") for (int i = 0; i < RC; ++i) {                                             \
+      const int c = g + NG * i;                                                                  \
+      const int ccl = c < RB ? c : RB - 1;                                                       \
+      rb[d][i] = sel(act && c < RB, rows[((size_t)rbi * RB + ccl) * nl + lc]);                   \
+    }                                                                                            \
+    if constexpr (GD) {                                                                          \
+      _Pragma("unroll") for (int a = 0; a < 3; ++a) ra[d][a] = sel(act, cpl[((size_t)rbi * 3 + a) * nl + lc]); \
+    }                                                                                            \
+  }
+#define BCH_STEP(k, d)                                                                           \
+  {                                                                                              \
+    cx<T> part[RB];                                                                              \
+    _Pragma("unroll") for (int c = 0; c < RB; ++c) part[c] = mk<T>(0, 0);                        \
+    _Pragma("unroll") for (int cc = 0; cc < CW; ++cc) {                                          \
+      const cx<T>* qr = q + (g * CW + cc) * RB;                                                  \
+      _Pragma("unroll") for (int c = 0; c < RB; ++c) cfma(part[c], rm[d][cc], qr[c]);            \
+    }                                                                                            \
+    _Pragma("unroll") for (int c = 0; c < RB; ++c) ps[(g * RB + c) * NB + l] = part[c];          \
+    __syncthreads();                                                                             \
+    const int rk = first + dir * (k);                                                            \
+    _Pragma("unroll") for (int i = 0; i < RC; ++i) {                                             \
+      const int c = g + NG * i;                                                                  \
+      const int ccl = c < RB ? c : RB - 1;                                                       \
+      cx<T> s = mk<T>(0, 0);                                                                     \
+      _Pragma("unroll") for (int gg = 0; gg < NG; ++gg) s += ps[(gg * RB + ccl) * NB + l];       \
+      cx<T> zk;                                                                                  \
+      if constexpr (GD)                                                                          \
+        zk = s;                                                                                  \
+      else                                                                                       \
+        zk = mk<T>(rb[d][i].re + sigma * s.re, rb[d][i].im + sigma * s.im);                      \
+      zk = sel(act && c < RB, zk);                                                               \
+      if (act && c < RB) rows[((size_t)rk * RB + c) * nl + l] = zk;                              \
+      cx<T> qn = zk;                                                                             \
+      if constexpr (GD) {                                                                        \
+        const cx<T> zl = sel(l > 0, shfl_up1(zk, NB));                                           \
+        const cx<T> zr = sel(l + 1 < nl, shfl_down1(zk, NB));                                    \
+        qn = rb[d][i];                                                                           \
+        cfma(qn, -ra[d][0], zl);                                                                 \
+        cfma(qn, -ra[d][1], zk);                                                                 \
+        cfma(qn, -ra[d][2], zr);                                                                 \
+      }                                                                                          \
+      if (c < RB) q[l * RB + c] = qn;                                                            \
+    }                                                                                            \
+    __syncthreads();                                                                             \
+  }
+  // first input: B_0 (GD) or zero
+#pragma unroll
+  for (int i = 0; i < RC; ++i) {
+    const int c = g + NG * i;
+    const int ccl = c < RB ? c : RB - 1;
+    cx<T> v = mk<T>(0, 0);
+    if constexpr (GD) v = sel(act && c < RB, rows[((size_t)first * RB + ccl) * nl + lc]);
+    if (c < RB) q[l * RB + c] = v;
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) BCH_FETCH(d, d)
+  __syncthreads();
+  int k0 = 0;
+  for (; k0 + D <= count; k0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      BCH_STEP(k0 + d, d)
+      BCH_FETCH(k0 + d + D, d)
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    if (k0 + d < count) BCH_STEP(k0 + d, d)
+  }
+#undef BCH_STEP
+#undef BCH_FETCH
+}
+
+// rows_t += Mat_t v for t in [s, e), v = LDS [nl][RB]; one (t, row) pair per
+// thread and all RB columns at once.
+template <class T, int RB>
+__device__ __forceinline__ void bfixup(const cx<T>* __restrict__ mat, cx<T>* rows, int s, int e, int nl,
+                                       const cx<T>* v) {
+  const int cnt = e - s;
+  for (int idx = threadIdx.x; idx < cnt * nl; idx += blockDim.x) {
+    const int t = s + idx / nl, l = idx - (idx / nl) * nl;
+    const cx<T>* mb = mat + (size_t)t * nl * nl + l;
+    cx<T> acc[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) acc[c] = mk<T>(0, 0);
+#pragma unroll 4
+    for (int j = 0; j < nl; ++j) {
+      const cx<T> mv = mb[(size_t)j * nl];
+#pragma unroll
+      for (int c = 0; c < RB; ++c) cfma(acc[c], mv, v[j * RB + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < RB; ++c) {
+      cx<T>& o = rows[((size_t)t * RB + c) * nl + l];
+      o = o + acc[c];
+    }
+  }
+}
+
+// Work item of block b: the tiles of one (task, chunk) pair are consecutive
+// items and land on one XCD (blocks are dealt to the 8 XCDs in turn).
+struct BWork {
+  int q, p, tile;
+};
+__device__ __forceinline__ bool decode_work(int ntasks, int P, int ntiles, BWork& w) {
+  const int nwork = ntasks * P * ntiles;
+  const int per = (nwork + 7) / 8;
+  const int id = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (id >= nwork) return false;
+  w.tile = id % ntiles;
+  const int rest = id / ntiles;
+  w.p = rest % P;
+  w.q = rest / P;
+  return true;
+}
+
+struct BArgs {
+  const TaskDev* tasks;  // the stage's tasks
+  const SlabDev* slabs;
+  LevelDev G;            // the DD level (transmission couplings)
+  int ntasks, ntiles, nact, nl_max, m, P;
+  size_t ld;             // elements per right-hand side of a level vector
+};
+
+template <class T, int NB, int RB, int D>
+__global__ void __launch_bounds__(256) k_bstage_fwd(BArgs A, const cx<T>* __restrict__ f, const cx<T>* __restrict__ g,
+                                                    const cx<T>* __restrict__ bufs, cx<T>* __restrict__ scratch,
+                                                    const cx<T>* __restrict__ factors, cx<T>* __restrict__ red,
+                                                    int* counters) {
+  __shared__ cx<T> q[NB * RB];
+  __shared__ cx<T> ps[256 * RB];
+  BWork w;
+  if (!decode_work(A.ntasks, A.P, A.ntiles, w)) return;
+  const int P = A.P, m = A.m, n2 = A.G.n2;
+  const int slot = w.q * A.ntiles + w.tile, r0 = w.tile * RB;
+  const int nr = min(RB, A.nact - r0);
+  const TaskDev tk = A.tasks[w.q];
+  const SlabDev sd = A.slabs[tk.slab];
+  const int nl = sd.nl;
+  const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
+  const SlabFac<T> F(factors + sd.fac_off, n2, nl);
+  cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
+  cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
+  const cx<T>* src = tk.src ? g : f;
+  // slab right-hand side of the chunk, t fastest (coalesced level reads)
+  for (int idx = threadIdx.x; idx < RB * nl * cnt; idx += 256) {
+    const int c = idx / (nl * cnt), rem = idx - c * (nl * cnt);
+    const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
+    const int gl = sd.x0 + ll;
+    cx<T> v = mk<T>(0, 0);
+    if (c < nr) {
+      const cx<T>* sr = src + (size_t)(r0 + c) * A.ld;
+      if (tk.a < gl && gl <= tk.b) v = sr[(size_t)(gl - 1) * n2 + t];
+      const cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
+      v = v + cvt<T>(transmission_rhs<T>(tk, A.G, gl, t, n2, bz + (size_t)tk.bin_f * 2 * n2,
+                                         bz + (size_t)tk.bin_b * 2 * n2));
+    }
+    y[((size_t)t * RB + c) * nl + ll] = v;
+  }
+  __syncthreads();
+  // chunk-local forward substitution y_t = G_t (f_t - A_t y_{t-1}) from zero
+  bchain<T, NB, RB, D, true>(F.G, (long)nl * nl, F.A, y, s, 1, cnt, nl, T(1), q, ps);
+  for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
+    const int c = idx / nl, l = idx - c * nl;
+    tips[((size_t)w.p * RB + c) * nl + l] = y[((size_t)(e - 1) * RB + c) * nl + l];
+  }
+  if (P == 1) return;
+  if (!last_arrival(counters + 2 * slot, P)) return;
+  // true chunk-end values: tip_q = raw_q + Y_{e_q - 1} tip_{q-1}
+  bchain<T, NB, RB, D, false>(F.Y + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0, 1, P - 1, nl,
+                              T(1), q, ps);
+}
+
+template <class T, int NB, int RB, int D>
+__global__ void __launch_bounds__(256) k_bstage_mid(BArgs A, cx<T>* __restrict__ scratch,
+                                                    const cx<T>* __restrict__ factors, cx<T>* __restrict__ red,
+                                                    int* counters) {
+  __shared__ cx<T> q[NB * RB];
+  __shared__ cx<T> ps[256 * RB];
+  BWork w;
+  if (!decode_work(A.ntasks, A.P, A.ntiles, w)) return;
+  const int P = A.P, m = A.m, n2 = A.G.n2;
+  const int slot = w.q * A.ntiles + w.tile;
+  const TaskDev tk = A.tasks[w.q];
+  const SlabDev sd = A.slabs[tk.slab];
+  const int nl = sd.nl;
+  const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
+  const SlabFac<T> F(factors + sd.fac_off, n2, nl);
+  cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
+  cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
+  cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
+  if (w.p > 0) {
+    for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
+      const int c = idx / nl, l = idx - c * nl;
+      q[l * RB + c] = tips[((size_t)(w.p - 1) * RB + c) * nl + l];
+    }
+    __syncthreads();
+    bfixup<T, RB>(F.Y, y, s, e, nl, q);
+    __syncthreads();
+  }
+  // chunk-local backward substitution x_t = y_t - E_t x_{t+1}
+  bchain<T, NB, RB, D, false>(F.E, (long)nl * nl, nullptr, y, e - 1, -1, cnt, nl, T(-1), q, ps);
+  for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
+    const int c = idx / nl, l = idx - c * nl;
+    heads[((size_t)w.p * RB + c) * nl + l] = y[((size_t)s * RB + c) * nl + l];
+  }
+  if (P == 1) return;
+  if (!last_arrival(counters + 2 * slot + 1, P)) return;
+  // true chunk-start values: head_q = raw_q + X_{s_q} head_{q+1}
+  bchain<T, NB, RB, D, false>(F.X, (long)m * nl * nl, nullptr, heads, P - 1, -1, P - 1, nl, T(1), q, ps);
+}
+
+template <class T, int NB, int RB>
+__global__ void __launch_bounds__(256) k_bstage_bwd(BArgs A, cx<T>* __restrict__ u, cx<T>* __restrict__ bufs,
+                                                    cx<T>* __restrict__ scratch, const cx<T>* __restrict__ factors,
+                                                    const cx<T>* __restrict__ red) {
+  __shared__ cx<T> hv[NB * RB];
+  BWork w;
+  if (!decode_work(A.ntasks, A.P, A.ntiles, w)) return;
+  const int P = A.P, m = A.m, n2 = A.G.n2;
+  const int slot = w.q * A.ntiles + w.tile, r0 = w.tile * RB;
+  const int nr = min(RB, A.nact - r0);
+  const TaskDev tk = A.tasks[w.q];
+  const SlabDev sd = A.slabs[tk.slab];
+  const int nl = sd.nl;
+  const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
+  const SlabFac<T> F(factors + sd.fac_off, n2, nl);
+  cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
+  const cx<T>* heads = red + (size_t)slot * 2 * P * A.nl_max * RB + (size_t)P * A.nl_max * RB;
+  if (w.p < P - 1) {
+    for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
+      const int c = idx / nl, l = idx - c * nl;
+      hv[l * RB + c] = heads[((size_t)(w.p + 1) * RB + c) * nl + l];
+    }
+    __syncthreads();
+    bfixup<T, RB>(F.X, y, s, e, nl, hv);
+    __syncthreads();
+  }
+  // u += J^T x over the task's layers, outgoing transmission layers
+  for (int idx = threadIdx.x; idx < nr * nl * cnt; idx += 256) {
+    const int c = idx / (nl * cnt), rem = idx - c * (nl * cnt);
+    const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
+    const int gl = sd.x0 + ll;
+    const cx<T> x = y[((size_t)t * RB + c) * nl + ll];
+    if (tk.at < gl && gl <= tk.bt) {
+      cx<T>& o = u[(size_t)(r0 + c) * A.ld + (size_t)(gl - 1) * n2 + t];
+      o = o + x;
+    }
+    cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
+    if (tk.t2) {
+      cx<T>* Bo = bz + (size_t)tk.bout_f * 2 * n2;
+      if (gl == tk.beta_out) Bo[t] = x;
+      if (gl == tk.beta_out + 1) Bo[(size_t)n2 + t] = x;
+    }
+    if (tk.t4) {
+      cx<T>* Bo = bz + (size_t)tk.bout_b * 2 * n2;
+      if (gl == tk.bt_out) Bo[t] = x;
+      if (gl == tk.bt_out + 1) Bo[(size_t)n2 + t] = x;
+    }
+  }
+}
+
+}  // namespace
+
+template <class T>
+void launch_stage_batch(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev, const LevelDev& G,
+                        const cx<T>* f, const cx<T>* g, cx<T>* u, cx<T>* bufs, cx<T>* scratch, const cx<T>* factors,
+                        int nl_max, int nl_launch, int m, int P, int nact, int rb, size_t ld, cx<T>* red,
+                        int* counters, hipStream_t s) {
+  if (nact < 1 || ntasks < 1) return;
+  BArgs A;
+  A.tasks = tasks_dev;
+  A.slabs = slabs_dev;
+  A.G = G;
+  A.ntasks = ntasks;
+  A.ntiles = (nact + rb - 1) / rb;
+  A.nact = nact;
+  A.nl_max = nl_max;
+  A.m = m;
+  A.P = P;
+  A.ld = ld;
+  const int nwork = ntasks * P * A.ntiles;
+  const dim3 grd(8 * ((nwork + 7) / 8));
+#define BLAUNCH(NB, RB, D)                                                                                      \
+  do {                                                                                                          \
+    hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D>), grd, dim3(256), 0, s, A, f, g, (const cx<T>*)bufs, scratch, \
+                       factors, red, counters);                                                                 \
+    hipLaunchKernelGGL((k_bstage_mid<T, NB, RB, D>), grd, dim3(256), 0, s, A, scratch, factors, red, counters);  \
+    hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB>), grd, dim3(256), 0, s, A, u, bufs, scratch, factors,           \
+                       (const cx<T>*)red);                                                                      \
+  } while (0)
+  constexpr int D32 = sizeof(T) == 4 ? 4 : 2;
+  constexpr int D64 = sizeof(T) == 4 ? 2 : 1;
+#define BRB(NB, D)                 \
+  do {                             \
+    switch (rb) {                  \
+      case 1: BLAUNCH(NB, 1, D); break; \
+      case 2: BLAUNCH(NB, 2, D); break; \
+      case 4: BLAUNCH(NB, 4, D); break; \
+      default: BLAUNCH(NB, 8, D); break; \
+    }                              \
+  } while (0)
+  if (nl_launch <= 32)
+    BRB(32, D32);
+  else
+    BRB(64, D64);
+#undef BRB
+#undef BLAUNCH
+}
+
+template void launch_stage_batch<double>(const TaskDev*, int, const SlabDev*, const LevelDev&, const cd*, const cd*,
+                                         cd*, cd*, cd*, const cd*, int, int, int, int, int, int, size_t, cd*, int*,
+                                         hipStream_t);
+template void launch_stage_batch<float>(const TaskDev*, int, const SlabDev*, const LevelDev&, const cf*, const cf*,
+                                        cf*, cf*, cf*, const cf*, int, int, int, int, int, int, size_t, cf*, int*,
+                                        hipStream_t);
+
+}  // namespace hsp

@@ -1,6 +1,7 @@
 // Vector kernels: conversions, the fused Gram-Schmidt pieces of FGMRES
 // (multi-dot, multi-axpy, normalisation), right-hand-side scaling and the
 // per-node / per-cell medium preprocessing of the setup.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -10,7 +11,10 @@ namespace hsp {
 namespace {
 
 template <class To, class Ti>
-__global__ void k_convert(const cx<Ti>* __restrict__ in, cx<To>* __restrict__ out, size_t n, int cj) {
+__global__ void k_convert(const cx<Ti>* __restrict__ in, cx<To>* __restrict__ out, size_t n, int cj, BIdx bi,
+                          BIdx bo) {
+  in += bi.off(blockIdx.y);
+  out += bo.off(blockIdx.y);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     cx<To> v = cvt<To>(in[i]);
     if (cj) v.im = -v.im;
@@ -22,6 +26,11 @@ template <class T>
 __global__ void k_zero(cx<T>* v, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     v[i] = mk<T>(0, 0);
+}
+
+__global__ void k_fill(cd* v, size_t n, cd value) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = value;
 }
 
 __device__ __forceinline__ cd block_sum(cd v, cd* sh) {
@@ -186,27 +195,91 @@ __global__ void k_grad_m(int n1, int n2, double scale, const cd* __restrict__ ix
   g[id] += scale * w.re;
 }
 
+// ---- batched Gram-Schmidt pieces: vector j of right-hand side z of a basis
+// is V + bv.off(z) + j * ldj; blockIdx.z (or .y) selects z.
+__global__ void __launch_bounds__(256) k_bmultidot(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
+                                                   const cd* __restrict__ w, BIdx bw, size_t n,
+                                                   cd* __restrict__ partial) {
+  __shared__ cd sh[4];
+  const int j = blockIdx.y, z = blockIdx.z;
+  const cd* v = V + bv.off(z) + (size_t)j * ldj;
+  w += bw.off(z);
+  cd acc = mk<double>(0, 0);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    cfma(acc, conj(v[i]), w[i]);
+  cd r = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[((size_t)z * cnt + j) * gridDim.x + blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(256) k_breduce(const cd* __restrict__ partial, int nb, int cnt,
+                                                 cd* __restrict__ out, size_t ldo) {
+  __shared__ cd sh[4];
+  const int j = blockIdx.x, z = blockIdx.y;
+  const cd* p = partial + ((size_t)z * cnt + j) * nb;
+  cd acc = mk<double>(0, 0);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += p[b];
+  cd r = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[(size_t)z * ldo + j] = r;
+}
+
+__global__ void __launch_bounds__(256) k_bmultiaxpy(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
+                                                    const cd* __restrict__ h, size_t ldh, cd* __restrict__ w,
+                                                    BIdx bw, size_t n, int sub) {
+  const int z = blockIdx.y;
+  const cd* v = V + bv.off(z);
+  const cd* hz = h + (size_t)z * ldh;
+  w += bw.off(z);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    cd acc = mk<double>(0, 0);
+    for (int j = 0; j < cnt; ++j) cfma(acc, hz[j], v[(size_t)j * ldj + i]);
+    w[i] = sub ? (w[i] - acc) : (w[i] + acc);
+  }
+}
+
+__global__ void k_bnormalize(const cd* __restrict__ w, BIdx bw, const cd* __restrict__ nrm2, size_t ldn,
+                             cd* __restrict__ v, BIdx bvv, size_t n) {
+  const int z = blockIdx.y;
+  const double s = 1.0 / sqrt(nrm2[(size_t)z * ldn].re);
+  w += bw.off(z);
+  v += bvv.off(z);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = s * w[i];
+}
+
 inline int nblk(size_t n) {
   size_t b = (n + 255) / 256;
   return (int)(b > 4096 ? 4096 : (b == 0 ? 1 : b));
 }
 
+// blocks per vector of a batched launch: about 2048 blocks in total
+inline int nblk_batch(size_t n, int nb) {
+  size_t b = (n + 255) / 256;
+  size_t cap = (size_t)std::max(8, 2048 / std::max(nb, 1));
+  return (int)(b > cap ? cap : (b == 0 ? 1 : b));
+}
+
 }  // namespace
 
 template <class To, class Ti>
-void launch_convert(const cx<Ti>* in, cx<To>* out, size_t n, int conjugate, hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<To, Ti>), dim3(nblk(n)), dim3(256), 0, s, in, out, n, conjugate);
+void launch_convert(const cx<Ti>* in, cx<To>* out, size_t n, int conjugate, hipStream_t s, int nb, BIdx bi,
+                    BIdx bo) {
+  if (nb < 1) return;
+  hipLaunchKernelGGL((k_convert<To, Ti>), dim3(nb == 1 ? nblk(n) : nblk_batch(n, nb), nb), dim3(256), 0, s, in,
+                     out, n, conjugate, bi, bo);
 }
-template void launch_convert<float, double>(const cd*, cf*, size_t, int, hipStream_t);
-template void launch_convert<double, float>(const cf*, cd*, size_t, int, hipStream_t);
-template void launch_convert<double, double>(const cd*, cd*, size_t, int, hipStream_t);
-template void launch_convert<float, float>(const cf*, cf*, size_t, int, hipStream_t);
+template void launch_convert<float, double>(const cd*, cf*, size_t, int, hipStream_t, int, BIdx, BIdx);
+template void launch_convert<double, float>(const cf*, cd*, size_t, int, hipStream_t, int, BIdx, BIdx);
+template void launch_convert<double, double>(const cd*, cd*, size_t, int, hipStream_t, int, BIdx, BIdx);
+template void launch_convert<float, float>(const cf*, cf*, size_t, int, hipStream_t, int, BIdx, BIdx);
 
 template <class T>
 void launch_zero(cx<T>* v, size_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_zero<T>), dim3(nblk(n)), dim3(256), 0, s, v, n);
 }
 template void launch_zero<double>(cd*, size_t, hipStream_t);
+void launch_fill(cd* v, size_t n, cd value, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, s, v, n, value);
+}
 template void launch_zero<float>(cf*, size_t, hipStream_t);
 
 void launch_multidot(const cd* V, size_t ldv, int m, const cd* w, size_t n, cd* partial, int nblocks,
@@ -221,6 +294,24 @@ void launch_multiaxpy(const cd* V, size_t ldv, int m, const cd* h, cd* w, size_t
 }
 void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_normalize, dim3(nblk(n)), dim3(256), 0, s, w, nrm2, v, n);
+}
+int batch_dot_blocks(size_t n, int nb) { return nblk_batch(n, nb); }
+void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BIdx bw, size_t n, cd* partial,
+                      int nblocks, cd* out, size_t ldo, int nb, hipStream_t s) {
+  if (nb < 1 || cnt < 1) return;
+  hipLaunchKernelGGL(k_bmultidot, dim3(nblocks, cnt, nb), dim3(256), 0, s, V, ldj, bv, cnt, w, bw, n, partial);
+  hipLaunchKernelGGL(k_breduce, dim3(cnt, nb), dim3(256), 0, s, (const cd*)partial, nblocks, cnt, out, ldo);
+}
+void launch_bmultiaxpy(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw, size_t n,
+                       int sub, int nb, hipStream_t s) {
+  if (nb < 1 || cnt < 1) return;
+  hipLaunchKernelGGL(k_bmultiaxpy, dim3(nblk_batch(n, nb), nb), dim3(256), 0, s, V, ldj, bv, cnt, h, ldh, w, bw, n,
+                     sub);
+}
+void launch_bnormalize(const cd* w, BIdx bw, const cd* nrm2, size_t ldn, cd* v, BIdx bv, size_t n, int nb,
+                       hipStream_t s) {
+  if (nb < 1) return;
+  hipLaunchKernelGGL(k_bnormalize, dim3(nblk_batch(n, nb), nb), dim3(256), 0, s, w, bw, nrm2, ldn, v, bv, n);
 }
 void launch_scale_rhs_arrays(int n1, int n2, double h2, const cd* ixn, const cd* iyn, const cd* f, cd* b,
                              hipStream_t s) {

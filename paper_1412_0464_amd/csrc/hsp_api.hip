@@ -318,6 +318,7 @@ struct Stage {
   int first, ntasks;
   int nl;        // thickest slab among the stage's tasks
   double bytes;  // algorithmic bytes per complex unit (times sizeof(T) at launch)
+  double fac;    // the factor part of bytes (shared by all right-hand sides of a batch)
 };
 
 // Event-pair timing per kernel class.
@@ -347,6 +348,8 @@ struct hsp_ctx {
   std::vector<TaskDev> tasks_host;
   void* factors = nullptr;
   Prof prof;
+  int tuned_rb = 0;    // right-hand-side tile chosen by hsp_tune_batch (0: none)
+  int tuned_nact = 0;  // batch size it was chosen for
   ~hsp_ctx() {
     for (int c = 0; c < HSP_PROF_NCLASS; ++c)
       for (auto& e : prof.ev[c]) {
@@ -412,7 +415,7 @@ void build_schedule(hsp_ctx* C) {
     return t;
   };
   auto push_stage = [&](std::vector<TaskDev> ts) {
-    Stage s{0, (int)T.size(), (int)ts.size(), 0, 0.0};
+    Stage s{0, (int)T.size(), (int)ts.size(), 0, 0.0, 0.0};
     const double n2 = P.dd_n2;
     for (auto& t : ts) {
       T.push_back(t);
@@ -420,6 +423,7 @@ void build_schedule(hsp_ctx* C) {
       s.nl = std::max(s.nl, nl);
       // factors G, E and the couplings; gathered rows; u read-modify-write;
       // transmission layers in and out (complex units)
+      s.fac += n2 * (2.0 * nl * nl + 3.0 * nl);
       s.bytes += n2 * (2.0 * nl * nl + 3.0 * nl) + n2 * (t.b - t.a) + 2.0 * n2 * (t.bt - t.at) +
                  2.0 * n2 * (t.t1 + t.t2 + t.t3 + t.t4);
     }
@@ -435,7 +439,7 @@ void build_schedule(hsp_ctx* C) {
       push_stage({t});
       mark(t);
     }
-    S.push_back(Stage{1, 0, 0, 0, 0.0});
+    S.push_back(Stage{1, 0, 0, 0, 0.0, 0.0});
     for (int j = J; j >= 1; --j) {
       TaskDev t = bwd(j, 1, 0);
       push_stage({t});
@@ -464,7 +468,7 @@ void build_schedule(hsp_ctx* C) {
     t.bt_in = bt[jm];
     push_stage({t});
   }
-  S.push_back(Stage{1, 0, 0, 0, 0.0});
+  S.push_back(Stage{1, 0, 0, 0, 0.0, 0.0});
   written[0] = written[1] = false;
   {  // MidSolveOut: forward output -> buffer 1, backward output -> buffer 0
     TaskDev t = blank(jm);
@@ -607,6 +611,180 @@ void precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
     run_precond<float>(C, r, z, s);
   else
     run_precond<double>(C, r, z, s);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched right-hand sides: layout of the caller's batch workspace
+// ---------------------------------------------------------------------------
+constexpr int kMaxTile = 8;
+
+// (task, tile) slots of a stage, times the tile: >= 2 ceil(R/rb) rb for every rb <= 8
+inline size_t batch_slots(int R) { return 2 * (size_t)(R + kMaxTile - 1); }
+
+struct BatchLayout {
+  int R = 0, m = 0, nblk = 0;
+  size_t hs = 0;  // hb entries per right-hand side: [h1 (m+1) | h2 (m+1) | nrm2 | spare]
+  size_t o_xa, o_xb, o_res, o_rc, o_ec, o_swf, o_swg, o_swu, o_swB, o_scr, o_red, o_ctr;
+  size_t o_V, o_Z, o_w, o_bc, o_part, o_hb, o_act, o_upd, o_y;
+  size_t total = 0;
+};
+
+BatchLayout batch_layout(const Plan& P, int R, int m) {
+  BatchLayout B;
+  B.R = R;
+  B.m = m;
+  Carver c;
+  const size_t nf = (size_t)P.nf1 * P.nf2, nd = (size_t)P.dd_n1 * P.dd_n2, T = P.tsize;
+  const size_t slots = batch_slots(R);
+  B.o_xa = c.take(R * nf * T);
+  B.o_xb = c.take(R * nf * T);
+  B.o_res = c.take(P.two_grid ? R * nf * sizeof(cd) : 0);
+  B.o_rc = c.take(P.two_grid ? R * nd * T : 0);
+  B.o_ec = c.take(P.two_grid ? R * nd * T : 0);
+  B.o_swf = c.take(R * nd * T);
+  B.o_swg = c.take(R * nd * T);
+  B.o_swu = c.take(R * nd * T);
+  B.o_swB = c.take(R * 4 * (size_t)P.dd_n2 * T);
+  B.o_scr = c.take(slots * P.dd_n2 * P.nl_max * T);
+  B.o_red = c.take(slots * 2 * P.nchunk * P.nl_max * T);
+  B.o_ctr = c.take(2 * slots * sizeof(int));
+  B.nblk = batch_dot_blocks(nf, R);
+  B.hs = 2 * (size_t)(m + 2) + 2;
+  B.o_V = c.take((size_t)R * (m + 1) * nf * sizeof(cd));
+  B.o_Z = c.take((size_t)R * m * nf * sizeof(cd));
+  B.o_w = c.take(R * nf * sizeof(cd));
+  B.o_bc = c.take(R * nf * sizeof(cd));
+  B.o_part = c.take((size_t)R * (m + 1) * B.nblk * sizeof(cd));
+  B.o_hb = c.take(R * B.hs * sizeof(cd));
+  B.o_act = c.take(R * sizeof(int));
+  B.o_upd = c.take(R * sizeof(int));
+  B.o_y = c.take((size_t)R * m * sizeof(cd));
+  B.total = c.off + 256;
+  return B;
+}
+
+template <class X>
+X* bat(void* ws, size_t off) {
+  return reinterpret_cast<X*>(reinterpret_cast<char*>(ws) + off);
+}
+
+// Default right-hand-side tile: the largest that still gives the stage
+// launches about two work items per compute unit.
+int default_tile(const hsp_ctx* C, int nact) {
+  if (C->tuned_rb > 0 && C->tuned_nact == nact) return C->tuned_rb;
+  for (int rb = kMaxTile; rb > 1; rb /= 2)
+    if (2 * C->P.nchunk * ((nact + rb - 1) / rb) >= 512) return rb;
+  return 1;
+}
+
+template <class T>
+void run_sweep_batch(hsp_ctx* C, const BatchLayout& B, void* ws, int nact, int rb, const cx<T>* f, cx<T>* u,
+                     hipStream_t s) {
+  const Plan& P = C->P;
+  const size_t nd = (size_t)P.dd_n1 * P.dd_n2;
+  cx<T>* g = bat<cx<T>>(ws, B.o_swg);
+  launch_zero<T>(u, (size_t)nact * nd, s);
+  BIdx bd;
+  bd.ld = nd;
+  for (const Stage& st : C->stages) {
+    if (st.residual) {
+      prof_begin(C, HSP_PROF_COARSE, s);
+      launch_stencil<T, T, T, T>(C->dd, 1, u, f, g, 0.0, s, nact, bd, bd, bd);
+      prof_end(C, HSP_PROF_COARSE, s, (double)nact * nd * (3.0 * sizeof(cx<T>) + 4.0 * sizeof(double)));
+    } else {
+      prof_begin(C, HSP_PROF_STAGE, s);
+      launch_stage_batch<T>(C->tasks_dev + st.first, st.ntasks, C->slabs_dev, C->dd, f, g, u,
+                            bat<cx<T>>(ws, B.o_swB), bat<cx<T>>(ws, B.o_scr),
+                            reinterpret_cast<const cx<T>*>(C->factors), P.nl_max, st.nl, P.chunk, P.nchunk, nact,
+                            rb, nd, bat<cx<T>>(ws, B.o_red), bat<int>(ws, B.o_ctr), s);
+      prof_end(C, HSP_PROF_STAGE, s, (st.fac + (double)nact * (st.bytes - st.fac)) * sizeof(cx<T>));
+    }
+  }
+}
+
+// z_j = M r_j for nact right-hand sides: r_j at r + br.off(j), z_j at
+// z + bz.off(j) (complex128), internal vectors compact per slot j.
+template <class T>
+void run_precond_batch(hsp_ctx* C, const BatchLayout& B, void* ws, int nact, int rb, const cd* r, BIdx br, cd* z,
+                       BIdx bz, hipStream_t s) {
+  const Plan& P = C->P;
+  const size_t nf = (size_t)P.nf1 * P.nf2, nd = (size_t)P.dd_n1 * P.dd_n2;
+  BIdx bf, bdd;
+  bf.ld = nf;
+  bdd.ld = nd;
+  if (!P.two_grid) {
+    cx<T>* fin = bat<cx<T>>(ws, B.o_swf);
+    cx<T>* uo = bat<cx<T>>(ws, B.o_swu);
+    launch_convert<T, double>(r, fin, nf, 0, s, nact, br, bf);
+    run_sweep_batch<T>(C, B, ws, nact, rb, fin, uo, s);
+    launch_convert<double, T>(uo, z, nf, 0, s, nact, bf, bz);
+    return;
+  }
+  const double wj = C->opt.omega_jac;
+  const int nu = C->opt.nu;
+  cx<T>* xa = bat<cx<T>>(ws, B.o_xa);
+  cx<T>* xb = bat<cx<T>>(ws, B.o_xb);
+  const double jb = (double)nact * nf * (sizeof(cd) + 2.0 * sizeof(cx<T>) + sizeof(double));
+  prof_begin(C, HSP_PROF_SMOOTH, s);
+  if (nu > 0) {
+    launch_stencil<T, T, double, T>(C->fine, 2, (const cx<T>*)nullptr, r, xa, wj, s, nact, BIdx{}, br, bf);
+    for (int k = 1; k < nu; ++k) {
+      launch_stencil<T, T, double, T>(C->fine, 2, xa, r, xb, wj, s, nact, bf, br, bf);
+      std::swap(xa, xb);
+    }
+  } else {
+    launch_zero<T>(xa, (size_t)nact * nf, s);
+  }
+  cd* res = bat<cd>(ws, B.o_res);
+  launch_stencil<double, T, double, double>(C->fine, 1, xa, r, res, 0.0, s, nact, bf, br, bf);
+  prof_end(C, HSP_PROF_SMOOTH, s,
+           nu * jb + (double)nact * nf * (2.0 * sizeof(cd) + sizeof(cx<T>) + sizeof(double)));
+  cx<T>* rc = bat<cx<T>>(ws, B.o_rc);
+  cx<T>* ec = bat<cx<T>>(ws, B.o_ec);
+  prof_begin(C, HSP_PROF_TRANSFER, s);
+  launch_restrict<double, T>(C->tr, res, rc, s, nact, bf, bdd);
+  prof_end(C, HSP_PROF_TRANSFER, s, (double)nact * ((double)nf * sizeof(cd) + (double)nd * sizeof(cx<T>)));
+  run_sweep_batch<T>(C, B, ws, nact, rb, rc, ec, s);
+  prof_begin(C, HSP_PROF_TRANSFER, s);
+  launch_prolong_add<T, T>(C->tr, ec, xa, s, nact, bdd, bf);
+  prof_end(C, HSP_PROF_TRANSFER, s, (double)nact * ((double)nd * sizeof(cx<T>) + 2.0 * nf * sizeof(cx<T>)));
+  if (nu == 0) {
+    launch_convert<double, T>(xa, z, nf, 0, s, nact, bf, bz);
+    return;
+  }
+  prof_begin(C, HSP_PROF_SMOOTH, s);
+  for (int k = 0; k < nu; ++k) {
+    if (k == nu - 1) {
+      launch_stencil<T, T, double, double>(C->fine, 2, xa, r, z, wj, s, nact, bf, br, bz);
+    } else {
+      launch_stencil<T, T, double, T>(C->fine, 2, xa, r, xb, wj, s, nact, bf, br, bf);
+      std::swap(xa, xb);
+    }
+  }
+  prof_end(C, HSP_PROF_SMOOTH, s, nu * jb);
+}
+
+void precond_batch(hsp_ctx* C, const BatchLayout& B, void* ws, int nact, int rb, const cd* r, BIdx br, cd* z,
+                   BIdx bz, hipStream_t s) {
+  if (C->opt.precision == HSP_MIXED)
+    run_precond_batch<float>(C, B, ws, nact, rb, r, br, z, bz, s);
+  else
+    run_precond_batch<double>(C, B, ws, nact, rb, r, br, z, bz, s);
+}
+
+hsp_status check_batch_args(hsp_ctx* C, int nrhs, int restart, void* ws, size_t bytes, int tile, BatchLayout& B) {
+  if (!C) return fail(HSP_EINVAL, "null handle");
+  if (nrhs < 0) return fail(HSP_EINVAL, "nrhs must be >= 0");
+  if (restart < 1) return fail(HSP_EINVAL, "restart must be >= 1");
+  if (tile != 0 && tile != 1 && tile != 2 && tile != 4 && tile != 8)
+    return fail(HSP_EINVAL, "tile must be 0 (automatic), 1, 2, 4 or 8");
+  if (nrhs == 0) return HSP_OK;
+  if (!ws) return fail(HSP_EINVAL, "null batch workspace");
+  if (((uintptr_t)ws) & 255) return fail(HSP_EINVAL, "batch workspace must be 256-byte aligned");
+  B = batch_layout(C->P, nrhs, restart);
+  if (bytes < B.total) return fail(HSP_ENOMEM, "batch workspace too small: need " + std::to_string(B.total) + " bytes");
+  return HSP_OK;
 }
 
 hipStream_t S_(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -1299,6 +1477,327 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
   if (iters) *iters = it;
   if (relres) *relres = rr;
   if (!done && rr > tol) return fail(HSP_ENOCONV, "maxit reached before the tolerance");
+  return HSP_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched right-hand sides (many sources or receivers of one medium and
+// frequency share the setup; Sec. 4 notes that the slab factors serve every
+// right-hand side)
+// ===========================================================================
+namespace {
+
+// Hessenberg matrix, Givens rotations and residual estimate of one
+// right-hand side's Arnoldi process (right-preconditioned FGMRES).
+struct Arnoldi {
+  int m = 0;
+  std::vector<cplx> H, g, sn;
+  std::vector<double> cs;
+  void reset(int m_, double beta) {
+    m = m_;
+    H.assign((size_t)(m + 1) * m, cplx(0));
+    g.assign(m + 1, cplx(0));
+    sn.assign(m, cplx(0));
+    cs.assign(m, 0.0);
+    g[0] = beta;
+  }
+  // column k from the two Gram-Schmidt passes and the new norm; returns
+  // the residual estimate |g_{k+1}|
+  double add_column(int k, const cd* h1, const cd* h2, double nrm2) {
+    for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = cplx(h1[i].re + h2[i].re, h1[i].im + h2[i].im);
+    H[(size_t)(k + 1) * m + k] = std::sqrt(std::max(nrm2, 0.0));
+    for (int i = 0; i < k; ++i) {
+      const cplx a = H[(size_t)i * m + k], bb = H[(size_t)(i + 1) * m + k];
+      H[(size_t)i * m + k] = cs[i] * a + sn[i] * bb;
+      H[(size_t)(i + 1) * m + k] = -std::conj(sn[i]) * a + cs[i] * bb;
+    }
+    const cplx a = H[(size_t)k * m + k], bb = H[(size_t)(k + 1) * m + k];
+    if (std::abs(bb) == 0) {
+      cs[k] = 1;
+      sn[k] = 0;
+    } else if (std::abs(a) == 0) {
+      cs[k] = 0;
+      sn[k] = 1;
+    } else {
+      const double t = std::sqrt(std::norm(a) + std::norm(bb));
+      cs[k] = std::abs(a) / t;
+      sn[k] = (a / std::abs(a)) * std::conj(bb) / t;
+    }
+    H[(size_t)k * m + k] = cs[k] * a + sn[k] * bb;
+    H[(size_t)(k + 1) * m + k] = 0;
+    g[k + 1] = -std::conj(sn[k]) * g[k];
+    g[k] = cs[k] * g[k];
+    return std::abs(g[k + 1]);
+  }
+  // y = H(0:k,0:k)^{-1} g(0:k)
+  void solve(int k, cd* y) const {
+    std::vector<cplx> yy(k);
+    for (int i = k - 1; i >= 0; --i) {
+      cplx acc = g[i];
+      for (int j = i + 1; j < k; ++j) acc -= H[(size_t)i * m + j] * yy[j];
+      yy[i] = acc / H[(size_t)i * m + i];
+    }
+    for (int i = 0; i < k; ++i) y[i] = to_cd(yy[i]);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+hsp_status hsp_batch_workspace_size(hsp_handle C, int nrhs, int restart, size_t* bytes) {
+  if (!C || !bytes) return fail(HSP_EINVAL, "null argument");
+  if (nrhs < 1 || restart < 1) return fail(HSP_EINVAL, "nrhs and restart must be >= 1");
+  *bytes = batch_layout(C->P, nrhs, restart).total;
+  return HSP_OK;
+}
+
+hsp_status hsp_apply_precond_batch(hsp_handle C, int nrhs, const void* r, void* z, int tile, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  BatchLayout B;
+  hsp_status st = check_batch_args(C, nrhs, 1, ws, ws_bytes, tile, B);
+  if (st != HSP_OK || nrhs == 0) return st;
+  if (!r || !z || r == z) return fail(HSP_EINVAL, "null or aliased argument");
+  hipStream_t s = S_(stream);
+  const size_t nf = (size_t)C->P.nf1 * C->P.nf2;
+  HIPCHK(hipMemsetAsync(bat<int>(ws, B.o_ctr), 0, 2 * batch_slots(nrhs) * sizeof(int), s));
+  BIdx bv;
+  bv.ld = nf;
+  precond_batch(C, B, ws, nrhs, tile ? tile : default_tile(C, nrhs), (const cd*)r, bv, (cd*)z, bv, s);
+  HIPCHK(hipGetLastError());
+  return HSP_OK;
+}
+
+hsp_status hsp_tune_batch(hsp_handle C, int nrhs, int restart, void* ws, size_t ws_bytes, int* tile_out,
+                          double* ms_out, void* stream) {
+  BatchLayout B;
+  hsp_status st = check_batch_args(C, nrhs, restart, ws, ws_bytes, 0, B);
+  if (st != HSP_OK) return st;
+  if (nrhs == 0) return fail(HSP_EINVAL, "nrhs must be >= 1");
+  hipStream_t s = S_(stream);
+  const size_t nf = (size_t)C->P.nf1 * C->P.nf2;
+  cd* r = bat<cd>(ws, B.o_V);
+  cd* z = bat<cd>(ws, B.o_Z);
+  HIPCHK(hipMemsetAsync(bat<int>(ws, B.o_ctr), 0, 2 * batch_slots(nrhs) * sizeof(int), s));
+  launch_fill(r, (size_t)nrhs * nf, mk<double>(1.0, 0.0), s);
+  BIdx bv;
+  bv.ld = nf;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HSP_EDEVICE, "hipEventCreate failed");
+  }
+  const bool prof = C->prof.on;
+  C->prof.on = false;
+  int best = 1;
+  double best_ms = 1e300;
+  hipError_t err = hipSuccess;
+  for (int rb = 1; rb <= kMaxTile && err == hipSuccess; rb *= 2) {
+    precond_batch(C, B, ws, nrhs, rb, r, bv, z, bv, s);  // warm-up
+    err = hipEventRecord(e0, s);
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) precond_batch(C, B, ws, nrhs, rb, r, bv, z, bv, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && 0.5 * ms < best_ms) {
+      best_ms = 0.5 * ms;
+      best = rb;
+    }
+  }
+  C->prof.on = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(HSP_EDEVICE, std::string("tuning: ") + hipGetErrorString(err));
+  HIPCHK(hipGetLastError());
+  C->tuned_rb = best;
+  C->tuned_nact = nrhs;
+  if (tile_out) *tile_out = best;
+  if (ms_out) *ms_out = best_ms;
+  return HSP_OK;
+}
+
+hsp_status hsp_solve_batch(hsp_handle C, int nrhs, const void* b_in, void* u_out, double tol, int maxit, int restart,
+                           int conj_transpose, int tile, void* ws, size_t ws_bytes, int* iters, double* relres,
+                           void* stream) {
+  BatchLayout B;
+  hsp_status st = check_batch_args(C, nrhs, restart, ws, ws_bytes, tile, B);
+  if (st != HSP_OK || nrhs == 0) return st;
+  if (!b_in || !u_out || b_in == u_out) return fail(HSP_EINVAL, "null or aliased argument");
+  if (!(tol > 0) || maxit < 1) return fail(HSP_EINVAL, "tol must be > 0 and maxit >= 1");
+  hipStream_t s = S_(stream);
+  const int R = nrhs, m = restart;
+  const size_t nf = (size_t)C->P.nf1 * C->P.nf2;
+  const size_t hs = B.hs;
+  cd* V = bat<cd>(ws, B.o_V);
+  cd* Z = bat<cd>(ws, B.o_Z);
+  cd* w = bat<cd>(ws, B.o_w);
+  cd* part = bat<cd>(ws, B.o_part);
+  cd* hb = bat<cd>(ws, B.o_hb);
+  cd* ydev = bat<cd>(ws, B.o_y);
+  int* act_d = bat<int>(ws, B.o_act);
+  int* upd_d = bat<int>(ws, B.o_upd);
+  cd* x = (cd*)u_out;
+  const cd* b = (const cd*)b_in;
+  const LevelDev& A = C->fine;
+  HIPCHK(hipMemsetAsync(bat<int>(ws, B.o_ctr), 0, 2 * batch_slots(R) * sizeof(int), s));
+  BIdx bid;  // identity map over all right-hand sides
+  bid.ld = nf;
+  if (conj_transpose) {
+    cd* bc = bat<cd>(ws, B.o_bc);
+    launch_convert<double, double>(b, bc, (size_t)R * nf, 1, s);
+    b = bc;
+  }
+  std::vector<cd> hh((size_t)R * hs);
+  auto read_hb = [&](int cnt) -> hsp_status {
+    HIPCHK(hipMemcpyAsync(hh.data(), hb, (size_t)cnt * hs * sizeof(cd), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HSP_OK;
+  };
+  // ||b_z||
+  launch_bmultidot(b, 0, bid, 1, b, bid, nf, part, B.nblk, hb + 2 * (m + 1), hs, R, s);
+  st = read_hb(R);
+  if (st != HSP_OK) return st;
+  std::vector<double> bnorm(R);
+  for (int z = 0; z < R; ++z) bnorm[z] = std::sqrt(std::max(hh[(size_t)z * hs + 2 * (m + 1)].re, 0.0));
+  launch_zero<double>(x, (size_t)R * nf, s);
+  std::vector<int> its(R, 0), done(R, 0), act, upd;
+  for (int z = 0; z < R; ++z) {
+    if (bnorm[z] == 0)
+      done[z] = 1;
+    else
+      act.push_back(z);
+  }
+  std::vector<Arnoldi> ar(R);
+  std::vector<cd> yh((size_t)R * m);
+  auto upload = [&](int* dst, const std::vector<int>& v) -> hsp_status {
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    return HSP_OK;
+  };
+  // x_z += Z_z y_z for the right-hand sides in `upd` (k basis vectors each)
+  auto update = [&](const std::vector<int>& list, int k) -> hsp_status {
+    if (list.empty() || k == 0) return HSP_OK;
+    // the host staging arrays yh / upd may still feed an earlier copy
+    HIPCHK(hipStreamSynchronize(s));
+    upd = list;
+    for (size_t i = 0; i < upd.size(); ++i) ar[upd[i]].solve(k, yh.data() + i * m);
+    HIPCHK(hipMemcpyAsync(ydev, yh.data(), upd.size() * m * sizeof(cd), hipMemcpyHostToDevice, s));
+    hsp_status e = upload(upd_d, upd);
+    if (e != HSP_OK) return e;
+    BIdx bz, bx;
+    bz.ld = (size_t)m * nf;
+    bz.map = upd_d;
+    bx.ld = nf;
+    bx.map = upd_d;
+    launch_bmultiaxpy(Z, nf, bz, k, ydev, m, x, bx, nf, 0, (int)upd.size(), s);
+    return HSP_OK;
+  };
+  const int rb_fixed = tile;
+  int it = 0;
+  while (it < maxit && !act.empty()) {
+    int nact = (int)act.size();
+    st = upload(act_d, act);
+    if (st != HSP_OK) return st;
+    BIdx bx, bV;
+    bx.ld = nf;
+    bx.map = act_d;
+    bV.ld = (size_t)(m + 1) * nf;
+    bV.map = act_d;
+    // r = b - A x into V_z0, its norm, normalisation
+    launch_stencil<double, double, double, double>(A, 1, x, b, V, 0.0, s, nact, bx, bx, bV);
+    launch_bmultidot(V, 0, bV, 1, V, bV, nf, part, B.nblk, hb + 2 * (m + 1), hs, nact, s);
+    launch_bnormalize(V, bV, hb + 2 * (m + 1), hs, V, bV, nf, nact, s);
+    st = read_hb(nact);
+    if (st != HSP_OK) return st;
+    {
+      std::vector<int> keep;
+      for (int zi = 0; zi < nact; ++zi) {
+        const int z = act[zi];
+        const double beta = std::sqrt(std::max(hh[(size_t)zi * hs + 2 * (m + 1)].re, 0.0));
+        if (beta <= tol * bnorm[z]) {
+          done[z] = 1;
+          continue;
+        }
+        ar[z].reset(m, beta);
+        keep.push_back(z);
+      }
+      act.swap(keep);
+    }
+    nact = (int)act.size();
+    if (nact == 0) break;
+    st = upload(act_d, act);
+    if (st != HSP_OK) return st;
+    int k = 0;
+    for (; k < m && it < maxit && nact > 0; ++k) {
+      const int rb = rb_fixed ? rb_fixed : default_tile(C, nact);
+      BIdx bVk, bZk, bw;
+      bVk.ld = (size_t)(m + 1) * nf;
+      bVk.map = act_d;
+      bZk.ld = (size_t)m * nf;
+      bZk.map = act_d;
+      bw.ld = nf;
+      precond_batch(C, B, ws, nact, rb, V + (size_t)k * nf, bVk, Z + (size_t)k * nf, bZk, s);
+      prof_begin(C, HSP_PROF_KRYLOV, s);
+      launch_stencil<double, double, double, double>(A, 0, Z + (size_t)k * nf, (const cd*)nullptr, w, 0.0, s, nact,
+                                                     bZk, BIdx{}, bw);
+      launch_bmultidot(V, nf, bVk, k + 1, w, bw, nf, part, B.nblk, hb, hs, nact, s);
+      launch_bmultiaxpy(V, nf, bVk, k + 1, hb, hs, w, bw, nf, 1, nact, s);
+      launch_bmultidot(V, nf, bVk, k + 1, w, bw, nf, part, B.nblk, hb + (m + 1), hs, nact, s);
+      launch_bmultiaxpy(V, nf, bVk, k + 1, hb + (m + 1), hs, w, bw, nf, 1, nact, s);
+      launch_bmultidot(w, 0, bw, 1, w, bw, nf, part, B.nblk, hb + 2 * (m + 1), hs, nact, s);
+      launch_bnormalize(w, bw, hb + 2 * (m + 1), hs, V + (size_t)(k + 1) * nf, bVk, nf, nact, s);
+      prof_end(C, HSP_PROF_KRYLOV, s,
+               (double)nact * ((double)nf * (2.0 * sizeof(cd) + sizeof(double)) +
+                               (double)nf * sizeof(cd) * (4.0 * k + 13.0)));
+      HIPCHK(hipGetLastError());
+      st = read_hb(nact);
+      if (st != HSP_OK) return st;
+      ++it;
+      std::vector<int> keep, conv;
+      for (int zi = 0; zi < nact; ++zi) {
+        const int z = act[zi];
+        const cd* hz = hh.data() + (size_t)zi * hs;
+        const double est = ar[z].add_column(k, hz, hz + (m + 1), hz[2 * (m + 1)].re);
+        its[z] = it;
+        if (est <= tol * bnorm[z]) {
+          conv.push_back(z);
+          done[z] = 1;
+        } else {
+          keep.push_back(z);
+        }
+      }
+      st = update(conv, k + 1);
+      if (st != HSP_OK) return st;
+      if (keep.size() != act.size()) {
+        act.swap(keep);
+        nact = (int)act.size();
+        st = upload(act_d, act);
+        if (st != HSP_OK) return st;
+      }
+    }
+    // end of a restart cycle (or maxit): fold the active corrections into x
+    st = update(act, k);
+    if (st != HSP_OK) return st;
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  // true residuals of every right-hand side
+  launch_stencil<double, double, double, double>(A, 1, x, b, w, 0.0, s, R, bid, bid, bid);
+  launch_bmultidot(w, 0, bid, 1, w, bid, nf, part, B.nblk, hb + 2 * (m + 1), hs, R, s);
+  st = read_hb(R);
+  if (st != HSP_OK) return st;
+  if (conj_transpose) launch_convert<double, double>(x, x, (size_t)R * nf, 1, s);
+  HIPCHK(hipGetLastError());
+  bool all = true;
+  for (int z = 0; z < R; ++z) {
+    const double rr = bnorm[z] > 0 ? std::sqrt(std::max(hh[(size_t)z * hs + 2 * (m + 1)].re, 0.0)) / bnorm[z] : 0.0;
+    if (iters) iters[z] = its[z];
+    if (relres) relres[z] = rr;
+    if (!done[z] && rr > tol) all = false;
+  }
+  if (!all) return fail(HSP_ENOCONV, "maxit reached before the tolerance for some right-hand sides");
   return HSP_OK;
 }
 

@@ -10,6 +10,15 @@ constexpr int kMaxSlabLayers = 56;   // 2-D slab thickness limit (LDS sized)
 constexpr int kMaxChunk = 64;        // longest chunk of the parallel substitutions
 constexpr int kWave = 64;
 
+// Batch addressing: vector z of a batch starts at base + off(z), with
+// off(z) = (map ? map[z] : z) * ld.  A default BIdx (ld = 0) addresses the
+// same vector for every z; single-vector calls use nb = 1.
+struct BIdx {
+  size_t ld = 0;
+  const int* map = nullptr;
+  __device__ __forceinline__ size_t off(int z) const { return (size_t)(map ? map[z] : z) * ld; }
+};
+
 // ---- stencil kernels (stencil.hip) ---------------------------------------
 // y = A x                         (mode 0)
 // y = b - A x                     (mode 1)
@@ -17,7 +26,7 @@ constexpr int kWave = 64;
 // Tx/Tb/Ty are the storage types of x, b, y; Ta the arithmetic type.
 template <class Ta, class Tx, class Tb, class Ty>
 void launch_stencil(const LevelDev& L, int mode, const cx<Tx>* x, const cx<Tb>* b, cx<Ty>* y,
-                    double w, hipStream_t s);
+                    double w, hipStream_t s, int nb = 1, BIdx bx = {}, BIdx bb = {}, BIdx by = {});
 
 // ---- transfers (transfer.hip) ---------------------------------------------
 struct TransferDev {
@@ -32,9 +41,11 @@ struct TransferDev {
   const double* pwy;
 };
 template <class Tin, class Tout>
-void launch_restrict(const TransferDev& T, const cx<Tin>* rf, cx<Tout>* rc, hipStream_t s);
+void launch_restrict(const TransferDev& T, const cx<Tin>* rf, cx<Tout>* rc, hipStream_t s, int nb = 1,
+                     BIdx bi = {}, BIdx bo = {});
 template <class Tc, class Tf>
-void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipStream_t s);
+void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipStream_t s, int nb = 1,
+                        BIdx bi = {}, BIdx bo = {});
 
 // ---- slab factorization and sweep stages (slab.hip) ------------------------
 struct SlabDev {
@@ -60,8 +71,31 @@ struct TaskDev {
 
 // Factor storage per slab (elements of cx<T>), column-major nl x nl blocks:
 // G_t, M_t = -G_t A_t, E_t, the chunk transfer matrices Y_t and X_t, each
-// [n2][nl][nl].
-inline size_t slab_factor_elems(int nl, int n2) { return (size_t)5 * n2 * nl * nl; }
+// [n2][nl][nl], then the couplings to the previous tangential node,
+// A_t[a][l] = coefficient of x_{t-1}[l+a-1] in row l, as [n2][3][nl].
+inline size_t slab_factor_elems(int nl, int n2) {
+  return (size_t)5 * n2 * nl * nl + (size_t)3 * n2 * nl;
+}
+
+// Factor block pointers of a slab.
+template <class T>
+struct SlabFac {
+  const cx<T>* G;
+  const cx<T>* M;
+  const cx<T>* E;
+  const cx<T>* Y;
+  const cx<T>* X;
+  const cx<T>* A;
+  __device__ SlabFac(const cx<T>* base, int n2, int nl) {
+    const size_t sz = (size_t)n2 * nl * nl;
+    G = base;
+    M = base + sz;
+    E = base + 2 * sz;
+    Y = base + 3 * sz;
+    X = base + 4 * sz;
+    A = base + 5 * sz;
+  }
+};
 // Setup scratch per slab (complex double): G_t, E_t and the couplings A_t.
 inline size_t slab_setup_elems(int nl, int n2) {
   return (size_t)2 * n2 * nl * nl + (size_t)3 * n2 * nl;
@@ -82,11 +116,25 @@ void launch_stage(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev
                   cx<T>* scratch, const cx<T>* factors, int nl_max, int nl_launch, int m, int P,
                   cx<T>* red, int* counters, hipStream_t s);
 
+// The same stage for nact right-hand sides (batch.hip): level vectors f, g, u
+// are [nact][ld] (right-hand side z at offset z ld), transmission buffers
+// [nact][2][2][n2]; work items (task, chunk, tile of rb right-hand sides).
+// scratch: 2 ceil(nact/rb) rb n2 nl_max; red: 2 ceil(nact/rb) 2 P nl_max rb;
+// counters: 4 ceil(nact/rb) ints, zero between launches.  rb in {1,2,4,8}.
+template <class T>
+void launch_stage_batch(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev, const LevelDev& G,
+                        const cx<T>* f, const cx<T>* g, cx<T>* u, cx<T>* bufs, cx<T>* scratch, const cx<T>* factors,
+                        int nl_max, int nl_launch, int m, int P, int nact, int rb, size_t ld, cx<T>* red,
+                        int* counters, hipStream_t s);
+
 // ---- BLAS-1 and utilities (blas.hip) ---------------------------------------
 template <class To, class Ti>
-void launch_convert(const cx<Ti>* in, cx<To>* out, size_t n, int conjugate, hipStream_t s);
+void launch_convert(const cx<Ti>* in, cx<To>* out, size_t n, int conjugate, hipStream_t s, int nb = 1,
+                    BIdx bi = {}, BIdx bo = {});
 template <class T>
 void launch_zero(cx<T>* v, size_t n, hipStream_t s);
+// v[i] = value for i < n
+void launch_fill(cd* v, size_t n, cd value, hipStream_t s);
 // partial[b*m + j] = sum over block b of conj(V_j) . w  (j < m), V_j = V + j*ldv
 void launch_multidot(const cd* V, size_t ldv, int m, const cd* w, size_t n, cd* partial,
                      int nblocks, hipStream_t s);
@@ -97,6 +145,17 @@ void launch_multiaxpy(const cd* V, size_t ldv, int m, const cd* h, cd* w, size_t
                       hipStream_t s);
 // v = w / sqrt(re(nrm2[0]))
 void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t s);
+// Batched forms over nb right-hand sides z (vector j of z: V + bv.off(z) + j ldj):
+// out[z ldo + j] = conj(V_zj) . w_z, j < cnt (partial: nb cnt nblocks entries)
+int batch_dot_blocks(size_t n, int nb);
+void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BIdx bw, size_t n, cd* partial,
+                      int nblocks, cd* out, size_t ldo, int nb, hipStream_t s);
+// w_z -= (or +=) sum_j h[z ldh + j] V_zj
+void launch_bmultiaxpy(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw, size_t n,
+                       int sub, int nb, hipStream_t s);
+// v_z = w_z / sqrt(re(nrm2[z ldn]))
+void launch_bnormalize(const cd* w, BIdx bw, const cd* nrm2, size_t ldn, cd* v, BIdx bv, size_t n, int nb,
+                       hipStream_t s);
 // b = h2 * f / (alpha_1(x_i) alpha_2(y_k)); ixn, iyn = 1/alpha at nodes 0..n+1
 void launch_scale_rhs_arrays(int n1, int n2, double h2, const cd* ixn, const cd* iyn, const cd* f, cd* b,
                              hipStream_t s);

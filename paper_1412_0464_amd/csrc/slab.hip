@@ -21,6 +21,7 @@
 // All blocks are stored column major (a thread owning output row l reads
 // them coalesced).
 #include "internal.h"
+#include "sweep_dev.h"
 
 namespace hsp {
 
@@ -41,6 +42,7 @@ __global__ void __launch_bounds__(256) k_factor(const SlabDev* __restrict__ slab
   cd* Ep = scratchE + (size_t)blockIdx.x * kMaxSlabLayers * kMaxSlabLayers;
   cx<T>* Gm = factors + sd.fac_off;
   cx<T>* Em = Gm + 2 * (size_t)n2 * nb;
+  cx<T>* Am = Gm + 5 * (size_t)n2 * nb;
   cd* Gd = setup + sd.scr_off;             // FP64 copies for the transfer matrices
   cd* Ed = Gd + (size_t)n2 * nb;
   cd* Ad = Ed + (size_t)n2 * nb;           // couplings A_t, [t][3][nl]
@@ -56,6 +58,7 @@ __global__ void __launch_bounds__(256) k_factor(const SlabDev* __restrict__ slab
 #pragma unroll
         for (int b = 0; b < 3; ++b) cfs[i * 9 + a * 3 + b] = c[a][b];
         Ad[((size_t)t * 3 + a) * nl + i] = c[a][0];
+        Am[((size_t)t * 3 + a) * nl + i] = cvt<T>(c[a][0]);
       }
     }
     __syncthreads();
@@ -237,52 +240,6 @@ __global__ void __launch_bounds__(256) k_chunk_transfer(const SlabDev* __restric
       __syncthreads();
     }
   }
-}
-
-// Transmission right-hand side of row gl at tangential node t (Sec. 2.2,
-// discrete transmission): T^(j) B adds +A_{b,b+1} B[1] to layer b and
-// -A_{b+1,b} B[0] to layer b+1 (b = beta_{j-1}); T~^(j) B adds
-// -A_{b,b+1} B[1] and +A_{b+1,b} B[0] (b = beta~_j).  A is the global
-// level operator, so the couplings are its (tridiagonal in t) blocks.
-template <class T>
-__device__ __forceinline__ cd transmission_rhs(const TaskDev& tk, const LevelDev& G, int gl, int t, int n2,
-                                               const cx<T>* Bif, const cx<T>* Bib) {
-  cd acc = mk<double>(0, 0);
-  const bool inF = tk.t1 && (gl == tk.beta_in || gl == tk.beta_in + 1);
-  const bool inB = tk.t3 && (gl == tk.bt_in || gl == tk.bt_in + 1);
-  if (!inF && !inB) return acc;
-  cd c[3][3];
-  stencil_coefs(G, gl, t + 1, c);
-  if (inF) {
-    const int s = (gl == tk.beta_in) ? 1 : 0;
-    cd a = mk<double>(0, 0);
-#pragma unroll
-    for (int dt = -1; dt <= 1; ++dt) {
-      const int tt = t + dt;
-      if (tt < 0 || tt >= n2) continue;
-      const cd cc = (s == 1) ? c[2][dt + 1] : c[0][dt + 1];
-      cfma(a, cc, cvt<double>(Bif[(size_t)s * n2 + tt]));
-    }
-    acc = (s == 1) ? acc + a : acc - a;
-  }
-  if (inB) {
-    const int s = (gl == tk.bt_in) ? 1 : 0;
-    cd a = mk<double>(0, 0);
-#pragma unroll
-    for (int dt = -1; dt <= 1; ++dt) {
-      const int tt = t + dt;
-      if (tt < 0 || tt >= n2) continue;
-      const cd cc = (s == 1) ? c[2][dt + 1] : c[0][dt + 1];
-      cfma(a, cc, cvt<double>(Bib[(size_t)s * n2 + tt]));
-    }
-    acc = (s == 1) ? acc - a : acc + a;
-  }
-  return acc;
-}
-
-template <class T>
-__device__ __forceinline__ cx<T> sel(bool ok, cx<T> v) {
-  return mk<T>(ok ? v.re : T(0), ok ? v.im : T(0));
 }
 
 // Row slice of a column-major block: entries (row lc, columns j0..j0+CW-1),
@@ -474,42 +431,6 @@ __device__ __forceinline__ void affine_chain(const cx<T>* __restrict__ mat, long
   else
     chain_workgroup<T, NB, NT, D>(mat, mstride, rows, first, dir, count, nl, sigma, vs, ps);
 }
-
-// The last workgroup of a (chunk-parallel) launch to arrive continues with
-// the chain over the chunk ends.  Release the block's results device-wide,
-// count arrivals, and make the other blocks' results visible to the last.
-__device__ __forceinline__ bool last_arrival(int* counter, int nblocks) {
-  __shared__ int sh_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int old = atomicAdd(counter, 1);
-    sh_last = (old == nblocks - 1) ? 1 : 0;
-    if (sh_last) atomicExch(counter, 0);  // ready for the next launch
-  }
-  __syncthreads();
-  const bool last = sh_last != 0;
-  if (last) __threadfence();
-  return last;
-}
-
-// Factor block pointers of a slab.
-template <class T>
-struct SlabFac {
-  const cx<T>* G;
-  const cx<T>* M;
-  const cx<T>* E;
-  const cx<T>* Y;
-  const cx<T>* X;
-  __device__ SlabFac(const cx<T>* base, int n2, int nl) {
-    const size_t sz = (size_t)n2 * nl * nl;
-    G = base;
-    M = base + sz;
-    E = base + 2 * sz;
-    Y = base + 3 * sz;
-    X = base + 4 * sz;
-  }
-};
 
 // ---- stage kernel 1: right-hand side, c_t = G_t f_t, forward chain per
 //      chunk, then (last workgroup) the chain over the chunk ends.

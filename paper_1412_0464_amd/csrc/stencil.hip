@@ -16,11 +16,16 @@ __device__ __forceinline__ cx<Ta> ld(const cx<Tx>* v, size_t i) {
 template <class Ta, class Tx, class Tb, class Ty>
 __global__ void __launch_bounds__(256) k_stencil(LevelDev L, int mode, const cx<Tx>* __restrict__ x,
                                                  const cx<Tb>* __restrict__ b, cx<Ty>* __restrict__ y,
-                                                 double w) {
+                                                 double w, BIdx bx, BIdx bb, BIdx by) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;  // y node 1..n2
   const int i = blockIdx.y + 1;                             // x node 1..n1
   const int n1 = L.n1, n2 = L.n2;
   if (k > n2) return;
+  // vector z of a batch (blockIdx.z)
+  const int z = blockIdx.z;
+  if (x != nullptr) x += bx.off(z);
+  if (b != nullptr) b += bb.off(z);
+  y += by.off(z);
   cd c[3][3];
   stencil_coefs(L, i, k, c);
   const size_t id = (size_t)(i - 1) * n2 + (k - 1);
@@ -60,14 +65,16 @@ __global__ void __launch_bounds__(256) k_stencil(LevelDev L, int mode, const cx<
 
 template <class Ta, class Tx, class Tb, class Ty>
 void launch_stencil(const LevelDev& L, int mode, const cx<Tx>* x, const cx<Tb>* b, cx<Ty>* y,
-                    double w, hipStream_t s) {
+                    double w, hipStream_t s, int nb, BIdx bx, BIdx bb, BIdx by) {
+  if (nb < 1) return;
   dim3 blk(256);
-  dim3 grd((L.n2 + 255) / 256, L.n1);
-  hipLaunchKernelGGL((k_stencil<Ta, Tx, Tb, Ty>), grd, blk, 0, s, L, mode, x, b, y, w);
+  dim3 grd((L.n2 + 255) / 256, L.n1, nb);
+  hipLaunchKernelGGL((k_stencil<Ta, Tx, Tb, Ty>), grd, blk, 0, s, L, mode, x, b, y, w, bx, bb, by);
 }
 
 #define INST(Ta, Tx, Tb, Ty) \
-  template void launch_stencil<Ta, Tx, Tb, Ty>(const LevelDev&, int, const cx<Tx>*, const cx<Tb>*, cx<Ty>*, double, hipStream_t);
+  template void launch_stencil<Ta, Tx, Tb, Ty>(const LevelDev&, int, const cx<Tx>*, const cx<Tb>*, cx<Ty>*, double, \
+                                               hipStream_t, int, BIdx, BIdx, BIdx);
 INST(double, double, double, double)
 INST(double, float, double, double)
 INST(double, float, double, float)

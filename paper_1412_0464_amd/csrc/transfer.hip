@@ -11,10 +11,12 @@ namespace {
 
 template <class Tin, class Tout>
 __global__ void __launch_bounds__(256) k_restrict(TransferDev T, const cx<Tin>* __restrict__ rf,
-                                                  cx<Tout>* __restrict__ rc) {
+                                                  cx<Tout>* __restrict__ rc, BIdx bi, BIdx bo) {
   const int K = blockIdx.x * blockDim.x + threadIdx.x;  // coarse y unknown (0-based)
   const int I = blockIdx.y;                             // coarse x unknown
   if (K >= T.nc2) return;
+  rf += bi.off(blockIdx.z);
+  rc += bo.off(blockIdx.z);
   cd acc = mk<double>(0, 0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -33,10 +35,12 @@ __global__ void __launch_bounds__(256) k_restrict(TransferDev T, const cx<Tin>* 
 
 template <class Tc, class Tf>
 __global__ void __launch_bounds__(256) k_prolong_add(TransferDev T, const cx<Tc>* __restrict__ ec,
-                                                     cx<Tf>* __restrict__ xf) {
+                                                     cx<Tf>* __restrict__ xf, BIdx bi, BIdx bo) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;  // fine y unknown
   const int i = blockIdx.y;
   if (k >= T.nf2) return;
+  ec += bi.off(blockIdx.z);
+  xf += bo.off(blockIdx.z);
   cd acc = mk<double>(0, 0);
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -57,20 +61,24 @@ __global__ void __launch_bounds__(256) k_prolong_add(TransferDev T, const cx<Tc>
 }  // namespace
 
 template <class Tin, class Tout>
-void launch_restrict(const TransferDev& T, const cx<Tin>* rf, cx<Tout>* rc, hipStream_t s) {
-  dim3 grd((T.nc2 + 255) / 256, T.nc1);
-  hipLaunchKernelGGL((k_restrict<Tin, Tout>), grd, dim3(256), 0, s, T, rf, rc);
+void launch_restrict(const TransferDev& T, const cx<Tin>* rf, cx<Tout>* rc, hipStream_t s, int nb, BIdx bi,
+                     BIdx bo) {
+  if (nb < 1) return;
+  dim3 grd((T.nc2 + 255) / 256, T.nc1, nb);
+  hipLaunchKernelGGL((k_restrict<Tin, Tout>), grd, dim3(256), 0, s, T, rf, rc, bi, bo);
 }
 template <class Tc, class Tf>
-void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipStream_t s) {
-  dim3 grd((T.nf2 + 255) / 256, T.nf1);
-  hipLaunchKernelGGL((k_prolong_add<Tc, Tf>), grd, dim3(256), 0, s, T, ec, xf);
+void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipStream_t s, int nb, BIdx bi,
+                        BIdx bo) {
+  if (nb < 1) return;
+  dim3 grd((T.nf2 + 255) / 256, T.nf1, nb);
+  hipLaunchKernelGGL((k_prolong_add<Tc, Tf>), grd, dim3(256), 0, s, T, ec, xf, bi, bo);
 }
 
-template void launch_restrict<double, double>(const TransferDev&, const cd*, cd*, hipStream_t);
-template void launch_restrict<double, float>(const TransferDev&, const cd*, cf*, hipStream_t);
-template void launch_prolong_add<double, double>(const TransferDev&, const cd*, cd*, hipStream_t);
-template void launch_prolong_add<float, float>(const TransferDev&, const cf*, cf*, hipStream_t);
-template void launch_prolong_add<float, double>(const TransferDev&, const cf*, cd*, hipStream_t);
+template void launch_restrict<double, double>(const TransferDev&, const cd*, cd*, hipStream_t, int, BIdx, BIdx);
+template void launch_restrict<double, float>(const TransferDev&, const cd*, cf*, hipStream_t, int, BIdx, BIdx);
+template void launch_prolong_add<double, double>(const TransferDev&, const cd*, cd*, hipStream_t, int, BIdx, BIdx);
+template void launch_prolong_add<float, float>(const TransferDev&, const cf*, cf*, hipStream_t, int, BIdx, BIdx);
+template void launch_prolong_add<float, double>(const TransferDev&, const cf*, cd*, hipStream_t, int, BIdx, BIdx);
 
 }  // namespace hsp

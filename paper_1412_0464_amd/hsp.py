@@ -48,7 +48,8 @@ EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", 
            "hsp_apply_precond", "hsp_solve", "hsp_destroy", "hsp_last_error", "hsp_get_info",
            "hsp_get_partition", "hsp_apply_level_operator", "hsp_restrict", "hsp_prolong_add",
            "hsp_smooth", "hsp_sweep", "hsp_slab_solve", "hsp_profile_enable", "hsp_profile_read",
-           "hsp_gradient_accumulate"]
+           "hsp_gradient_accumulate", "hsp_batch_workspace_size", "hsp_apply_precond_batch",
+           "hsp_tune_batch", "hsp_solve_batch"]
 PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4}
 
 
@@ -87,6 +88,10 @@ def load():
         "hsp_profile_enable": [P, I],
         "hsp_gradient_accumulate": [P, P, P, P, P],
         "hsp_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D)],
+        "hsp_batch_workspace_size": [P, I, I, ctypes.POINTER(S)],
+        "hsp_apply_precond_batch": [P, I, P, P, I, P, S, P],
+        "hsp_tune_batch": [P, I, I, P, S, ctypes.POINTER(I), ctypes.POINTER(D), P],
+        "hsp_solve_batch": [P, I, P, P, D, I, I, I, I, P, S, ctypes.POINTER(I), ctypes.POINTER(D), P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -302,3 +307,71 @@ class Helmholtz:
             return u, it.value, rr.value
         _check(st)
         return u, it.value, rr.value
+
+    # -- batched right-hand sides (one medium and frequency, shared factors) --
+    def batch_workspace(self, nrhs, restart=None):
+        """Device workspace of the batched calls for up to ``nrhs`` right-hand
+        sides and FGMRES restart ``restart`` (cached on the object)."""
+        restart = int(restart or self.opts.restart)
+        key = (int(nrhs), restart)
+        if getattr(self, "_bws_key", None) == key:
+            return self._bws
+        S = ctypes.c_size_t()
+        _check(load().hsp_batch_workspace_size(self.handle, int(nrhs), restart, ctypes.byref(S)))
+        self._bws = None
+        self._bws = torch.empty(S.value, dtype=torch.uint8, device=self.ws.device)
+        self._bws_key = key
+        return self._bws
+
+    def _batch(self, t, name):
+        if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous() and t.dim() == 3
+                and tuple(t.shape[1:]) == tuple(self.n_fine)):
+            raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape (nrhs, {self.n_fine[0]}, "
+                             f"{self.n_fine[1]})")
+        return t
+
+    def apply_precond_batch(self, r, tile=0, out=None):
+        """z_j = M r_j for every right-hand side j of r (nrhs, n1, n2)
+        (hsp_apply_precond_batch)."""
+        self._batch(r, "r")
+        nrhs = r.shape[0]
+        z = torch.empty_like(r) if out is None else self._batch(out, "out")
+        if nrhs == 0:
+            return z
+        key = getattr(self, "_bws_key", None)
+        ws = self._bws if key is not None and key[0] == nrhs else self.batch_workspace(nrhs, 1)
+        _check(load().hsp_apply_precond_batch(self.handle, int(nrhs), _ptr(r), _ptr(z), int(tile), _ptr(ws),
+                                              ws.numel(), _stream()))
+        return z
+
+    def tune_batch(self, nrhs, restart=None):
+        """Time the batched preconditioner for every right-hand-side tile and
+        keep the fastest for this batch size (hsp_tune_batch).  Returns
+        (tile, ms per application)."""
+        restart = int(restart or self.opts.restart)
+        ws = self.batch_workspace(nrhs, restart)
+        tile = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(load().hsp_tune_batch(self.handle, int(nrhs), restart, _ptr(ws), ws.numel(), ctypes.byref(tile),
+                                     ctypes.byref(ms), _stream()))
+        return tile.value, ms.value
+
+    def solve_batch(self, b, tol=1e-6, maxit=200, restart=None, tile=0, conj_transpose=False, out=None,
+                    raise_on_noconv=True):
+        """FGMRES on A u_j = b_j for every right-hand side of b (nrhs, n1, n2),
+        each stopped at its own tolerance (hsp_solve_batch).  Returns
+        (u, iterations per right-hand side, true relative residuals)."""
+        self._batch(b, "b")
+        nrhs = b.shape[0]
+        u = torch.empty_like(b) if out is None else self._batch(out, "out")
+        its = (ctypes.c_int * max(nrhs, 1))()
+        rr = (ctypes.c_double * max(nrhs, 1))()
+        if nrhs == 0:
+            return u, [], []
+        restart = int(restart or self.opts.restart)
+        ws = self.batch_workspace(nrhs, restart)
+        st = load().hsp_solve_batch(self.handle, int(nrhs), _ptr(b), _ptr(u), float(tol), int(maxit), restart,
+                                    int(bool(conj_transpose)), int(tile), _ptr(ws), ws.numel(), its, rr, _stream())
+        if not (st == HSP_ENOCONV and not raise_on_noconv):
+            _check(st)
+        return u, list(its)[:nrhs], list(rr)[:nrhs]

@@ -1,0 +1,193 @@
+"""GPU parity of the batched multi-right-hand-side path against the CPU oracle.
+
+The batched preconditioner is the same linear map as the single one, applied
+to every column: each column is compared with the oracle's preconditioner
+(FP64 1e-10, complex64 2e-5 relative).  The batched FGMRES runs one Arnoldi
+process per right-hand side with its own stopping test, so each column must
+reproduce the oracle's FGMRES on that right-hand side: iteration counts
+within +-1 and solutions within 1e-6 (FP64) or, after refinement to 1e-10,
+within 1e-4 of the direct solution (mixed).  Batches are ragged with respect
+to every tile size, mix sources that converge at different iterations, and
+include a zero right-hand side (0 iterations, u = 0).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.problem import Problem2D  # noqa: E402
+from oracle.krylov import fgmres  # noqa: E402
+from synth.media import layered_medium_2d, extend_into_pml, point_source, random_rhs  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")]
+
+# (n1, n2, w, J, fine, two_grid, sweep, ppw)
+CASES = {
+    "fd5_1lvl_x": (61, 45, 6, 3, "fd5", False, "x", 8.0),
+    "fe9_1lvl_x": (47, 53, 5, 4, "fe9", False, "x", 10.0),
+    "tg_ud": (79, 63, 8, 2, "fd5", True, "ud", 8.0),
+    "tg_x_j5": (127, 95, 8, 5, "fd5", True, "x", 8.0),
+}
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _build(name, precision="fp64", chunk=0, restart=40):
+    n1, n2, w, J, fine, tg, sweep, ppw = CASES[name]
+    c = extend_into_pml(layered_medium_2d(n1, n2, 1412046, n_layers=7, corr_len=6.0), w)
+    h = 0.02
+    om = 2 * np.pi * 1.5 / (ppw * h)
+    print(f"[batch case {name} precision={precision} chunk={chunk} shape={c.shape}]", flush=True)
+    ref = Problem2D(c, om, h, w, S_outer=5.0 * w, J=J, w_dd=4, fine=fine, two_grid=tg, sweep=sweep)
+    from paper_1412_0464_amd import Helmholtz
+    hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, J, S_outer=5.0 * w,
+                   fine_stencil=5 if fine == "fd5" else 9, two_grid=tg, sweep=sweep, precision=precision,
+                   chunk=chunk, restart=restart)
+    return c, ref, hs
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.complex128, device=_dev())
+
+
+def _relerr(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _sources(shape, h, nsrc):
+    """Point sources spread over the interior (they converge at different
+    iterations), plus a zero right-hand side at index 1."""
+    rng = np.random.default_rng(1412047)
+    fs = []
+    for s in range(nsrc):
+        if s == 1:
+            fs.append(np.zeros(shape, dtype=complex))
+            continue
+        i = int(rng.integers(shape[0] // 5, 4 * shape[0] // 5))
+        k = int(rng.integers(shape[1] // 5, 4 * shape[1] // 5))
+        fs.append(point_source(shape, (i, k), h))
+    return fs
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,precision,tol", [
+    ("fd5_1lvl_x", "fp64", 1e-10), ("fe9_1lvl_x", "fp64", 1e-10), ("tg_ud", "fp64", 1e-10),
+    ("tg_x_j5", "fp64", 1e-10), ("tg_x_j5", "mixed", 2e-5), ("fd5_1lvl_x", "mixed", 2e-5)])
+@pytest.mark.parametrize("tile", [1, 2, 4, 8])
+def test_batch_precond_columns(name, precision, tol, tile):
+    c, ref, hs = _build(name, precision)
+    nrhs = 5  # ragged for tiles 2, 4 and 8
+    R = np.stack([random_rhs(c.shape, 300 + j) for j in range(nrhs)])
+    Z = hs.apply_precond_batch(_t(R), tile=tile).cpu().numpy()
+    for j in range(nrhs):
+        assert _relerr(Z[j], ref.precond(R[j].ravel())) < tol, f"column {j}"
+
+
+@pytest.mark.parametrize("chunk", [7, 64])
+def test_batch_precond_chunk_geometry(chunk):
+    c, ref, hs = _build("tg_x_j5", "fp64", chunk=chunk)
+    nrhs = 9
+    R = np.stack([random_rhs(c.shape, 320 + j) for j in range(nrhs)])
+    Z = hs.apply_precond_batch(_t(R), tile=8).cpu().numpy()
+    for j in range(nrhs):
+        assert _relerr(Z[j], ref.precond(R[j].ravel())) < 1e-10, f"column {j}"
+
+
+def test_batch_precond_single_column_equals_single_path():
+    c, ref, hs = _build("tg_x_j5", "mixed")
+    r = random_rhs(c.shape, 330)
+    z1 = hs.apply_precond(_t(r)).cpu().numpy()
+    zb = hs.apply_precond_batch(_t(r[None])).cpu().numpy()[0]
+    # same factors and the same linear map; only the evaluation order differs
+    assert _relerr(zb, z1) < 2e-5
+
+
+@pytest.mark.parametrize("name", ["fd5_1lvl_x", "tg_x_j5", "tg_ud"])
+def test_batch_solve_fp64(name):
+    c, ref, hs = _build(name)
+    fs = _sources(c.shape, 0.02, 6)
+    B = torch.stack([hs.rhs(_t(f)) for f in fs])
+    U, its, rrs = hs.solve_batch(B, tol=1e-6, maxit=100)
+    U = U.cpu().numpy()
+    for j, f in enumerate(fs):
+        if not np.any(f):
+            assert its[j] == 0 and rrs[j] == 0 and not np.any(U[j])
+            continue
+        uo, ito, _, _ = ref.solve(f, tol=1e-6, maxit=100)
+        assert abs(its[j] - ito) <= 1 and rrs[j] <= 1e-6, f"column {j}: {its[j]} vs {ito}, {rrs[j]}"
+        assert _relerr(U[j], uo) < 1e-6, f"column {j}"
+
+
+def test_batch_solve_mixed_after_refinement():
+    c, ref, hs = _build("tg_x_j5", "mixed")
+    fs = _sources(c.shape, 0.02, 5)
+    B = torch.stack([hs.rhs(_t(f)) for f in fs])
+    U, its, rrs = hs.solve_batch(B, tol=1e-10, maxit=200)
+    U = U.cpu().numpy()
+    for j, f in enumerate(fs):
+        if not np.any(f):
+            continue
+        assert rrs[j] <= 1e-10
+        assert _relerr(U[j], ref.direct(f)) < 1e-4, f"column {j}"
+    _, its6, rrs6 = hs.solve_batch(B, tol=1e-6, maxit=200)
+    for j, f in enumerate(fs):
+        if not np.any(f):
+            continue
+        _, ito6, _, _ = ref.solve(f, tol=1e-6, maxit=200)
+        assert rrs6[j] <= 1e-6 and abs(its6[j] - ito6) <= 1, f"column {j}: {its6[j]} vs {ito6}"
+
+
+def test_batch_solve_restarted():
+    restart = 4
+    c, ref, hs = _build("tg_x_j5", "fp64", restart=restart)
+    fs = _sources(c.shape, 0.02, 3)
+    B = torch.stack([hs.rhs(_t(f)) for f in fs])
+    U, its, rrs = hs.solve_batch(B, tol=1e-8, maxit=200, restart=restart)
+    U = U.cpu().numpy()
+    for j, f in enumerate(fs):
+        if not np.any(f):
+            continue
+        uo, ito, _, _ = fgmres(ref.matvec, ref.precond, ref.rhs(f), tol=1e-8, maxit=200, restart=restart)
+        assert abs(its[j] - ito) <= 1 and rrs[j] <= 1e-8, f"column {j}: {its[j]} vs {ito}"
+        assert _relerr(U[j], uo) < 1e-6
+
+
+def test_batch_conjugate_transpose():
+    c, ref, hs = _build("tg_ud")
+    B = np.stack([random_rhs(c.shape, 340 + j) for j in range(3)])
+    U, its, rrs = hs.solve_batch(_t(B), tol=1e-10, maxit=100, conj_transpose=True)
+    U = U.cpu().numpy()
+    AH = ref.A.conj().T
+    for j in range(3):
+        res = AH @ U[j].ravel() - B[j].ravel()
+        assert np.linalg.norm(res) / np.linalg.norm(B[j]) < 1e-9
+
+
+def test_batch_empty_and_tune():
+    c, ref, hs = _build("fd5_1lvl_x", "mixed")
+    B = torch.zeros((0,) + tuple(c.shape), dtype=torch.complex128, device=_dev())
+    U, its, rrs = hs.solve_batch(B)
+    assert U.shape[0] == 0 and its == [] and rrs == []
+    tile, ms = hs.tune_batch(6)
+    assert tile in (1, 2, 4, 8) and ms > 0
+    R = np.stack([random_rhs(c.shape, 350 + j) for j in range(6)])
+    Z = hs.apply_precond_batch(_t(R)).cpu().numpy()
+    for j in range(6):
+        assert _relerr(Z[j], ref.precond(R[j].ravel())) < 2e-5
+
+
+def test_batch_invalid_arguments():
+    c, ref, hs = _build("fd5_1lvl_x")
+    from paper_1412_0464_amd.hsp import HspError
+    B = _t(np.stack([random_rhs(c.shape, 360)]))
+    with pytest.raises(HspError):
+        hs.solve_batch(B, tile=3)
+    with pytest.raises(HspError):
+        hs.solve_batch(B, tol=0.0)
