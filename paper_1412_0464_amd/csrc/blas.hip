@@ -48,28 +48,6 @@ __device__ __forceinline__ cd block_sum(cd v, cd* sh) {
   return r;
 }
 
-__global__ void __launch_bounds__(256) k_multidot(const cd* __restrict__ V, size_t ldv, const cd* __restrict__ w,
-                                                  size_t n, cd* __restrict__ partial, int m) {
-  __shared__ cd sh[4];
-  const int j = blockIdx.y;
-  const cd* v = V + (size_t)j * ldv;
-  cd acc = mk<double>(0, 0);
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    cfma(acc, conj(v[i]), w[i]);
-  cd r = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * m + j] = r;
-}
-
-__global__ void __launch_bounds__(256) k_reduce_partials(const cd* __restrict__ partial, int nb, int m,
-                                                         cd* __restrict__ out) {
-  __shared__ cd sh[4];
-  const int j = blockIdx.x;
-  cd acc = mk<double>(0, 0);
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[(size_t)b * m + j];
-  cd r = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[j] = r;
-}
-
 __global__ void __launch_bounds__(256) k_multiaxpy(const cd* __restrict__ V, size_t ldv, int m,
                                                    const cd* __restrict__ h, cd* __restrict__ w, size_t n,
                                                    int sub) {
@@ -197,18 +175,58 @@ __global__ void k_grad_m(int n1, int n2, double scale, const cd* __restrict__ ix
 
 // ---- batched Gram-Schmidt pieces: vector j of right-hand side z of a basis
 // is V + bv.off(z) + j * ldj; blockIdx.z (or .y) selects z.
+// Sum of NV complex values over the 256 threads of a block: thread q < NV
+// returns the total of entry q.
+template <int NV>
+__device__ __forceinline__ cd block_sum_arr(cd (&v)[NV], cd* sh) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    for (int off = 32; off > 0; off >>= 1) {
+      v[q].re += __shfl_xor(v[q].re, off, 64);
+      v[q].im += __shfl_xor(v[q].im, off, 64);
+    }
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[wv * NV + q] = v[q];
+  __syncthreads();
+  cd r = mk<double>(0, 0);
+  if (t < NV)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w * NV + t];
+  return r;
+}
+
+// Basis vectors j0 .. j0+kDotTile-1 (blockIdx.y tile) against w: w is read
+// once per tile.
+constexpr int kDotTile = 8;
 __global__ void __launch_bounds__(256) k_bmultidot(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
                                                    const cd* __restrict__ w, BIdx bw, size_t n,
                                                    cd* __restrict__ partial) {
-  __shared__ cd sh[4];
-  const int j = blockIdx.y, z = blockIdx.z;
-  const cd* v = V + bv.off(z) + (size_t)j * ldj;
+  __shared__ cd sh[4 * kDotTile];
+  const int z = blockIdx.z, j0 = blockIdx.y * kDotTile;
+  const int jn = min(kDotTile, cnt - j0);
+  const cd* v = V + bv.off(z) + (size_t)j0 * ldj;
   w += bw.off(z);
-  cd acc = mk<double>(0, 0);
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    cfma(acc, conj(v[i]), w[i]);
-  cd r = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[((size_t)z * cnt + j) * gridDim.x + blockIdx.x] = r;
+  cd acc[kDotTile];
+#pragma unroll
+  for (int q = 0; q < kDotTile; ++q) acc[q] = mk<double>(0, 0);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  if (jn == kDotTile) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+      const cd wi = w[i];
+#pragma unroll
+      for (int q = 0; q < kDotTile; ++q) cfma(acc[q], conj(v[(size_t)q * ldj + i]), wi);
+    }
+  } else {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+      const cd wi = w[i];
+#pragma unroll
+      for (int q = 0; q < kDotTile; ++q)
+        if (q < jn) cfma(acc[q], conj(v[(size_t)q * ldj + i]), wi);
+    }
+  }
+  const cd r = block_sum_arr<kDotTile>(acc, sh);
+  if ((int)threadIdx.x < jn) partial[((size_t)z * cnt + j0 + threadIdx.x) * gridDim.x + blockIdx.x] = r;
 }
 
 __global__ void __launch_bounds__(256) k_breduce(const cd* __restrict__ partial, int nb, int cnt,
@@ -234,6 +252,126 @@ __global__ void __launch_bounds__(256) k_bmultiaxpy(const cd* __restrict__ V, si
     for (int j = 0; j < cnt; ++j) cfma(acc, hz[j], v[(size_t)j * ldj + i]);
     w[i] = sub ? (w[i] - acc) : (w[i] + acc);
   }
+}
+
+// Delayed classical Gram-Schmidt, one projection pass: for basis vectors
+// j < cnt of right-hand side z (slot cnt-1 holds the once-projected,
+// unnormalised vector u), conj(V_zj) . u and conj(V_zj) . w; both read once.
+// partial[((z 2 cnt) + q cnt + j) nblk + block], q = 0 (u) or 1 (w).
+__global__ void __launch_bounds__(256) k_bmultidot2(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
+                                                    const cd* __restrict__ w, BIdx bw, size_t n,
+                                                    cd* __restrict__ partial) {
+  __shared__ cd sh[4 * 2 * kDotTile];
+  const int z = blockIdx.z, j0 = blockIdx.y * kDotTile;
+  const int jn = min(kDotTile, cnt - j0);
+  const cd* vz = V + bv.off(z);
+  const cd* v = vz + (size_t)j0 * ldj;
+  const cd* u = vz + (size_t)(cnt - 1) * ldj;
+  w += bw.off(z);
+  cd acc[2 * kDotTile];
+#pragma unroll
+  for (int q = 0; q < 2 * kDotTile; ++q) acc[q] = mk<double>(0, 0);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const cd ui = u[i], wi = w[i];
+#pragma unroll
+    for (int q = 0; q < kDotTile; ++q)
+      if (q < jn) {
+        const cd vj = conj(v[(size_t)q * ldj + i]);
+        cfma(acc[q], vj, ui);
+        cfma(acc[kDotTile + q], vj, wi);
+      }
+  }
+  const cd r = block_sum_arr<2 * kDotTile>(acc, sh);
+  const int t = threadIdx.x;
+  if (t < 2 * kDotTile) {
+    const int q = t / kDotTile, jj = t - q * kDotTile;
+    if (jj < jn) partial[(((size_t)z * 2 + q) * cnt + j0 + jj) * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+// Per right-hand side (one thread each) after k_bmultidot2 with cnt = k+1:
+// d = hb + z ldh holds s_j = conj(v_j) . u (j < k), sigma = u . u (at k),
+// then p_j = conj(v_j) . w (j < k) and pi = u . w (at cnt + k).  The
+// reorthogonalised basis vector is v_k = (u - sum_j s_j v_j) / nu with
+// nu^2 = sigma - |s|^2 (nu = 1 at k = 0, where u is already final), and
+// h_kk = conj(v_k) . w = (pi - s^H p) / nu.  Writes nu and h_kk at d[off],
+// d[off + 1].
+__global__ void k_bdcgs_coef(cd* __restrict__ hb, size_t ldh, int k, int off, int nb) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nb) return;
+  cd* d = hb + (size_t)z * ldh;
+  const int cnt = k + 1;
+  double ss = 0;
+  cd sp = mk<double>(0, 0);
+  for (int j = 0; j < k; ++j) {
+    ss += abs2(d[j]);
+    cfma(sp, conj(d[j]), d[cnt + j]);
+  }
+  double nu = 1.0;
+  if (k > 0) nu = sqrt(fmax(d[k].re - ss, 1e-300));
+  const cd pi = d[cnt + k];
+  d[off] = mk<double>(nu, 0.0);
+  d[off + 1] = mk<double>((pi.re - sp.re) / nu, (pi.im - sp.im) / nu);
+}
+
+// The update pass of the delayed Gram-Schmidt step: with s, p, nu, h_kk as
+// above, v_k = (u - V s) / nu overwrites slot k and
+// u' = w - V p - h_kk v_k (the next once-projected vector) goes to slot k+1,
+// with the block partials of ||u'||^2.  Reads V (k vectors), u and w once.
+__global__ void __launch_bounds__(256) k_bdcgs_update(cd* __restrict__ V, size_t ldj, BIdx bv, int k,
+                                                      const cd* __restrict__ hb, size_t ldh, int off,
+                                                      const cd* __restrict__ w, BIdx bw, size_t n,
+                                                      cd* __restrict__ partial) {
+  __shared__ cd sh[4];
+  const int z = blockIdx.y;
+  cd* vz = V + bv.off(z);
+  const cd* d = hb + (size_t)z * ldh;
+  const cd* sv = d;
+  const cd* pv = d + (k + 1);
+  const double inu = 1.0 / d[off].re;
+  const cd hkk = d[off + 1];
+  cd* u = vz + (size_t)k * ldj;
+  cd* un = vz + (size_t)(k + 1) * ldj;
+  w += bw.off(z);
+  double nrm = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    cd t1 = mk<double>(0, 0), t2 = mk<double>(0, 0);
+    for (int j = 0; j < k; ++j) {
+      const cd vj = vz[(size_t)j * ldj + i];
+      cfma(t1, sv[j], vj);
+      cfma(t2, pv[j], vj);
+    }
+    const cd vk = inu * (u[i] - t1);
+    u[i] = vk;
+    cd wn = w[i] - t2;
+    cfma(wn, -hkk, vk);
+    un[i] = wn;
+    nrm += abs2(wn);
+  }
+  const cd r = block_sum(mk<double>(nrm, 0.0), sh);
+  if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = r;
+}
+
+// w_z -= sum_j h[z ldh + j] V_zj, with the block partials of ||w_z||^2
+__global__ void __launch_bounds__(256) k_bmultiaxpy_norm(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
+                                                         const cd* __restrict__ h, size_t ldh, cd* __restrict__ w,
+                                                         BIdx bw, size_t n, cd* __restrict__ partial) {
+  __shared__ cd sh[4];
+  const int z = blockIdx.y;
+  const cd* v = V + bv.off(z);
+  const cd* hz = h + (size_t)z * ldh;
+  w += bw.off(z);
+  double nrm = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    cd acc = mk<double>(0, 0);
+    for (int j = 0; j < cnt; ++j) cfma(acc, hz[j], v[(size_t)j * ldj + i]);
+    const cd wn = w[i] - acc;
+    w[i] = wn;
+    nrm += abs2(wn);
+  }
+  const cd r = block_sum(mk<double>(nrm, 0.0), sh);
+  if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = r;
 }
 
 __global__ void k_bnormalize(const cd* __restrict__ w, BIdx bw, const cd* __restrict__ nrm2, size_t ldn,
@@ -282,13 +420,6 @@ void launch_fill(cd* v, size_t n, cd value, hipStream_t s) {
 }
 template void launch_zero<float>(cf*, size_t, hipStream_t);
 
-void launch_multidot(const cd* V, size_t ldv, int m, const cd* w, size_t n, cd* partial, int nblocks,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_multidot, dim3(nblocks, m), dim3(256), 0, s, V, ldv, w, n, partial, m);
-}
-void launch_reduce_partials(const cd* partial, int nblocks, int m, cd* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(m), dim3(256), 0, s, partial, nblocks, m, out);
-}
 void launch_multiaxpy(const cd* V, size_t ldv, int m, const cd* h, cd* w, size_t n, int sub, hipStream_t s) {
   hipLaunchKernelGGL(k_multiaxpy, dim3(nblk(n)), dim3(256), 0, s, V, ldv, m, h, w, n, sub);
 }
@@ -299,7 +430,8 @@ int batch_dot_blocks(size_t n, int nb) { return nblk_batch(n, nb); }
 void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BIdx bw, size_t n, cd* partial,
                       int nblocks, cd* out, size_t ldo, int nb, hipStream_t s) {
   if (nb < 1 || cnt < 1) return;
-  hipLaunchKernelGGL(k_bmultidot, dim3(nblocks, cnt, nb), dim3(256), 0, s, V, ldj, bv, cnt, w, bw, n, partial);
+  const int tiles = (cnt + kDotTile - 1) / kDotTile;
+  hipLaunchKernelGGL(k_bmultidot, dim3(nblocks, tiles, nb), dim3(256), 0, s, V, ldj, bv, cnt, w, bw, n, partial);
   hipLaunchKernelGGL(k_breduce, dim3(cnt, nb), dim3(256), 0, s, (const cd*)partial, nblocks, cnt, out, ldo);
 }
 void launch_bmultiaxpy(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw, size_t n,
@@ -307,6 +439,29 @@ void launch_bmultiaxpy(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, s
   if (nb < 1 || cnt < 1) return;
   hipLaunchKernelGGL(k_bmultiaxpy, dim3(nblk_batch(n, nb), nb), dim3(256), 0, s, V, ldj, bv, cnt, h, ldh, w, bw, n,
                      sub);
+}
+void launch_bmultiaxpy_norm(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw,
+                            size_t n, cd* partial, int nblocks, cd* nrm2, size_t ldo, int nb, hipStream_t s) {
+  if (nb < 1) return;
+  hipLaunchKernelGGL(k_bmultiaxpy_norm, dim3(nblocks, nb), dim3(256), 0, s, V, ldj, bv, cnt, h, ldh, w, bw, n,
+                     partial);
+  hipLaunchKernelGGL(k_breduce, dim3(1, nb), dim3(256), 0, s, (const cd*)partial, nblocks, 1, nrm2, ldo);
+}
+void launch_bdcgs_project(const cd* V, size_t ldj, BIdx bv, int k, const cd* w, BIdx bw, size_t n, cd* partial,
+                          int nblocks, cd* hb, size_t ldh, int off, int nb, hipStream_t s) {
+  if (nb < 1) return;
+  const int cnt = k + 1;
+  const int tiles = (cnt + kDotTile - 1) / kDotTile;
+  hipLaunchKernelGGL(k_bmultidot2, dim3(nblocks, tiles, nb), dim3(256), 0, s, V, ldj, bv, cnt, w, bw, n, partial);
+  hipLaunchKernelGGL(k_breduce, dim3(2 * cnt, nb), dim3(256), 0, s, (const cd*)partial, nblocks, 2 * cnt, hb, ldh);
+  hipLaunchKernelGGL(k_bdcgs_coef, dim3((nb + 63) / 64), dim3(64), 0, s, hb, ldh, k, off, nb);
+}
+void launch_bdcgs_update(cd* V, size_t ldj, BIdx bv, int k, const cd* hb, size_t ldh, int off, const cd* w, BIdx bw,
+                         size_t n, cd* partial, int nblocks, cd* nrm2, int nb, hipStream_t s) {
+  if (nb < 1) return;
+  hipLaunchKernelGGL(k_bdcgs_update, dim3(nblocks, nb), dim3(256), 0, s, V, ldj, bv, k, hb, ldh, off, w, bw, n,
+                     partial);
+  hipLaunchKernelGGL(k_breduce, dim3(1, nb), dim3(256), 0, s, (const cd*)partial, nblocks, 1, nrm2, ldh);
 }
 void launch_bnormalize(const cd* w, BIdx bw, const cd* nrm2, size_t ldn, cd* v, BIdx bv, size_t n, int nb,
                        hipStream_t s) {

@@ -655,7 +655,7 @@ BatchLayout batch_layout(const Plan& P, int R, int m) {
   B.o_Z = c.take((size_t)R * m * nf * sizeof(cd));
   B.o_w = c.take(R * nf * sizeof(cd));
   B.o_bc = c.take(R * nf * sizeof(cd));
-  B.o_part = c.take((size_t)R * (m + 1) * B.nblk * sizeof(cd));
+  B.o_part = c.take((size_t)2 * R * (m + 1) * B.nblk * sizeof(cd));
   B.o_hb = c.take(R * B.hs * sizeof(cd));
   B.o_act = c.take(R * sizeof(int));
   B.o_upd = c.take(R * sizeof(int));
@@ -1367,9 +1367,9 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
     b = bc;
   }
   const LevelDev& A = C->fine;
+  // conj(vecs_j) . vv for j < cnt into out[j] (w read once per tile of basis vectors)
   auto dotn = [&](const cd* vecs, int cnt, const cd* vv, cd* out) {
-    launch_multidot(vecs, n, cnt, vv, n, part, kPartBlocks, s);
-    launch_reduce_partials(part, kPartBlocks, cnt, out, s);
+    launch_bmultidot(vecs, n, BIdx{}, cnt, vv, BIdx{}, n, part, kPartBlocks, out, 1, 1, s);
   };
   // ||b||
   dotn(b, 1, b, hb + 2 * (m + 1));
@@ -1489,57 +1489,62 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
 // ===========================================================================
 namespace {
 
-// Hessenberg matrix, Givens rotations and residual estimate of one
-// right-hand side's Arnoldi process (right-preconditioned FGMRES).
+// Hessenberg matrix of one right-hand side's flexible Arnoldi process.  With
+// the delayed Gram-Schmidt the newest column is provisional (its
+// reorthogonalisation terms arrive with the next step); the least-squares
+// problem min ||beta e_1 - H y|| is solved from scratch by Givens rotations
+// whenever it is needed (k <= restart, negligible host work).
 struct Arnoldi {
   int m = 0;
-  std::vector<cplx> H, g, sn;
-  std::vector<double> cs;
-  void reset(int m_, double beta) {
+  double beta = 0;
+  std::vector<cplx> H;  // (m+1) x m, H[i m + j]
+  void reset(int m_, double b) {
     m = m_;
+    beta = b;
     H.assign((size_t)(m + 1) * m, cplx(0));
-    g.assign(m + 1, cplx(0));
-    sn.assign(m, cplx(0));
-    cs.assign(m, 0.0);
+  }
+  cplx& at(int i, int j) { return H[(size_t)i * m + j]; }
+  // residual estimate over columns 0..k-1; y (optional) receives the
+  // minimiser
+  double lsq(int k, cd* y) const {
+    std::vector<cplx> R((size_t)(k + 1) * k), g(k + 1, cplx(0)), sn(k);
+    std::vector<double> cs(k);
+    for (int i = 0; i <= k; ++i)
+      for (int j = 0; j < k; ++j) R[(size_t)i * k + j] = H[(size_t)i * m + j];
     g[0] = beta;
-  }
-  // column k from the two Gram-Schmidt passes and the new norm; returns
-  // the residual estimate |g_{k+1}|
-  double add_column(int k, const cd* h1, const cd* h2, double nrm2) {
-    for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = cplx(h1[i].re + h2[i].re, h1[i].im + h2[i].im);
-    H[(size_t)(k + 1) * m + k] = std::sqrt(std::max(nrm2, 0.0));
-    for (int i = 0; i < k; ++i) {
-      const cplx a = H[(size_t)i * m + k], bb = H[(size_t)(i + 1) * m + k];
-      H[(size_t)i * m + k] = cs[i] * a + sn[i] * bb;
-      H[(size_t)(i + 1) * m + k] = -std::conj(sn[i]) * a + cs[i] * bb;
+    for (int j = 0; j < k; ++j) {
+      for (int i = 0; i < j; ++i) {
+        const cplx a = R[(size_t)i * k + j], bb = R[(size_t)(i + 1) * k + j];
+        R[(size_t)i * k + j] = cs[i] * a + sn[i] * bb;
+        R[(size_t)(i + 1) * k + j] = -std::conj(sn[i]) * a + cs[i] * bb;
+      }
+      const cplx a = R[(size_t)j * k + j], bb = R[(size_t)(j + 1) * k + j];
+      if (std::abs(bb) == 0) {
+        cs[j] = 1;
+        sn[j] = 0;
+      } else if (std::abs(a) == 0) {
+        cs[j] = 0;
+        sn[j] = 1;
+      } else {
+        const double t = std::sqrt(std::norm(a) + std::norm(bb));
+        cs[j] = std::abs(a) / t;
+        sn[j] = (a / std::abs(a)) * std::conj(bb) / t;
+      }
+      R[(size_t)j * k + j] = cs[j] * a + sn[j] * bb;
+      R[(size_t)(j + 1) * k + j] = 0;
+      g[j + 1] = -std::conj(sn[j]) * g[j];
+      g[j] = cs[j] * g[j];
     }
-    const cplx a = H[(size_t)k * m + k], bb = H[(size_t)(k + 1) * m + k];
-    if (std::abs(bb) == 0) {
-      cs[k] = 1;
-      sn[k] = 0;
-    } else if (std::abs(a) == 0) {
-      cs[k] = 0;
-      sn[k] = 1;
-    } else {
-      const double t = std::sqrt(std::norm(a) + std::norm(bb));
-      cs[k] = std::abs(a) / t;
-      sn[k] = (a / std::abs(a)) * std::conj(bb) / t;
+    if (y) {
+      std::vector<cplx> yy(k);
+      for (int i = k - 1; i >= 0; --i) {
+        cplx acc = g[i];
+        for (int j = i + 1; j < k; ++j) acc -= R[(size_t)i * k + j] * yy[j];
+        yy[i] = acc / R[(size_t)i * k + i];
+      }
+      for (int i = 0; i < k; ++i) y[i] = to_cd(yy[i]);
     }
-    H[(size_t)k * m + k] = cs[k] * a + sn[k] * bb;
-    H[(size_t)(k + 1) * m + k] = 0;
-    g[k + 1] = -std::conj(sn[k]) * g[k];
-    g[k] = cs[k] * g[k];
-    return std::abs(g[k + 1]);
-  }
-  // y = H(0:k,0:k)^{-1} g(0:k)
-  void solve(int k, cd* y) const {
-    std::vector<cplx> yy(k);
-    for (int i = k - 1; i >= 0; --i) {
-      cplx acc = g[i];
-      for (int j = i + 1; j < k; ++j) acc -= H[(size_t)i * m + j] * yy[j];
-      yy[i] = acc / H[(size_t)i * m + i];
-    }
-    for (int i = 0; i < k; ++i) y[i] = to_cd(yy[i]);
+    return std::abs(g[k]);
   }
 };
 
@@ -1683,7 +1688,7 @@ hsp_status hsp_solve_batch(hsp_handle C, int nrhs, const void* b_in, void* u_out
     // the host staging arrays yh / upd may still feed an earlier copy
     HIPCHK(hipStreamSynchronize(s));
     upd = list;
-    for (size_t i = 0; i < upd.size(); ++i) ar[upd[i]].solve(k, yh.data() + i * m);
+    for (size_t i = 0; i < upd.size(); ++i) ar[upd[i]].lsq(k, yh.data() + i * m);
     HIPCHK(hipMemcpyAsync(ydev, yh.data(), upd.size() * m * sizeof(cd), hipMemcpyHostToDevice, s));
     hsp_status e = upload(upd_d, upd);
     if (e != HSP_OK) return e;
@@ -1696,6 +1701,7 @@ hsp_status hsp_solve_batch(hsp_handle C, int nrhs, const void* b_in, void* u_out
     return HSP_OK;
   };
   const int rb_fixed = tile;
+  const int koff = 2 * (m + 1);  // hb offset of nu, h_kk, ||u_{k+1}||^2
   int it = 0;
   while (it < maxit && !act.empty()) {
     int nact = (int)act.size();
@@ -1743,15 +1749,18 @@ hsp_status hsp_solve_batch(hsp_handle C, int nrhs, const void* b_in, void* u_out
       prof_begin(C, HSP_PROF_KRYLOV, s);
       launch_stencil<double, double, double, double>(A, 0, Z + (size_t)k * nf, (const cd*)nullptr, w, 0.0, s, nact,
                                                      bZk, BIdx{}, bw);
-      launch_bmultidot(V, nf, bVk, k + 1, w, bw, nf, part, B.nblk, hb, hs, nact, s);
-      launch_bmultiaxpy(V, nf, bVk, k + 1, hb, hs, w, bw, nf, 1, nact, s);
-      launch_bmultidot(V, nf, bVk, k + 1, w, bw, nf, part, B.nblk, hb + (m + 1), hs, nact, s);
-      launch_bmultiaxpy(V, nf, bVk, k + 1, hb + (m + 1), hs, w, bw, nf, 1, nact, s);
-      launch_bmultidot(w, 0, bw, 1, w, bw, nf, part, B.nblk, hb + 2 * (m + 1), hs, nact, s);
-      launch_bnormalize(w, bw, hb + 2 * (m + 1), hs, V + (size_t)(k + 1) * nf, bVk, nf, nact, s);
+      // delayed classical Gram-Schmidt: one projection pass (basis against
+      // u_k and w) and one update pass (v_k final, u_{k+1} and its norm)
+      BIdx bVb;
+      bVb.ld = (size_t)(m + 1) * nf;
+      bVb.map = act_d;
+      launch_bdcgs_project(V, nf, bVb, k, w, bw, nf, part, B.nblk, hb, hs, koff, nact, s);
+      launch_bdcgs_update(V, nf, bVb, k, hb, hs, koff, w, bw, nf, part, B.nblk, hb + koff + 2, nact, s);
+      // matvec (z, k^2 read, w written); projection reads k+1 basis vectors
+      // and w; update reads k basis vectors, u_k and w and writes v_k, u_{k+1}
       prof_end(C, HSP_PROF_KRYLOV, s,
                (double)nact * ((double)nf * (2.0 * sizeof(cd) + sizeof(double)) +
-                               (double)nf * sizeof(cd) * (4.0 * k + 13.0)));
+                               (double)nf * sizeof(cd) * (2.0 * k + 6.0)));
       HIPCHK(hipGetLastError());
       st = read_hb(nact);
       if (st != HSP_OK) return st;
@@ -1759,8 +1768,16 @@ hsp_status hsp_solve_batch(hsp_handle C, int nrhs, const void* b_in, void* u_out
       std::vector<int> keep, conv;
       for (int zi = 0; zi < nact; ++zi) {
         const int z = act[zi];
-        const cd* hz = hh.data() + (size_t)zi * hs;
-        const double est = ar[z].add_column(k, hz, hz + (m + 1), hz[2 * (m + 1)].re);
+        const cd* d = hh.data() + (size_t)zi * hs;
+        Arnoldi& a = ar[z];
+        if (k > 0) {  // finalise column k-1 with the reorthogonalisation terms
+          for (int j = 0; j < k; ++j) a.at(j, k - 1) += cplx(d[j].re, d[j].im);
+          a.at(k, k - 1) = d[koff].re;
+        }
+        for (int j = 0; j < k; ++j) a.at(j, k) = cplx(d[k + 1 + j].re, d[k + 1 + j].im);
+        a.at(k, k) = cplx(d[koff + 1].re, d[koff + 1].im);
+        a.at(k + 1, k) = std::sqrt(std::max(d[koff + 2].re, 0.0));
+        const double est = a.lsq(k + 1, nullptr);
         its[z] = it;
         if (est <= tol * bnorm[z]) {
           conv.push_back(z);

@@ -135,11 +135,6 @@ template <class T>
 void launch_zero(cx<T>* v, size_t n, hipStream_t s);
 // v[i] = value for i < n
 void launch_fill(cd* v, size_t n, cd value, hipStream_t s);
-// partial[b*m + j] = sum over block b of conj(V_j) . w  (j < m), V_j = V + j*ldv
-void launch_multidot(const cd* V, size_t ldv, int m, const cd* w, size_t n, cd* partial,
-                     int nblocks, hipStream_t s);
-// out[j] = sum_b partial[b*m + j]   (+ out[j] if accumulate)
-void launch_reduce_partials(const cd* partial, int nblocks, int m, cd* out, hipStream_t s);
 // w -= sum_j h[j] V_j   (h on device)
 void launch_multiaxpy(const cd* V, size_t ldv, int m, const cd* h, cd* w, size_t n, int sub,
                       hipStream_t s);
@@ -153,6 +148,19 @@ void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BI
 // w_z -= (or +=) sum_j h[z ldh + j] V_zj
 void launch_bmultiaxpy(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw, size_t n,
                        int sub, int nb, hipStream_t s);
+// the same with nrm2[z ldo] = ||w_z||^2 after the update (partial: nb nblocks)
+void launch_bmultiaxpy_norm(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw,
+                            size_t n, cd* partial, int nblocks, cd* nrm2, size_t ldo, int nb, hipStream_t s);
+// Delayed classical Gram-Schmidt (one projection pass and one update pass
+// per Arnoldi step).  Slot k of right-hand side z holds the once-projected
+// vector u_k.  project: hb[z ldh + (0..k)] = V^H u_k, hb[.. + k+1 + (0..k)] =
+// V^H w, then nu and h_kk at hb[.. + off], hb[.. + off + 1].  update: slot k
+// <- v_k (final), slot k+1 <- u_{k+1} = w - V p - h_kk v_k, ||u_{k+1}||^2 at
+// nrm2[z ldh].
+void launch_bdcgs_project(const cd* V, size_t ldj, BIdx bv, int k, const cd* w, BIdx bw, size_t n, cd* partial,
+                          int nblocks, cd* hb, size_t ldh, int off, int nb, hipStream_t s);
+void launch_bdcgs_update(cd* V, size_t ldj, BIdx bv, int k, const cd* hb, size_t ldh, int off, const cd* w, BIdx bw,
+                         size_t n, cd* partial, int nblocks, cd* nrm2, int nb, hipStream_t s);
 // v_z = w_z / sqrt(re(nrm2[z ldn]))
 void launch_bnormalize(const cd* w, BIdx bw, const cd* nrm2, size_t ldn, cd* v, BIdx bv, size_t n, int nb,
                        hipStream_t s);
