@@ -70,6 +70,10 @@ __device__ __forceinline__ void bchain(const cx<T>* __restrict__ mat, long mstri
   cx<T> ra[D][3];
   // Ring slot d of step kk holds Mat_{r_kk} and what the reduction of step kk
   // needs: GD: B and couplings of step kk+1 (the next input); else B_kk.
+  // The loads are plain loads from clamped (valid) addresses; masks are
+  // applied where the values are consumed, so that no wait for a load is
+  // placed right after it.  Matrix entries of columns j >= nl meet zero
+  // product inputs (q rows >= nl are kept zero), rows l >= nl are masked.
 #define BCH_FETCH(kk, d)                                                                         \
   {                                                                                              \
     const int kc = (kk) < count ? (kk) : count - 1;                                              \
@@ -77,17 +81,17 @@ __device__ __forceinline__ void bchain(const cx<T>* __restrict__ mat, long mstri
     _Pragma("unroll") for (int cc = 0; cc < CW; ++cc) {                                          \
       const int j = g * CW + cc;                                                                 \
       const int jc = j < nl ? j : nl - 1;                                                        \
-      rm[d][cc] = sel(act && j < nl, Mk[(size_t)jc * nl + lc]);                                  \
+      rm[d][cc] = Mk[(size_t)jc * nl + lc];                                                      \
     }                                                                                            \
     const int kb = GD ? ((kk) + 1 < count ? (kk) + 1 : count - 1) : kc;                          \
     const int rbi = first + dir * kb;                                                            \
     _Pragma("unroll") for (int i = 0; i < RC; ++i) {                                             \
       const int c = g + NG * i;                                                                  \
       const int ccl = c < RB ? c : RB - 1;                                                       \
-      rb[d][i] = sel(act && c < RB, rows[((size_t)rbi * RB + ccl) * nl + lc]);                   \
+      rb[d][i] = rows[((size_t)rbi * RB + ccl) * nl + lc];                                       \
     }                                                                                            \
     if constexpr (GD) {                                                                          \
-      _Pragma("unroll") for (int a = 0; a < 3; ++a) ra[d][a] = sel(act, cpl[((size_t)rbi * 3 + a) * nl + lc]); \
+      _Pragma("unroll") for (int a = 0; a < 3; ++a) ra[d][a] = cpl[((size_t)rbi * 3 + a) * nl + lc]; \
     }                                                                                            \
   }
 #define BCH_STEP(k, d)                                                                           \
@@ -121,6 +125,7 @@ __device__ __forceinline__ void bchain(const cx<T>* __restrict__ mat, long mstri
         cfma(qn, -ra[d][0], zl);                                                                 \
         cfma(qn, -ra[d][1], zk);                                                                 \
         cfma(qn, -ra[d][2], zr);                                                                 \
+        qn = sel(act && c < RB, qn);                                                             \
       }                                                                                          \
       if (c < RB) q[l * RB + c] = qn;                                                            \
     }                                                                                            \
@@ -155,28 +160,39 @@ __device__ __forceinline__ void bchain(const cx<T>* __restrict__ mat, long mstri
 }
 
 // rows_t += Mat_t v for t in [s, e), v = LDS [nl][RB]; one (t, row) pair per
-// thread and all RB columns at once.
+// thread and all RB columns at once.  The row of Mat_t is fetched in blocks
+// of JB entries (unconditional loads from clamped addresses) so that each
+// block costs one memory round trip.
 template <class T, int RB>
 __device__ __forceinline__ void bfixup(const cx<T>* __restrict__ mat, cx<T>* rows, int s, int e, int nl,
                                        const cx<T>* v) {
+  constexpr int JB = sizeof(T) == 4 ? 32 : 16;
   const int cnt = e - s;
   for (int idx = threadIdx.x; idx < cnt * nl; idx += blockDim.x) {
     const int t = s + idx / nl, l = idx - (idx / nl) * nl;
     const cx<T>* mb = mat + (size_t)t * nl * nl + l;
+    cx<T>* o = rows + (size_t)t * RB * nl + l;
     cx<T> acc[RB];
 #pragma unroll
-    for (int c = 0; c < RB; ++c) acc[c] = mk<T>(0, 0);
-#pragma unroll 4
-    for (int j = 0; j < nl; ++j) {
-      const cx<T> mv = mb[(size_t)j * nl];
+    for (int c = 0; c < RB; ++c) acc[c] = o[(size_t)c * nl];
+    for (int j0 = 0; j0 < nl; j0 += JB) {
+      cx<T> mv[JB];
 #pragma unroll
-      for (int c = 0; c < RB; ++c) cfma(acc[c], mv, v[j * RB + c]);
+      for (int jj = 0; jj < JB; ++jj) {
+        const int j = j0 + jj;
+        const int jc = j < nl ? j : nl - 1;
+        mv[jj] = sel(j < nl, mb[(size_t)jc * nl]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        const int j = j0 + jj;
+        const int jc = j < nl ? j : nl - 1;
+#pragma unroll
+        for (int c = 0; c < RB; ++c) cfma(acc[c], mv[jj], v[jc * RB + c]);
+      }
     }
 #pragma unroll
-    for (int c = 0; c < RB; ++c) {
-      cx<T>& o = rows[((size_t)t * RB + c) * nl + l];
-      o = o + acc[c];
-    }
+    for (int c = 0; c < RB; ++c) o[(size_t)c * nl] = acc[c];
   }
 }
 
@@ -225,20 +241,45 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(BArgs A, const cx<T>* __rest
   cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
   cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
   const cx<T>* src = tk.src ? g : f;
-  // slab right-hand side of the chunk, t fastest (coalesced level reads)
-  for (int idx = threadIdx.x; idx < RB * nl * cnt; idx += 256) {
-    const int c = idx / (nl * cnt), rem = idx - c * (nl * cnt);
-    const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
-    const int gl = sd.x0 + ll;
-    cx<T> v = mk<T>(0, 0);
-    if (c < nr) {
-      const cx<T>* sr = src + (size_t)(r0 + c) * A.ld;
-      if (tk.a < gl && gl <= tk.b) v = sr[(size_t)(gl - 1) * n2 + t];
-      const cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
-      v = v + cvt<T>(transmission_rhs<T>(tk, A.G, gl, t, n2, bz + (size_t)tk.bin_f * 2 * n2,
-                                         bz + (size_t)tk.bin_b * 2 * n2));
+  // slab right-hand side of the chunk, t fastest (coalesced level reads);
+  // U entries per thread and round: all loads first, then the stores
+  {
+    constexpr int U = 4;
+    const int tot = RB * nl * cnt;
+    for (int base = threadIdx.x; base < tot; base += 256 * U) {
+      cx<T> val[U];
+      size_t dst[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int idx = base + q * 256;
+        const int ic = idx < tot ? idx : tot - 1;
+        const int c = ic / (nl * cnt), rem = ic - c * (nl * cnt);
+        const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
+        const int gl = sd.x0 + ll;
+        const int cc = c < nr ? c : 0;
+        const bool inside = c < nr && tk.a < gl && gl <= tk.b;
+        const int glc = inside ? gl : tk.b;
+        const cx<T> v = src[(size_t)(r0 + cc) * A.ld + (size_t)(glc - 1) * n2 + t];
+        val[q] = sel(inside, v);
+        dst[q] = ((size_t)t * RB + c) * nl + ll;
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int idx = base + q * 256;
+        if (idx < tot) {
+          const int c = idx / (nl * cnt), rem = idx - c * (nl * cnt);
+          const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
+          const int gl = sd.x0 + ll;
+          cx<T> v = val[q];
+          if (c < nr) {
+            const cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
+            v = v + cvt<T>(transmission_rhs<T>(tk, A.G, gl, t, n2, bz + (size_t)tk.bin_f * 2 * n2,
+                                               bz + (size_t)tk.bin_b * 2 * n2));
+          }
+          y[dst[q]] = v;
+        }
+      }
     }
-    y[((size_t)t * RB + c) * nl + ll] = v;
   }
   __syncthreads();
   // chunk-local forward substitution y_t = G_t (f_t - A_t y_{t-1}) from zero
@@ -319,26 +360,45 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(BArgs A, cx<T>* __restrict__
     bfixup<T, RB>(F.X, y, s, e, nl, hv);
     __syncthreads();
   }
-  // u += J^T x over the task's layers, outgoing transmission layers
-  for (int idx = threadIdx.x; idx < nr * nl * cnt; idx += 256) {
-    const int c = idx / (nl * cnt), rem = idx - c * (nl * cnt);
-    const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
-    const int gl = sd.x0 + ll;
-    const cx<T> x = y[((size_t)t * RB + c) * nl + ll];
-    if (tk.at < gl && gl <= tk.bt) {
-      cx<T>& o = u[(size_t)(r0 + c) * A.ld + (size_t)(gl - 1) * n2 + t];
-      o = o + x;
+  // u += J^T x over the task's layers, outgoing transmission layers; U
+  // entries per thread and round, loads first
+  constexpr int U = 4;
+  const int tot = nr * nl * cnt;
+  for (int base = threadIdx.x; base < tot; base += 256 * U) {
+    cx<T> xv[U], uv[U];
+    size_t uid[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int idx = base + q * 256;
+      const int ic = idx < tot ? idx : tot - 1;
+      const int c = ic / (nl * cnt), rem = ic - c * (nl * cnt);
+      const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
+      const int gl = sd.x0 + ll;
+      const int glc = (tk.at < gl && gl <= tk.bt) ? gl : tk.bt;
+      xv[q] = y[((size_t)t * RB + c) * nl + ll];
+      uid[q] = (size_t)(r0 + c) * A.ld + (size_t)(glc - 1) * n2 + t;
+      uv[q] = u[uid[q]];
     }
-    cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
-    if (tk.t2) {
-      cx<T>* Bo = bz + (size_t)tk.bout_f * 2 * n2;
-      if (gl == tk.beta_out) Bo[t] = x;
-      if (gl == tk.beta_out + 1) Bo[(size_t)n2 + t] = x;
-    }
-    if (tk.t4) {
-      cx<T>* Bo = bz + (size_t)tk.bout_b * 2 * n2;
-      if (gl == tk.bt_out) Bo[t] = x;
-      if (gl == tk.bt_out + 1) Bo[(size_t)n2 + t] = x;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int idx = base + q * 256;
+      if (idx >= tot) continue;
+      const int c = idx / (nl * cnt), rem = idx - c * (nl * cnt);
+      const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
+      const int gl = sd.x0 + ll;
+      const cx<T> x = xv[q];
+      if (tk.at < gl && gl <= tk.bt) u[uid[q]] = uv[q] + x;
+      cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
+      if (tk.t2) {
+        cx<T>* Bo = bz + (size_t)tk.bout_f * 2 * n2;
+        if (gl == tk.beta_out) Bo[t] = x;
+        if (gl == tk.beta_out + 1) Bo[(size_t)n2 + t] = x;
+      }
+      if (tk.t4) {
+        cx<T>* Bo = bz + (size_t)tk.bout_b * 2 * n2;
+        if (gl == tk.bt_out) Bo[t] = x;
+        if (gl == tk.bt_out + 1) Bo[(size_t)n2 + t] = x;
+      }
     }
   }
 }
