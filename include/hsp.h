@@ -211,14 +211,12 @@ hsp_status hsp_gradient_accumulate(hsp_handle hd, const void* u_dev, const void*
  *      medium and frequency share the setup: the slab factors serve every
  *      right-hand side, which is the multi-RHS pipelining of Sec. 4.  A
  *      batch is nrhs contiguous complex128 fine vectors, right-hand side j
- *      at offset j * (N1-1)(N2-1).  Every sweep stage is one set of three
- *      launches over (slab task, tangential chunk, tile of right-hand
- *      sides).  These calls need a second caller-owned device workspace,
- *      256-byte aligned, of hsp_batch_workspace_size bytes; it holds the
- *      per-right-hand-side vectors, the FGMRES bases and the slab scratch,
- *      and may be reused between calls.  tile selects the number of right-
- *      hand sides per work item (1, 2, 4 or 8; 0 = the tile found by
- *      hsp_tune_batch for this batch size, else a size heuristic); it
+ *      at offset j * (N1-1)(N2-1).  These calls need a second caller-owned
+ *      device workspace, 256-byte aligned, which holds the per-right-hand-
+ *      side vectors, the FGMRES bases and the slab scratch, and may be
+ *      reused between calls.  tile selects the number of right-hand sides
+ *      per work item of the stage launches (1, 2, 4 or 8; 0 = the tile found
+ *      by hsp_tune_batch for this batch size, else a size heuristic); it
  *      changes the evaluation order only. ------------------------------- */
 
 /* Bytes of batch workspace for up to nrhs right-hand sides (>= 1) and FGMRES
@@ -244,15 +242,44 @@ hsp_status hsp_tune_batch(hsp_handle hd, int nrhs, int restart, void* ws_dev, si
  * preconditioned FGMRES process per right-hand side (x0 = 0, restart
  * length restart), all advanced together; each stops at its own test
  * ||b_j - A u_j||_2 <= tol ||b_j||_2 and leaves the batch, so later
- * iterations work on the remaining ones only.  b_j = 0 gives u_j = 0 with 0
- * iterations.  iters[nrhs] and relres[nrhs] (host arrays, may be NULL)
- * receive the iteration counts and true relative residuals.  One host
- * synchronisation per iteration.
+ * iterations work on the remaining ones only.  The Arnoldi vectors are
+ * orthogonalised by classical Gram-Schmidt with one reorthogonalisation,
+ * the reorthogonalisation of each vector being carried out with the
+ * projection of the next one (one pass over the basis for both).  b_j = 0
+ * gives u_j = 0 with 0 iterations.  iters[nrhs] and relres[nrhs] (host
+ * arrays, may be NULL) receive the iteration counts and true relative
+ * residuals.  One host synchronisation per iteration.
  * Errors: HSP_EINVAL, HSP_ENOMEM, HSP_ENOCONV (some right-hand side reached
  * maxit; all u_j hold their last iterates). */
 hsp_status hsp_solve_batch(hsp_handle hd, int nrhs, const void* b_dev, void* u_dev, double tol, int maxit,
                            int restart, int conj_transpose, int tile, void* ws_dev, size_t ws_bytes,
                            int* iters, double* relres, void* stream);
+
+/* ---- Groups: the right-hand sides of several problems (media, frequencies,
+ *      grid sizes; each set up with its own handle and workspace) solved
+ *      together.  The sweep stages of all problems are aligned on the
+ *      coarse residual of the sweep (Table 3) and each step of the aligned
+ *      schedule is one set of three launches over the work items of every
+ *      problem.  All handles must share the precision; a handle may appear
+ *      once.  Vectors: b_dev[p], u_dev[p] (or r_dev[p], z_dev[p]) hold
+ *      nrhs[p] contiguous complex128 fine vectors of problem p (nrhs[p] = 0
+ *      allowed).  Group workspace: caller-owned, 256-byte aligned.
+ *      flags: HSP_GROUP_GRAPH captures one preconditioner application in a
+ *      HIP graph (re-captured when the set of active right-hand sides
+ *      changes) and replays it. ------------------------------------------ */
+enum { HSP_GROUP_GRAPH = 1 };
+
+hsp_status hsp_group_workspace_size(int nprob, const hsp_handle* hds, const int* nrhs, int restart, size_t* bytes);
+
+hsp_status hsp_apply_precond_group(int nprob, const hsp_handle* hds, const int* nrhs, const void* const* r_dev,
+                                   void* const* z_dev, int tile, int flags, void* ws_dev, size_t ws_bytes,
+                                   void* stream);
+
+/* As hsp_solve_batch for every right-hand side of every problem; iters and
+ * relres hold sum(nrhs) entries, problem by problem. */
+hsp_status hsp_solve_group(int nprob, const hsp_handle* hds, const int* nrhs, const void* const* b_dev,
+                           void* const* u_dev, double tol, int maxit, int restart, int conj_transpose, int tile,
+                           int flags, void* ws_dev, size_t ws_bytes, int* iters, double* relres, void* stream);
 
 /* ---- Timing (tracing aid).  When enabled, every kernel launch of the
  *      classes below is bracketed by a pair of HIP events on the stream it

@@ -196,40 +196,43 @@ __device__ __forceinline__ void bfixup(const cx<T>* __restrict__ mat, cx<T>* row
   }
 }
 
-// Work item of block b: the tiles of one (task, chunk) pair are consecutive
-// items and land on one XCD (blocks are dealt to the 8 XCDs in turn).
+// Work item of block b: blocks are dealt to the 8 XCDs in turn, so block b
+// takes item (b mod 8) per + b / 8; the tiles of one (task, chunk) pair are
+// consecutive items and so share an XCD and its L2.  The segment is found by
+// a scan over the (few) problems of the launch.
 struct BWork {
   int q, p, tile;
 };
-__device__ __forceinline__ bool decode_work(int ntasks, int P, int ntiles, BWork& w) {
-  const int nwork = ntasks * P * ntiles;
-  const int per = (nwork + 7) / 8;
+__device__ __forceinline__ bool decode_work(const BSeg* __restrict__ segs, int nseg, int nitems, BSeg& S,
+                                            BWork& w) {
+  const int per = (nitems + 7) / 8;
   const int id = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (id >= nwork) return false;
-  w.tile = id % ntiles;
-  const int rest = id / ntiles;
-  w.p = rest % P;
-  w.q = rest / P;
+  if (id >= nitems) return false;
+  int k = nseg - 1;
+  while (k > 0 && segs[k].item0 > id) --k;
+  S = segs[k];
+  const int local = id - S.item0;
+  w.tile = local % S.ntiles;
+  const int rest = local / S.ntiles;
+  w.p = rest % S.P;
+  w.q = rest / S.P;
   return true;
 }
 
-struct BArgs {
-  const TaskDev* tasks;  // the stage's tasks
-  const SlabDev* slabs;
-  LevelDev G;            // the DD level (transmission couplings)
-  int ntasks, ntiles, nact, nl_max, m, P;
-  size_t ld;             // elements per right-hand side of a level vector
-};
-
 template <class T, int NB, int RB, int D>
-__global__ void __launch_bounds__(256) k_bstage_fwd(BArgs A, const cx<T>* __restrict__ f, const cx<T>* __restrict__ g,
-                                                    const cx<T>* __restrict__ bufs, cx<T>* __restrict__ scratch,
-                                                    const cx<T>* __restrict__ factors, cx<T>* __restrict__ red,
-                                                    int* counters) {
+__global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ segs, int nseg, int nitems) {
   __shared__ cx<T> q[NB * RB];
   __shared__ cx<T> ps[256 * RB];
   BWork w;
-  if (!decode_work(A.ntasks, A.P, A.ntiles, w)) return;
+  BSeg A;
+  if (!decode_work(segs, nseg, nitems, A, w)) return;
+  const cx<T>* __restrict__ f = static_cast<const cx<T>*>(A.f);
+  const cx<T>* __restrict__ g = static_cast<const cx<T>*>(A.g);
+  const cx<T>* __restrict__ bufs = static_cast<const cx<T>*>(A.bufs);
+  cx<T>* __restrict__ scratch = static_cast<cx<T>*>(A.scratch);
+  const cx<T>* __restrict__ factors = static_cast<const cx<T>*>(A.factors);
+  cx<T>* __restrict__ red = static_cast<cx<T>*>(A.red);
+  int* counters = A.counters;
   const int P = A.P, m = A.m, n2 = A.G.n2;
   const int slot = w.q * A.ntiles + w.tile, r0 = w.tile * RB;
   const int nr = min(RB, A.nact - r0);
@@ -296,13 +299,16 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(BArgs A, const cx<T>* __rest
 }
 
 template <class T, int NB, int RB, int D>
-__global__ void __launch_bounds__(256) k_bstage_mid(BArgs A, cx<T>* __restrict__ scratch,
-                                                    const cx<T>* __restrict__ factors, cx<T>* __restrict__ red,
-                                                    int* counters) {
+__global__ void __launch_bounds__(256) k_bstage_mid(const BSeg* __restrict__ segs, int nseg, int nitems) {
   __shared__ cx<T> q[NB * RB];
   __shared__ cx<T> ps[256 * RB];
   BWork w;
-  if (!decode_work(A.ntasks, A.P, A.ntiles, w)) return;
+  BSeg A;
+  if (!decode_work(segs, nseg, nitems, A, w)) return;
+  cx<T>* __restrict__ scratch = static_cast<cx<T>*>(A.scratch);
+  const cx<T>* __restrict__ factors = static_cast<const cx<T>*>(A.factors);
+  cx<T>* __restrict__ red = static_cast<cx<T>*>(A.red);
+  int* counters = A.counters;
   const int P = A.P, m = A.m, n2 = A.G.n2;
   const int slot = w.q * A.ntiles + w.tile;
   const TaskDev tk = A.tasks[w.q];
@@ -335,12 +341,16 @@ __global__ void __launch_bounds__(256) k_bstage_mid(BArgs A, cx<T>* __restrict__
 }
 
 template <class T, int NB, int RB>
-__global__ void __launch_bounds__(256) k_bstage_bwd(BArgs A, cx<T>* __restrict__ u, cx<T>* __restrict__ bufs,
-                                                    cx<T>* __restrict__ scratch, const cx<T>* __restrict__ factors,
-                                                    const cx<T>* __restrict__ red) {
+__global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ segs, int nseg, int nitems) {
   __shared__ cx<T> hv[NB * RB];
   BWork w;
-  if (!decode_work(A.ntasks, A.P, A.ntiles, w)) return;
+  BSeg A;
+  if (!decode_work(segs, nseg, nitems, A, w)) return;
+  cx<T>* __restrict__ u = static_cast<cx<T>*>(A.u);
+  cx<T>* __restrict__ bufs = static_cast<cx<T>*>(A.bufs);
+  cx<T>* __restrict__ scratch = static_cast<cx<T>*>(A.scratch);
+  const cx<T>* __restrict__ factors = static_cast<const cx<T>*>(A.factors);
+  const cx<T>* __restrict__ red = static_cast<const cx<T>*>(A.red);
   const int P = A.P, m = A.m, n2 = A.G.n2;
   const int slot = w.q * A.ntiles + w.tile, r0 = w.tile * RB;
   const int nr = min(RB, A.nact - r0);
@@ -406,42 +416,25 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(BArgs A, cx<T>* __restrict__
 }  // namespace
 
 template <class T>
-void launch_stage_batch(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev, const LevelDev& G,
-                        const cx<T>* f, const cx<T>* g, cx<T>* u, cx<T>* bufs, cx<T>* scratch, const cx<T>* factors,
-                        int nl_max, int nl_launch, int m, int P, int nact, int rb, size_t ld, cx<T>* red,
-                        int* counters, hipStream_t s) {
-  if (nact < 1 || ntasks < 1) return;
-  BArgs A;
-  A.tasks = tasks_dev;
-  A.slabs = slabs_dev;
-  A.G = G;
-  A.ntasks = ntasks;
-  A.ntiles = (nact + rb - 1) / rb;
-  A.nact = nact;
-  A.nl_max = nl_max;
-  A.m = m;
-  A.P = P;
-  A.ld = ld;
-  const int nwork = ntasks * P * A.ntiles;
-  const dim3 grd(8 * ((nwork + 7) / 8));
-#define BLAUNCH(NB, RB, D)                                                                                      \
-  do {                                                                                                          \
-    hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D>), grd, dim3(256), 0, s, A, f, g, (const cx<T>*)bufs, scratch, \
-                       factors, red, counters);                                                                 \
-    hipLaunchKernelGGL((k_bstage_mid<T, NB, RB, D>), grd, dim3(256), 0, s, A, scratch, factors, red, counters);  \
-    hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB>), grd, dim3(256), 0, s, A, u, bufs, scratch, factors,           \
-                       (const cx<T>*)red);                                                                      \
+void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launch, int rb, hipStream_t s) {
+  if (nseg < 1 || nitems < 1) return;
+  const dim3 grd(8 * ((nitems + 7) / 8));
+#define BLAUNCH(NB, RB, D)                                                                                \
+  do {                                                                                                    \
+    hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);      \
+    hipLaunchKernelGGL((k_bstage_mid<T, NB, RB, D>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);      \
+    hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);         \
   } while (0)
   constexpr int D32 = sizeof(T) == 4 ? 4 : 2;
   constexpr int D64 = sizeof(T) == 4 ? 2 : 1;
-#define BRB(NB, D)                 \
-  do {                             \
-    switch (rb) {                  \
+#define BRB(NB, D)                      \
+  do {                                  \
+    switch (rb) {                       \
       case 1: BLAUNCH(NB, 1, D); break; \
       case 2: BLAUNCH(NB, 2, D); break; \
       case 4: BLAUNCH(NB, 4, D); break; \
       default: BLAUNCH(NB, 8, D); break; \
-    }                              \
+    }                                   \
   } while (0)
   if (nl_launch <= 32)
     BRB(32, D32);
@@ -451,11 +444,7 @@ void launch_stage_batch(const TaskDev* tasks_dev, int ntasks, const SlabDev* sla
 #undef BLAUNCH
 }
 
-template void launch_stage_batch<double>(const TaskDev*, int, const SlabDev*, const LevelDev&, const cd*, const cd*,
-                                         cd*, cd*, cd*, const cd*, int, int, int, int, int, int, size_t, cd*, int*,
-                                         hipStream_t);
-template void launch_stage_batch<float>(const TaskDev*, int, const SlabDev*, const LevelDev&, const cf*, const cf*,
-                                        cf*, cf*, cf*, const cf*, int, int, int, int, int, int, size_t, cf*, int*,
-                                        hipStream_t);
+template void launch_stage_group<double>(const BSeg*, int, int, int, int, hipStream_t);
+template void launch_stage_group<float>(const BSeg*, int, int, int, int, hipStream_t);
 
 }  // namespace hsp

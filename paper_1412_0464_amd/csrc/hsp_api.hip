@@ -11,30 +11,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hsp.h"
-#include "internal.h"
+#include "ctx.h"
 
 using namespace hsp;
 
 namespace {
 
 thread_local std::string g_err = "no error";
-
-hsp_status fail(hsp_status st, const std::string& msg) {
-  g_err = msg;
-  return st;
-}
-
-#define HIPCHK(expr)                                                                   \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(HSP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
-  } while (0)
-
-using cplx = std::complex<double>;
-
-inline cd to_cd(cplx z) { return mk<double>(z.real(), z.imag()); }
 
 // PML damping sigma(x): C (lo - x)^2 left of lo, C (x - hi)^2 right of hi.
 struct Sigma {
@@ -80,45 +63,6 @@ void axis_arrays(const AxisH& ax, int kind, double omega, const std::vector<doub
   }
 }
 
-struct Carver {
-  size_t off = 0;
-  size_t take(size_t bytes) {
-    off = (off + 255) & ~(size_t)255;
-    const size_t o = off;
-    off += bytes;
-    return o;
-  }
-};
-
-// Everything that depends on sizes only.
-struct Plan {
-  int nf1 = 0, nf2 = 0, Nf1 = 0, Nf2 = 0;  // fine unknowns / cells
-  int two_grid = 0;
-  int nc1 = 0, nc2 = 0;                   // coarse unknowns
-  std::vector<int> ifp1, ifp2;            // coarse -> fine node maps
-  std::vector<char> ref1, ref2;           // refined coarse cells
-  int dd_kind = 5, dd_n1 = 0, dd_n2 = 0;  // DD level
-  int fine_kind = 5;
-  std::vector<int> beta, bt, x0, x1;
-  int nl_max = 0;
-  int chunk = 0, nchunk = 0;              // parallel substitution: chunk length m, count P
-  size_t tsize = 16;                      // bytes per preconditioner complex
-  int m = 0;                              // FGMRES restart
-  // workspace offsets
-  size_t o_fxA, o_fxB, o_fyA, o_fyB, o_k2n, o_fk2c, o_fcoef, o_ixn, o_iyn;
-  size_t o_cxA, o_cxB, o_cyA, o_cyB, o_ck2c, o_ccoef;
-  size_t o_avgx0, o_avgwx, o_avgy0, o_avgwy;
-  size_t o_rx, o_rwx, o_ry, o_rwy, o_px, o_pwx, o_py, o_pwy;
-  size_t o_slabs, o_slabA, o_slabB, o_xmap, o_fac, o_facscr, o_status, o_tasks;
-  size_t o_swf, o_swg, o_swu, o_swB, o_swscr;
-  size_t o_tgx0, o_tgx1, o_tgres, o_tgrc, o_tgec, o_cvin, o_cvout;
-  size_t o_V, o_Z, o_w, o_part, o_hbuf, o_stats, o_bconj;
-  size_t o_red, o_ctr, o_setup, o_ttmp;  // chunk tips/heads, arrival counters, setup scratch (aliases V, Z)
-  size_t n_slabA = 0, n_xmap = 0, n_fac = 0, n_tasks = 0;
-  size_t total = 0;
-};
-
-constexpr int kPartBlocks = 512;
 
 hsp_status validate(const hsp_grid* g, int J, const hsp_options* o) {
   if (!g || !o) return fail(HSP_EINVAL, "null grid or options");
@@ -313,59 +257,8 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   return HSP_OK;
 }
 
-struct Stage {
-  int residual;
-  int first, ntasks;
-  int nl;        // thickest slab among the stage's tasks
-  double bytes;  // algorithmic bytes per complex unit (times sizeof(T) at launch)
-  double fac;    // the factor part of bytes (shared by all right-hand sides of a batch)
-};
-
-// Event-pair timing per kernel class.
-struct Prof {
-  bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[HSP_PROF_NCLASS];
-  size_t used[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
-  double bytes[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
-  long long n[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
-};
-
 }  // namespace
 
-struct hsp_ctx {
-  Plan P;
-  hsp_grid grid;
-  hsp_options opt;
-  int J = 0;
-  double omega = 0, c_pml = 0, h = 0;
-  char* ws = nullptr;
-  LevelDev fine{}, coarse{}, dd{};
-  TransferDev tr{};
-  SlabDev* slabs_dev = nullptr;
-  std::vector<SlabDev> slabs_host;
-  std::vector<Stage> stages;
-  TaskDev* tasks_dev = nullptr;
-  std::vector<TaskDev> tasks_host;
-  void* factors = nullptr;
-  Prof prof;
-  int tuned_rb = 0;    // right-hand-side tile chosen by hsp_tune_batch (0: none)
-  int tuned_nact = 0;  // batch size it was chosen for
-  ~hsp_ctx() {
-    for (int c = 0; c < HSP_PROF_NCLASS; ++c)
-      for (auto& e : prof.ev[c]) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
-      }
-  }
-  template <class T>
-  cx<T>* at(size_t off) const {
-    return reinterpret_cast<cx<T>*>(ws + off);
-  }
-  template <class X>
-  X* raw(size_t off) const {
-    return reinterpret_cast<X*>(ws + off);
-  }
-};
 
 namespace {
 
@@ -496,30 +389,6 @@ void build_schedule(hsp_ctx* C) {
 // ---------------------------------------------------------------------------
 // Sweep, two-grid cycle and preconditioner
 // ---------------------------------------------------------------------------
-void prof_begin(hsp_ctx* C, int cls, hipStream_t s) {
-  Prof& P = C->prof;
-  if (!P.on) return;
-  if (P.used[cls] == P.ev[cls].size()) {
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess) return;
-    if (hipEventCreate(&b) != hipSuccess) {
-      (void)hipEventDestroy(a);
-      return;
-    }
-    P.ev[cls].push_back({a, b});
-  }
-  (void)hipEventRecord(P.ev[cls][P.used[cls]].first, s);
-}
-
-void prof_end(hsp_ctx* C, int cls, hipStream_t s, double bytes) {
-  Prof& P = C->prof;
-  if (!P.on || P.used[cls] >= P.ev[cls].size()) return;
-  (void)hipEventRecord(P.ev[cls][P.used[cls]].second, s);
-  ++P.used[cls];
-  ++P.n[cls];
-  P.bytes[cls] += bytes;
-}
-
 template <class T>
 void run_sweep(hsp_ctx* C, const cx<T>* f, cx<T>* u, hipStream_t s) {
   const Plan& P = C->P;
@@ -614,182 +483,42 @@ void precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
 }
 
 
-// ---------------------------------------------------------------------------
-// Batched right-hand sides: layout of the caller's batch workspace
-// ---------------------------------------------------------------------------
-constexpr int kMaxTile = 8;
 
-// (task, tile) slots of a stage, times the tile: >= 2 ceil(R/rb) rb for every rb <= 8
-inline size_t batch_slots(int R) { return 2 * (size_t)(R + kMaxTile - 1); }
-
-struct BatchLayout {
-  int R = 0, m = 0, nblk = 0;
-  size_t hs = 0;  // hb entries per right-hand side: [h1 (m+1) | h2 (m+1) | nrm2 | spare]
-  size_t o_xa, o_xb, o_res, o_rc, o_ec, o_swf, o_swg, o_swu, o_swB, o_scr, o_red, o_ctr;
-  size_t o_V, o_Z, o_w, o_bc, o_part, o_hb, o_act, o_upd, o_y;
-  size_t total = 0;
-};
-
-BatchLayout batch_layout(const Plan& P, int R, int m) {
-  BatchLayout B;
-  B.R = R;
-  B.m = m;
-  Carver c;
-  const size_t nf = (size_t)P.nf1 * P.nf2, nd = (size_t)P.dd_n1 * P.dd_n2, T = P.tsize;
-  const size_t slots = batch_slots(R);
-  B.o_xa = c.take(R * nf * T);
-  B.o_xb = c.take(R * nf * T);
-  B.o_res = c.take(P.two_grid ? R * nf * sizeof(cd) : 0);
-  B.o_rc = c.take(P.two_grid ? R * nd * T : 0);
-  B.o_ec = c.take(P.two_grid ? R * nd * T : 0);
-  B.o_swf = c.take(R * nd * T);
-  B.o_swg = c.take(R * nd * T);
-  B.o_swu = c.take(R * nd * T);
-  B.o_swB = c.take(R * 4 * (size_t)P.dd_n2 * T);
-  B.o_scr = c.take(slots * P.dd_n2 * P.nl_max * T);
-  B.o_red = c.take(slots * 2 * P.nchunk * P.nl_max * T);
-  B.o_ctr = c.take(2 * slots * sizeof(int));
-  B.nblk = batch_dot_blocks(nf, R);
-  B.hs = 2 * (size_t)(m + 2) + 2;
-  B.o_V = c.take((size_t)R * (m + 1) * nf * sizeof(cd));
-  B.o_Z = c.take((size_t)R * m * nf * sizeof(cd));
-  B.o_w = c.take(R * nf * sizeof(cd));
-  B.o_bc = c.take(R * nf * sizeof(cd));
-  B.o_part = c.take((size_t)2 * R * (m + 1) * B.nblk * sizeof(cd));
-  B.o_hb = c.take(R * B.hs * sizeof(cd));
-  B.o_act = c.take(R * sizeof(int));
-  B.o_upd = c.take(R * sizeof(int));
-  B.o_y = c.take((size_t)R * m * sizeof(cd));
-  B.total = c.off + 256;
-  return B;
-}
-
-template <class X>
-X* bat(void* ws, size_t off) {
-  return reinterpret_cast<X*>(reinterpret_cast<char*>(ws) + off);
-}
-
-// Default right-hand-side tile: the largest that still gives the stage
-// launches about two work items per compute unit.
-int default_tile(const hsp_ctx* C, int nact) {
-  if (C->tuned_rb > 0 && C->tuned_nact == nact) return C->tuned_rb;
-  for (int rb = kMaxTile; rb > 1; rb /= 2)
-    if (2 * C->P.nchunk * ((nact + rb - 1) / rb) >= 512) return rb;
-  return 1;
-}
-
-template <class T>
-void run_sweep_batch(hsp_ctx* C, const BatchLayout& B, void* ws, int nact, int rb, const cx<T>* f, cx<T>* u,
-                     hipStream_t s) {
-  const Plan& P = C->P;
-  const size_t nd = (size_t)P.dd_n1 * P.dd_n2;
-  cx<T>* g = bat<cx<T>>(ws, B.o_swg);
-  launch_zero<T>(u, (size_t)nact * nd, s);
-  BIdx bd;
-  bd.ld = nd;
-  for (const Stage& st : C->stages) {
-    if (st.residual) {
-      prof_begin(C, HSP_PROF_COARSE, s);
-      launch_stencil<T, T, T, T>(C->dd, 1, u, f, g, 0.0, s, nact, bd, bd, bd);
-      prof_end(C, HSP_PROF_COARSE, s, (double)nact * nd * (3.0 * sizeof(cx<T>) + 4.0 * sizeof(double)));
-    } else {
-      prof_begin(C, HSP_PROF_STAGE, s);
-      launch_stage_batch<T>(C->tasks_dev + st.first, st.ntasks, C->slabs_dev, C->dd, f, g, u,
-                            bat<cx<T>>(ws, B.o_swB), bat<cx<T>>(ws, B.o_scr),
-                            reinterpret_cast<const cx<T>*>(C->factors), P.nl_max, st.nl, P.chunk, P.nchunk, nact,
-                            rb, nd, bat<cx<T>>(ws, B.o_red), bat<int>(ws, B.o_ctr), s);
-      prof_end(C, HSP_PROF_STAGE, s, (st.fac + (double)nact * (st.bytes - st.fac)) * sizeof(cx<T>));
-    }
-  }
-}
-
-// z_j = M r_j for nact right-hand sides: r_j at r + br.off(j), z_j at
-// z + bz.off(j) (complex128), internal vectors compact per slot j.
-template <class T>
-void run_precond_batch(hsp_ctx* C, const BatchLayout& B, void* ws, int nact, int rb, const cd* r, BIdx br, cd* z,
-                       BIdx bz, hipStream_t s) {
-  const Plan& P = C->P;
-  const size_t nf = (size_t)P.nf1 * P.nf2, nd = (size_t)P.dd_n1 * P.dd_n2;
-  BIdx bf, bdd;
-  bf.ld = nf;
-  bdd.ld = nd;
-  if (!P.two_grid) {
-    cx<T>* fin = bat<cx<T>>(ws, B.o_swf);
-    cx<T>* uo = bat<cx<T>>(ws, B.o_swu);
-    launch_convert<T, double>(r, fin, nf, 0, s, nact, br, bf);
-    run_sweep_batch<T>(C, B, ws, nact, rb, fin, uo, s);
-    launch_convert<double, T>(uo, z, nf, 0, s, nact, bf, bz);
-    return;
-  }
-  const double wj = C->opt.omega_jac;
-  const int nu = C->opt.nu;
-  cx<T>* xa = bat<cx<T>>(ws, B.o_xa);
-  cx<T>* xb = bat<cx<T>>(ws, B.o_xb);
-  const double jb = (double)nact * nf * (sizeof(cd) + 2.0 * sizeof(cx<T>) + sizeof(double));
-  prof_begin(C, HSP_PROF_SMOOTH, s);
-  if (nu > 0) {
-    launch_stencil<T, T, double, T>(C->fine, 2, (const cx<T>*)nullptr, r, xa, wj, s, nact, BIdx{}, br, bf);
-    for (int k = 1; k < nu; ++k) {
-      launch_stencil<T, T, double, T>(C->fine, 2, xa, r, xb, wj, s, nact, bf, br, bf);
-      std::swap(xa, xb);
-    }
-  } else {
-    launch_zero<T>(xa, (size_t)nact * nf, s);
-  }
-  cd* res = bat<cd>(ws, B.o_res);
-  launch_stencil<double, T, double, double>(C->fine, 1, xa, r, res, 0.0, s, nact, bf, br, bf);
-  prof_end(C, HSP_PROF_SMOOTH, s,
-           nu * jb + (double)nact * nf * (2.0 * sizeof(cd) + sizeof(cx<T>) + sizeof(double)));
-  cx<T>* rc = bat<cx<T>>(ws, B.o_rc);
-  cx<T>* ec = bat<cx<T>>(ws, B.o_ec);
-  prof_begin(C, HSP_PROF_TRANSFER, s);
-  launch_restrict<double, T>(C->tr, res, rc, s, nact, bf, bdd);
-  prof_end(C, HSP_PROF_TRANSFER, s, (double)nact * ((double)nf * sizeof(cd) + (double)nd * sizeof(cx<T>)));
-  run_sweep_batch<T>(C, B, ws, nact, rb, rc, ec, s);
-  prof_begin(C, HSP_PROF_TRANSFER, s);
-  launch_prolong_add<T, T>(C->tr, ec, xa, s, nact, bdd, bf);
-  prof_end(C, HSP_PROF_TRANSFER, s, (double)nact * ((double)nd * sizeof(cx<T>) + 2.0 * nf * sizeof(cx<T>)));
-  if (nu == 0) {
-    launch_convert<double, T>(xa, z, nf, 0, s, nact, bf, bz);
-    return;
-  }
-  prof_begin(C, HSP_PROF_SMOOTH, s);
-  for (int k = 0; k < nu; ++k) {
-    if (k == nu - 1) {
-      launch_stencil<T, T, double, double>(C->fine, 2, xa, r, z, wj, s, nact, bf, br, bz);
-    } else {
-      launch_stencil<T, T, double, T>(C->fine, 2, xa, r, xb, wj, s, nact, bf, br, bf);
-      std::swap(xa, xb);
-    }
-  }
-  prof_end(C, HSP_PROF_SMOOTH, s, nu * jb);
-}
-
-void precond_batch(hsp_ctx* C, const BatchLayout& B, void* ws, int nact, int rb, const cd* r, BIdx br, cd* z,
-                   BIdx bz, hipStream_t s) {
-  if (C->opt.precision == HSP_MIXED)
-    run_precond_batch<float>(C, B, ws, nact, rb, r, br, z, bz, s);
-  else
-    run_precond_batch<double>(C, B, ws, nact, rb, r, br, z, bz, s);
-}
-
-hsp_status check_batch_args(hsp_ctx* C, int nrhs, int restart, void* ws, size_t bytes, int tile, BatchLayout& B) {
-  if (!C) return fail(HSP_EINVAL, "null handle");
-  if (nrhs < 0) return fail(HSP_EINVAL, "nrhs must be >= 0");
-  if (restart < 1) return fail(HSP_EINVAL, "restart must be >= 1");
-  if (tile != 0 && tile != 1 && tile != 2 && tile != 4 && tile != 8)
-    return fail(HSP_EINVAL, "tile must be 0 (automatic), 1, 2, 4 or 8");
-  if (nrhs == 0) return HSP_OK;
-  if (!ws) return fail(HSP_EINVAL, "null batch workspace");
-  if (((uintptr_t)ws) & 255) return fail(HSP_EINVAL, "batch workspace must be 256-byte aligned");
-  B = batch_layout(C->P, nrhs, restart);
-  if (bytes < B.total) return fail(HSP_ENOMEM, "batch workspace too small: need " + std::to_string(B.total) + " bytes");
-  return HSP_OK;
-}
-
-hipStream_t S_(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
+
+namespace hsp {
+
+hsp_status fail(hsp_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+void prof_begin(hsp_ctx* C, int cls, hipStream_t s) {
+  Prof& P = C->prof;
+  if (!P.on) return;
+  if (P.used[cls] == P.ev[cls].size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return;
+    }
+    P.ev[cls].push_back({a, b});
+  }
+  (void)hipEventRecord(P.ev[cls][P.used[cls]].first, s);
+}
+
+void prof_end(hsp_ctx* C, int cls, hipStream_t s, double bytes) {
+  Prof& P = C->prof;
+  if (!P.on || P.used[cls] >= P.ev[cls].size()) return;
+  (void)hipEventRecord(P.ev[cls][P.used[cls]].second, s);
+  ++P.used[cls];
+  ++P.n[cls];
+  P.bytes[cls] += bytes;
+}
+
+}  // namespace hsp
 
 // ===========================================================================
 // C ABI
@@ -1482,340 +1211,3 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
 
 }  // extern "C"
 
-// ===========================================================================
-// Batched right-hand sides (many sources or receivers of one medium and
-// frequency share the setup; Sec. 4 notes that the slab factors serve every
-// right-hand side)
-// ===========================================================================
-namespace {
-
-// Hessenberg matrix of one right-hand side's flexible Arnoldi process.  With
-// the delayed Gram-Schmidt the newest column is provisional (its
-// reorthogonalisation terms arrive with the next step); the least-squares
-// problem min ||beta e_1 - H y|| is solved from scratch by Givens rotations
-// whenever it is needed (k <= restart, negligible host work).
-struct Arnoldi {
-  int m = 0;
-  double beta = 0;
-  std::vector<cplx> H;  // (m+1) x m, H[i m + j]
-  void reset(int m_, double b) {
-    m = m_;
-    beta = b;
-    H.assign((size_t)(m + 1) * m, cplx(0));
-  }
-  cplx& at(int i, int j) { return H[(size_t)i * m + j]; }
-  // residual estimate over columns 0..k-1; y (optional) receives the
-  // minimiser
-  double lsq(int k, cd* y) const {
-    std::vector<cplx> R((size_t)(k + 1) * k), g(k + 1, cplx(0)), sn(k);
-    std::vector<double> cs(k);
-    for (int i = 0; i <= k; ++i)
-      for (int j = 0; j < k; ++j) R[(size_t)i * k + j] = H[(size_t)i * m + j];
-    g[0] = beta;
-    for (int j = 0; j < k; ++j) {
-      for (int i = 0; i < j; ++i) {
-        const cplx a = R[(size_t)i * k + j], bb = R[(size_t)(i + 1) * k + j];
-        R[(size_t)i * k + j] = cs[i] * a + sn[i] * bb;
-        R[(size_t)(i + 1) * k + j] = -std::conj(sn[i]) * a + cs[i] * bb;
-      }
-      const cplx a = R[(size_t)j * k + j], bb = R[(size_t)(j + 1) * k + j];
-      if (std::abs(bb) == 0) {
-        cs[j] = 1;
-        sn[j] = 0;
-      } else if (std::abs(a) == 0) {
-        cs[j] = 0;
-        sn[j] = 1;
-      } else {
-        const double t = std::sqrt(std::norm(a) + std::norm(bb));
-        cs[j] = std::abs(a) / t;
-        sn[j] = (a / std::abs(a)) * std::conj(bb) / t;
-      }
-      R[(size_t)j * k + j] = cs[j] * a + sn[j] * bb;
-      R[(size_t)(j + 1) * k + j] = 0;
-      g[j + 1] = -std::conj(sn[j]) * g[j];
-      g[j] = cs[j] * g[j];
-    }
-    if (y) {
-      std::vector<cplx> yy(k);
-      for (int i = k - 1; i >= 0; --i) {
-        cplx acc = g[i];
-        for (int j = i + 1; j < k; ++j) acc -= R[(size_t)i * k + j] * yy[j];
-        yy[i] = acc / R[(size_t)i * k + i];
-      }
-      for (int i = 0; i < k; ++i) y[i] = to_cd(yy[i]);
-    }
-    return std::abs(g[k]);
-  }
-};
-
-}  // namespace
-
-extern "C" {
-
-hsp_status hsp_batch_workspace_size(hsp_handle C, int nrhs, int restart, size_t* bytes) {
-  if (!C || !bytes) return fail(HSP_EINVAL, "null argument");
-  if (nrhs < 1 || restart < 1) return fail(HSP_EINVAL, "nrhs and restart must be >= 1");
-  *bytes = batch_layout(C->P, nrhs, restart).total;
-  return HSP_OK;
-}
-
-hsp_status hsp_apply_precond_batch(hsp_handle C, int nrhs, const void* r, void* z, int tile, void* ws,
-                                   size_t ws_bytes, void* stream) {
-  BatchLayout B;
-  hsp_status st = check_batch_args(C, nrhs, 1, ws, ws_bytes, tile, B);
-  if (st != HSP_OK || nrhs == 0) return st;
-  if (!r || !z || r == z) return fail(HSP_EINVAL, "null or aliased argument");
-  hipStream_t s = S_(stream);
-  const size_t nf = (size_t)C->P.nf1 * C->P.nf2;
-  HIPCHK(hipMemsetAsync(bat<int>(ws, B.o_ctr), 0, 2 * batch_slots(nrhs) * sizeof(int), s));
-  BIdx bv;
-  bv.ld = nf;
-  precond_batch(C, B, ws, nrhs, tile ? tile : default_tile(C, nrhs), (const cd*)r, bv, (cd*)z, bv, s);
-  HIPCHK(hipGetLastError());
-  return HSP_OK;
-}
-
-hsp_status hsp_tune_batch(hsp_handle C, int nrhs, int restart, void* ws, size_t ws_bytes, int* tile_out,
-                          double* ms_out, void* stream) {
-  BatchLayout B;
-  hsp_status st = check_batch_args(C, nrhs, restart, ws, ws_bytes, 0, B);
-  if (st != HSP_OK) return st;
-  if (nrhs == 0) return fail(HSP_EINVAL, "nrhs must be >= 1");
-  hipStream_t s = S_(stream);
-  const size_t nf = (size_t)C->P.nf1 * C->P.nf2;
-  cd* r = bat<cd>(ws, B.o_V);
-  cd* z = bat<cd>(ws, B.o_Z);
-  HIPCHK(hipMemsetAsync(bat<int>(ws, B.o_ctr), 0, 2 * batch_slots(nrhs) * sizeof(int), s));
-  launch_fill(r, (size_t)nrhs * nf, mk<double>(1.0, 0.0), s);
-  BIdx bv;
-  bv.ld = nf;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return fail(HSP_EDEVICE, "hipEventCreate failed");
-  }
-  const bool prof = C->prof.on;
-  C->prof.on = false;
-  int best = 1;
-  double best_ms = 1e300;
-  hipError_t err = hipSuccess;
-  for (int rb = 1; rb <= kMaxTile && err == hipSuccess; rb *= 2) {
-    precond_batch(C, B, ws, nrhs, rb, r, bv, z, bv, s);  // warm-up
-    err = hipEventRecord(e0, s);
-    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) precond_batch(C, B, ws, nrhs, rb, r, bv, z, bv, s);
-    if (err == hipSuccess) err = hipEventRecord(e1, s);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    float ms = 0;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    if (err == hipSuccess && 0.5 * ms < best_ms) {
-      best_ms = 0.5 * ms;
-      best = rb;
-    }
-  }
-  C->prof.on = prof;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (err != hipSuccess) return fail(HSP_EDEVICE, std::string("tuning: ") + hipGetErrorString(err));
-  HIPCHK(hipGetLastError());
-  C->tuned_rb = best;
-  C->tuned_nact = nrhs;
-  if (tile_out) *tile_out = best;
-  if (ms_out) *ms_out = best_ms;
-  return HSP_OK;
-}
-
-hsp_status hsp_solve_batch(hsp_handle C, int nrhs, const void* b_in, void* u_out, double tol, int maxit, int restart,
-                           int conj_transpose, int tile, void* ws, size_t ws_bytes, int* iters, double* relres,
-                           void* stream) {
-  BatchLayout B;
-  hsp_status st = check_batch_args(C, nrhs, restart, ws, ws_bytes, tile, B);
-  if (st != HSP_OK || nrhs == 0) return st;
-  if (!b_in || !u_out || b_in == u_out) return fail(HSP_EINVAL, "null or aliased argument");
-  if (!(tol > 0) || maxit < 1) return fail(HSP_EINVAL, "tol must be > 0 and maxit >= 1");
-  hipStream_t s = S_(stream);
-  const int R = nrhs, m = restart;
-  const size_t nf = (size_t)C->P.nf1 * C->P.nf2;
-  const size_t hs = B.hs;
-  cd* V = bat<cd>(ws, B.o_V);
-  cd* Z = bat<cd>(ws, B.o_Z);
-  cd* w = bat<cd>(ws, B.o_w);
-  cd* part = bat<cd>(ws, B.o_part);
-  cd* hb = bat<cd>(ws, B.o_hb);
-  cd* ydev = bat<cd>(ws, B.o_y);
-  int* act_d = bat<int>(ws, B.o_act);
-  int* upd_d = bat<int>(ws, B.o_upd);
-  cd* x = (cd*)u_out;
-  const cd* b = (const cd*)b_in;
-  const LevelDev& A = C->fine;
-  HIPCHK(hipMemsetAsync(bat<int>(ws, B.o_ctr), 0, 2 * batch_slots(R) * sizeof(int), s));
-  BIdx bid;  // identity map over all right-hand sides
-  bid.ld = nf;
-  if (conj_transpose) {
-    cd* bc = bat<cd>(ws, B.o_bc);
-    launch_convert<double, double>(b, bc, (size_t)R * nf, 1, s);
-    b = bc;
-  }
-  std::vector<cd> hh((size_t)R * hs);
-  auto read_hb = [&](int cnt) -> hsp_status {
-    HIPCHK(hipMemcpyAsync(hh.data(), hb, (size_t)cnt * hs * sizeof(cd), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return HSP_OK;
-  };
-  // ||b_z||
-  launch_bmultidot(b, 0, bid, 1, b, bid, nf, part, B.nblk, hb + 2 * (m + 1), hs, R, s);
-  st = read_hb(R);
-  if (st != HSP_OK) return st;
-  std::vector<double> bnorm(R);
-  for (int z = 0; z < R; ++z) bnorm[z] = std::sqrt(std::max(hh[(size_t)z * hs + 2 * (m + 1)].re, 0.0));
-  launch_zero<double>(x, (size_t)R * nf, s);
-  std::vector<int> its(R, 0), done(R, 0), act, upd;
-  for (int z = 0; z < R; ++z) {
-    if (bnorm[z] == 0)
-      done[z] = 1;
-    else
-      act.push_back(z);
-  }
-  std::vector<Arnoldi> ar(R);
-  std::vector<cd> yh((size_t)R * m);
-  auto upload = [&](int* dst, const std::vector<int>& v) -> hsp_status {
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    return HSP_OK;
-  };
-  // x_z += Z_z y_z for the right-hand sides in `upd` (k basis vectors each)
-  auto update = [&](const std::vector<int>& list, int k) -> hsp_status {
-    if (list.empty() || k == 0) return HSP_OK;
-    // the host staging arrays yh / upd may still feed an earlier copy
-    HIPCHK(hipStreamSynchronize(s));
-    upd = list;
-    for (size_t i = 0; i < upd.size(); ++i) ar[upd[i]].lsq(k, yh.data() + i * m);
-    HIPCHK(hipMemcpyAsync(ydev, yh.data(), upd.size() * m * sizeof(cd), hipMemcpyHostToDevice, s));
-    hsp_status e = upload(upd_d, upd);
-    if (e != HSP_OK) return e;
-    BIdx bz, bx;
-    bz.ld = (size_t)m * nf;
-    bz.map = upd_d;
-    bx.ld = nf;
-    bx.map = upd_d;
-    launch_bmultiaxpy(Z, nf, bz, k, ydev, m, x, bx, nf, 0, (int)upd.size(), s);
-    return HSP_OK;
-  };
-  const int rb_fixed = tile;
-  const int koff = 2 * (m + 1);  // hb offset of nu, h_kk, ||u_{k+1}||^2
-  int it = 0;
-  while (it < maxit && !act.empty()) {
-    int nact = (int)act.size();
-    st = upload(act_d, act);
-    if (st != HSP_OK) return st;
-    BIdx bx, bV;
-    bx.ld = nf;
-    bx.map = act_d;
-    bV.ld = (size_t)(m + 1) * nf;
-    bV.map = act_d;
-    // r = b - A x into V_z0, its norm, normalisation
-    launch_stencil<double, double, double, double>(A, 1, x, b, V, 0.0, s, nact, bx, bx, bV);
-    launch_bmultidot(V, 0, bV, 1, V, bV, nf, part, B.nblk, hb + 2 * (m + 1), hs, nact, s);
-    launch_bnormalize(V, bV, hb + 2 * (m + 1), hs, V, bV, nf, nact, s);
-    st = read_hb(nact);
-    if (st != HSP_OK) return st;
-    {
-      std::vector<int> keep;
-      for (int zi = 0; zi < nact; ++zi) {
-        const int z = act[zi];
-        const double beta = std::sqrt(std::max(hh[(size_t)zi * hs + 2 * (m + 1)].re, 0.0));
-        if (beta <= tol * bnorm[z]) {
-          done[z] = 1;
-          continue;
-        }
-        ar[z].reset(m, beta);
-        keep.push_back(z);
-      }
-      act.swap(keep);
-    }
-    nact = (int)act.size();
-    if (nact == 0) break;
-    st = upload(act_d, act);
-    if (st != HSP_OK) return st;
-    int k = 0;
-    for (; k < m && it < maxit && nact > 0; ++k) {
-      const int rb = rb_fixed ? rb_fixed : default_tile(C, nact);
-      BIdx bVk, bZk, bw;
-      bVk.ld = (size_t)(m + 1) * nf;
-      bVk.map = act_d;
-      bZk.ld = (size_t)m * nf;
-      bZk.map = act_d;
-      bw.ld = nf;
-      precond_batch(C, B, ws, nact, rb, V + (size_t)k * nf, bVk, Z + (size_t)k * nf, bZk, s);
-      prof_begin(C, HSP_PROF_KRYLOV, s);
-      launch_stencil<double, double, double, double>(A, 0, Z + (size_t)k * nf, (const cd*)nullptr, w, 0.0, s, nact,
-                                                     bZk, BIdx{}, bw);
-      // delayed classical Gram-Schmidt: one projection pass (basis against
-      // u_k and w) and one update pass (v_k final, u_{k+1} and its norm)
-      BIdx bVb;
-      bVb.ld = (size_t)(m + 1) * nf;
-      bVb.map = act_d;
-      launch_bdcgs_project(V, nf, bVb, k, w, bw, nf, part, B.nblk, hb, hs, koff, nact, s);
-      launch_bdcgs_update(V, nf, bVb, k, hb, hs, koff, w, bw, nf, part, B.nblk, hb + koff + 2, nact, s);
-      // matvec (z, k^2 read, w written); projection reads k+1 basis vectors
-      // and w; update reads k basis vectors, u_k and w and writes v_k, u_{k+1}
-      prof_end(C, HSP_PROF_KRYLOV, s,
-               (double)nact * ((double)nf * (2.0 * sizeof(cd) + sizeof(double)) +
-                               (double)nf * sizeof(cd) * (2.0 * k + 6.0)));
-      HIPCHK(hipGetLastError());
-      st = read_hb(nact);
-      if (st != HSP_OK) return st;
-      ++it;
-      std::vector<int> keep, conv;
-      for (int zi = 0; zi < nact; ++zi) {
-        const int z = act[zi];
-        const cd* d = hh.data() + (size_t)zi * hs;
-        Arnoldi& a = ar[z];
-        if (k > 0) {  // finalise column k-1 with the reorthogonalisation terms
-          for (int j = 0; j < k; ++j) a.at(j, k - 1) += cplx(d[j].re, d[j].im);
-          a.at(k, k - 1) = d[koff].re;
-        }
-        for (int j = 0; j < k; ++j) a.at(j, k) = cplx(d[k + 1 + j].re, d[k + 1 + j].im);
-        a.at(k, k) = cplx(d[koff + 1].re, d[koff + 1].im);
-        a.at(k + 1, k) = std::sqrt(std::max(d[koff + 2].re, 0.0));
-        const double est = a.lsq(k + 1, nullptr);
-        its[z] = it;
-        if (est <= tol * bnorm[z]) {
-          conv.push_back(z);
-          done[z] = 1;
-        } else {
-          keep.push_back(z);
-        }
-      }
-      st = update(conv, k + 1);
-      if (st != HSP_OK) return st;
-      if (keep.size() != act.size()) {
-        act.swap(keep);
-        nact = (int)act.size();
-        st = upload(act_d, act);
-        if (st != HSP_OK) return st;
-      }
-    }
-    // end of a restart cycle (or maxit): fold the active corrections into x
-    st = update(act, k);
-    if (st != HSP_OK) return st;
-    HIPCHK(hipStreamSynchronize(s));
-  }
-  // true residuals of every right-hand side
-  launch_stencil<double, double, double, double>(A, 1, x, b, w, 0.0, s, R, bid, bid, bid);
-  launch_bmultidot(w, 0, bid, 1, w, bid, nf, part, B.nblk, hb + 2 * (m + 1), hs, R, s);
-  st = read_hb(R);
-  if (st != HSP_OK) return st;
-  if (conj_transpose) launch_convert<double, double>(x, x, (size_t)R * nf, 1, s);
-  HIPCHK(hipGetLastError());
-  bool all = true;
-  for (int z = 0; z < R; ++z) {
-    const double rr = bnorm[z] > 0 ? std::sqrt(std::max(hh[(size_t)z * hs + 2 * (m + 1)].re, 0.0)) / bnorm[z] : 0.0;
-    if (iters) iters[z] = its[z];
-    if (relres) relres[z] = rr;
-    if (!done[z] && rr > tol) all = false;
-  }
-  if (!all) return fail(HSP_ENOCONV, "maxit reached before the tolerance for some right-hand sides");
-  return HSP_OK;
-}
-
-}  // extern "C"

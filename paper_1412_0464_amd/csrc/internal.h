@@ -13,10 +13,16 @@ constexpr int kWave = 64;
 // Batch addressing: vector z of a batch starts at base + off(z), with
 // off(z) = (map ? map[z] : z) * ld.  A default BIdx (ld = 0) addresses the
 // same vector for every z; single-vector calls use nb = 1.
+// dyn (optional) adds an element offset read from device memory, so that a
+// captured launch sequence can be pointed at another vector without
+// re-capturing it.
 struct BIdx {
   size_t ld = 0;
   const int* map = nullptr;
-  __device__ __forceinline__ size_t off(int z) const { return (size_t)(map ? map[z] : z) * ld; }
+  const long long* dyn = nullptr;
+  __device__ __forceinline__ size_t off(int z) const {
+    return (size_t)(map ? map[z] : z) * ld + (dyn ? (size_t)*dyn : 0);
+  }
 };
 
 // ---- stencil kernels (stencil.hip) ---------------------------------------
@@ -116,16 +122,33 @@ void launch_stage(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev
                   cx<T>* scratch, const cx<T>* factors, int nl_max, int nl_launch, int m, int P,
                   cx<T>* red, int* counters, hipStream_t s);
 
-// The same stage for nact right-hand sides (batch.hip): level vectors f, g, u
-// are [nact][ld] (right-hand side z at offset z ld), transmission buffers
-// [nact][2][2][n2]; work items (task, chunk, tile of rb right-hand sides).
-// scratch: 2 ceil(nact/rb) rb n2 nl_max; red: 2 ceil(nact/rb) 2 P nl_max rb;
-// counters: 4 ceil(nact/rb) ints, zero between launches.  rb in {1,2,4,8}.
+// The same stage for many right-hand sides of several problems (batch.hip).
+// One segment per problem taking part in the launch: its tasks of this
+// stage, its level vectors f, g, u ([nact][ld], right-hand side z at offset
+// z ld, storage type of the launch), transmission buffers [nact][2][2][n2],
+// scratch 2 ceil(nact/rb) rb n2 nl_max, chunk tips / heads
+// 2 ceil(nact/rb) 2 P nl_max rb, counters 4 ceil(nact/rb) ints (zero
+// between launches).  Work items of a segment: (task, chunk, tile of rb
+// right-hand sides); item0 is the segment's first item in the launch.
+struct BSeg {
+  const TaskDev* tasks;
+  const SlabDev* slabs;
+  LevelDev G;
+  const void* f;
+  const void* g;
+  void* u;
+  void* bufs;
+  void* scratch;
+  const void* factors;
+  void* red;
+  int* counters;
+  size_t ld;
+  int ntasks, ntiles, nact, nl_max, m, P, item0, pad;
+};
+// segs_dev: nseg segments in device memory, nitems work items in total,
+// nl_launch the thickest slab, rb in {1, 2, 4, 8}.
 template <class T>
-void launch_stage_batch(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev, const LevelDev& G,
-                        const cx<T>* f, const cx<T>* g, cx<T>* u, cx<T>* bufs, cx<T>* scratch, const cx<T>* factors,
-                        int nl_max, int nl_launch, int m, int P, int nact, int rb, size_t ld, cx<T>* red,
-                        int* counters, hipStream_t s);
+void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launch, int rb, hipStream_t s);
 
 // ---- BLAS-1 and utilities (blas.hip) ---------------------------------------
 template <class To, class Ti>

@@ -49,7 +49,9 @@ EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", 
            "hsp_get_partition", "hsp_apply_level_operator", "hsp_restrict", "hsp_prolong_add",
            "hsp_smooth", "hsp_sweep", "hsp_slab_solve", "hsp_profile_enable", "hsp_profile_read",
            "hsp_gradient_accumulate", "hsp_batch_workspace_size", "hsp_apply_precond_batch",
-           "hsp_tune_batch", "hsp_solve_batch"]
+           "hsp_tune_batch", "hsp_solve_batch", "hsp_group_workspace_size", "hsp_apply_precond_group",
+           "hsp_solve_group"]
+GROUP_GRAPH = 1
 PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4}
 
 
@@ -92,6 +94,11 @@ def load():
         "hsp_apply_precond_batch": [P, I, P, P, I, P, S, P],
         "hsp_tune_batch": [P, I, I, P, S, ctypes.POINTER(I), ctypes.POINTER(D), P],
         "hsp_solve_batch": [P, I, P, P, D, I, I, I, I, P, S, ctypes.POINTER(I), ctypes.POINTER(D), P],
+        "hsp_group_workspace_size": [I, ctypes.POINTER(P), ctypes.POINTER(I), I, ctypes.POINTER(S)],
+        "hsp_apply_precond_group": [I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(P),
+                                    ctypes.POINTER(P), I, I, P, S, P],
+        "hsp_solve_group": [I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(P), D, I,
+                            I, I, I, I, P, S, ctypes.POINTER(I), ctypes.POINTER(D), P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -375,3 +382,83 @@ class Helmholtz:
         if not (st == HSP_ENOCONV and not raise_on_noconv):
             _check(st)
         return u, list(its)[:nrhs], list(rr)[:nrhs]
+
+
+# -- groups: right-hand sides of several problems solved together ------------
+class Group:
+    """Several set-up problems (Helmholtz objects of one precision) whose
+    right-hand sides are solved together: the sweep stages of all problems
+    share launches (hsp_solve_group).  The group workspace is allocated on
+    first use for the given right-hand-side counts and restart."""
+
+    def __init__(self, problems, restart=40):
+        self.problems = list(problems)
+        self.restart = int(restart)
+        self._ws = None
+        self._key = None
+
+    def _arrays(self, nrhs):
+        n = len(self.problems)
+        hds = (ctypes.c_void_p * n)(*[p.handle for p in self.problems])
+        cnt = (ctypes.c_int * n)(*[int(k) for k in nrhs])
+        return n, hds, cnt
+
+    def workspace(self, nrhs, restart=None):
+        restart = int(restart or self.restart)
+        key = (tuple(int(k) for k in nrhs), restart)
+        if key == self._key:
+            return self._ws
+        n, hds, cnt = self._arrays(nrhs)
+        S = ctypes.c_size_t()
+        _check(load().hsp_group_workspace_size(n, hds, cnt, restart, ctypes.byref(S)))
+        self._ws = None
+        self._ws = torch.empty(S.value, dtype=torch.uint8, device=self.problems[0].ws.device)
+        self._key = key
+        return self._ws
+
+    def _check_vecs(self, vecs, name):
+        if len(vecs) != len(self.problems):
+            raise ValueError(f"{name}: one tensor per problem expected")
+        for p, v in zip(self.problems, vecs):
+            p._batch(v, name)
+
+    def apply_precond(self, rs, tile=0, graph=False):
+        """z_j = M_p r_j for every right-hand side of every problem p
+        (hsp_apply_precond_group); rs[p] has shape (nrhs_p, n1_p, n2_p)."""
+        self._check_vecs(rs, "r")
+        zs = [torch.empty_like(r) for r in rs]
+        nrhs = [r.shape[0] for r in rs]
+        ws = self.workspace(nrhs, self.restart)
+        n, hds, cnt = self._arrays(nrhs)
+        rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rs])
+        zp = (ctypes.c_void_p * n)(*[z.data_ptr() for z in zs])
+        _check(load().hsp_apply_precond_group(n, hds, cnt, rp, zp, int(tile), GROUP_GRAPH if graph else 0, _ptr(ws),
+                                              ws.numel(), _stream()))
+        return zs
+
+    def solve(self, bs, tol=1e-6, maxit=200, tile=0, graph=False, conj_transpose=False, outs=None,
+              raise_on_noconv=True):
+        """FGMRES on every right-hand side of every problem (hsp_solve_group).
+        Returns (list of solutions, list of iteration lists, list of
+        relative-residual lists), problem by problem."""
+        self._check_vecs(bs, "b")
+        us = [torch.empty_like(b) for b in bs] if outs is None else list(outs)
+        nrhs = [b.shape[0] for b in bs]
+        tot = max(sum(nrhs), 1)
+        ws = self.workspace(nrhs, self.restart)
+        n, hds, cnt = self._arrays(nrhs)
+        bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+        up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        its = (ctypes.c_int * tot)()
+        rr = (ctypes.c_double * tot)()
+        st = load().hsp_solve_group(n, hds, cnt, bp, up, float(tol), int(maxit), self.restart,
+                                    int(bool(conj_transpose)), int(tile), GROUP_GRAPH if graph else 0, _ptr(ws),
+                                    ws.numel(), its, rr, _stream())
+        if not (st == HSP_ENOCONV and not raise_on_noconv):
+            _check(st)
+        out_it, out_rr, o = [], [], 0
+        for k in nrhs:
+            out_it.append(list(its)[o:o + k])
+            out_rr.append(list(rr)[o:o + k])
+            o += k
+        return us, out_it, out_rr

@@ -191,3 +191,66 @@ def test_batch_invalid_arguments():
         hs.solve_batch(B, tile=3)
     with pytest.raises(HspError):
         hs.solve_batch(B, tol=0.0)
+
+
+# ---------------------------------------------------------------------------
+# groups: several problems (sizes, slab counts, sweeps, one- and two-level)
+# whose sweep stages share launches
+# ---------------------------------------------------------------------------
+GROUP = [("tg_x_j5", 3), ("tg_ud", 2), ("fd5_1lvl_x", 5), ("fe9_1lvl_x", 0)]
+
+
+def _group(precision):
+    from paper_1412_0464_amd import Group
+    built = [_build(name, precision) for name, _ in GROUP]
+    return built, Group([hs for _, _, hs in built], restart=40)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
+def test_group_precond_columns(precision, tol):
+    built, grp = _group(precision)
+    Rs = [np.stack([random_rhs(c.shape, 400 + 10 * p + j) for j in range(k)]) if k else
+          np.zeros((0,) + c.shape, dtype=complex) for p, ((c, _, _), (_, k)) in enumerate(zip(built, GROUP))]
+    Zs = grp.apply_precond([_t(R) for R in Rs], tile=2)
+    for p, ((c, ref, _), (name, k)) in enumerate(zip(built, GROUP)):
+        Z = Zs[p].cpu().numpy()
+        for j in range(k):
+            assert _relerr(Z[j], ref.precond(Rs[p][j].ravel())) < tol, f"{name} column {j}"
+
+
+def test_group_graph_replays_match_eager():
+    built, grp = _group("mixed")
+    Rs = [_t(np.stack([random_rhs(c.shape, 450 + 10 * p + j) for j in range(max(k, 1))]))
+          for p, ((c, _, _), (_, k)) in enumerate(zip(built, GROUP))]
+    eager = [z.cpu().numpy() for z in grp.apply_precond(Rs, tile=4)]
+    for rep in range(3):
+        # eager work and a synchronisation between the replays
+        grp.apply_precond(Rs, tile=1)
+        torch.cuda.synchronize()
+        got = [z.cpu().numpy() for z in grp.apply_precond(Rs, tile=4, graph=True)]
+        for p in range(len(Rs)):
+            assert np.array_equal(got[p], eager[p]), f"replay {rep} problem {p}"
+
+
+@pytest.mark.parametrize("precision,graph", [("fp64", False), ("mixed", True)])
+def test_group_solve(precision, graph):
+    built, grp = _group(precision)
+    fss = [_sources(c.shape, 0.02, k) if k else [] for (c, _, _), (_, k) in zip(built, GROUP)]
+    Bs = [torch.stack([hs.rhs(_t(f)) for f in fs]) if fs else
+          torch.zeros((0,) + tuple(c.shape), dtype=torch.complex128, device=_dev())
+          for (c, _, hs), fs in zip(built, fss)]
+    tol = 1e-6 if precision == "fp64" else 1e-10
+    Us, its, rrs = grp.solve(Bs, tol=tol, maxit=200, graph=graph)
+    for p, ((c, ref, hs), fs) in enumerate(zip(built, fss)):
+        U = Us[p].cpu().numpy()
+        for j, f in enumerate(fs):
+            if not np.any(f):
+                assert its[p][j] == 0 and not np.any(U[j])
+                continue
+            assert rrs[p][j] <= tol
+            if precision == "fp64":
+                uo, ito, _, _ = ref.solve(f, tol=tol, maxit=200)
+                assert abs(its[p][j] - ito) <= 1, f"problem {p} column {j}: {its[p][j]} vs {ito}"
+                assert _relerr(U[j], uo) < 1e-6
+            else:
+                assert _relerr(U[j], ref.direct(f)) < 1e-4
