@@ -109,6 +109,53 @@ def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile
     return res
 
 
+# (n, points per wavelength at 1.5 km/s, J): higher frequencies on finer
+# grids; below 8 points per wavelength the coarse level of the two-grid
+# method is too coarse for it to converge
+C3_GRIDS = [(255, 12.0, 8), (511, 10.0, 16), (767, 9.0, 24), (1023, 8.0, 32)]
+
+
+def c3_run(steps, warmup, tol, nsrc=64, graph=False):
+    """The batched multi-frequency workload: one seeded layered medium on a
+    10.24 km square sampled on four grids (255^2 .. 1023^2 interior nodes +
+    16 PML cells), one frequency per grid (8-12 points per wavelength at
+    1.5 km/s, higher frequencies on finer grids), nsrc point sources per
+    grid; all 4 x nsrc right-hand sides solved to tol in one group (every
+    aligned sweep step is one launch triple over all grids)."""
+    import torch
+    from paper_1412_0464_amd import Group, Helmholtz
+    from synth.media import layered_medium_2d, extend_into_pml, resample_nodes
+    dev = torch.device("cuda:0")
+    L, w = 10.24, 16
+    base = layered_medium_2d(1023, 1023, 1412046)
+    probs, Bs, dofs = [], [], []
+    for n, ppw, J in C3_GRIDS:
+        h = L / (n + 1)
+        c = extend_into_pml(resample_nodes(base, n), w)
+        om = 2 * np.pi * 1.5 / (ppw * h)
+        hs = Helmholtz(torch.tensor(c, device=dev), om, h, w, J, two_grid=True, precision="mixed", restart=40)
+        cfg = dict(w=w, h=h)
+        fs = sources(cfg, c.shape, nsrc, seed=1412049 + n)
+        Bs.append(torch.stack([hs.rhs(torch.tensor(f, dtype=torch.complex128, device=dev)) for f in fs]))
+        probs.append(hs)
+        dofs.append(n * n)
+    grp = Group(probs, restart=40)
+    for _ in range(warmup):
+        grp.solve(Bs, tol=tol, maxit=200, graph=graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    work = 0
+    for _ in range(steps):
+        _, its, rrs = grp.solve(Bs, tol=tol, maxit=200, graph=graph)
+        work += sum(d * sum(it) for d, it in zip(dofs, its))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": work / dt, "unit": UNIT, "solve_s": dt / steps, "sources_per_grid": nsrc,
+            "grids": [f"{n}^2 + {w} PML, ppw {ppw}, J={J}" for n, ppw, J in C3_GRIDS],
+            "iterations": [[min(it), max(it)] for it in its], "relres_max": max(max(r) for r in rrs),
+            "graph": bool(graph)}
+
+
 def gpu_run(cfg, c, f, precision, steps, warmup, tol, profile=False):
     """Setup once, then time ``steps`` complete solves after ``warmup`` ones.
     With ``profile`` the library brackets every kernel launch of each class
@@ -182,6 +229,8 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="skip the single-source mixed run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--c3", action="store_true", help="also time the batched multi-frequency group workload")
+    ap.add_argument("--c3-sources", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -252,6 +301,12 @@ def main():
                                / HBM_PEAK_GBS,
                                "kernel_ms_per_solve": {k: v[0] / args.steps for k, v in scl.items()}}
         del sm
+    if args.c3:
+        for graph in (False, True):
+            r3 = c3_run(max(1, args.steps - 1), 1, args.tol, nsrc=args.c3_sources, graph=graph)
+            print(f"[bench] c3 group (graph={graph}): {r3['solve_s'] * 1e3:.1f} ms, {r3['value']:.3e} dof*iter/s",
+                  file=sys.stderr, flush=True)
+            out["c3_graph" if graph else "c3"] = r3
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, c, fs[0], args.cpu_iters, args.tol)

@@ -86,6 +86,20 @@ def gaussian_anomaly(shape, centre, sigma_cells, amp):
     return 1.0 + amp * np.exp(-r2 / (2.0 * sigma_cells ** 2))
 
 
+def resample_nodes(c, n_new):
+    """Bilinear resampling of a model given at the interior nodes of a unit
+    square (n nodes per axis, spacing 1/(n+1)) onto n_new nodes per axis, so
+    that grids of several resolutions carry the same medium."""
+    c = np.asarray(c, dtype=float)
+    out = c
+    for ax in range(c.ndim):
+        n = out.shape[ax]
+        x_old = np.arange(1, n + 1) / (n + 1.0)
+        x_new = np.arange(1, n_new + 1) / (n_new + 1.0)
+        out = np.apply_along_axis(lambda v: np.interp(x_new, x_old, v), ax, out)
+    return out
+
+
 def extend_into_pml(c_interior, w):
     """Constant (edge-value) extension of an interior model by w nodes per side."""
     return np.pad(c_interior, w, mode="edge")
