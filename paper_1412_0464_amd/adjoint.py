@@ -1,13 +1,14 @@
 """Receiver-data misfit and its gradient with respect to the squared slowness
 m = 1/c^2, as a ``torch.autograd.Function`` over the GPU library.
 
-forward(m) solves A(m) u_s = b_s for every source with FGMRES and the
-preconditioner of the handle (hsp_solve) and returns the predicted data
-d_s = u_s[receivers] (complex, shape (n_sources, n_receivers)).
-backward(g_d) solves the adjoint systems A^H lam_s = R^T g_d,s with the same
-handle (hsp_solve with conj_transpose = 1, A being complex symmetric) and
-accumulates dL/dm = h^2 omega^2 sum_s Re(conj(lam_s) u_s / (alpha_1 alpha_2))
-in a device kernel (hsp_gradient_accumulate).  ``g_d`` is torch's
+forward(m) solves A(m) u_s = b_s for all sources in one batch (one FGMRES
+process per source, the preconditioner of the handle; hsp_solve_batch) and
+returns the predicted data d_s = u_s[receivers] (complex, shape
+(n_sources, n_receivers)).  backward(g_d) solves the adjoint systems
+A^H lam_s = R^T g_d,s as one batch with the same handle (conj_transpose = 1,
+A being complex symmetric) and accumulates
+dL/dm = h^2 omega^2 sum_s Re(conj(lam_s) u_s / (alpha_1 alpha_2)) in a
+device kernel (hsp_gradient_accumulate).  ``g_d`` is torch's
 conjugate-Wirtinger gradient of a real loss (for L = 1/2 ||d - d_obs||^2 it
 is d - d_obs).
 
@@ -30,28 +31,25 @@ class HelmholtzMisfit(torch.autograd.Function):
         opts.setdefault("fine_stencil", 5)
         c = torch.rsqrt(m.detach()).contiguous()
         hs = Helmholtz(c, omega, h, pml, J, c_pml=c_pml, **opts)
-        us, ds = [], []
-        for s in range(sources.shape[0]):
-            b = hs.rhs(sources[s].contiguous())
-            u, it, rr = hs.solve(b, tol=tol, maxit=500)
-            us.append(u)
-            ds.append(u.reshape(-1)[receivers])
+        B = torch.stack([hs.rhs(sources[s].contiguous()) for s in range(sources.shape[0])])
+        U, its, rrs = hs.solve_batch(B, tol=tol, maxit=500)
         ctx.hs = hs
         ctx.tol = tol
         ctx.receivers = receivers
-        ctx.save_for_backward(*us)
-        return torch.stack(ds)
+        ctx.save_for_backward(U)
+        return U.reshape(U.shape[0], -1)[:, receivers]
 
     @staticmethod
     def backward(ctx, grad_d):
         hs = ctx.hs
-        us = ctx.saved_tensors
+        (U,) = ctx.saved_tensors
+        ns = U.shape[0]
         g = torch.zeros(hs.n_fine, dtype=torch.float64, device=grad_d.device)
-        for s, u in enumerate(us):
-            rt = torch.zeros(hs.n_fine, dtype=torch.complex128, device=grad_d.device)
-            rt.view(-1)[ctx.receivers] = grad_d[s].to(torch.complex128)
-            lam, it, rr = hs.solve(rt, tol=ctx.tol, maxit=500, conj_transpose=True)
-            hs.gradient_accumulate(u, lam, g)
+        RT = torch.zeros((ns,) + tuple(hs.n_fine), dtype=torch.complex128, device=grad_d.device)
+        RT.view(ns, -1)[:, ctx.receivers] = grad_d.to(torch.complex128)
+        LAM, its, rrs = hs.solve_batch(RT, tol=ctx.tol, maxit=500, conj_transpose=True)
+        for s in range(ns):
+            hs.gradient_accumulate(U[s], LAM[s], g)
         return g, None, None, None, None, None, None, None, None, None
 
 
