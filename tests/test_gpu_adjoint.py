@@ -1,7 +1,5 @@
 """GPU adjoint gradient (torch.autograd.Function over the library) against
 the oracle's adjoint and against central finite differences."""
-import os
-
 import numpy as np
 import pytest
 
@@ -72,12 +70,7 @@ def test_gradient_central_differences_small():
         assert abs(fd - g.ravel()[c]) <= 1e-5 * np.abs(g).max()
 
 
-@pytest.mark.parametrize("ncells", [
-    4,
-    pytest.param(32, marks=pytest.mark.skipif(not os.environ.get("HSP_SLOW_GPU_TESTS"),
-                                               reason="about 9 minutes; set HSP_SLOW_GPU_TESTS=1")),
-])
-def test_config5_full_size(ncells):
+def test_config5_full_size(ncells=32):
     """511^2 + 12 PML, 16 sources, 511 receivers, two-grid J = 16: the GPU
     gradient against the oracle's adjoint (direct solves) and against central
     differences (step 1e-6) at random cells (32 cells in the long variant)."""
