@@ -1,7 +1,8 @@
 // Compact-stencil Helmholtz operator kernels: apply, residual and the
 // omega-Jacobi smoothing step (Sec. 4: V-cycle with omega-Jacobi smoothers).
 // One thread per unknown node; the fastest grid axis (y) maps to threadIdx.x
-// so that the loads of x along y are coalesced.
+// so that the loads of x along y are coalesced.  One kernel per operator
+// kind.
 #include "internal.h"
 
 namespace hsp {
@@ -13,38 +14,18 @@ __device__ __forceinline__ cx<Ta> ld(const cx<Tx>* v, size_t i) {
   return cvt<Ta>(v[i]);
 }
 
-template <class Ta, class Tx, class Tb, class Ty>
-__global__ void __launch_bounds__(256) k_stencil(LevelDev L, int mode, const cx<Tx>* __restrict__ x,
-                                                 const cx<Tb>* __restrict__ b, cx<Ty>* __restrict__ y,
-                                                 double w, BIdx bx, BIdx bb, BIdx by) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;  // y node 1..n2
-  const int i = blockIdx.y + 1;                             // x node 1..n1
-  const int n1 = L.n1, n2 = L.n2;
-  if (k > n2) return;
-  // vector z of a batch (blockIdx.z)
-  const int z = blockIdx.z;
-  if (x != nullptr) x += bx.off(z);
-  if (b != nullptr) b += bb.off(z);
-  y += by.off(z);
-  cd c[3][3];
-  stencil_coefs(L, i, k, c);
-  const size_t id = (size_t)(i - 1) * n2 + (k - 1);
-  cx<Ta> ax = mk<Ta>(0, 0);
-  if (x != nullptr) {
-#pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const int ii = i + di;
-      if (ii < 1 || ii > n1) continue;
-#pragma unroll
-      for (int dk = -1; dk <= 1; ++dk) {
-        const int kk = k + dk;
-        if (kk < 1 || kk > n2) continue;
-        const cd cc = c[di + 1][dk + 1];
-        if (cc.re == 0.0 && cc.im == 0.0) continue;
-        cfma(ax, cvt<Ta>(cc), ld<Ta>(x, (size_t)(ii - 1) * n2 + (kk - 1)));
-      }
-    }
-  }
+// Loads are unconditional, from clamped (valid) addresses, and neighbours
+// outside the grid are masked by a zero coefficient afterwards: a load inside
+// a branch would make the compiler wait for it before the join.
+
+// v where ok, else 0, component by component (a select of the whole struct
+// would be lowered through private memory).
+__device__ __forceinline__ cd keep(bool ok, cd v) { return mk<double>(ok ? v.re : 0.0, ok ? v.im : 0.0); }
+
+// The output stage shared by both kinds: ax = (A x)_id.
+template <class Ta, class Tb, class Ty>
+__device__ __forceinline__ void stencil_out(int mode, cx<Ta> ax, cx<Ta> xc, bool has_x, const cx<Tb>* b, size_t id,
+                                            cd c11, double w, cx<Ty>* y) {
   if (mode == 0) {
     y[id] = cvt<Ty>(ax);
     return;
@@ -55,10 +36,101 @@ __global__ void __launch_bounds__(256) k_stencil(LevelDev L, int mode, const cx<
     return;
   }
   // Jacobi: x + w D^{-1} r
-  const cx<Ta> dinv = cvt<Ta>(cinv(c[1][1]));
-  cx<Ta> out = (x != nullptr) ? ld<Ta>(x, id) : mk<Ta>(0, 0);
+  const cx<Ta> dinv = cvt<Ta>(cinv(c11));
+  cx<Ta> out = mk<Ta>(has_x ? xc.re : Ta(0), has_x ? xc.im : Ta(0));
   cfma(out, cvt<Ta>(mk<double>(w, 0.0)) * dinv, r);
   y[id] = cvt<Ty>(out);
+}
+
+// 5-point kind (eq. define_pml_fd): coefficients from the per-axis arrays and
+// k^2 (the arithmetic of stencil_coefs, kind 5), neighbours in the order
+// west, south, centre, north, east.
+template <class Ta, class Tx, class Tb, class Ty>
+__global__ void __launch_bounds__(256) k_stencil5(LevelDev L, int mode, const cx<Tx>* __restrict__ x,
+                                                  const cx<Tb>* __restrict__ b, cx<Ty>* __restrict__ y,
+                                                  double w, BIdx bx, BIdx bb, BIdx by) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;  // y node 1..n2
+  const int i = blockIdx.y + 1;                             // x node 1..n1
+  const int n1 = L.n1, n2 = L.n2;
+  if (k > n2) return;
+  const int z = blockIdx.z;
+  const bool has_x = x != nullptr;
+  if (has_x) x += bx.off(z);
+  if (b != nullptr) b += bb.off(z);
+  y += by.off(z);
+  const size_t id = (size_t)(i - 1) * n2 + (k - 1);
+  cx<Ta> xw = mk<Ta>(0, 0), xs = xw, xc = xw, xn = xw, xe = xw;
+  if (has_x) {
+    const size_t iw = i > 1 ? id - n2 : id, ie = i < n1 ? id + n2 : id;
+    const size_t is = k > 1 ? id - 1 : id, in = k < n2 ? id + 1 : id;
+    xw = ld<Ta>(x, iw);
+    xs = ld<Ta>(x, is);
+    xc = ld<Ta>(x, id);
+    xn = ld<Ta>(x, in);
+    xe = ld<Ta>(x, ie);
+  }
+  const int row = L.xmap ? L.xmap[i - 1] : (i - 1);
+  const double k2 = L.k2[(size_t)row * n2 + (k - 1)];
+  const cd ian = L.xB[i], ikn = L.yB[k];
+  cd cw = -(L.xA[i - 1] * ikn), ce = -(L.xA[i] * ikn);
+  cd cs = -(L.yA[k - 1] * ian), cn = -(L.yA[k] * ian);
+  const cd c11 = -(cw + ce + cs + cn) - (L.h2 * k2) * (ian * ikn);
+  cw = keep(i > 1, cw);
+  ce = keep(i < n1, ce);
+  cs = keep(k > 1, cs);
+  cn = keep(k < n2, cn);
+  cx<Ta> ax = mk<Ta>(0, 0);
+  if (has_x) {
+    cfma(ax, cvt<Ta>(cw), xw);
+    cfma(ax, cvt<Ta>(cs), xs);
+    cfma(ax, cvt<Ta>(c11), xc);
+    cfma(ax, cvt<Ta>(cn), xn);
+    cfma(ax, cvt<Ta>(ce), xe);
+  }
+  stencil_out<Ta, Tb, Ty>(mode, ax, xc, has_x, b, id, c11, w, y);
+}
+
+// 9-point finite-element kind (App. A): stencil_coefs, all nine neighbours
+// loaded from clamped addresses.
+template <class Ta, class Tx, class Tb, class Ty>
+__global__ void __launch_bounds__(256) k_stencil9(LevelDev L, int mode, const cx<Tx>* __restrict__ x,
+                                                  const cx<Tb>* __restrict__ b, cx<Ty>* __restrict__ y,
+                                                  double w, BIdx bx, BIdx bb, BIdx by) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;  // y node 1..n2
+  const int i = blockIdx.y + 1;                             // x node 1..n1
+  const int n1 = L.n1, n2 = L.n2;
+  if (k > n2) return;
+  const int z = blockIdx.z;
+  const bool has_x = x != nullptr;
+  if (has_x) x += bx.off(z);
+  if (b != nullptr) b += bb.off(z);
+  y += by.off(z);
+  const size_t id = (size_t)(i - 1) * n2 + (k - 1);
+  cx<Ta> xv[3][3];
+#pragma unroll
+  for (int di = -1; di <= 1; ++di)
+#pragma unroll
+    for (int dk = -1; dk <= 1; ++dk) {
+      int ii = i + di, kk = k + dk;
+      ii = ii < 1 ? 1 : (ii > n1 ? n1 : ii);
+      kk = kk < 1 ? 1 : (kk > n2 ? n2 : kk);
+      xv[di + 1][dk + 1] = mk<Ta>(0, 0);
+      if (has_x) xv[di + 1][dk + 1] = ld<Ta>(x, (size_t)(ii - 1) * n2 + (kk - 1));
+    }
+  cd c[3][3];
+  stencil_coefs(L, i, k, c);
+  cx<Ta> ax = mk<Ta>(0, 0);
+#pragma unroll
+  for (int di = -1; di <= 1; ++di) {
+    const bool okx = i + di >= 1 && i + di <= n1;
+#pragma unroll
+    for (int dk = -1; dk <= 1; ++dk) {
+      const bool ok = okx && k + dk >= 1 && k + dk <= n2;
+      const cd cc = keep(ok, c[di + 1][dk + 1]);
+      cfma(ax, cvt<Ta>(cc), xv[di + 1][dk + 1]);
+    }
+  }
+  stencil_out<Ta, Tb, Ty>(mode, ax, xv[1][1], has_x, b, id, c[1][1], w, y);
 }
 
 }  // namespace
@@ -69,7 +141,10 @@ void launch_stencil(const LevelDev& L, int mode, const cx<Tx>* x, const cx<Tb>* 
   if (nb < 1) return;
   dim3 blk(256);
   dim3 grd((L.n2 + 255) / 256, L.n1, nb);
-  hipLaunchKernelGGL((k_stencil<Ta, Tx, Tb, Ty>), grd, blk, 0, s, L, mode, x, b, y, w, bx, bb, by);
+  if (L.kind == 5)
+    hipLaunchKernelGGL((k_stencil5<Ta, Tx, Tb, Ty>), grd, blk, 0, s, L, mode, x, b, y, w, bx, bb, by);
+  else
+    hipLaunchKernelGGL((k_stencil9<Ta, Tx, Tb, Ty>), grd, blk, 0, s, L, mode, x, b, y, w, bx, bb, by);
 }
 
 #define INST(Ta, Tx, Tb, Ty) \

@@ -17,19 +17,27 @@ __global__ void __launch_bounds__(256) k_restrict(TransferDev T, const cx<Tin>* 
   if (K >= T.nc2) return;
   rf += bi.off(blockIdx.z);
   rc += bo.off(blockIdx.z);
-  cd acc = mk<double>(0, 0);
+  // all taps loaded unconditionally: a missing tap (index -1) has weight 0
+  // and reads row / column 0 instead
+  int fi[3], fk[3];
+  double wi[3], wk[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int fi = T.rx[3 * I + a];
-    if (fi < 0) continue;
-    const double wa = T.rwx[3 * I + a];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int fk = T.ry[3 * K + b];
-      if (fk < 0) continue;
-      acc += (wa * T.rwy[3 * K + b]) * cvt<double>(rf[(size_t)fi * T.nf2 + fk]);
-    }
+    fi[a] = max(T.rx[3 * I + a], 0);
+    wi[a] = T.rwx[3 * I + a];
+    fk[a] = max(T.ry[3 * K + a], 0);
+    wk[a] = T.rwy[3 * K + a];
   }
+  cx<Tin> v[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) v[a][b] = rf[(size_t)fi[a] * T.nf2 + fk[b]];
+  cd acc = mk<double>(0, 0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) acc += (wi[a] * wk[b]) * cvt<double>(v[a][b]);
   rc[(size_t)I * T.nc2 + K] = cvt<Tout>(acc);
 }
 
@@ -41,21 +49,30 @@ __global__ void __launch_bounds__(256) k_prolong_add(TransferDev T, const cx<Tc>
   if (k >= T.nf2) return;
   ec += bi.off(blockIdx.z);
   xf += bo.off(blockIdx.z);
-  cd acc = mk<double>(0, 0);
+  // all taps loaded unconditionally: a missing tap (index -1) has weight 0
+  // and reads row / column 0 instead
+  int ci[2], ck[2];
+  double wi[2], wk[2];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
-    const int ci = T.px[2 * i + a];
-    if (ci < 0) continue;
-    const double wa = T.pwx[2 * i + a];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int ck = T.py[2 * k + b];
-      if (ck < 0) continue;
-      acc += (wa * T.pwy[2 * k + b]) * cvt<double>(ec[(size_t)ci * T.nc2 + ck]);
-    }
+    ci[a] = max(T.px[2 * i + a], 0);
+    wi[a] = T.pwx[2 * i + a];
+    ck[a] = max(T.py[2 * k + a], 0);
+    wk[a] = T.pwy[2 * k + a];
   }
   const size_t id = (size_t)i * T.nf2 + k;
-  xf[id] = cvt<Tf>(cvt<double>(xf[id]) + acc);
+  cx<Tc> v[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) v[a][b] = ec[(size_t)ci[a] * T.nc2 + ck[b]];
+  const cx<Tf> x0 = xf[id];
+  cd acc = mk<double>(0, 0);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc += (wi[a] * wk[b]) * cvt<double>(v[a][b]);
+  xf[id] = cvt<Tf>(cvt<double>(x0) + acc);
 }
 
 }  // namespace
