@@ -8,7 +8,7 @@ fine level, optimized 9-point FE coarse level, X-sweep over J = 32 slabs,
 w_dd = 4, nu = 3, omega_jac = 0.8) inside FGMRES, point source at the centre,
 solved to a 1e-6 relative residual.
 
-One step = one complete batched solve: 32 point sources at seeded random
+One step = one complete batched solve: 64 point sources at seeded random
 interior positions on that medium, every one solved to 1e-6 by its own FGMRES
 process (FGMRES + every preconditioner application), with the medium,
 factors and right-hand sides resident in HBM.  The metric is
@@ -223,7 +223,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--sources", type=int, default=32, help="right-hand sides of the batched solve")
+    ap.add_argument("--sources", type=int, default=64, help="right-hand sides of the batched solve")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-single", action="store_true", help="skip the single-source mixed run")

@@ -80,7 +80,7 @@ typedef struct hsp_options {
                        residual and the restriction / prolongation complex128 */
   int restart;      /* FGMRES restart length (sizes the workspace)            */
   int chunk;        /* blocks per chunk of the parallel slab substitutions
-                       (1..64); 0 selects about sqrt(2 n_t) for n_t tangential
+                       (1..64); 0 selects about sqrt(n_t) for n_t tangential
                        nodes.  Changes the evaluation order only.             */
 } hsp_options;
 

@@ -294,8 +294,8 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
   if (P == 1) return;
   if (!last_arrival(counters + 2 * slot, P)) return;
   // true chunk-end values: tip_q = raw_q + Y_{e_q - 1} tip_{q-1}
-  bchain<T, NB, RB, D, false>(F.Y + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0, 1, P - 1, nl,
-                              T(1), q, ps);
+  bchain<T, NB, RB, D, false>(F.Y + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0, 1, P - 1,
+                                  nl, T(1), q, ps);
 }
 
 template <class T, int NB, int RB, int D>
@@ -425,7 +425,7 @@ void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launc
     hipLaunchKernelGGL((k_bstage_mid<T, NB, RB, D>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);      \
     hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);         \
   } while (0)
-  constexpr int D32 = sizeof(T) == 4 ? 4 : 2;
+  constexpr int D32 = sizeof(T) == 4 ? 2 : 2;
   constexpr int D64 = sizeof(T) == 4 ? 2 : 1;
 #define BRB(NB, D)                      \
   do {                                  \

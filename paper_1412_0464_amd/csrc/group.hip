@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.h"
@@ -261,6 +262,17 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     const int nu = C->opt.nu;
     cx<T>* xa = mptr<cx<T>>(mb, B.o_xa);
     cx<T>* xb = mptr<cx<T>>(mb, B.o_xb);
+    if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
+      cd* res = mptr<cd>(mb, B.o_res);
+      prof_begin(C, HSP_PROF_SMOOTH, s);
+      launch_smooth_pre(C->fine, nu, wj, io[p].r, io[p].br, reinterpret_cast<cf*>(xa), bf, res, bf, na, s);
+      prof_end(C, HSP_PROF_SMOOTH, s, (double)na * nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)));
+      prof_begin(C, HSP_PROF_TRANSFER, s);
+      launch_restrict<double, T>(C->tr, res, mptr<cx<T>>(mb, B.o_rc), s, na, bf, bdd);
+      prof_end(C, HSP_PROF_TRANSFER, s, (double)na * ((double)nf * sizeof(cd) + (double)nd * sizeof(cx<T>)));
+      launch_zero<T>(mptr<cx<T>>(mb, B.o_ec), (size_t)na * nd, s);
+      continue;
+    }
     const double jb = (double)na * nf * (sizeof(cd) + 2.0 * sizeof(cx<T>) + sizeof(double));
     prof_begin(C, HSP_PROF_SMOOTH, s);
     if (nu > 0) {
@@ -334,6 +346,15 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     const int nu = C->opt.nu;
     cx<T>* xa = mptr<cx<T>>(mb, B.o_xa);
     cx<T>* xb = mptr<cx<T>>(mb, B.o_xb);
+    if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
+      prof_begin(C, HSP_PROF_SMOOTH, s);
+      launch_smooth_post(C->fine, C->tr, nu, wj, io[p].r, io[p].br, reinterpret_cast<const cf*>(xa), bf,
+                         reinterpret_cast<const cf*>(mptr<cx<T>>(mb, B.o_ec)), bdd, io[p].z, io[p].bz, na, s);
+      prof_end(C, HSP_PROF_SMOOTH, s,
+               (double)na * ((double)nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)) +
+                             (double)nd * sizeof(cx<T>)));
+      continue;
+    }
     if (nu > 0 && nu % 2 == 0) std::swap(xa, xb);  // where the pre-smoothing ended
     prof_begin(C, HSP_PROF_TRANSFER, s);
     launch_prolong_add<T, T>(C->tr, mptr<cx<T>>(mb, B.o_ec), xa, s, na, bdd, bf);

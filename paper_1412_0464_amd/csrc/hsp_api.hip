@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.h"
@@ -155,7 +156,9 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   if (o->chunk > 0) {
     P.chunk = o->chunk;
   } else {
-    P.chunk = (int)std::ceil(std::sqrt(2.0 * P.dd_n2));
+    // about sqrt(n2): balances the chunk-local chains (m steps) against the
+    // chains over the chunk ends (P - 1 steps)
+    P.chunk = (int)std::ceil(std::sqrt((double)P.dd_n2));
     P.chunk = std::max(8, std::min(kMaxChunk, P.chunk));
   }
   P.chunk = std::min(P.chunk, P.dd_n2);
@@ -432,6 +435,27 @@ void run_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
   cx<T>* xa = C->at<T>(P.o_tgx0);
   cx<T>* xb = C->at<T>(P.o_tgx1);
   const size_t nc = (size_t)P.nc1 * P.nc2;
+  if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
+    // each smoothing phase as one kernel (LDS tiles with a halo of nu nodes)
+    cd* res = C->at<double>(P.o_tgres);
+    cx<T>* rc = C->at<T>(P.o_tgrc);
+    cx<T>* ec = C->at<T>(P.o_tgec);
+    prof_begin(C, HSP_PROF_SMOOTH, s);
+    launch_smooth_pre(C->fine, nu, wj, r, BIdx{}, reinterpret_cast<cf*>(xa), BIdx{}, res, BIdx{}, 1, s);
+    // r, k^2 read; x_nu and the residual written
+    prof_end(C, HSP_PROF_SMOOTH, s, (double)nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)));
+    prof_begin(C, HSP_PROF_TRANSFER, s);
+    launch_restrict<double, T>(C->tr, res, rc, s);
+    prof_end(C, HSP_PROF_TRANSFER, s, (double)nf * sizeof(cd) + (double)nc * sizeof(cx<T>));
+    run_sweep<T>(C, rc, ec, s);
+    prof_begin(C, HSP_PROF_SMOOTH, s);
+    launch_smooth_post(C->fine, C->tr, nu, wj, r, BIdx{}, reinterpret_cast<const cf*>(xa), BIdx{},
+                       reinterpret_cast<const cf*>(ec), BIdx{}, z, BIdx{}, 1, s);
+    // x, r, k^2 read, the coarse correction read, z written
+    prof_end(C, HSP_PROF_SMOOTH, s,
+             (double)nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)) + (double)nc * sizeof(cx<T>));
+    return;
+  }
   // bytes of one smoothing step: r, x read, x written, k^2 per node
   const double jb = (double)nf * (sizeof(cd) + 2.0 * sizeof(cx<T>) + sizeof(double));
   // pre-smoothing from x = 0

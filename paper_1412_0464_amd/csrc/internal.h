@@ -53,6 +53,16 @@ template <class Tc, class Tf>
 void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipStream_t s, int nb = 1,
                         BIdx bi = {}, BIdx bo = {});
 
+// ---- fused smoothing phases, complex64 smoother on a 5-point fine level ----
+// (smooth.hip)
+// pre:  xo = x_nu of nu Jacobi steps from 0, res = r - A x_nu (complex128)
+// post: x_0 = xin + P ec, nu Jacobi steps, zo = x_nu (complex128)
+bool smooth_fused_ok(const LevelDev& L, int nu);
+void launch_smooth_pre(const LevelDev& L, int nu, double w, const cd* r, BIdx br, cf* xo, BIdx bxo, cd* res,
+                       BIdx bres, int nb, hipStream_t s);
+void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cd* r, BIdx br,
+                        const cf* xin, BIdx bxin, const cf* ec, BIdx bec, cd* zo, BIdx bzo, int nb, hipStream_t s);
+
 // ---- slab factorization and sweep stages (slab.hip) ------------------------
 struct SlabDev {
   int x0;          // first global layer (1-based)

@@ -257,15 +257,6 @@ __device__ __forceinline__ void fetch_slice(const cx<T>* __restrict__ blk, int n
   }
 }
 
-// LDS ordering between the lanes of one wavefront: the LDS executes a
-// wave's instructions in order, so only the compiler must be kept from
-// reordering (wavefront-scope fences) - no s_barrier is needed.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Lane layout of the dependent chains (one wavefront): R row slots (32 when
 // the slab has <= 32 layers, else 64) times NG = 64 / R column groups; lane
 // (l, h) owns row l and columns [h CW, (h+1) CW) of every block.

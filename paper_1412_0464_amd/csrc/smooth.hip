@@ -1,0 +1,311 @@
+// Fused smoothing phases of the two-grid cycle (Sec. 4) on a 5-point fine
+// level: the nu omega-Jacobi steps of a phase run inside one kernel on an
+// LDS tile with a halo of nu nodes (each step shrinks the valid region by
+// one node), so the vectors cross HBM once per phase instead of once per
+// step.
+//
+//   pre:  x_1 = w D^{-1} r, x_{s+1} = x_s + w D^{-1} (r - A x_s), s < nu;
+//         outputs x_nu and the fine residual r - A x_nu (complex128);
+//   post: x_0 = x + P e_c (prolongation of the coarse correction), then nu
+//         steps; output x_nu in complex128.
+//
+// Complex64 smoother (the mixed-precision path): the coefficients are formed
+// in complex64 from complex64 row / column factors and k^2 (the diagonal and
+// w D^{-1} once per node, the off-diagonals per step); the residual and the
+// prolongation sums are in double, as in the separate kernels (stencil.hip,
+// transfer.hip).
+#include "internal.h"
+
+namespace hsp {
+
+namespace {
+
+constexpr int kTX = 16;  // tile rows (x)
+constexpr int kTY = 64;  // tile columns (y, the contiguous axis)
+
+// Extended tile (tile + halo of NU nodes) of the complex64 smoother.
+template <int NU>
+struct SmoothTile {
+  static constexpr int H = NU;
+  static constexpr int EX = kTX + 2 * H, EY = kTY + 2 * H, NE = EX * EY;
+};
+
+// Row / column factors of the off-diagonal coefficients, complex64:
+// west = -xA[i-1] yB[k], east = -xA[i] yB[k], south = -yA[k-1] xB[i],
+// north = -yA[k] xB[i]; zero toward a Dirichlet boundary.
+struct Axes5 {
+  cf rAm[kTX + 8], rAp[kTX + 8], rB[kTX + 8];
+  cf cAm[kTY + 8], cAp[kTY + 8], cB[kTY + 8];
+};
+
+__device__ __forceinline__ void load_axes(const LevelDev& L, int i0, int k0, int EX, int EY, Axes5& ax) {
+  for (int t = threadIdx.x; t < EX; t += blockDim.x) {
+    const int i = i0 + t;
+    const bool ok = i >= 1 && i <= L.n1;
+    const int ic = ok ? i : 1;
+    ax.rAm[t] = cvt<float>(L.xA[ic - 1]);
+    ax.rAp[t] = cvt<float>(L.xA[ic]);
+    ax.rB[t] = cvt<float>(L.xB[ic]);
+  }
+  for (int t = threadIdx.x; t < EY; t += blockDim.x) {
+    const int k = k0 + t;
+    const bool ok = k >= 1 && k <= L.n2;
+    const int kc = ok ? k : 1;
+    ax.cAm[t] = cvt<float>(L.yA[kc - 1]);
+    ax.cAp[t] = cvt<float>(L.yA[kc]);
+    ax.cB[t] = cvt<float>(L.yB[kc]);
+  }
+}
+
+__device__ __forceinline__ cf keepf(bool ok, cf v) { return mk<float>(ok ? v.re : 0.f, ok ? v.im : 0.f); }
+
+// A cur at tile node (ti, tk) with the diagonal c11 (complex64).
+template <int EY>
+__device__ __forceinline__ cf apply5(const Axes5& ax, const cf* cur, int e, int ti, int tk, cf c11, bool iw, bool ie,
+                                     bool ks, bool kn) {
+  const cf ian = ax.rB[ti], ikn = ax.cB[tk];
+  const cf cw = keepf(iw, -(ax.rAm[ti] * ikn)), ce = keepf(ie, -(ax.rAp[ti] * ikn));
+  const cf cs = keepf(ks, -(ax.cAm[tk] * ian)), cn = keepf(kn, -(ax.cAp[tk] * ian));
+  cf a = mk<float>(0, 0);
+  cfma(a, cw, cur[e - EY]);
+  cfma(a, cs, cur[e - 1]);
+  cfma(a, c11, cur[e]);
+  cfma(a, cn, cur[e + 1]);
+  cfma(a, ce, cur[e + EY]);
+  return a;
+}
+
+// One Jacobi step on the region of halo hs: nxt = cur + (w D^{-1}) (r - A cur).
+template <int NU>
+__device__ __forceinline__ void jacobi_region(const LevelDev& L, int i0, int k0, int hs, const cf* cur, cf* nxt,
+                                              const cf* rr, const cf* c11s, const cf* dws, const Axes5& ax) {
+  using S = SmoothTile<NU>;
+  const int RX = S::EX - 2 * hs, RY = S::EY - 2 * hs;
+  for (int idx = threadIdx.x; idx < RX * RY; idx += blockDim.x) {
+    const int ti = hs + idx / RY, tk = hs + idx % RY;
+    const int i = i0 + ti, k = k0 + tk;
+    const int e = ti * S::EY + tk;
+    const bool in = i >= 1 && i <= L.n1 && k >= 1 && k <= L.n2;
+    const cf a = apply5<S::EY>(ax, cur, e, ti, tk, c11s[e], i > 1, i < L.n1, k > 1, k < L.n2);
+    cf out = cur[e];
+    cfma(out, dws[e], rr[e] - a);
+    nxt[e] = keepf(in, out);
+  }
+}
+
+// Node data of the extended tile: r (complex64), the diagonal and w D^{-1}
+// (formed in complex64 from the row / column factors and k^2).  All global
+// loads of a thread are issued before any is used (one memory round trip for
+// the whole tile); the axes must already be in LDS.
+template <int NU>
+struct NodeLoads {
+  static constexpr int NI = (SmoothTile<NU>::NE + 255) / 256;
+  cd r[NI];
+  double k2[NI];
+};
+
+template <int NU>
+__device__ __forceinline__ void fetch_nodes(const LevelDev& L, int i0, int k0, const cd* r, NodeLoads<NU>& ld) {
+  using S = SmoothTile<NU>;
+#pragma unroll
+  for (int q = 0; q < NodeLoads<NU>::NI; ++q) {
+    const int idx = min((int)threadIdx.x + 256 * q, S::NE - 1);
+    const int i = i0 + idx / S::EY, k = k0 + idx % S::EY;
+    const bool in = i >= 1 && i <= L.n1 && k >= 1 && k <= L.n2;
+    const size_t g = in ? (size_t)(i - 1) * L.n2 + (k - 1) : 0;
+    ld.r[q] = r[g];
+    ld.k2[q] = L.k2[g];
+  }
+}
+
+template <int NU>
+__device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, double w, const NodeLoads<NU>& ld,
+                                            const Axes5& ax, cf* rr, cf* c11s, cf* dws) {
+  using S = SmoothTile<NU>;
+  const cf wt = cvt<float>(mk<double>(w, 0.0));
+  const float h2 = (float)L.h2;
+#pragma unroll
+  for (int q = 0; q < NodeLoads<NU>::NI; ++q) {
+    const int idx = (int)threadIdx.x + 256 * q;
+    if (idx >= S::NE) break;
+    const int ti = idx / S::EY, tk = idx % S::EY;
+    const int i = i0 + ti, k = k0 + tk;
+    const bool in = i >= 1 && i <= L.n1 && k >= 1 && k <= L.n2;
+    const cf ian = ax.rB[ti], ikn = ax.cB[tk];
+    const cf cw = -(ax.rAm[ti] * ikn), ce = -(ax.rAp[ti] * ikn);
+    const cf cs = -(ax.cAm[tk] * ian), cn = -(ax.cAp[tk] * ian);
+    const cf c11 = -(cw + ce + cs + cn) - (h2 * (float)ld.k2[q]) * (ian * ikn);
+    rr[idx] = keepf(in, cvt<float>(ld.r[q]));
+    c11s[idx] = c11;
+    dws[idx] = wt * cinv(c11);
+  }
+}
+
+template <int NU>
+__global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const cd* __restrict__ r, BIdx br,
+                                                    cf* __restrict__ xo, BIdx bxo, cd* __restrict__ res, BIdx bres) {
+  using S = SmoothTile<NU>;
+  constexpr int EY = S::EY, NE = S::NE, H = S::H;
+  __shared__ cf xa[NE], xb[NE], rr[NE], c11s[NE], dws[NE];
+  __shared__ Axes5 ax;
+  const int n1 = L.n1, n2 = L.n2;
+  const int i0 = blockIdx.y * kTX + 1 - H, k0 = blockIdx.x * kTY + 1 - H;
+  const int z = blockIdx.z;
+  r += br.off(z);
+  xo += bxo.off(z);
+  res += bres.off(z);
+  NodeLoads<NU> ld;
+  fetch_nodes<NU>(L, i0, k0, r, ld);
+  load_axes(L, i0, k0, S::EX, EY, ax);
+  __syncthreads();
+  store_nodes<NU>(L, i0, k0, w, ld, ax, rr, c11s, dws);
+  __syncthreads();
+  // x_1 = (w D^{-1}) r
+  for (int idx = threadIdx.x; idx < NE; idx += blockDim.x) {
+    cf out = mk<float>(0, 0);
+    cfma(out, dws[idx], rr[idx]);
+    xa[idx] = out;
+  }
+  __syncthreads();
+  cf* cur = xa;
+  cf* nxt = xb;
+  for (int s = 2; s <= NU; ++s) {
+    jacobi_region<NU>(L, i0, k0, s - 1, cur, nxt, rr, c11s, dws, ax);
+    __syncthreads();
+    cf* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  // x_nu and the residual r - A x_nu in double (stencil_coefs arithmetic)
+  for (int idx = threadIdx.x; idx < kTX * kTY; idx += blockDim.x) {
+    const int ti = H + idx / kTY, tk = H + idx % kTY;
+    const int i = i0 + ti, k = k0 + tk;
+    if (i > n1 || k > n2) continue;
+    const int e = ti * EY + tk;
+    const size_t g = (size_t)(i - 1) * n2 + (k - 1);
+    const cd ian = L.xB[i], ikn = L.yB[k];
+    cd cw = -(L.xA[i - 1] * ikn), ce = -(L.xA[i] * ikn);
+    cd cs = -(L.yA[k - 1] * ian), cn = -(L.yA[k] * ian);
+    const cd c11 = -(cw + ce + cs + cn) - (L.h2 * L.k2[g]) * (ian * ikn);
+    cd a = mk<double>(0, 0);
+    if (i > 1) cfma(a, cw, cvt<double>(cur[e - EY]));
+    if (k > 1) cfma(a, cs, cvt<double>(cur[e - 1]));
+    cfma(a, c11, cvt<double>(cur[e]));
+    if (k < n2) cfma(a, cn, cvt<double>(cur[e + 1]));
+    if (i < n1) cfma(a, ce, cvt<double>(cur[e + EY]));
+    xo[g] = cur[e];
+    res[g] = r[g] - a;
+  }
+}
+
+template <int NU>
+__global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr, double w, const cd* __restrict__ r,
+                                                     BIdx br, const cf* __restrict__ xin, BIdx bxin,
+                                                     const cf* __restrict__ ec, BIdx bec, cd* __restrict__ zo,
+                                                     BIdx bzo) {
+  using S = SmoothTile<NU>;
+  constexpr int EY = S::EY, NE = S::NE, H = S::H;
+  __shared__ cf xa[NE], xb[NE], rr[NE], c11s[NE], dws[NE];
+  __shared__ Axes5 ax;
+  const int n1 = L.n1, n2 = L.n2;
+  const int i0 = blockIdx.y * kTX + 1 - H, k0 = blockIdx.x * kTY + 1 - H;
+  const int z = blockIdx.z;
+  r += br.off(z);
+  xin += bxin.off(z);
+  ec += bec.off(z);
+  zo += bzo.off(z);
+  NodeLoads<NU> ld;
+  fetch_nodes<NU>(L, i0, k0, r, ld);
+  // x_0 = x + P e_c (prolongation sums in double, as k_prolong_add); the
+  // taps of all nodes of the thread are fetched first
+  constexpr int NI = NodeLoads<NU>::NI;
+  cf x0[NI], v[NI][2][2];
+  double wgt[NI][2][2];
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    const int idx = min((int)threadIdx.x + 256 * q, NE - 1);
+    const int i = i0 + idx / EY, k = k0 + idx % EY;
+    const bool in = i >= 1 && i <= n1 && k >= 1 && k <= n2;
+    const int ic = in ? i - 1 : 0, kc = in ? k - 1 : 0;  // 0-based fine indices
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int ci = max(Tr.px[2 * ic + a], 0), ck = max(Tr.py[2 * kc + b], 0);
+        wgt[q][a][b] = Tr.pwx[2 * ic + a] * Tr.pwy[2 * kc + b];
+        v[q][a][b] = ec[(size_t)ci * Tr.nc2 + ck];
+      }
+    x0[q] = xin[(size_t)ic * n2 + kc];
+  }
+  load_axes(L, i0, k0, S::EX, EY, ax);
+  __syncthreads();
+  store_nodes<NU>(L, i0, k0, w, ld, ax, rr, c11s, dws);
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    const int idx = (int)threadIdx.x + 256 * q;
+    if (idx >= NE) break;
+    const int i = i0 + idx / EY, k = k0 + idx % EY;
+    const bool in = i >= 1 && i <= n1 && k >= 1 && k <= n2;
+    cd acc = mk<double>(0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc += wgt[q][a][b] * cvt<double>(v[q][a][b]);
+    xa[idx] = keepf(in, cvt<float>(cvt<double>(x0[q]) + acc));
+  }
+  __syncthreads();
+  cf* cur = xa;
+  cf* nxt = xb;
+  for (int s = 1; s < NU; ++s) {
+    jacobi_region<NU>(L, i0, k0, s, cur, nxt, rr, c11s, dws, ax);
+    __syncthreads();
+    cf* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  // the last step on the tile, written in double
+  for (int idx = threadIdx.x; idx < kTX * kTY; idx += blockDim.x) {
+    const int ti = H + idx / kTY, tk = H + idx % kTY;
+    const int i = i0 + ti, k = k0 + tk;
+    if (i > n1 || k > n2) continue;
+    const int e = ti * EY + tk;
+    const cf a = apply5<EY>(ax, cur, e, ti, tk, c11s[e], i > 1, i < n1, k > 1, k < n2);
+    cf out = cur[e];
+    cfma(out, dws[e], rr[e] - a);
+    zo[(size_t)(i - 1) * n2 + (k - 1)] = cvt<double>(out);
+  }
+}
+
+}  // namespace
+
+bool smooth_fused_ok(const LevelDev& L, int nu) { return L.kind == 5 && L.xmap == nullptr && nu >= 1 && nu <= 3; }
+
+void launch_smooth_pre(const LevelDev& L, int nu, double w, const cd* r, BIdx br, cf* xo, BIdx bxo, cd* res,
+                       BIdx bres, int nb, hipStream_t s) {
+  if (nb < 1) return;
+  const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
+  switch (nu) {
+    case 1: hipLaunchKernelGGL((k_smooth_pre<1>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+    case 2: hipLaunchKernelGGL((k_smooth_pre<2>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+    default: hipLaunchKernelGGL((k_smooth_pre<3>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+  }
+}
+
+void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cd* r, BIdx br,
+                        const cf* xin, BIdx bxin, const cf* ec, BIdx bec, cd* zo, BIdx bzo, int nb, hipStream_t s) {
+  if (nb < 1) return;
+  const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
+  switch (nu) {
+    case 1:
+      hipLaunchKernelGGL((k_smooth_post<1>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_smooth_post<2>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      break;
+    default:
+      hipLaunchKernelGGL((k_smooth_post<3>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      break;
+  }
+}
+
+}  // namespace hsp

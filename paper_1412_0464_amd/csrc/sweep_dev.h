@@ -53,6 +53,15 @@ __device__ __forceinline__ cx<T> sel(bool ok, cx<T> v) {
   return mk<T>(ok ? v.re : T(0), ok ? v.im : T(0));
 }
 
+// LDS ordering between the lanes of one wavefront: the LDS executes a
+// wave's instructions in order, so only the compiler must be kept from
+// reordering (wavefront-scope fences) - no s_barrier is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The last workgroup of a (chunk-parallel) launch to arrive continues with
 // the chain over the chunk ends.  Release the block's results device-wide,
 // count arrivals, and make the other blocks' results visible to the last.

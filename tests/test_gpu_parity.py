@@ -266,3 +266,26 @@ def test_config1_end_to_end():
     u, it, rr = hs.solve(hs.rhs(_t(f)), tol=1e-6)
     assert it == ito and rr <= 1e-6
     assert _relerr(u.cpu().numpy(), uo) < 1e-6
+
+
+@pytest.mark.parametrize("fine,nu,precision,tol", [
+    ("fd5", 1, "fp64", 1e-10), ("fd5", 2, "mixed", 2e-5), ("fd5", 4, "fp64", 1e-10), ("fe9", 3, "mixed", 2e-5)])
+def test_precond_smoothing_variants(fine, nu, precision, tol):
+    """Two-grid preconditioner with 1, 2 or 4 smoothing steps and with the
+    9-point fine operator (fused single-kernel smoothing phases for the
+    5-point fine level with nu <= 3, step-by-step kernels otherwise)."""
+    n1, n2, w, J = 79, 63, 8, 3
+    c = extend_into_pml(layered_medium_2d(n1, n2, 1412046, n_layers=7, corr_len=6.0), w)
+    h = 0.02
+    om = 2 * np.pi * 1.5 / (8.0 * h)
+    print(f"[smoothing variant fine={fine} nu={nu} {precision}]", flush=True)
+    ref = Problem2D(c, om, h, w, S_outer=5.0 * w, J=J, w_dd=4, fine=fine, two_grid=True, nu=nu)
+    from paper_1412_0464_amd import Helmholtz
+    hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, J, S_outer=5.0 * w,
+                   fine_stencil=5 if fine == "fd5" else 9, two_grid=True, nu=nu, precision=precision)
+    r = _rand(c.shape, 70 + nu)
+    assert _relerr(hs.apply_precond(_t(r)).cpu().numpy(), ref.precond(r.ravel())) < tol
+    R = np.stack([_rand(c.shape, 80 + j) for j in range(3)])
+    Z = hs.apply_precond_batch(_t(R), tile=2).cpu().numpy()
+    for j in range(3):
+        assert _relerr(Z[j], ref.precond(R[j].ravel())) < tol
