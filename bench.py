@@ -32,9 +32,97 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+# HBM traffic of the batched stage kernels, measured with rocprofv3 counters
+# (FETCH_SIZE and WRITE_SIZE runs, scaled by the same counters on a copy of
+# known size); valid only for the kernel sources it was taken on
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_bstage_layered1023_64src.md")
+STAGE_SOURCES = ["batch.hip", "sweep_dev.h", "internal.h", "common.h"]
+COPY_BYTES = 256 << 20
+
 METRIC = "dof·iter/s and solve time to 1e-6 rel. residual: FP32-batched vs plain FP64"
 UNIT = "dof·iter/s"
 HBM_PEAK_GBS = 8000.0
+
+
+def stage_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_0464_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(tile, nsrc):
+    """Measured HBM bytes per batched stage from the counter record, or None
+    when there is none for this tile and batch size or the stage kernels
+    changed since it was taken."""
+    import re
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            txt = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"traffic-record: bytes_per_stage=(\S+) tile=(\d+) sources=(\d+) digest=(\w+)", txt)
+    if not m or int(m.group(2)) != tile or int(m.group(3)) != nsrc or m.group(4) != stage_sources_digest():
+        return None
+    return float(m.group(1))
+
+
+def copy_calibration():
+    """A plain streaming kernel of known size (torch's elementwise negation
+    of COPY_BYTES of float32: reads and writes COPY_BYTES each), run three
+    times so that counter runs can scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: 3 x neg over {COPY_BYTES} bytes", file=sys.stderr, flush=True)
+
+
+def reduce_counters(fetch_csv, write_csv, tile, nsrc):
+    """Per-kernel averages of the rocprofv3 counter files of a FETCH_SIZE run
+    and a WRITE_SIZE run (KiB per dispatch), the copy scale factors, and the
+    traffic record of the batched stage for ``tile``."""
+    import csv
+    import re
+    from collections import defaultdict
+
+    def load_csv(path):
+        tot, disp = defaultdict(float), defaultdict(set)
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                name = row["Kernel_Name"]
+                tot[name] += float(row["Counter_Value"])
+                disp[name].add(row["Dispatch_Id"])
+        return {k: (len(disp[k]), tot[k]) for k in tot}
+
+    out = {}
+    for label, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        d = load_csv(path)
+        print(f"{label} (KiB per dispatch)")
+        for k, (n, v) in sorted(d.items(), key=lambda kv: -kv[1][1])[:14]:
+            print(f"  {n:7d} x {v / n:14.1f}  {k[:110]}")
+        copy = [(n, v) for k, (n, v) in d.items() if "neg_kernel" in k]
+        if not copy:
+            raise SystemExit(f"{path}: no copy calibration kernel")
+        copy_kib = copy[0][1] / copy[0][0]
+        scale = (COPY_BYTES / 1024) / copy_kib
+        stage_kib, stages = 0.0, 0
+        for k, (n, v) in d.items():
+            m = re.search(r"k_bstage_(fwd|mid|bwd)<float, (\d+), (\d+)", k)
+            if m and int(m.group(3)) == tile:
+                stage_kib += v
+                if m.group(1) == "fwd":
+                    stages += n
+        print(f"  copy: {copy_kib:.1f} KiB per dispatch for {COPY_BYTES // 1024} KiB -> scale {scale:.4f}")
+        print(f"  stage (tile {tile}): {stages} stages, {stage_kib / max(stages, 1):.1f} KiB per stage raw")
+        out[label] = stage_kib / max(stages, 1) * 1024 * scale
+    tot = out["FETCH_SIZE"] + out["WRITE_SIZE"]
+    print(f"fetch {out['FETCH_SIZE']:.4e} B + write {out['WRITE_SIZE']:.4e} B per stage (scaled)")
+    print(f"traffic-record: bytes_per_stage={tot:.5e} tile={tile} sources={nsrc} digest={stage_sources_digest()}")
 
 
 def config(name):
@@ -71,9 +159,9 @@ def sources(cfg, shape, nsrc, seed=1412048):
     return out
 
 
-def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile=False):
-    """Setup once, tune the right-hand-side tile, then time ``steps``
-    batched solves of all sources after ``warmup`` ones."""
+def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile=False, tile=0):
+    """Setup once, tune the right-hand-side tile (unless ``tile`` fixes it),
+    then time ``steps`` batched solves of all sources after ``warmup`` ones."""
     import torch
     from paper_1412_0464_amd import Helmholtz
     dev = torch.device("cuda:0")
@@ -86,9 +174,12 @@ def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile
     setup_s = time.perf_counter() - t0
     B = torch.stack([hs.rhs(torch.tensor(f, dtype=torch.complex128, device=dev)) for f in fs])
     U = torch.empty_like(B)
-    tile, tile_ms = hs.tune_batch(len(fs), restart)
+    if tile:
+        tile_ms = None
+    else:
+        tile, tile_ms = hs.tune_batch(len(fs), restart)
     for _ in range(warmup):
-        hs.solve_batch(B, tol=tol, maxit=200, restart=restart, out=U)
+        hs.solve_batch(B, tol=tol, maxit=200, restart=restart, tile=tile, out=U)
     torch.cuda.synchronize()
     if profile:
         hs.profile(True)
@@ -97,7 +188,7 @@ def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile
     tot = 0
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, its, rrs = hs.solve_batch(B, tol=tol, maxit=200, restart=restart, out=U)
+        _, its, rrs = hs.solve_batch(B, tol=tol, maxit=200, restart=restart, tile=tile, out=U)
         tot += sum(its)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -231,7 +322,15 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--c3", action="store_true", help="also time the batched multi-frequency group workload")
     ap.add_argument("--c3-sources", type=int, default=64)
+    ap.add_argument("--tile", type=int, default=0, help="right-hand-side tile (0: tuned)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a streaming kernel of known size (for counter scaling)")
+    ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise rocprofv3 counter files of the batched stage and exit (no GPU)")
     args = ap.parse_args()
+    if args.reduce_counters:
+        reduce_counters(*args.reduce_counters, tile=args.tile or 4, nsrc=args.sources)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not a measured path", file=sys.stderr)
@@ -244,7 +343,9 @@ def main():
     print(f"[bench] {cfg['workload']}: {dof} interior dof, {c.size} unknowns, {len(fs)} sources",
           file=sys.stderr, flush=True)
 
-    bat = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, profile=True)
+    if args.copy_calibration:
+        copy_calibration()
+    bat = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, profile=True, tile=args.tile)
     its = bat["iters"]
     print(f"[bench] batched mixed: setup {bat['setup_s']:.3f} s, tile {bat['tile']}, solve {bat['solve_s'] * 1e3:.1f} ms "
           f"for {len(fs)} sources, iterations {min(its)}..{max(its)}, max relres {max(bat['relres']):.2e}",
@@ -270,12 +371,12 @@ def main():
     per_launch_s = st_ms * 1e-3 / max(st_n, 1)
     achieved = per_launch_bytes / per_launch_s / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(bat["tile"], len(fs)),
                        "kernel": "batched SubdomSolve stage (k_bstage_fwd + k_bstage_mid + k_bstage_bwd)",
                        "launches": st_n, "avg_launch_us": per_launch_s * 1e6,
                        "alg_bytes_per_launch": per_launch_bytes}
     out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
-    Ub = bat["U"].cpu().numpy()
+    Ub = None if args.no_fp64 else bat["U"][0].cpu().numpy()
     del bat
     if not args.no_fp64:
         fp = gpu_run(cfg, c, fs[0], "fp64", args.steps, args.warmup, args.tol)
@@ -284,7 +385,7 @@ def main():
         uf = fp["u"].cpu().numpy()
         out["fp64"] = {"value": dof * fp["total_iters"] / fp["time_s"], "solve_s": fp["solve_s"],
                        "setup_s": fp["setup_s"], "iterations": fp["iters"], "relres": fp["relres"],
-                       "batched_mixed_vs_fp64_rel_l2_source0": float(np.linalg.norm(Ub[0] - uf) / np.linalg.norm(uf)),
+                       "batched_mixed_vs_fp64_rel_l2_source0": float(np.linalg.norm(Ub - uf) / np.linalg.norm(uf)),
                        "speedup_batched_mixed_over_fp64_per_source":
                            fp["solve_s"] / out["config"]["solve_s_per_source"]}
         del fp
