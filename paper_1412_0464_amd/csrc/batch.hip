@@ -23,6 +23,35 @@ namespace hsp {
 
 namespace {
 
+// Pointers taken from the segment table are generic (flat) to the compiler;
+// flat loads count against the LDS wait counter too, so every LDS wait of a
+// chain step would also wait for the loads prefetched for later steps.
+// Casting them to the global address space keeps the two counters apart.
+// (The host pass of the same source only parses the kernels; there the
+// qualifier is left out.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GAS __attribute__((address_space(1)))
+#define CAS __attribute__((address_space(4)))
+#else
+#define GAS
+#define CAS
+#endif
+template <class X>
+__device__ __forceinline__ GAS X* gp(X* p) {
+  return (GAS X*)p;
+}
+template <class X>
+__device__ __forceinline__ const GAS X* gp(const X* p) {
+  return (const GAS X*)p;
+}
+// Task and slab descriptors are read-only for the whole launch and the same
+// for every thread of a workgroup: read them as constants (scalar loads, so
+// that the index arithmetic derived from them stays scalar).
+template <class X>
+__device__ __forceinline__ X cload(const X* p, int i) {
+  return ((const CAS X*)p)[i];
+}
+
 // Thread layout of a 256-thread workgroup for slabs of up to NB layers.
 // Product phase: thread (l, g), l = tid % NB, owns row l and the CW columns
 // [g CW, (g+1) CW) of a block.  Reduction phase: thread (l, g) owns row l of
@@ -55,9 +84,9 @@ __device__ __forceinline__ cx<T> shfl_down1(cx<T> v, int width) {
 // loads are unconditional from clamped addresses.  LDS: q [NB][RB] holds the
 // product input, ps [NG][RB][NB] the partial products.
 template <class T, int NB, int RB, int D, bool GD>
-__device__ __forceinline__ void bchain(const cx<T>* __restrict__ mat, long mstride, const cx<T>* __restrict__ cpl,
-                                       cx<T>* rows, int first, int dir, int count, int nl, T sigma, cx<T>* q,
-                                       cx<T>* ps) {
+__device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long mstride,
+                                       const GAS cx<T>* __restrict__ cpl, GAS cx<T>* rows, int first, int dir,
+                                       int count, int nl, T sigma, cx<T>* q, cx<T>* ps) {
   using LY = BLay<NB, RB>;
   constexpr int NG = LY::NG, CW = LY::CW, RC = LY::RC;
   if (count <= 0) return;
@@ -77,7 +106,7 @@ __device__ __forceinline__ void bchain(const cx<T>* __restrict__ mat, long mstri
 #define BCH_FETCH(kk, d)                                                                         \
   {                                                                                              \
     const int kc = (kk) < count ? (kk) : count - 1;                                              \
-    const cx<T>* Mk = mat + (long)(first + dir * kc) * mstride;                                  \
+    const GAS cx<T>* Mk = mat + (long)(first + dir * kc) * mstride;                                  \
     _Pragma("unroll") for (int cc = 0; cc < CW; ++cc) {                                          \
       const int j = g * CW + cc;                                                                 \
       const int jc = j < nl ? j : nl - 1;                                                        \
@@ -164,14 +193,14 @@ __device__ __forceinline__ void bchain(const cx<T>* __restrict__ mat, long mstri
 // of JB entries (unconditional loads from clamped addresses) so that each
 // block costs one memory round trip.
 template <class T, int RB>
-__device__ __forceinline__ void bfixup(const cx<T>* __restrict__ mat, cx<T>* rows, int s, int e, int nl,
+__device__ __forceinline__ void bfixup(const GAS cx<T>* __restrict__ mat, GAS cx<T>* rows, int s, int e, int nl,
                                        const cx<T>* v) {
   constexpr int JB = sizeof(T) == 4 ? 32 : 16;
   const int cnt = e - s;
   for (int idx = threadIdx.x; idx < cnt * nl; idx += blockDim.x) {
     const int t = s + idx / nl, l = idx - (idx / nl) * nl;
-    const cx<T>* mb = mat + (size_t)t * nl * nl + l;
-    cx<T>* o = rows + (size_t)t * RB * nl + l;
+    const GAS cx<T>* mb = mat + (size_t)t * nl * nl + l;
+    GAS cx<T>* o = rows + (size_t)t * RB * nl + l;
     cx<T> acc[RB];
 #pragma unroll
     for (int c = 0; c < RB; ++c) acc[c] = o[(size_t)c * nl];
@@ -186,9 +215,10 @@ __device__ __forceinline__ void bfixup(const cx<T>* __restrict__ mat, cx<T>* row
 #pragma unroll
       for (int jj = 0; jj < JB; ++jj) {
         const int j = j0 + jj;
-        const int jc = j < nl ? j : nl - 1;
+        if (j < nl) {  // the same for every thread: padding columns are skipped
 #pragma unroll
-        for (int c = 0; c < RB; ++c) cfma(acc[c], mv[jj], v[jc * RB + c]);
+          for (int c = 0; c < RB; ++c) cfma(acc[c], mv[jj], v[j * RB + c]);
+        }
       }
     }
 #pragma unroll
@@ -219,6 +249,32 @@ __device__ __forceinline__ bool decode_work(const BSeg* __restrict__ segs, int n
   return true;
 }
 
+// Decomposition of a flat index i = (c nl + l) cnt + t (t fastest) that
+// follows i -> i + 256 by carries instead of divisions.
+struct IdxWalk {
+  int c, l, t;
+  int dc, dl, dt, cnt, nl;
+  __device__ IdxWalk(int i, int cnt_, int nl_) : cnt(cnt_), nl(nl_) {
+    const int row = i / cnt;
+    t = i - row * cnt;
+    c = row / nl;
+    l = row - c * nl;
+    const int drow = 256 / cnt;
+    dt = 256 - drow * cnt;
+    dc = drow / nl;
+    dl = drow - dc * nl;
+  }
+  __device__ __forceinline__ void step() {
+    t += dt;
+    const int ct = t >= cnt;
+    t -= ct ? cnt : 0;
+    l += dl + ct;
+    const int cl = l >= nl;
+    l -= cl ? nl : 0;
+    c += dc + cl;
+  }
+};
+
 template <class T, int NB, int RB, int D>
 __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ segs, int nseg, int nitems) {
   __shared__ cx<T> q[NB * RB];
@@ -226,67 +282,96 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
   BWork w;
   BSeg A;
   if (!decode_work(segs, nseg, nitems, A, w)) return;
-  const cx<T>* __restrict__ f = static_cast<const cx<T>*>(A.f);
-  const cx<T>* __restrict__ g = static_cast<const cx<T>*>(A.g);
-  const cx<T>* __restrict__ bufs = static_cast<const cx<T>*>(A.bufs);
-  cx<T>* __restrict__ scratch = static_cast<cx<T>*>(A.scratch);
+  const GAS cx<T>* __restrict__ f = gp(static_cast<const cx<T>*>(A.f));
+  const GAS cx<T>* __restrict__ g = gp(static_cast<const cx<T>*>(A.g));
+  const GAS cx<T>* __restrict__ bufs = gp(static_cast<const cx<T>*>(A.bufs));
+  GAS cx<T>* __restrict__ scratch = gp(static_cast<cx<T>*>(A.scratch));
   const cx<T>* __restrict__ factors = static_cast<const cx<T>*>(A.factors);
-  cx<T>* __restrict__ red = static_cast<cx<T>*>(A.red);
+  GAS cx<T>* __restrict__ red = gp(static_cast<cx<T>*>(A.red));
   int* counters = A.counters;
   const int P = A.P, m = A.m, n2 = A.G.n2;
   const int slot = w.q * A.ntiles + w.tile, r0 = w.tile * RB;
   const int nr = min(RB, A.nact - r0);
-  const TaskDev tk = A.tasks[w.q];
-  const SlabDev sd = A.slabs[tk.slab];
+  const TaskDev tk = cload(A.tasks, w.q);
+  const SlabDev sd = cload(A.slabs, tk.slab);
   const int nl = sd.nl;
   const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
   const SlabFac<T> F(factors + sd.fac_off, n2, nl);
-  cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
-  cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
-  const cx<T>* src = tk.src ? g : f;
+  GAS cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
+  GAS cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
+  const GAS cx<T>* src = tk.src ? g : f;
   // slab right-hand side of the chunk, t fastest (coalesced level reads);
-  // U entries per thread and round: all loads first, then the stores
+  // U entries per thread and round: all loads first, then the stores.  The
+  // (at most four) incoming transmission layers are left to a second pass,
+  // so that their coefficient evaluation runs only where it is needed.
+  auto trans_layer = [&](int gl) {
+    return (tk.t1 && (gl == tk.beta_in || gl == tk.beta_in + 1)) || (tk.t3 && (gl == tk.bt_in || gl == tk.bt_in + 1));
+  };
   {
     constexpr int U = 4;
-    const int tot = RB * nl * cnt;
-    for (int base = threadIdx.x; base < tot; base += 256 * U) {
+    IdxWalk it(threadIdx.x, cnt, nl);
+    for (int base = threadIdx.x; base < RB * nl * cnt; base += 256 * U) {
       cx<T> val[U];
-      size_t dst[U];
+      int dst[U];
+      bool st[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const int idx = base + q * 256;
-        const int ic = idx < tot ? idx : tot - 1;
-        const int c = ic / (nl * cnt), rem = ic - c * (nl * cnt);
-        const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
-        const int gl = sd.x0 + ll;
-        const int cc = c < nr ? c : 0;
-        const bool inside = c < nr && tk.a < gl && gl <= tk.b;
+        const int gl = sd.x0 + it.l;
+        const int cc = it.c < nr ? it.c : 0;
+        const bool inside = it.c < nr && tk.a < gl && gl <= tk.b;
         const int glc = inside ? gl : tk.b;
-        const cx<T> v = src[(size_t)(r0 + cc) * A.ld + (size_t)(glc - 1) * n2 + t];
+        const cx<T> v = src[(size_t)(r0 + cc) * A.ld + (size_t)(glc - 1) * n2 + s + it.t];
         val[q] = sel(inside, v);
-        dst[q] = ((size_t)t * RB + c) * nl + ll;
+        dst[q] = ((s + it.t) * RB + it.c) * nl + it.l;
+        st[q] = it.c < RB && !trans_layer(gl);
+        it.step();
       }
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int idx = base + q * 256;
-        if (idx < tot) {
-          const int c = idx / (nl * cnt), rem = idx - c * (nl * cnt);
-          const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
-          const int gl = sd.x0 + ll;
-          cx<T> v = val[q];
-          if (c < nr) {
-            const cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
-            v = v + cvt<T>(transmission_rhs<T>(tk, A.G, gl, t, n2, bz + (size_t)tk.bin_f * 2 * n2,
-                                               bz + (size_t)tk.bin_b * 2 * n2));
+      for (int q = 0; q < U; ++q)
+        if (st[q]) y[dst[q]] = val[q];
+    }
+  }
+  // transmission layers from the precomputed coefficients: slot k < 2 is
+  // layer beta_in + k, k >= 2 layer bt_in + k - 2; a layer that is listed
+  // twice is written once (with both terms), one outside the slab not at all
+  {
+    const GAS cd* tc = gp(A.tcoef) + (size_t)w.q * trans_coef_elems(n2);
+    auto slot_gl = [&](int kk) {
+      return kk < 2 ? (tk.t1 ? tk.beta_in + kk : -1) : (tk.t3 ? tk.bt_in + kk - 2 : -1);
+    };
+    const int tot = RB * 4 * cnt;
+    for (int idx = threadIdx.x; idx < tot; idx += 256) {
+      const int c = idx / (4 * cnt), rem = idx - c * (4 * cnt);
+      const int k = rem / cnt, t = s + rem - k * cnt;
+      const int gl = slot_gl(k);
+      bool use = gl >= sd.x0 && gl < sd.x0 + nl;
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2)
+        if (k2 < k && slot_gl(k2) == gl) use = false;
+      if (!use) continue;
+      cx<T> v = mk<T>(0, 0);
+      if (c < nr) {
+        if (tk.a < gl && gl <= tk.b) v = src[(size_t)(r0 + c) * A.ld + (size_t)(gl - 1) * n2 + t];
+        const GAS cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
+        cd acc = mk<double>(0, 0);
+        for (int k2 = k; k2 < 4; ++k2) {
+          if (slot_gl(k2) != gl) continue;
+          const GAS cx<T>* Bk = bz + (size_t)(k2 < 2 ? tk.bin_f : tk.bin_b) * 2 * n2 + ((k2 & 1) ? 0 : n2);
+          const GAS cd* ck = tc + ((size_t)k2 * n2 + t) * 3;
+#pragma unroll
+          for (int dt = 0; dt < 3; ++dt) {
+            const int tt = min(max(t + dt - 1, 0), n2 - 1);
+            cfma(acc, ck[dt], cvt<double>(Bk[tt]));
           }
-          y[dst[q]] = v;
         }
+        v = v + cvt<T>(acc);
       }
+      y[((size_t)t * RB + c) * nl + (gl - sd.x0)] = v;
     }
   }
   __syncthreads();
   // chunk-local forward substitution y_t = G_t (f_t - A_t y_{t-1}) from zero
-  bchain<T, NB, RB, D, true>(F.G, (long)nl * nl, F.A, y, s, 1, cnt, nl, T(1), q, ps);
+  bchain<T, NB, RB, D, true>(gp(F.G), (long)nl * nl, gp(F.A), y, s, 1, cnt, nl, T(1), q, ps);
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
     tips[((size_t)w.p * RB + c) * nl + l] = y[((size_t)(e - 1) * RB + c) * nl + l];
@@ -294,8 +379,8 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
   if (P == 1) return;
   if (!last_arrival(counters + 2 * slot, P)) return;
   // true chunk-end values: tip_q = raw_q + Y_{e_q - 1} tip_{q-1}
-  bchain<T, NB, RB, D, false>(F.Y + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0, 1, P - 1,
-                                  nl, T(1), q, ps);
+  bchain<T, NB, RB, D, false>(gp(F.Y) + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0, 1,
+                              P - 1, nl, T(1), q, ps);
 }
 
 template <class T, int NB, int RB, int D>
@@ -305,31 +390,31 @@ __global__ void __launch_bounds__(256) k_bstage_mid(const BSeg* __restrict__ seg
   BWork w;
   BSeg A;
   if (!decode_work(segs, nseg, nitems, A, w)) return;
-  cx<T>* __restrict__ scratch = static_cast<cx<T>*>(A.scratch);
+  GAS cx<T>* __restrict__ scratch = gp(static_cast<cx<T>*>(A.scratch));
   const cx<T>* __restrict__ factors = static_cast<const cx<T>*>(A.factors);
-  cx<T>* __restrict__ red = static_cast<cx<T>*>(A.red);
+  GAS cx<T>* __restrict__ red = gp(static_cast<cx<T>*>(A.red));
   int* counters = A.counters;
   const int P = A.P, m = A.m, n2 = A.G.n2;
   const int slot = w.q * A.ntiles + w.tile;
-  const TaskDev tk = A.tasks[w.q];
-  const SlabDev sd = A.slabs[tk.slab];
+  const TaskDev tk = cload(A.tasks, w.q);
+  const SlabDev sd = cload(A.slabs, tk.slab);
   const int nl = sd.nl;
   const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
   const SlabFac<T> F(factors + sd.fac_off, n2, nl);
-  cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
-  cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
-  cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
+  GAS cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
+  GAS cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
+  GAS cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
   if (w.p > 0) {
     for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
       const int c = idx / nl, l = idx - c * nl;
       q[l * RB + c] = tips[((size_t)(w.p - 1) * RB + c) * nl + l];
     }
     __syncthreads();
-    bfixup<T, RB>(F.Y, y, s, e, nl, q);
+    bfixup<T, RB>(gp(F.Y), y, s, e, nl, q);
     __syncthreads();
   }
   // chunk-local backward substitution x_t = y_t - E_t x_{t+1}
-  bchain<T, NB, RB, D, false>(F.E, (long)nl * nl, nullptr, y, e - 1, -1, cnt, nl, T(-1), q, ps);
+  bchain<T, NB, RB, D, false>(gp(F.E), (long)nl * nl, nullptr, y, e - 1, -1, cnt, nl, T(-1), q, ps);
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
     heads[((size_t)w.p * RB + c) * nl + l] = y[((size_t)s * RB + c) * nl + l];
@@ -337,7 +422,7 @@ __global__ void __launch_bounds__(256) k_bstage_mid(const BSeg* __restrict__ seg
   if (P == 1) return;
   if (!last_arrival(counters + 2 * slot + 1, P)) return;
   // true chunk-start values: head_q = raw_q + X_{s_q} head_{q+1}
-  bchain<T, NB, RB, D, false>(F.X, (long)m * nl * nl, nullptr, heads, P - 1, -1, P - 1, nl, T(1), q, ps);
+  bchain<T, NB, RB, D, false>(gp(F.X), (long)m * nl * nl, nullptr, heads, P - 1, -1, P - 1, nl, T(1), q, ps);
 }
 
 template <class T, int NB, int RB>
@@ -346,66 +431,68 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ seg
   BWork w;
   BSeg A;
   if (!decode_work(segs, nseg, nitems, A, w)) return;
-  cx<T>* __restrict__ u = static_cast<cx<T>*>(A.u);
-  cx<T>* __restrict__ bufs = static_cast<cx<T>*>(A.bufs);
-  cx<T>* __restrict__ scratch = static_cast<cx<T>*>(A.scratch);
+  GAS cx<T>* __restrict__ u = gp(static_cast<cx<T>*>(A.u));
+  GAS cx<T>* __restrict__ bufs = gp(static_cast<cx<T>*>(A.bufs));
+  GAS cx<T>* __restrict__ scratch = gp(static_cast<cx<T>*>(A.scratch));
   const cx<T>* __restrict__ factors = static_cast<const cx<T>*>(A.factors);
-  const cx<T>* __restrict__ red = static_cast<const cx<T>*>(A.red);
+  const GAS cx<T>* __restrict__ red = gp(static_cast<const cx<T>*>(A.red));
   const int P = A.P, m = A.m, n2 = A.G.n2;
   const int slot = w.q * A.ntiles + w.tile, r0 = w.tile * RB;
   const int nr = min(RB, A.nact - r0);
-  const TaskDev tk = A.tasks[w.q];
-  const SlabDev sd = A.slabs[tk.slab];
+  const TaskDev tk = cload(A.tasks, w.q);
+  const SlabDev sd = cload(A.slabs, tk.slab);
   const int nl = sd.nl;
   const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
   const SlabFac<T> F(factors + sd.fac_off, n2, nl);
-  cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
-  const cx<T>* heads = red + (size_t)slot * 2 * P * A.nl_max * RB + (size_t)P * A.nl_max * RB;
+  GAS cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
+  const GAS cx<T>* heads = red + (size_t)slot * 2 * P * A.nl_max * RB + (size_t)P * A.nl_max * RB;
   if (w.p < P - 1) {
     for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
       const int c = idx / nl, l = idx - c * nl;
       hv[l * RB + c] = heads[((size_t)(w.p + 1) * RB + c) * nl + l];
     }
     __syncthreads();
-    bfixup<T, RB>(F.X, y, s, e, nl, hv);
+    bfixup<T, RB>(gp(F.X), y, s, e, nl, hv);
     __syncthreads();
   }
   // u += J^T x over the task's layers, outgoing transmission layers; U
   // entries per thread and round, loads first
   constexpr int U = 4;
   const int tot = nr * nl * cnt;
+  IdxWalk it(threadIdx.x, cnt, nl);
   for (int base = threadIdx.x; base < tot; base += 256 * U) {
     cx<T> xv[U], uv[U];
     size_t uid[U];
+    int cq[U], lq[U], tq[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int idx = base + q * 256;
-      const int ic = idx < tot ? idx : tot - 1;
-      const int c = ic / (nl * cnt), rem = ic - c * (nl * cnt);
-      const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
+      const int c = it.c < nr ? it.c : nr - 1;
+      const int ll = it.l, t = s + it.t;
       const int gl = sd.x0 + ll;
       const int glc = (tk.at < gl && gl <= tk.bt) ? gl : tk.bt;
       xv[q] = y[((size_t)t * RB + c) * nl + ll];
       uid[q] = (size_t)(r0 + c) * A.ld + (size_t)(glc - 1) * n2 + t;
       uv[q] = u[uid[q]];
+      cq[q] = it.c;
+      lq[q] = ll;
+      tq[q] = t;
+      it.step();
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int idx = base + q * 256;
-      if (idx >= tot) continue;
-      const int c = idx / (nl * cnt), rem = idx - c * (nl * cnt);
-      const int ll = rem / cnt, t = s + rem - (rem / cnt) * cnt;
+      if (cq[q] >= nr) continue;
+      const int c = cq[q], ll = lq[q], t = tq[q];
       const int gl = sd.x0 + ll;
       const cx<T> x = xv[q];
       if (tk.at < gl && gl <= tk.bt) u[uid[q]] = uv[q] + x;
-      cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
+      GAS cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
       if (tk.t2) {
-        cx<T>* Bo = bz + (size_t)tk.bout_f * 2 * n2;
+        GAS cx<T>* Bo = bz + (size_t)tk.bout_f * 2 * n2;
         if (gl == tk.beta_out) Bo[t] = x;
         if (gl == tk.beta_out + 1) Bo[(size_t)n2 + t] = x;
       }
       if (tk.t4) {
-        cx<T>* Bo = bz + (size_t)tk.bout_b * 2 * n2;
+        GAS cx<T>* Bo = bz + (size_t)tk.bout_b * 2 * n2;
         if (gl == tk.bt_out) Bo[t] = x;
         if (gl == tk.bt_out + 1) Bo[(size_t)n2 + t] = x;
       }
@@ -413,7 +500,46 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ seg
   }
 }
 
+// One thread per (task, slot, t): the coupling of the incoming transmission
+// layer to the buffer nodes t-1, t, t+1 (row beta+1 of the global operator
+// towards beta for the first layer of a pair, row beta towards beta+1 for
+// the second), signed as in the transmission operators T and T~ of Sec. 2.2.
+__global__ void __launch_bounds__(256) k_trans_coef(const TaskDev* __restrict__ tasks, int ntasks,
+                                                     const SlabDev* __restrict__ slabs, LevelDev G,
+                                                     cd* __restrict__ out) {
+  const int n2 = G.n2;
+  const long total = (long)ntasks * 4 * n2;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+    const int t = (int)(i % n2), k = (int)((i / n2) % 4), q = (int)(i / (4L * n2));
+    const TaskDev tk = tasks[q];
+    const int gl = k < 2 ? tk.beta_in + k : tk.bt_in + k - 2;
+    const int x0 = slabs[tk.slab].x0, nl = slabs[tk.slab].nl;
+    const bool on = (k < 2 ? tk.t1 : tk.t3) && gl >= x0 && gl < x0 + nl;
+    cd* o = out + (size_t)i * 3;
+    cd c[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) c[a][b] = mk<double>(0, 0);
+    if (on) stencil_coefs(G, gl, t + 1, c);
+    // slots 0 and 3 add the term, slots 1 and 2 subtract it
+    const double sg = (k == 0 || k == 3) ? 1.0 : -1.0;
+#pragma unroll
+    for (int dt = 0; dt < 3; ++dt) {
+      const int tt = t + dt - 1;
+      const cd cc = (k & 1) ? c[0][dt] : c[2][dt];
+      o[dt] = (on && tt >= 0 && tt < n2) ? mk<double>(sg * cc.re, sg * cc.im) : mk<double>(0, 0);
+    }
+  }
+}
+
 }  // namespace
+
+void launch_trans_coef(const TaskDev* tasks, int ntasks, const SlabDev* slabs, const LevelDev& G, cd* out,
+                       hipStream_t s) {
+  if (ntasks < 1) return;
+  const long total = (long)ntasks * 4 * G.n2;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_trans_coef, dim3(blocks), dim3(256), 0, s, tasks, ntasks, slabs, G, out);
+}
 
 template <class T>
 void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launch, int rb, hipStream_t s) {
@@ -446,5 +572,8 @@ void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launc
 
 template void launch_stage_group<double>(const BSeg*, int, int, int, int, hipStream_t);
 template void launch_stage_group<float>(const BSeg*, int, int, int, int, hipStream_t);
+
+#undef GAS
+#undef CAS
 
 }  // namespace hsp

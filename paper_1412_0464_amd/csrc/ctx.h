@@ -57,7 +57,7 @@ struct Plan {
   size_t o_cxA, o_cxB, o_cyA, o_cyB, o_ck2c, o_ccoef;
   size_t o_avgx0, o_avgwx, o_avgy0, o_avgwy;
   size_t o_rx, o_rwx, o_ry, o_rwy, o_px, o_pwx, o_py, o_pwy;
-  size_t o_slabs, o_slabA, o_slabB, o_xmap, o_fac, o_facscr, o_status, o_tasks;
+  size_t o_slabs, o_slabA, o_slabB, o_xmap, o_fac, o_facscr, o_status, o_tasks, o_tcoef;
   size_t o_swf, o_swg, o_swu, o_swB, o_swscr;
   size_t o_tgx0, o_tgx1, o_tgres, o_tgrc, o_tgec, o_cvin, o_cvout;
   size_t o_V, o_Z, o_w, o_part, o_hbuf, o_stats, o_bconj;
@@ -102,6 +102,7 @@ struct hsp_ctx {
   hsp::TaskDev* tasks_dev = nullptr;
   std::vector<hsp::TaskDev> tasks_host;
   void* factors = nullptr;
+  const hsp::cd* tcoef = nullptr;  // transmission coefficients per task (batched stages)
   hsp::Prof prof;
   int tuned_rb = 0;    // right-hand-side tile chosen by hsp_tune_batch (0: none)
   int tuned_nact = 0;  // batch size it was chosen for

@@ -210,6 +210,7 @@ hsp_status build_segments(Group& G, const std::vector<int>& nact, int rb, hipStr
       q.factors = mb.C->factors;
       q.red = mb.ws + B.o_red;
       q.counters = mb.at<int>(B.o_ctr);
+      q.tcoef = mb.C->tcoef + (size_t)sg.first * trans_coef_elems(P.dd_n2);
       q.ld = (size_t)P.dd_n1 * P.dd_n2;
       q.ntasks = sg.ntasks;
       q.ntiles = (nact[p] + rb - 1) / rb;

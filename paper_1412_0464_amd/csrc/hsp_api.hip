@@ -224,6 +224,7 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   P.o_status = c.take(64);
   P.n_tasks = 2 * (size_t)J + 8;
   P.o_tasks = c.take(P.n_tasks * sizeof(TaskDev));
+  P.o_tcoef = c.take(P.n_tasks * trans_coef_elems(P.dd_n2) * sizeof(cd));
   // sweep vectors (DD level, precision of the preconditioner)
   P.o_swf = c.take(nd * P.tsize);
   P.o_swg = c.take(nd * P.tsize);
@@ -879,6 +880,8 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
   if (C->tasks_host.size() > P.n_tasks) return cleanup(fail(HSP_EINVAL, "internal: schedule too long"));
   up(P.o_tasks, C->tasks_host.data(), C->tasks_host.size() * sizeof(TaskDev));
   C->tasks_dev = C->raw<TaskDev>(P.o_tasks);
+  C->tcoef = C->raw<cd>(P.o_tcoef);
+  launch_trans_coef(C->tasks_dev, (int)C->tasks_host.size(), C->slabs_dev, C->dd, C->raw<cd>(P.o_tcoef), s);
   for (hipError_t e : errs)
     if (e != hipSuccess) return cleanup(fail(HSP_EDEVICE, std::string("upload: ") + hipGetErrorString(e)));
 

@@ -152,9 +152,20 @@ struct BSeg {
   const void* factors;
   void* red;
   int* counters;
+  const cd* tcoef;  // transmission coefficients of the segment's first task
   size_t ld;
   int ntasks, ntiles, nact, nl_max, m, P, item0, pad;
 };
+// Incoming transmission terms of a task as a table, [4][n2][3] complex
+// double per task: slot k of the (up to) four incoming transmission layers
+// (beta_{j-1}, beta_{j-1} + 1, beta~_j, beta~_j + 1), tangential node t, and
+// the coupling to buffer node t + dt - 1 with the sign of the transmission
+// operator folded in (zero where the flag is off or t + dt - 1 is outside).
+__host__ __device__ inline size_t trans_coef_elems(int n2) {
+  return (size_t)4 * n2 * 3;
+}
+void launch_trans_coef(const TaskDev* tasks, int ntasks, const SlabDev* slabs, const LevelDev& G, cd* out,
+                       hipStream_t s);
 // segs_dev: nseg segments in device memory, nitems work items in total,
 // nl_launch the thickest slab, rb in {1, 2, 4, 8}.
 template <class T>
