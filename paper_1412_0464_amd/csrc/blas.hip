@@ -257,27 +257,30 @@ __global__ void __launch_bounds__(256) k_bmultiaxpy(const cd* __restrict__ V, si
 // Delayed classical Gram-Schmidt, one projection pass: for basis vectors
 // j < cnt of right-hand side z (slot cnt-1 holds the once-projected,
 // unnormalised vector u), conj(V_zj) . u and conj(V_zj) . w; both read once.
-// partial[((z 2 cnt) + q cnt + j) nblk + block], q = 0 (u) or 1 (w).
-__global__ void __launch_bounds__(256) k_bmultidot2(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
+// partial[((z 2 cnt) + q cnt + j) nblk + block], q = 0 (u) or 1 (w).  The
+// basis is stored in TV (complex128, or complex64 for the mixed-precision
+// solver); the products are formed in double.
+template <class TV>
+__global__ void __launch_bounds__(256) k_bmultidot2(const cx<TV>* __restrict__ V, size_t ldj, BIdx bv, int cnt,
                                                     const cd* __restrict__ w, BIdx bw, size_t n,
                                                     cd* __restrict__ partial) {
   __shared__ cd sh[4 * 2 * kDotTile];
   const int z = blockIdx.z, j0 = blockIdx.y * kDotTile;
   const int jn = min(kDotTile, cnt - j0);
-  const cd* vz = V + bv.off(z);
-  const cd* v = vz + (size_t)j0 * ldj;
-  const cd* u = vz + (size_t)(cnt - 1) * ldj;
+  const cx<TV>* vz = V + bv.off(z);
+  const cx<TV>* v = vz + (size_t)j0 * ldj;
+  const cx<TV>* u = vz + (size_t)(cnt - 1) * ldj;
   w += bw.off(z);
   cd acc[2 * kDotTile];
 #pragma unroll
   for (int q = 0; q < 2 * kDotTile; ++q) acc[q] = mk<double>(0, 0);
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
-    const cd ui = u[i], wi = w[i];
+    const cd ui = cvt<double>(u[i]), wi = w[i];
 #pragma unroll
     for (int q = 0; q < kDotTile; ++q)
       if (q < jn) {
-        const cd vj = conj(v[(size_t)q * ldj + i]);
+        const cd vj = conj(cvt<double>(v[(size_t)q * ldj + i]));
         cfma(acc[q], vj, ui);
         cfma(acc[kDotTile + q], vj, wi);
       }
@@ -319,35 +322,39 @@ __global__ void k_bdcgs_coef(cd* __restrict__ hb, size_t ldh, int k, int off, in
 // above, v_k = (u - V s) / nu overwrites slot k and
 // u' = w - V p - h_kk v_k (the next once-projected vector) goes to slot k+1,
 // with the block partials of ||u'||^2.  Reads V (k vectors), u and w once.
-__global__ void __launch_bounds__(256) k_bdcgs_update(cd* __restrict__ V, size_t ldj, BIdx bv, int k,
+// With a complex64 basis, v_k and u' are rounded before they are used, so
+// that the recurrences see exactly the stored vectors.
+template <class TV>
+__global__ void __launch_bounds__(256) k_bdcgs_update(cx<TV>* __restrict__ V, size_t ldj, BIdx bv, int k,
                                                       const cd* __restrict__ hb, size_t ldh, int off,
                                                       const cd* __restrict__ w, BIdx bw, size_t n,
                                                       cd* __restrict__ partial) {
   __shared__ cd sh[4];
   const int z = blockIdx.y;
-  cd* vz = V + bv.off(z);
+  cx<TV>* vz = V + bv.off(z);
   const cd* d = hb + (size_t)z * ldh;
   const cd* sv = d;
   const cd* pv = d + (k + 1);
   const double inu = 1.0 / d[off].re;
   const cd hkk = d[off + 1];
-  cd* u = vz + (size_t)k * ldj;
-  cd* un = vz + (size_t)(k + 1) * ldj;
+  cx<TV>* u = vz + (size_t)k * ldj;
+  cx<TV>* un = vz + (size_t)(k + 1) * ldj;
   w += bw.off(z);
   double nrm = 0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     cd t1 = mk<double>(0, 0), t2 = mk<double>(0, 0);
     for (int j = 0; j < k; ++j) {
-      const cd vj = vz[(size_t)j * ldj + i];
+      const cd vj = cvt<double>(vz[(size_t)j * ldj + i]);
       cfma(t1, sv[j], vj);
       cfma(t2, pv[j], vj);
     }
-    const cd vk = inu * (u[i] - t1);
-    u[i] = vk;
+    const cx<TV> vks = cvt<TV>(inu * (cvt<double>(u[i]) - t1));
+    u[i] = vks;
     cd wn = w[i] - t2;
-    cfma(wn, -hkk, vk);
-    un[i] = wn;
-    nrm += abs2(wn);
+    cfma(wn, -hkk, cvt<double>(vks));
+    const cx<TV> wns = cvt<TV>(wn);
+    un[i] = wns;
+    nrm += abs2(cvt<double>(wns));
   }
   const cd r = block_sum(mk<double>(nrm, 0.0), sh);
   if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = r;
@@ -374,14 +381,15 @@ __global__ void __launch_bounds__(256) k_bmultiaxpy_norm(const cd* __restrict__ 
   if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = r;
 }
 
+template <class TV>
 __global__ void k_bnormalize(const cd* __restrict__ w, BIdx bw, const cd* __restrict__ nrm2, size_t ldn,
-                             cd* __restrict__ v, BIdx bvv, size_t n) {
+                             cx<TV>* __restrict__ v, BIdx bvv, size_t n) {
   const int z = blockIdx.y;
   const double s = 1.0 / sqrt(nrm2[(size_t)z * ldn].re);
   w += bw.off(z);
   v += bvv.off(z);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    v[i] = s * w[i];
+    v[i] = cvt<TV>(s * w[i]);
 }
 
 inline int nblk(size_t n) {
@@ -447,27 +455,41 @@ void launch_bmultiaxpy_norm(const cd* V, size_t ldj, BIdx bv, int cnt, const cd*
                      partial);
   hipLaunchKernelGGL(k_breduce, dim3(1, nb), dim3(256), 0, s, (const cd*)partial, nblocks, 1, nrm2, ldo);
 }
-void launch_bdcgs_project(const cd* V, size_t ldj, BIdx bv, int k, const cd* w, BIdx bw, size_t n, cd* partial,
-                          int nblocks, cd* hb, size_t ldh, int off, int nb, hipStream_t s) {
+template <class TV>
+void launch_bdcgs_project(const cx<TV>* V, size_t ldj, BIdx bv, int k, const cd* w, BIdx bw, size_t n,
+                          cd* partial, int nblocks, cd* hb, size_t ldh, int off, int nb, hipStream_t s) {
   if (nb < 1) return;
   const int cnt = k + 1;
   const int tiles = (cnt + kDotTile - 1) / kDotTile;
-  hipLaunchKernelGGL(k_bmultidot2, dim3(nblocks, tiles, nb), dim3(256), 0, s, V, ldj, bv, cnt, w, bw, n, partial);
+  hipLaunchKernelGGL(k_bmultidot2<TV>, dim3(nblocks, tiles, nb), dim3(256), 0, s, V, ldj, bv, cnt, w, bw, n,
+                     partial);
   hipLaunchKernelGGL(k_breduce, dim3(2 * cnt, nb), dim3(256), 0, s, (const cd*)partial, nblocks, 2 * cnt, hb, ldh);
   hipLaunchKernelGGL(k_bdcgs_coef, dim3((nb + 63) / 64), dim3(64), 0, s, hb, ldh, k, off, nb);
 }
-void launch_bdcgs_update(cd* V, size_t ldj, BIdx bv, int k, const cd* hb, size_t ldh, int off, const cd* w, BIdx bw,
-                         size_t n, cd* partial, int nblocks, cd* nrm2, int nb, hipStream_t s) {
+template <class TV>
+void launch_bdcgs_update(cx<TV>* V, size_t ldj, BIdx bv, int k, const cd* hb, size_t ldh, int off, const cd* w,
+                         BIdx bw, size_t n, cd* partial, int nblocks, cd* nrm2, int nb, hipStream_t s) {
   if (nb < 1) return;
-  hipLaunchKernelGGL(k_bdcgs_update, dim3(nblocks, nb), dim3(256), 0, s, V, ldj, bv, k, hb, ldh, off, w, bw, n,
+  hipLaunchKernelGGL(k_bdcgs_update<TV>, dim3(nblocks, nb), dim3(256), 0, s, V, ldj, bv, k, hb, ldh, off, w, bw, n,
                      partial);
   hipLaunchKernelGGL(k_breduce, dim3(1, nb), dim3(256), 0, s, (const cd*)partial, nblocks, 1, nrm2, ldh);
 }
-void launch_bnormalize(const cd* w, BIdx bw, const cd* nrm2, size_t ldn, cd* v, BIdx bv, size_t n, int nb,
+template <class TV>
+void launch_bnormalize(const cd* w, BIdx bw, const cd* nrm2, size_t ldn, cx<TV>* v, BIdx bv, size_t n, int nb,
                        hipStream_t s) {
   if (nb < 1) return;
-  hipLaunchKernelGGL(k_bnormalize, dim3(nblk_batch(n, nb), nb), dim3(256), 0, s, w, bw, nrm2, ldn, v, bv, n);
+  hipLaunchKernelGGL(k_bnormalize<TV>, dim3(nblk_batch(n, nb), nb), dim3(256), 0, s, w, bw, nrm2, ldn, v, bv, n);
 }
+template void launch_bdcgs_project<double>(const cd*, size_t, BIdx, int, const cd*, BIdx, size_t, cd*, int, cd*,
+                                           size_t, int, int, hipStream_t);
+template void launch_bdcgs_project<float>(const cf*, size_t, BIdx, int, const cd*, BIdx, size_t, cd*, int, cd*,
+                                          size_t, int, int, hipStream_t);
+template void launch_bdcgs_update<double>(cd*, size_t, BIdx, int, const cd*, size_t, int, const cd*, BIdx, size_t,
+                                          cd*, int, cd*, int, hipStream_t);
+template void launch_bdcgs_update<float>(cf*, size_t, BIdx, int, const cd*, size_t, int, const cd*, BIdx, size_t,
+                                         cd*, int, cd*, int, hipStream_t);
+template void launch_bnormalize<double>(const cd*, BIdx, const cd*, size_t, cd*, BIdx, size_t, int, hipStream_t);
+template void launch_bnormalize<float>(const cd*, BIdx, const cd*, size_t, cf*, BIdx, size_t, int, hipStream_t);
 void launch_scale_rhs_arrays(int n1, int n2, double h2, const cd* ixn, const cd* iyn, const cd* f, cd* b,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_scale_rhs, dim3((n2 + 255) / 256, n1), dim3(256), 0, s, n1, n2, h2, ixn, iyn, f, b);

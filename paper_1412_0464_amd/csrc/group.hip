@@ -62,7 +62,9 @@ BatchLayout batch_layout(const Plan& P, int R, int m) {
   B.o_ctr = c.take(2 * slots * sizeof(int));
   B.nblk = batch_dot_blocks(nf, R);
   B.hs = 2 * (size_t)(m + 2) + 2;
-  B.o_V = c.take((size_t)R * (m + 1) * nf * sizeof(cd));
+  // Krylov basis in the precision of the preconditioner (complex64 for the
+  // mixed-precision solver); everything else of FGMRES in complex128
+  B.o_V = c.take((size_t)R * (m + 1) * nf * T);
   B.o_Z = c.take((size_t)R * m * nf * sizeof(cd));
   B.o_w = c.take(R * nf * sizeof(cd));
   B.o_bc = c.take(R * nf * sizeof(cd));
@@ -98,7 +100,8 @@ struct Member {
 // Input / output vectors of one member's preconditioner application:
 // right-hand side j (slot j) at r + br.off(j), result at z + bz.off(j).
 struct PrecIO {
-  const cd* r = nullptr;
+  const void* r = nullptr;
+  int r32 = 0;  // r is complex64 (else complex128)
   BIdx br;
   cd* z = nullptr;
   BIdx bz;
@@ -255,7 +258,12 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     bf.ld = nf;
     bdd.ld = nd;
     if (!P.two_grid) {
-      launch_convert<T, double>(io[p].r, mptr<cx<T>>(mb, B.o_swf), nf, 0, s, na, io[p].br, bf);
+      if (io[p].r32)
+        launch_convert<T, float>(static_cast<const cf*>(io[p].r), mptr<cx<T>>(mb, B.o_swf), nf, 0, s, na, io[p].br,
+                                 bf);
+      else
+        launch_convert<T, double>(static_cast<const cd*>(io[p].r), mptr<cx<T>>(mb, B.o_swf), nf, 0, s, na,
+                                  io[p].br, bf);
       launch_zero<T>(mptr<cx<T>>(mb, B.o_swu), (size_t)na * nd, s);
       continue;
     }
@@ -266,7 +274,12 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
       cd* res = mptr<cd>(mb, B.o_res);
       prof_begin(C, HSP_PROF_SMOOTH, s);
-      launch_smooth_pre(C->fine, nu, wj, io[p].r, io[p].br, reinterpret_cast<cf*>(xa), bf, res, bf, na, s);
+      if (io[p].r32)
+        launch_smooth_pre<float>(C->fine, nu, wj, static_cast<const cf*>(io[p].r), io[p].br,
+                                 reinterpret_cast<cf*>(xa), bf, res, bf, na, s);
+      else
+        launch_smooth_pre<double>(C->fine, nu, wj, static_cast<const cd*>(io[p].r), io[p].br,
+                                  reinterpret_cast<cf*>(xa), bf, res, bf, na, s);
       prof_end(C, HSP_PROF_SMOOTH, s, (double)na * nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)));
       prof_begin(C, HSP_PROF_TRANSFER, s);
       launch_restrict<double, T>(C->tr, res, mptr<cx<T>>(mb, B.o_rc), s, na, bf, bdd);
@@ -276,18 +289,26 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     }
     const double jb = (double)na * nf * (sizeof(cd) + 2.0 * sizeof(cx<T>) + sizeof(double));
     prof_begin(C, HSP_PROF_SMOOTH, s);
-    if (nu > 0) {
-      launch_stencil<T, T, double, T>(C->fine, 2, (const cx<T>*)nullptr, io[p].r, xa, wj, s, na, BIdx{}, io[p].br,
-                                      bf);
-      for (int k = 1; k < nu; ++k) {
-        launch_stencil<T, T, double, T>(C->fine, 2, xa, io[p].r, xb, wj, s, na, bf, io[p].br, bf);
-        std::swap(xa, xb);
+    // the same steps for a complex128 or a complex64 right-hand side
+    auto presmooth = [&](auto tag) {
+      using TR = decltype(tag);
+      const cx<TR>* r = static_cast<const cx<TR>*>(io[p].r);
+      if (nu > 0) {
+        launch_stencil<T, T, TR, T>(C->fine, 2, (const cx<T>*)nullptr, r, xa, wj, s, na, BIdx{}, io[p].br, bf);
+        for (int k = 1; k < nu; ++k) {
+          launch_stencil<T, T, TR, T>(C->fine, 2, xa, r, xb, wj, s, na, bf, io[p].br, bf);
+          std::swap(xa, xb);
+        }
+      } else {
+        launch_zero<T>(xa, (size_t)na * nf, s);
       }
-    } else {
-      launch_zero<T>(xa, (size_t)na * nf, s);
-    }
+      launch_stencil<double, T, TR, double>(C->fine, 1, xa, r, mptr<cd>(mb, B.o_res), 0.0, s, na, bf, io[p].br, bf);
+    };
+    if (io[p].r32)
+      presmooth(0.0f);
+    else
+      presmooth(0.0);
     cd* res = mptr<cd>(mb, B.o_res);
-    launch_stencil<double, T, double, double>(C->fine, 1, xa, io[p].r, res, 0.0, s, na, bf, io[p].br, bf);
     prof_end(C, HSP_PROF_SMOOTH, s, nu * jb + (double)na * nf * (2.0 * sizeof(cd) + sizeof(cx<T>) + sizeof(double)));
     prof_begin(C, HSP_PROF_TRANSFER, s);
     launch_restrict<double, T>(C->tr, res, mptr<cx<T>>(mb, B.o_rc), s, na, bf, bdd);
@@ -349,8 +370,14 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     cx<T>* xb = mptr<cx<T>>(mb, B.o_xb);
     if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
       prof_begin(C, HSP_PROF_SMOOTH, s);
-      launch_smooth_post(C->fine, C->tr, nu, wj, io[p].r, io[p].br, reinterpret_cast<const cf*>(xa), bf,
-                         reinterpret_cast<const cf*>(mptr<cx<T>>(mb, B.o_ec)), bdd, io[p].z, io[p].bz, na, s);
+      const cf* xin = reinterpret_cast<const cf*>(xa);
+      const cf* ec = reinterpret_cast<const cf*>(mptr<cx<T>>(mb, B.o_ec));
+      if (io[p].r32)
+        launch_smooth_post<float>(C->fine, C->tr, nu, wj, static_cast<const cf*>(io[p].r), io[p].br, xin, bf, ec,
+                                  bdd, io[p].z, io[p].bz, na, s);
+      else
+        launch_smooth_post<double>(C->fine, C->tr, nu, wj, static_cast<const cd*>(io[p].r), io[p].br, xin, bf, ec,
+                                   bdd, io[p].z, io[p].bz, na, s);
       prof_end(C, HSP_PROF_SMOOTH, s,
                (double)na * ((double)nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)) +
                              (double)nd * sizeof(cx<T>)));
@@ -366,14 +393,22 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     }
     const double jb = (double)na * nf * (sizeof(cd) + 2.0 * sizeof(cx<T>) + sizeof(double));
     prof_begin(C, HSP_PROF_SMOOTH, s);
-    for (int k = 0; k < nu; ++k) {
-      if (k == nu - 1) {
-        launch_stencil<T, T, double, double>(C->fine, 2, xa, io[p].r, io[p].z, wj, s, na, bf, io[p].br, io[p].bz);
-      } else {
-        launch_stencil<T, T, double, T>(C->fine, 2, xa, io[p].r, xb, wj, s, na, bf, io[p].br, bf);
-        std::swap(xa, xb);
+    auto postsmooth = [&](auto tag) {
+      using TR = decltype(tag);
+      const cx<TR>* r = static_cast<const cx<TR>*>(io[p].r);
+      for (int k = 0; k < nu; ++k) {
+        if (k == nu - 1) {
+          launch_stencil<T, T, TR, double>(C->fine, 2, xa, r, io[p].z, wj, s, na, bf, io[p].br, io[p].bz);
+        } else {
+          launch_stencil<T, T, TR, T>(C->fine, 2, xa, r, xb, wj, s, na, bf, io[p].br, bf);
+          std::swap(xa, xb);
+        }
       }
-    }
+    };
+    if (io[p].r32)
+      postsmooth(0.0f);
+    else
+      postsmooth(0.0);
     prof_end(C, HSP_PROF_SMOOTH, s, nu * jb);
   }
 }
@@ -607,177 +642,223 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
   };
   const int koff = 2 * (m + 1);  // hb offset of nu, h_kk, ||u_{k+1}||^2
   int it = 0;
-  while (it < maxit && any_active()) {
-    // residuals, their norms and the first basis vectors
-    for (size_t p = 0; p < nm; ++p) {
-      MemberSolve& S = ms[p];
-      if (S.act.empty()) continue;
-      const Member& mb = G.mem[p];
-      const BatchLayout& B = mb.B;
-      const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
-      st = upload_act(p);
-      if (st != HSP_OK) return st;
-      const int na = (int)S.act.size();
-      int* act_d = mptr<int>(mb, B.o_act);
-      cd* V = mptr<cd>(mb, B.o_V);
-      cd* hb = mptr<cd>(mb, B.o_hb);
-      BIdx bx, bV;
-      bx.ld = nf;
-      bx.map = act_d;
-      bV.ld = (size_t)(m + 1) * nf;
-      bV.map = act_d;
-      launch_stencil<double, double, double, double>(mb.C->fine, 1, S.x, S.b, V, 0.0, s, na, bx, bx, bV);
-      launch_bmultidot(V, 0, bV, 1, V, bV, nf, mptr<cd>(mb, B.o_part), B.nblk, hb + 2 * (m + 1), B.hs, na, s);
-      launch_bnormalize(V, bV, hb + 2 * (m + 1), B.hs, V, bV, nf, na, s);
-      HIPCHK(hipMemcpyAsync(S.hh.data(), hb, (size_t)na * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    for (size_t p = 0; p < nm; ++p) {
-      MemberSolve& S = ms[p];
-      std::vector<int> keep;
-      for (size_t zi = 0; zi < S.act.size(); ++zi) {
-        const int z = S.act[zi];
-        const double beta = std::sqrt(std::max(S.hh[zi * G.mem[p].B.hs + 2 * (m + 1)].re, 0.0));
-        if (beta <= tol * S.bnorm[z]) {
-          S.done[z] = 1;
-          continue;
-        }
-        S.ar[z].reset(m, beta);
-        keep.push_back(z);
-      }
-      S.act.swap(keep);
-      st = upload_act(p);
-      if (st != HSP_OK) return st;
-    }
-    if (!any_active()) break;
-    int k = 0;
-    for (; k < m && it < maxit && any_active(); ++k) {
-      std::vector<int> nact(nm);
-      for (size_t p = 0; p < nm; ++p) nact[p] = (int)ms[p].act.size();
-      const int rb = tile ? tile : default_tile(G, nact);
-      st = build_segments(G, nact, rb, s);
-      if (st != HSP_OK) return st;
-      // z_k = M v_k (slot k of every active right-hand side)
-      std::vector<PrecIO> io(nm);
-      for (size_t p = 0; p < nm; ++p) {
-        if (nact[p] == 0) continue;
-        const Member& mb = G.mem[p];
-        const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
-        int* act_d = mptr<int>(mb, mb.B.o_act);
-        io[p].br.ld = (size_t)(m + 1) * nf;
-        io[p].br.map = act_d;
-        io[p].bz.ld = (size_t)m * nf;
-        io[p].bz.map = act_d;
-        if (graph) {
-          long long* dyn = mptr<long long>(mb, mb.B.o_dyn);
-          ms[p].dyn = (long long)k * (long long)nf;
-          HIPCHK(hipMemcpyAsync(dyn, &ms[p].dyn, sizeof(long long), hipMemcpyHostToDevice, s));
-          io[p].br.dyn = dyn;
-          io[p].bz.dyn = dyn;
-          io[p].r = mptr<cd>(mb, mb.B.o_V);
-          io[p].z = mptr<cd>(mb, mb.B.o_Z);
-        } else {
-          io[p].r = mptr<cd>(mb, mb.B.o_V) + (size_t)k * nf;
-          io[p].z = mptr<cd>(mb, mb.B.o_Z) + (size_t)k * nf;
-        }
-      }
-      if (graph) {
-        st = precond_group_graph(G, nact, io, s);
-        if (st != HSP_OK) return st;
-      } else {
-        precond_group(G, nact, io, s);
-      }
-      // w = A z_k, delayed classical Gram-Schmidt: one projection pass
-      // (basis against u_k and w) and one update pass (v_k final, u_{k+1}
-      // and its norm)
-      for (size_t p = 0; p < nm; ++p) {
-        if (nact[p] == 0) continue;
-        const Member& mb = G.mem[p];
-        const BatchLayout& B = mb.B;
-        const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
-        int* act_d = mptr<int>(mb, B.o_act);
-        cd* V = mptr<cd>(mb, B.o_V);
-        cd* Z = mptr<cd>(mb, B.o_Z);
-        cd* w = mptr<cd>(mb, B.o_w);
-        cd* hb = mptr<cd>(mb, B.o_hb);
-        cd* part = mptr<cd>(mb, B.o_part);
-        BIdx bZk, bw, bVb;
-        bZk.ld = (size_t)m * nf;
-        bZk.map = act_d;
-        bw.ld = nf;
-        bVb.ld = (size_t)(m + 1) * nf;
-        bVb.map = act_d;
-        prof_begin(mb.C, HSP_PROF_KRYLOV, s);
-        launch_stencil<double, double, double, double>(mb.C->fine, 0, Z + (size_t)k * nf, (const cd*)nullptr, w, 0.0,
-                                                       s, nact[p], bZk, BIdx{}, bw);
-        launch_bdcgs_project(V, nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff, nact[p], s);
-        launch_bdcgs_update(V, nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk, hb + koff + 2, nact[p], s);
-        // matvec (z, k^2 read, w written); projection reads k+1 basis vectors
-        // and w; update reads k basis vectors, u_k and w and writes v_k, u_{k+1}
-        prof_end(mb.C, HSP_PROF_KRYLOV, s,
-                 (double)nact[p] * ((double)nf * (2.0 * sizeof(cd) + sizeof(double)) +
-                                    (double)nf * sizeof(cd) * (2.0 * k + 6.0)));
-        HIPCHK(hipMemcpyAsync(ms[p].hh.data(), hb, (size_t)nact[p] * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
-      }
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(s));
-      ++it;
+  // relative true residual of right-hand side z of member p (after the
+  // residual pass below)
+  auto true_relres = [&](size_t p, int z) {
+    const MemberSolve& S = ms[p];
+    return S.bnorm[z] > 0 ? std::sqrt(std::max(S.hh[(size_t)z * G.mem[p].B.hs + 2 * (m + 1)].re, 0.0)) / S.bnorm[z]
+                          : 0.0;
+  };
+  for (;;) {
+    while (it < maxit && any_active()) {
+      // residuals, their norms and the first basis vectors
       for (size_t p = 0; p < nm; ++p) {
         MemberSolve& S = ms[p];
         if (S.act.empty()) continue;
-        const size_t hs = G.mem[p].B.hs;
-        std::vector<int> keep, conv;
+        const Member& mb = G.mem[p];
+        const BatchLayout& B = mb.B;
+        const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
+        st = upload_act(p);
+        if (st != HSP_OK) return st;
+        const int na = (int)S.act.size();
+        int* act_d = mptr<int>(mb, B.o_act);
+        cd* w = mptr<cd>(mb, B.o_w);
+        cd* hb = mptr<cd>(mb, B.o_hb);
+        BIdx bx, bV, bw;
+        bx.ld = nf;
+        bx.map = act_d;
+        bV.ld = (size_t)(m + 1) * nf;
+        bV.map = act_d;
+        bw.ld = nf;
+        // r = b - A x in complex128, its norm, v_0 = r / ||r|| in the basis precision
+        launch_stencil<double, double, double, double>(mb.C->fine, 1, S.x, S.b, w, 0.0, s, na, bx, bx, bw);
+        launch_bmultidot(w, 0, bw, 1, w, bw, nf, mptr<cd>(mb, B.o_part), B.nblk, hb + 2 * (m + 1), B.hs, na, s);
+        if (G.mixed)
+          launch_bnormalize<float>(w, bw, hb + 2 * (m + 1), B.hs, mptr<cf>(mb, B.o_V), bV, nf, na, s);
+        else
+          launch_bnormalize<double>(w, bw, hb + 2 * (m + 1), B.hs, mptr<cd>(mb, B.o_V), bV, nf, na, s);
+        HIPCHK(hipMemcpyAsync(S.hh.data(), hb, (size_t)na * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
+      }
+      HIPCHK(hipStreamSynchronize(s));
+      for (size_t p = 0; p < nm; ++p) {
+        MemberSolve& S = ms[p];
+        std::vector<int> keep;
         for (size_t zi = 0; zi < S.act.size(); ++zi) {
           const int z = S.act[zi];
-          const cd* d = S.hh.data() + zi * hs;
-          Arnoldi& a = S.ar[z];
-          if (k > 0) {  // finalise column k-1 with the reorthogonalisation terms
-            for (int j = 0; j < k; ++j) a.at(j, k - 1) += cplx(d[j].re, d[j].im);
-            a.at(k, k - 1) = d[koff].re;
-          }
-          for (int j = 0; j < k; ++j) a.at(j, k) = cplx(d[k + 1 + j].re, d[k + 1 + j].im);
-          a.at(k, k) = cplx(d[koff + 1].re, d[koff + 1].im);
-          a.at(k + 1, k) = std::sqrt(std::max(d[koff + 2].re, 0.0));
-          const double est = a.lsq(k + 1, nullptr);
-          S.its[z] = it;
-          if (est <= tol * S.bnorm[z]) {
-            conv.push_back(z);
+          const double beta = std::sqrt(std::max(S.hh[zi * G.mem[p].B.hs + 2 * (m + 1)].re, 0.0));
+          if (beta <= tol * S.bnorm[z]) {
             S.done[z] = 1;
-          } else {
-            keep.push_back(z);
+            continue;
+          }
+          S.ar[z].reset(m, beta);
+          keep.push_back(z);
+        }
+        S.act.swap(keep);
+        st = upload_act(p);
+        if (st != HSP_OK) return st;
+      }
+      if (!any_active()) break;
+      int k = 0;
+      for (; k < m && it < maxit && any_active(); ++k) {
+        std::vector<int> nact(nm);
+        for (size_t p = 0; p < nm; ++p) nact[p] = (int)ms[p].act.size();
+        const int rb = tile ? tile : default_tile(G, nact);
+        st = build_segments(G, nact, rb, s);
+        if (st != HSP_OK) return st;
+        // z_k = M v_k (slot k of every active right-hand side)
+        std::vector<PrecIO> io(nm);
+        for (size_t p = 0; p < nm; ++p) {
+          if (nact[p] == 0) continue;
+          const Member& mb = G.mem[p];
+          const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
+          int* act_d = mptr<int>(mb, mb.B.o_act);
+          io[p].br.ld = (size_t)(m + 1) * nf;
+          io[p].br.map = act_d;
+          io[p].bz.ld = (size_t)m * nf;
+          io[p].bz.map = act_d;
+          // slot k of the basis (complex64 for the mixed-precision solver)
+          const size_t vk = graph ? 0 : (size_t)k * nf;
+          io[p].r32 = G.mixed ? 1 : 0;
+          io[p].r = G.mixed ? (const void*)(mptr<cf>(mb, mb.B.o_V) + vk) : (const void*)(mptr<cd>(mb, mb.B.o_V) + vk);
+          io[p].z = mptr<cd>(mb, mb.B.o_Z) + vk;
+          if (graph) {
+            long long* dyn = mptr<long long>(mb, mb.B.o_dyn);
+            ms[p].dyn = (long long)k * (long long)nf;
+            HIPCHK(hipMemcpyAsync(dyn, &ms[p].dyn, sizeof(long long), hipMemcpyHostToDevice, s));
+            io[p].br.dyn = dyn;
+            io[p].bz.dyn = dyn;
           }
         }
-        st = update(p, conv, k + 1);
-        if (st != HSP_OK) return st;
-        if (keep.size() != S.act.size()) {
-          S.act.swap(keep);
-          st = upload_act(p);
+        if (graph) {
+          st = precond_group_graph(G, nact, io, s);
           if (st != HSP_OK) return st;
+        } else {
+          precond_group(G, nact, io, s);
+        }
+        // w = A z_k, delayed classical Gram-Schmidt: one projection pass
+        // (basis against u_k and w) and one update pass (v_k final, u_{k+1}
+        // and its norm)
+        for (size_t p = 0; p < nm; ++p) {
+          if (nact[p] == 0) continue;
+          const Member& mb = G.mem[p];
+          const BatchLayout& B = mb.B;
+          const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
+          int* act_d = mptr<int>(mb, B.o_act);
+          cd* Z = mptr<cd>(mb, B.o_Z);
+          cd* w = mptr<cd>(mb, B.o_w);
+          cd* hb = mptr<cd>(mb, B.o_hb);
+          cd* part = mptr<cd>(mb, B.o_part);
+          BIdx bZk, bw, bVb;
+          bZk.ld = (size_t)m * nf;
+          bZk.map = act_d;
+          bw.ld = nf;
+          bVb.ld = (size_t)(m + 1) * nf;
+          bVb.map = act_d;
+          prof_begin(mb.C, HSP_PROF_KRYLOV, s);
+          launch_stencil<double, double, double, double>(mb.C->fine, 0, Z + (size_t)k * nf, (const cd*)nullptr, w, 0.0,
+                                                         s, nact[p], bZk, BIdx{}, bw);
+          if (G.mixed) {
+            cf* V = mptr<cf>(mb, B.o_V);
+            launch_bdcgs_project<float>(V, nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff, nact[p], s);
+            launch_bdcgs_update<float>(V, nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk, hb + koff + 2,
+                                       nact[p], s);
+          } else {
+            cd* V = mptr<cd>(mb, B.o_V);
+            launch_bdcgs_project<double>(V, nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff, nact[p], s);
+            launch_bdcgs_update<double>(V, nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk, hb + koff + 2,
+                                        nact[p], s);
+          }
+          // matvec (z, k^2 read, w written); projection reads k+1 basis vectors
+          // and w; update reads k basis vectors, u_k and w and writes v_k,
+          // u_{k+1} (basis vectors in the basis precision)
+          const double vb = G.mixed ? sizeof(cf) : sizeof(cd);
+          prof_end(mb.C, HSP_PROF_KRYLOV, s,
+                   (double)nact[p] * ((double)nf * (2.0 * sizeof(cd) + sizeof(double)) +
+                                      (double)nf * (vb * (2.0 * k + 4.0) + 2.0 * sizeof(cd))));
+          HIPCHK(hipMemcpyAsync(ms[p].hh.data(), hb, (size_t)nact[p] * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+        ++it;
+        for (size_t p = 0; p < nm; ++p) {
+          MemberSolve& S = ms[p];
+          if (S.act.empty()) continue;
+          const size_t hs = G.mem[p].B.hs;
+          std::vector<int> keep, conv;
+          for (size_t zi = 0; zi < S.act.size(); ++zi) {
+            const int z = S.act[zi];
+            const cd* d = S.hh.data() + zi * hs;
+            Arnoldi& a = S.ar[z];
+            if (k > 0) {  // finalise column k-1 with the reorthogonalisation terms
+              for (int j = 0; j < k; ++j) a.at(j, k - 1) += cplx(d[j].re, d[j].im);
+              a.at(k, k - 1) = d[koff].re;
+            }
+            for (int j = 0; j < k; ++j) a.at(j, k) = cplx(d[k + 1 + j].re, d[k + 1 + j].im);
+            a.at(k, k) = cplx(d[koff + 1].re, d[koff + 1].im);
+            a.at(k + 1, k) = std::sqrt(std::max(d[koff + 2].re, 0.0));
+            const double est = a.lsq(k + 1, nullptr);
+            S.its[z] = it;
+            if (est <= tol * S.bnorm[z]) {
+              conv.push_back(z);
+              S.done[z] = 1;
+            } else {
+              keep.push_back(z);
+            }
+          }
+          st = update(p, conv, k + 1);
+          if (st != HSP_OK) return st;
+          if (keep.size() != S.act.size()) {
+            S.act.swap(keep);
+            st = upload_act(p);
+            if (st != HSP_OK) return st;
+          }
         }
       }
+      // end of a restart cycle (or maxit): fold the active corrections into x
+      for (size_t p = 0; p < nm; ++p) {
+        st = update(p, ms[p].act, k);
+        if (st != HSP_OK) return st;
+      }
+      HIPCHK(hipStreamSynchronize(s));
     }
-    // end of a restart cycle (or maxit): fold the active corrections into x
+    // true residuals of every right-hand side
     for (size_t p = 0; p < nm; ++p) {
-      st = update(p, ms[p].act, k);
-      if (st != HSP_OK) return st;
+      const Member& mb = G.mem[p];
+      if (mb.R == 0) continue;
+      const BatchLayout& B = mb.B;
+      const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
+      BIdx bid;
+      bid.ld = nf;
+      cd* w = mptr<cd>(mb, B.o_w);
+      cd* hb = mptr<cd>(mb, B.o_hb);
+      launch_stencil<double, double, double, double>(mb.C->fine, 1, ms[p].x, ms[p].b, w, 0.0, s, mb.R, bid, bid,
+                                                     bid);
+      launch_bmultidot(w, 0, bid, 1, w, bid, nf, mptr<cd>(mb, B.o_part), B.nblk, hb + 2 * (m + 1), B.hs, mb.R, s);
+      HIPCHK(hipMemcpyAsync(ms[p].hh.data(), hb, (size_t)mb.R * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
     }
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
+    // A right-hand side whose true residual misses the tolerance although
+    // the least-squares estimate met it (with a complex64 basis the
+    // estimate is only as good as the stored basis) gets another restart
+    // cycle from its complex128 residual.
+    bool again = false;
+    for (size_t p = 0; p < nm && it < maxit; ++p) {
+      MemberSolve& S = ms[p];
+      for (int z = 0; z < G.mem[p].R; ++z)
+        if (S.done[z] && S.bnorm[z] > 0 && true_relres(p, z) > tol) {
+          S.done[z] = 0;
+          S.act.push_back(z);
+          again = true;
+        }
+    }
+    if (!again) break;
   }
-  // true residuals of every right-hand side
-  for (size_t p = 0; p < nm; ++p) {
-    const Member& mb = G.mem[p];
-    if (mb.R == 0) continue;
-    const BatchLayout& B = mb.B;
-    const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
-    BIdx bid;
-    bid.ld = nf;
-    cd* w = mptr<cd>(mb, B.o_w);
-    cd* hb = mptr<cd>(mb, B.o_hb);
-    launch_stencil<double, double, double, double>(mb.C->fine, 1, ms[p].x, ms[p].b, w, 0.0, s, mb.R, bid, bid, bid);
-    launch_bmultidot(w, 0, bid, 1, w, bid, nf, mptr<cd>(mb, B.o_part), B.nblk, hb + 2 * (m + 1), B.hs, mb.R, s);
-    HIPCHK(hipMemcpyAsync(ms[p].hh.data(), hb, (size_t)mb.R * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
-    if (conj) launch_convert<double, double>(ms[p].x, ms[p].x, (size_t)mb.R * nf, 1, s);
-  }
+  if (conj)
+    for (size_t p = 0; p < nm; ++p)
+      if (G.mem[p].R > 0)
+        launch_convert<double, double>(ms[p].x, ms[p].x,
+                                       (size_t)G.mem[p].R * ((size_t)G.mem[p].C->P.nf1 * G.mem[p].C->P.nf2), 1, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   bool all = true;
@@ -786,18 +867,20 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
     const Member& mb = G.mem[p];
     const MemberSolve& S = ms[p];
     for (int z = 0; z < mb.R; ++z, ++o) {
-      const double rr =
-          S.bnorm[z] > 0 ? std::sqrt(std::max(S.hh[(size_t)z * mb.B.hs + 2 * (m + 1)].re, 0.0)) / S.bnorm[z] : 0.0;
+      const double rr = true_relres(p, z);
       if (iters) iters[o] = S.its[z];
       if (relres) relres[o] = rr;
-      if (!S.done[z] && rr > tol) all = false;
+      if (S.bnorm[z] > 0 && rr > tol) all = false;
     }
   }
   if (!all) return fail(HSP_ENOCONV, "maxit reached before the tolerance for some right-hand sides");
   return HSP_OK;
 }
 
-hsp_status group_precond(Group& G, const void* const* r, void* const* z, int tile, int flags, hipStream_t s) {
+// r32: the right-hand sides are complex64 (the Krylov basis of the
+// mixed-precision solver), else complex128.
+hsp_status group_precond(Group& G, const void* const* r, void* const* z, int tile, int flags, hipStream_t s,
+                         int r32 = 0) {
   const size_t nm = G.mem.size();
   std::vector<int> nact(nm);
   std::vector<PrecIO> io(nm);
@@ -807,7 +890,8 @@ hsp_status group_precond(Group& G, const void* const* r, void* const* z, int til
     if (mb.R == 0) continue;
     if (!r[p] || !z[p] || r[p] == z[p]) return fail(HSP_EINVAL, "null or aliased vectors");
     const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
-    io[p].r = (const cd*)r[p];
+    io[p].r = r[p];
+    io[p].r32 = r32;
     io[p].z = (cd*)z[p];
     io[p].br.ld = nf;
     io[p].bz.ld = nf;
@@ -895,9 +979,17 @@ hsp_status hsp_tune_batch(hsp_handle C, int nrhs, int restart, void* ws, size_t 
   hipStream_t s = S_(stream);
   const Member& mb = G.mem[0];
   const size_t nf = (size_t)C->P.nf1 * C->P.nf2;
-  cd* r = mptr<cd>(mb, mb.B.o_V);
+  // constant right-hand sides in the type the solver hands to the
+  // preconditioner (its Krylov basis)
+  cd* w = mptr<cd>(mb, mb.B.o_w);
   cd* z = mptr<cd>(mb, mb.B.o_Z);
-  launch_fill(r, (size_t)nrhs * nf, mk<double>(1.0, 0.0), s);
+  launch_fill(w, (size_t)nrhs * nf, mk<double>(1.0, 0.0), s);
+  const void* r = w;
+  if (G.mixed) {
+    cf* r32 = mptr<cf>(mb, mb.B.o_V);
+    launch_convert<float, double>(w, r32, (size_t)nrhs * nf, 0, s);
+    r = r32;
+  }
   const void* rr[1] = {r};
   void* zz[1] = {z};
   hipEvent_t e0, e1;
@@ -912,10 +1004,11 @@ hsp_status hsp_tune_batch(hsp_handle C, int nrhs, int restart, void* ws, size_t 
   double best_ms = 1e300;
   hipError_t err = hipSuccess;
   for (int rb = 1; rb <= kMaxTile && err == hipSuccess && st == HSP_OK; rb *= 2) {
-    st = group_precond(G, rr, zz, rb, 0, s);  // warm-up
+    st = group_precond(G, rr, zz, rb, 0, s, G.mixed ? 1 : 0);  // warm-up
     if (st != HSP_OK) break;
     err = hipEventRecord(e0, s);
-    for (int rep = 0; rep < 2 && err == hipSuccess && st == HSP_OK; ++rep) st = group_precond(G, rr, zz, rb, 0, s);
+    for (int rep = 0; rep < 2 && err == hipSuccess && st == HSP_OK; ++rep)
+      st = group_precond(G, rr, zz, rb, 0, s, G.mixed ? 1 : 0);
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0;

@@ -58,9 +58,12 @@ void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipS
 // pre:  xo = x_nu of nu Jacobi steps from 0, res = r - A x_nu (complex128)
 // post: x_0 = xin + P ec, nu Jacobi steps, zo = x_nu (complex128)
 bool smooth_fused_ok(const LevelDev& L, int nu);
-void launch_smooth_pre(const LevelDev& L, int nu, double w, const cd* r, BIdx br, cf* xo, BIdx bxo, cd* res,
+// (r is complex128 or complex64: TR = double or float)
+template <class TR>
+void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cd* res,
                        BIdx bres, int nb, hipStream_t s);
-void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cd* r, BIdx br,
+template <class TR>
+void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cx<TR>* r, BIdx br,
                         const cf* xin, BIdx bxin, const cf* ec, BIdx bec, cd* zo, BIdx bzo, int nb, hipStream_t s);
 
 // ---- slab factorization and sweep stages (slab.hip) ------------------------
@@ -201,12 +204,17 @@ void launch_bmultiaxpy_norm(const cd* V, size_t ldj, BIdx bv, int cnt, const cd*
 // V^H w, then nu and h_kk at hb[.. + off], hb[.. + off + 1].  update: slot k
 // <- v_k (final), slot k+1 <- u_{k+1} = w - V p - h_kk v_k, ||u_{k+1}||^2 at
 // nrm2[z ldh].
-void launch_bdcgs_project(const cd* V, size_t ldj, BIdx bv, int k, const cd* w, BIdx bw, size_t n, cd* partial,
-                          int nblocks, cd* hb, size_t ldh, int off, int nb, hipStream_t s);
-void launch_bdcgs_update(cd* V, size_t ldj, BIdx bv, int k, const cd* hb, size_t ldh, int off, const cd* w, BIdx bw,
-                         size_t n, cd* partial, int nblocks, cd* nrm2, int nb, hipStream_t s);
-// v_z = w_z / sqrt(re(nrm2[z ldn]))
-void launch_bnormalize(const cd* w, BIdx bw, const cd* nrm2, size_t ldn, cd* v, BIdx bv, size_t n, int nb,
+// The basis is complex128 (TV = double) or complex64 (TV = float; the
+// products and sums are still formed in double).
+template <class TV>
+void launch_bdcgs_project(const cx<TV>* V, size_t ldj, BIdx bv, int k, const cd* w, BIdx bw, size_t n,
+                          cd* partial, int nblocks, cd* hb, size_t ldh, int off, int nb, hipStream_t s);
+template <class TV>
+void launch_bdcgs_update(cx<TV>* V, size_t ldj, BIdx bv, int k, const cd* hb, size_t ldh, int off, const cd* w,
+                         BIdx bw, size_t n, cd* partial, int nblocks, cd* nrm2, int nb, hipStream_t s);
+// v_z = w_z / sqrt(re(nrm2[z ldn])), rounded to TV
+template <class TV>
+void launch_bnormalize(const cd* w, BIdx bw, const cd* nrm2, size_t ldn, cx<TV>* v, BIdx bv, size_t n, int nb,
                        hipStream_t s);
 // b = h2 * f / (alpha_1(x_i) alpha_2(y_k)); ixn, iyn = 1/alpha at nodes 0..n+1
 void launch_scale_rhs_arrays(int n1, int n2, double h2, const cd* ixn, const cd* iyn, const cd* f, cd* b,

@@ -97,18 +97,19 @@ __device__ __forceinline__ void jacobi_region(const LevelDev& L, int i0, int k0,
 // (formed in complex64 from the row / column factors and k^2).  All global
 // loads of a thread are issued before any is used (one memory round trip for
 // the whole tile); the axes must already be in LDS.
-template <int NU>
+template <int NU, class TR>
 struct NodeLoads {
   static constexpr int NI = (SmoothTile<NU>::NE + 255) / 256;
-  cd r[NI];
+  cx<TR> r[NI];
   double k2[NI];
 };
 
-template <int NU>
-__device__ __forceinline__ void fetch_nodes(const LevelDev& L, int i0, int k0, const cd* r, NodeLoads<NU>& ld) {
+template <int NU, class TR>
+__device__ __forceinline__ void fetch_nodes(const LevelDev& L, int i0, int k0, const cx<TR>* r,
+                                            NodeLoads<NU, TR>& ld) {
   using S = SmoothTile<NU>;
 #pragma unroll
-  for (int q = 0; q < NodeLoads<NU>::NI; ++q) {
+  for (int q = 0; q < NodeLoads<NU, TR>::NI; ++q) {
     const int idx = min((int)threadIdx.x + 256 * q, S::NE - 1);
     const int i = i0 + idx / S::EY, k = k0 + idx % S::EY;
     const bool in = i >= 1 && i <= L.n1 && k >= 1 && k <= L.n2;
@@ -118,14 +119,14 @@ __device__ __forceinline__ void fetch_nodes(const LevelDev& L, int i0, int k0, c
   }
 }
 
-template <int NU>
-__device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, double w, const NodeLoads<NU>& ld,
+template <int NU, class TR>
+__device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, double w, const NodeLoads<NU, TR>& ld,
                                             const Axes5& ax, cf* rr, cf* c11s, cf* dws) {
   using S = SmoothTile<NU>;
   const cf wt = cvt<float>(mk<double>(w, 0.0));
   const float h2 = (float)L.h2;
 #pragma unroll
-  for (int q = 0; q < NodeLoads<NU>::NI; ++q) {
+  for (int q = 0; q < NodeLoads<NU, TR>::NI; ++q) {
     const int idx = (int)threadIdx.x + 256 * q;
     if (idx >= S::NE) break;
     const int ti = idx / S::EY, tk = idx % S::EY;
@@ -141,8 +142,8 @@ __device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, d
   }
 }
 
-template <int NU>
-__global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const cd* __restrict__ r, BIdx br,
+template <int NU, class TR>
+__global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const cx<TR>* __restrict__ r, BIdx br,
                                                     cf* __restrict__ xo, BIdx bxo, cd* __restrict__ res, BIdx bres) {
   using S = SmoothTile<NU>;
   constexpr int EY = S::EY, NE = S::NE, H = S::H;
@@ -154,11 +155,11 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
   r += br.off(z);
   xo += bxo.off(z);
   res += bres.off(z);
-  NodeLoads<NU> ld;
-  fetch_nodes<NU>(L, i0, k0, r, ld);
+  NodeLoads<NU, TR> ld;
+  fetch_nodes<NU, TR>(L, i0, k0, r, ld);
   load_axes(L, i0, k0, S::EX, EY, ax);
   __syncthreads();
-  store_nodes<NU>(L, i0, k0, w, ld, ax, rr, c11s, dws);
+  store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, c11s, dws);
   __syncthreads();
   // x_1 = (w D^{-1}) r
   for (int idx = threadIdx.x; idx < NE; idx += blockDim.x) {
@@ -194,12 +195,12 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
     if (k < n2) cfma(a, cn, cvt<double>(cur[e + 1]));
     if (i < n1) cfma(a, ce, cvt<double>(cur[e + EY]));
     xo[g] = cur[e];
-    res[g] = r[g] - a;
+    res[g] = cvt<double>(r[g]) - a;
   }
 }
 
-template <int NU>
-__global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr, double w, const cd* __restrict__ r,
+template <int NU, class TR>
+__global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr, double w, const cx<TR>* __restrict__ r,
                                                      BIdx br, const cf* __restrict__ xin, BIdx bxin,
                                                      const cf* __restrict__ ec, BIdx bec, cd* __restrict__ zo,
                                                      BIdx bzo) {
@@ -214,11 +215,11 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
   xin += bxin.off(z);
   ec += bec.off(z);
   zo += bzo.off(z);
-  NodeLoads<NU> ld;
-  fetch_nodes<NU>(L, i0, k0, r, ld);
+  NodeLoads<NU, TR> ld;
+  fetch_nodes<NU, TR>(L, i0, k0, r, ld);
   // x_0 = x + P e_c (prolongation sums in double, as k_prolong_add); the
   // taps of all nodes of the thread are fetched first
-  constexpr int NI = NodeLoads<NU>::NI;
+  constexpr int NI = NodeLoads<NU, TR>::NI;
   cf x0[NI], v[NI][2][2];
   double wgt[NI][2][2];
 #pragma unroll
@@ -239,7 +240,7 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
   }
   load_axes(L, i0, k0, S::EX, EY, ax);
   __syncthreads();
-  store_nodes<NU>(L, i0, k0, w, ld, ax, rr, c11s, dws);
+  store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, c11s, dws);
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
     const int idx = (int)threadIdx.x + 256 * q;
@@ -280,32 +281,43 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
 
 bool smooth_fused_ok(const LevelDev& L, int nu) { return L.kind == 5 && L.xmap == nullptr && nu >= 1 && nu <= 3; }
 
-void launch_smooth_pre(const LevelDev& L, int nu, double w, const cd* r, BIdx br, cf* xo, BIdx bxo, cd* res,
+template <class TR>
+void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cd* res,
                        BIdx bres, int nb, hipStream_t s) {
   if (nb < 1) return;
   const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
   switch (nu) {
-    case 1: hipLaunchKernelGGL((k_smooth_pre<1>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
-    case 2: hipLaunchKernelGGL((k_smooth_pre<2>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
-    default: hipLaunchKernelGGL((k_smooth_pre<3>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+    case 1: hipLaunchKernelGGL((k_smooth_pre<1, TR>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+    case 2: hipLaunchKernelGGL((k_smooth_pre<2, TR>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+    default: hipLaunchKernelGGL((k_smooth_pre<3, TR>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
   }
 }
 
-void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cd* r, BIdx br,
+template <class TR>
+void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cx<TR>* r, BIdx br,
                         const cf* xin, BIdx bxin, const cf* ec, BIdx bec, cd* zo, BIdx bzo, int nb, hipStream_t s) {
   if (nb < 1) return;
   const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
   switch (nu) {
     case 1:
-      hipLaunchKernelGGL((k_smooth_post<1>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      hipLaunchKernelGGL((k_smooth_post<1, TR>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
       break;
     case 2:
-      hipLaunchKernelGGL((k_smooth_post<2>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      hipLaunchKernelGGL((k_smooth_post<2, TR>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
       break;
     default:
-      hipLaunchKernelGGL((k_smooth_post<3>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      hipLaunchKernelGGL((k_smooth_post<3, TR>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
       break;
   }
 }
+
+#define INST(TR)                                                                                                \
+  template void launch_smooth_pre<TR>(const LevelDev&, int, double, const cx<TR>*, BIdx, cf*, BIdx, cd*, BIdx,  \
+                                      int, hipStream_t);                                                        \
+  template void launch_smooth_post<TR>(const LevelDev&, const TransferDev&, int, double, const cx<TR>*, BIdx,   \
+                                       const cf*, BIdx, const cf*, BIdx, cd*, BIdx, int, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
 
 }  // namespace hsp

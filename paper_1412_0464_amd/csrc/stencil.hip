@@ -158,6 +158,9 @@ INST(float, float, double, float)
 INST(double, double, double, float)
 INST(double, float, float, float)
 INST(float, float, double, double)
+INST(double, float, float, double)
+INST(float, float, float, double)
+INST(double, double, float, double)
 #undef INST
 
 }  // namespace hsp
