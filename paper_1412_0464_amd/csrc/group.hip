@@ -272,7 +272,7 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     cx<T>* xa = mptr<cx<T>>(mb, B.o_xa);
     cx<T>* xb = mptr<cx<T>>(mb, B.o_xb);
     if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
-      cd* res = mptr<cd>(mb, B.o_res);
+      cf* res = mptr<cf>(mb, B.o_res);  // complex64 residual of the fused smoother
       prof_begin(C, HSP_PROF_SMOOTH, s);
       if (io[p].r32)
         launch_smooth_pre<float>(C->fine, nu, wj, static_cast<const cf*>(io[p].r), io[p].br,
@@ -280,10 +280,12 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
       else
         launch_smooth_pre<double>(C->fine, nu, wj, static_cast<const cd*>(io[p].r), io[p].br,
                                   reinterpret_cast<cf*>(xa), bf, res, bf, na, s);
-      prof_end(C, HSP_PROF_SMOOTH, s, (double)na * nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)));
+      // r read, k^2 read, the last iterate and the residual written
+      const double rb = io[p].r32 ? sizeof(cf) : sizeof(cd);
+      prof_end(C, HSP_PROF_SMOOTH, s, (double)na * nf * (rb + sizeof(double) + 2.0 * sizeof(cf)));
       prof_begin(C, HSP_PROF_TRANSFER, s);
-      launch_restrict<double, T>(C->tr, res, mptr<cx<T>>(mb, B.o_rc), s, na, bf, bdd);
-      prof_end(C, HSP_PROF_TRANSFER, s, (double)na * ((double)nf * sizeof(cd) + (double)nd * sizeof(cx<T>)));
+      launch_restrict<float, T>(C->tr, res, mptr<cx<T>>(mb, B.o_rc), s, na, bf, bdd);
+      prof_end(C, HSP_PROF_TRANSFER, s, (double)na * ((double)nf * sizeof(cf) + (double)nd * sizeof(cx<T>)));
       launch_zero<T>(mptr<cx<T>>(mb, B.o_ec), (size_t)na * nd, s);
       continue;
     }
@@ -378,9 +380,10 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
       else
         launch_smooth_post<double>(C->fine, C->tr, nu, wj, static_cast<const cd*>(io[p].r), io[p].br, xin, bf, ec,
                                    bdd, io[p].z, io[p].bz, na, s);
+      // r, the pre-smoothed iterate, k^2 and the coarse correction read, z written
+      const double rb = io[p].r32 ? sizeof(cf) : sizeof(cd);
       prof_end(C, HSP_PROF_SMOOTH, s,
-               (double)na * ((double)nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)) +
-                             (double)nd * sizeof(cx<T>)));
+               (double)na * ((double)nf * (rb + sizeof(cf) + sizeof(double) + sizeof(cd)) + (double)nd * sizeof(cx<T>)));
       continue;
     }
     if (nu > 0 && nu % 2 == 0) std::swap(xa, xb);  // where the pre-smoothing ended

@@ -438,16 +438,16 @@ void run_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
   const size_t nc = (size_t)P.nc1 * P.nc2;
   if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
     // each smoothing phase as one kernel (LDS tiles with a halo of nu nodes)
-    cd* res = C->at<double>(P.o_tgres);
+    cf* res = C->at<float>(P.o_tgres);  // complex64 residual of the fused smoother
     cx<T>* rc = C->at<T>(P.o_tgrc);
     cx<T>* ec = C->at<T>(P.o_tgec);
     prof_begin(C, HSP_PROF_SMOOTH, s);
     launch_smooth_pre(C->fine, nu, wj, r, BIdx{}, reinterpret_cast<cf*>(xa), BIdx{}, res, BIdx{}, 1, s);
     // r, k^2 read; x_nu and the residual written
-    prof_end(C, HSP_PROF_SMOOTH, s, (double)nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cx<T>)));
+    prof_end(C, HSP_PROF_SMOOTH, s, (double)nf * (sizeof(cd) + sizeof(double) + 2.0 * sizeof(cf)));
     prof_begin(C, HSP_PROF_TRANSFER, s);
-    launch_restrict<double, T>(C->tr, res, rc, s);
-    prof_end(C, HSP_PROF_TRANSFER, s, (double)nf * sizeof(cd) + (double)nc * sizeof(cx<T>));
+    launch_restrict<float, T>(C->tr, res, rc, s);
+    prof_end(C, HSP_PROF_TRANSFER, s, (double)nf * sizeof(cf) + (double)nc * sizeof(cx<T>));
     run_sweep<T>(C, rc, ec, s);
     prof_begin(C, HSP_PROF_SMOOTH, s);
     launch_smooth_post(C->fine, C->tr, nu, wj, r, BIdx{}, reinterpret_cast<const cf*>(xa), BIdx{},

@@ -60,7 +60,7 @@ void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipS
 bool smooth_fused_ok(const LevelDev& L, int nu);
 // (r is complex128 or complex64: TR = double or float)
 template <class TR>
-void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cd* res,
+void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cf* res,
                        BIdx bres, int nb, hipStream_t s);
 template <class TR>
 void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cx<TR>* r, BIdx br,

@@ -144,7 +144,7 @@ __device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, d
 
 template <int NU, class TR>
 __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const cx<TR>* __restrict__ r, BIdx br,
-                                                    cf* __restrict__ xo, BIdx bxo, cd* __restrict__ res, BIdx bres) {
+                                                    cf* __restrict__ xo, BIdx bxo, cf* __restrict__ res, BIdx bres) {
   using S = SmoothTile<NU>;
   constexpr int EY = S::EY, NE = S::NE, H = S::H;
   __shared__ cf xa[NE], xb[NE], rr[NE], c11s[NE], dws[NE];
@@ -177,25 +177,17 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
     cur = nxt;
     nxt = t;
   }
-  // x_nu and the residual r - A x_nu in double (stencil_coefs arithmetic)
+  // x_nu and the residual r - A x_nu, in complex64 from the tile like the
+  // smoothing steps
   for (int idx = threadIdx.x; idx < kTX * kTY; idx += blockDim.x) {
     const int ti = H + idx / kTY, tk = H + idx % kTY;
     const int i = i0 + ti, k = k0 + tk;
     if (i > n1 || k > n2) continue;
     const int e = ti * EY + tk;
     const size_t g = (size_t)(i - 1) * n2 + (k - 1);
-    const cd ian = L.xB[i], ikn = L.yB[k];
-    cd cw = -(L.xA[i - 1] * ikn), ce = -(L.xA[i] * ikn);
-    cd cs = -(L.yA[k - 1] * ian), cn = -(L.yA[k] * ian);
-    const cd c11 = -(cw + ce + cs + cn) - (L.h2 * L.k2[g]) * (ian * ikn);
-    cd a = mk<double>(0, 0);
-    if (i > 1) cfma(a, cw, cvt<double>(cur[e - EY]));
-    if (k > 1) cfma(a, cs, cvt<double>(cur[e - 1]));
-    cfma(a, c11, cvt<double>(cur[e]));
-    if (k < n2) cfma(a, cn, cvt<double>(cur[e + 1]));
-    if (i < n1) cfma(a, ce, cvt<double>(cur[e + EY]));
+    const cf a = apply5<EY>(ax, cur, e, ti, tk, c11s[e], i > 1, i < n1, k > 1, k < n2);
     xo[g] = cur[e];
-    res[g] = cvt<double>(r[g]) - a;
+    res[g] = rr[e] - a;
   }
 }
 
@@ -282,7 +274,7 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
 bool smooth_fused_ok(const LevelDev& L, int nu) { return L.kind == 5 && L.xmap == nullptr && nu >= 1 && nu <= 3; }
 
 template <class TR>
-void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cd* res,
+void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cf* res,
                        BIdx bres, int nb, hipStream_t s) {
   if (nb < 1) return;
   const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
@@ -312,7 +304,7 @@ void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double
 }
 
 #define INST(TR)                                                                                                \
-  template void launch_smooth_pre<TR>(const LevelDev&, int, double, const cx<TR>*, BIdx, cf*, BIdx, cd*, BIdx,  \
+  template void launch_smooth_pre<TR>(const LevelDev&, int, double, const cx<TR>*, BIdx, cf*, BIdx, cf*, BIdx,  \
                                       int, hipStream_t);                                                        \
   template void launch_smooth_post<TR>(const LevelDev&, const TransferDev&, int, double, const cx<TR>*, BIdx,   \
                                        const cf*, BIdx, const cf*, BIdx, cd*, BIdx, int, hipStream_t);

@@ -94,6 +94,8 @@ void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipS
 
 template void launch_restrict<double, double>(const TransferDev&, const cd*, cd*, hipStream_t, int, BIdx, BIdx);
 template void launch_restrict<double, float>(const TransferDev&, const cd*, cf*, hipStream_t, int, BIdx, BIdx);
+template void launch_restrict<float, float>(const TransferDev&, const cf*, cf*, hipStream_t, int, BIdx, BIdx);
+template void launch_restrict<float, double>(const TransferDev&, const cf*, cd*, hipStream_t, int, BIdx, BIdx);
 template void launch_prolong_add<double, double>(const TransferDev&, const cd*, cd*, hipStream_t, int, BIdx, BIdx);
 template void launch_prolong_add<float, float>(const TransferDev&, const cf*, cf*, hipStream_t, int, BIdx, BIdx);
 template void launch_prolong_add<float, double>(const TransferDev&, const cf*, cd*, hipStream_t, int, BIdx, BIdx);
