@@ -240,16 +240,17 @@ __global__ void __launch_bounds__(256) k_breduce(const cd* __restrict__ partial,
   if (threadIdx.x == 0) out[(size_t)z * ldo + j] = r;
 }
 
-__global__ void __launch_bounds__(256) k_bmultiaxpy(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
+template <class TV>
+__global__ void __launch_bounds__(256) k_bmultiaxpy(const cx<TV>* __restrict__ V, size_t ldj, BIdx bv, int cnt,
                                                     const cd* __restrict__ h, size_t ldh, cd* __restrict__ w,
                                                     BIdx bw, size_t n, int sub) {
   const int z = blockIdx.y;
-  const cd* v = V + bv.off(z);
+  const cx<TV>* v = V + bv.off(z);
   const cd* hz = h + (size_t)z * ldh;
   w += bw.off(z);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     cd acc = mk<double>(0, 0);
-    for (int j = 0; j < cnt; ++j) cfma(acc, hz[j], v[(size_t)j * ldj + i]);
+    for (int j = 0; j < cnt; ++j) cfma(acc, hz[j], cvt<double>(v[(size_t)j * ldj + i]));
     w[i] = sub ? (w[i] - acc) : (w[i] + acc);
   }
 }
@@ -442,12 +443,17 @@ void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BI
   hipLaunchKernelGGL(k_bmultidot, dim3(nblocks, tiles, nb), dim3(256), 0, s, V, ldj, bv, cnt, w, bw, n, partial);
   hipLaunchKernelGGL(k_breduce, dim3(cnt, nb), dim3(256), 0, s, (const cd*)partial, nblocks, cnt, out, ldo);
 }
-void launch_bmultiaxpy(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw, size_t n,
-                       int sub, int nb, hipStream_t s) {
+template <class TV>
+void launch_bmultiaxpy(const cx<TV>* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw,
+                       size_t n, int sub, int nb, hipStream_t s) {
   if (nb < 1 || cnt < 1) return;
-  hipLaunchKernelGGL(k_bmultiaxpy, dim3(nblk_batch(n, nb), nb), dim3(256), 0, s, V, ldj, bv, cnt, h, ldh, w, bw, n,
-                     sub);
+  hipLaunchKernelGGL(k_bmultiaxpy<TV>, dim3(nblk_batch(n, nb), nb), dim3(256), 0, s, V, ldj, bv, cnt, h, ldh, w, bw,
+                     n, sub);
 }
+template void launch_bmultiaxpy<double>(const cd*, size_t, BIdx, int, const cd*, size_t, cd*, BIdx, size_t, int, int,
+                                        hipStream_t);
+template void launch_bmultiaxpy<float>(const cf*, size_t, BIdx, int, const cd*, size_t, cd*, BIdx, size_t, int, int,
+                                       hipStream_t);
 void launch_bmultiaxpy_norm(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw,
                             size_t n, cd* partial, int nblocks, cd* nrm2, size_t ldo, int nb, hipStream_t s) {
   if (nb < 1) return;

@@ -62,10 +62,11 @@ BatchLayout batch_layout(const Plan& P, int R, int m) {
   B.o_ctr = c.take(2 * slots * sizeof(int));
   B.nblk = batch_dot_blocks(nf, R);
   B.hs = 2 * (size_t)(m + 2) + 2;
-  // Krylov basis in the precision of the preconditioner (complex64 for the
-  // mixed-precision solver); everything else of FGMRES in complex128
+  // Krylov basis V and preconditioned vectors Z in the precision of the
+  // preconditioner (complex64 for the mixed-precision solver); everything
+  // else of FGMRES in complex128
   B.o_V = c.take((size_t)R * (m + 1) * nf * T);
-  B.o_Z = c.take((size_t)R * m * nf * sizeof(cd));
+  B.o_Z = c.take((size_t)R * m * nf * T);
   B.o_w = c.take(R * nf * sizeof(cd));
   B.o_bc = c.take(R * nf * sizeof(cd));
   B.o_part = c.take((size_t)2 * R * (m + 1) * B.nblk * sizeof(cd));
@@ -103,7 +104,8 @@ struct PrecIO {
   const void* r = nullptr;
   int r32 = 0;  // r is complex64 (else complex128)
   BIdx br;
-  cd* z = nullptr;
+  void* z = nullptr;
+  int z32 = 0;  // z is complex64 (else complex128)
   BIdx bz;
 };
 
@@ -363,7 +365,11 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     bf.ld = nf;
     bdd.ld = nd;
     if (!P.two_grid) {
-      launch_convert<double, T>(mptr<cx<T>>(mb, B.o_swu), io[p].z, nf, 0, s, na, bf, io[p].bz);
+      if (io[p].z32)
+        launch_convert<float, T>(mptr<cx<T>>(mb, B.o_swu), static_cast<cf*>(io[p].z), nf, 0, s, na, bf, io[p].bz);
+      else
+        launch_convert<double, T>(mptr<cx<T>>(mb, B.o_swu), static_cast<cd*>(io[p].z), nf, 0, s, na, bf,
+                                  io[p].bz);
       continue;
     }
     const double wj = C->opt.omega_jac;
@@ -374,16 +380,24 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
       prof_begin(C, HSP_PROF_SMOOTH, s);
       const cf* xin = reinterpret_cast<const cf*>(xa);
       const cf* ec = reinterpret_cast<const cf*>(mptr<cx<T>>(mb, B.o_ec));
-      if (io[p].r32)
-        launch_smooth_post<float>(C->fine, C->tr, nu, wj, static_cast<const cf*>(io[p].r), io[p].br, xin, bf, ec,
-                                  bdd, io[p].z, io[p].bz, na, s);
+      auto post = [&](auto rtag, auto ztag) {
+        using TR = decltype(rtag);
+        using TZ = decltype(ztag);
+        launch_smooth_post<TR, TZ>(C->fine, C->tr, nu, wj, static_cast<const cx<TR>*>(io[p].r), io[p].br, xin, bf,
+                                   ec, bdd, static_cast<cx<TZ>*>(io[p].z), io[p].bz, na, s);
+      };
+      if (io[p].r32 && io[p].z32)
+        post(0.0f, 0.0f);
+      else if (io[p].r32)
+        post(0.0f, 0.0);
+      else if (io[p].z32)
+        post(0.0, 0.0f);
       else
-        launch_smooth_post<double>(C->fine, C->tr, nu, wj, static_cast<const cd*>(io[p].r), io[p].br, xin, bf, ec,
-                                   bdd, io[p].z, io[p].bz, na, s);
+        post(0.0, 0.0);
       // r, the pre-smoothed iterate, k^2 and the coarse correction read, z written
-      const double rb = io[p].r32 ? sizeof(cf) : sizeof(cd);
+      const double rb = io[p].r32 ? sizeof(cf) : sizeof(cd), zb = io[p].z32 ? sizeof(cf) : sizeof(cd);
       prof_end(C, HSP_PROF_SMOOTH, s,
-               (double)na * ((double)nf * (rb + sizeof(cf) + sizeof(double) + sizeof(cd)) + (double)nd * sizeof(cx<T>)));
+               (double)na * ((double)nf * (rb + sizeof(cf) + sizeof(double) + zb) + (double)nd * sizeof(cx<T>)));
       continue;
     }
     if (nu > 0 && nu % 2 == 0) std::swap(xa, xb);  // where the pre-smoothing ended
@@ -391,27 +405,36 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     launch_prolong_add<T, T>(C->tr, mptr<cx<T>>(mb, B.o_ec), xa, s, na, bdd, bf);
     prof_end(C, HSP_PROF_TRANSFER, s, (double)na * ((double)nd * sizeof(cx<T>) + 2.0 * nf * sizeof(cx<T>)));
     if (nu == 0) {
-      launch_convert<double, T>(xa, io[p].z, nf, 0, s, na, bf, io[p].bz);
+      if (io[p].z32)
+        launch_convert<float, T>(xa, static_cast<cf*>(io[p].z), nf, 0, s, na, bf, io[p].bz);
+      else
+        launch_convert<double, T>(xa, static_cast<cd*>(io[p].z), nf, 0, s, na, bf, io[p].bz);
       continue;
     }
     const double jb = (double)na * nf * (sizeof(cd) + 2.0 * sizeof(cx<T>) + sizeof(double));
     prof_begin(C, HSP_PROF_SMOOTH, s);
-    auto postsmooth = [&](auto tag) {
-      using TR = decltype(tag);
+    auto postsmooth = [&](auto rtag, auto ztag) {
+      using TR = decltype(rtag);
+      using TZ = decltype(ztag);
       const cx<TR>* r = static_cast<const cx<TR>*>(io[p].r);
       for (int k = 0; k < nu; ++k) {
         if (k == nu - 1) {
-          launch_stencil<T, T, TR, double>(C->fine, 2, xa, r, io[p].z, wj, s, na, bf, io[p].br, io[p].bz);
+          launch_stencil<T, T, TR, TZ>(C->fine, 2, xa, r, static_cast<cx<TZ>*>(io[p].z), wj, s, na, bf, io[p].br,
+                                       io[p].bz);
         } else {
           launch_stencil<T, T, TR, T>(C->fine, 2, xa, r, xb, wj, s, na, bf, io[p].br, bf);
           std::swap(xa, xb);
         }
       }
     };
-    if (io[p].r32)
-      postsmooth(0.0f);
+    if (io[p].r32 && io[p].z32)
+      postsmooth(0.0f, 0.0f);
+    else if (io[p].r32)
+      postsmooth(0.0f, 0.0);
+    else if (io[p].z32)
+      postsmooth(0.0, 0.0f);
     else
-      postsmooth(0.0);
+      postsmooth(0.0, 0.0);
     prof_end(C, HSP_PROF_SMOOTH, s, nu * jb);
   }
 }
@@ -633,7 +656,10 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
     bz.map = upd_d;
     bx.ld = nf;
     bx.map = upd_d;
-    launch_bmultiaxpy(mptr<cd>(mb, mb.B.o_Z), nf, bz, k, ydev, m, S.x, bx, nf, 0, (int)S.upd.size(), s);
+    if (G.mixed)
+      launch_bmultiaxpy<float>(mptr<cf>(mb, mb.B.o_Z), nf, bz, k, ydev, m, S.x, bx, nf, 0, (int)S.upd.size(), s);
+    else
+      launch_bmultiaxpy<double>(mptr<cd>(mb, mb.B.o_Z), nf, bz, k, ydev, m, S.x, bx, nf, 0, (int)S.upd.size(), s);
     return HSP_OK;
   };
   auto upload_act = [&](size_t p) -> hsp_status {
@@ -723,7 +749,8 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           const size_t vk = graph ? 0 : (size_t)k * nf;
           io[p].r32 = G.mixed ? 1 : 0;
           io[p].r = G.mixed ? (const void*)(mptr<cf>(mb, mb.B.o_V) + vk) : (const void*)(mptr<cd>(mb, mb.B.o_V) + vk);
-          io[p].z = mptr<cd>(mb, mb.B.o_Z) + vk;
+          io[p].z32 = G.mixed ? 1 : 0;
+        io[p].z = G.mixed ? (void*)(mptr<cf>(mb, mb.B.o_Z) + vk) : (void*)(mptr<cd>(mb, mb.B.o_Z) + vk);
           if (graph) {
             long long* dyn = mptr<long long>(mb, mb.B.o_dyn);
             ms[p].dyn = (long long)k * (long long)nf;
@@ -747,7 +774,6 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           const BatchLayout& B = mb.B;
           const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
           int* act_d = mptr<int>(mb, B.o_act);
-          cd* Z = mptr<cd>(mb, B.o_Z);
           cd* w = mptr<cd>(mb, B.o_w);
           cd* hb = mptr<cd>(mb, B.o_hb);
           cd* part = mptr<cd>(mb, B.o_part);
@@ -758,8 +784,12 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           bVb.ld = (size_t)(m + 1) * nf;
           bVb.map = act_d;
           prof_begin(mb.C, HSP_PROF_KRYLOV, s);
-          launch_stencil<double, double, double, double>(mb.C->fine, 0, Z + (size_t)k * nf, (const cd*)nullptr, w, 0.0,
-                                                         s, nact[p], bZk, BIdx{}, bw);
+          if (G.mixed)
+            launch_stencil<double, float, double, double>(mb.C->fine, 0, mptr<cf>(mb, B.o_Z) + (size_t)k * nf,
+                                                          (const cd*)nullptr, w, 0.0, s, nact[p], bZk, BIdx{}, bw);
+          else
+            launch_stencil<double, double, double, double>(mb.C->fine, 0, mptr<cd>(mb, B.o_Z) + (size_t)k * nf,
+                                                           (const cd*)nullptr, w, 0.0, s, nact[p], bZk, BIdx{}, bw);
           if (G.mixed) {
             cf* V = mptr<cf>(mb, B.o_V);
             launch_bdcgs_project<float>(V, nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff, nact[p], s);
@@ -776,7 +806,7 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           // u_{k+1} (basis vectors in the basis precision)
           const double vb = G.mixed ? sizeof(cf) : sizeof(cd);
           prof_end(mb.C, HSP_PROF_KRYLOV, s,
-                   (double)nact[p] * ((double)nf * (2.0 * sizeof(cd) + sizeof(double)) +
+                   (double)nact[p] * ((double)nf * (vb + sizeof(cd) + sizeof(double)) +
                                       (double)nf * (vb * (2.0 * k + 4.0) + 2.0 * sizeof(cd))));
           HIPCHK(hipMemcpyAsync(ms[p].hh.data(), hb, (size_t)nact[p] * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
         }
@@ -880,8 +910,8 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
   return HSP_OK;
 }
 
-// r32: the right-hand sides are complex64 (the Krylov basis of the
-// mixed-precision solver), else complex128.
+// r32: the right-hand sides and results are complex64 (the Krylov vectors of
+// the mixed-precision solver), else complex128.
 hsp_status group_precond(Group& G, const void* const* r, void* const* z, int tile, int flags, hipStream_t s,
                          int r32 = 0) {
   const size_t nm = G.mem.size();
@@ -895,7 +925,8 @@ hsp_status group_precond(Group& G, const void* const* r, void* const* z, int til
     const size_t nf = (size_t)mb.C->P.nf1 * mb.C->P.nf2;
     io[p].r = r[p];
     io[p].r32 = r32;
-    io[p].z = (cd*)z[p];
+    io[p].z = z[p];
+    io[p].z32 = r32;
     io[p].br.ld = nf;
     io[p].bz.ld = nf;
   }
@@ -985,7 +1016,7 @@ hsp_status hsp_tune_batch(hsp_handle C, int nrhs, int restart, void* ws, size_t 
   // constant right-hand sides in the type the solver hands to the
   // preconditioner (its Krylov basis)
   cd* w = mptr<cd>(mb, mb.B.o_w);
-  cd* z = mptr<cd>(mb, mb.B.o_Z);
+  void* z = mb.ws + mb.B.o_Z;
   launch_fill(w, (size_t)nrhs * nf, mk<double>(1.0, 0.0), s);
   const void* r = w;
   if (G.mixed) {

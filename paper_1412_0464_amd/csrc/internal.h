@@ -62,9 +62,9 @@ bool smooth_fused_ok(const LevelDev& L, int nu);
 template <class TR>
 void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cf* res,
                        BIdx bres, int nb, hipStream_t s);
-template <class TR>
+template <class TR, class TZ>
 void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cx<TR>* r, BIdx br,
-                        const cf* xin, BIdx bxin, const cf* ec, BIdx bec, cd* zo, BIdx bzo, int nb, hipStream_t s);
+                        const cf* xin, BIdx bxin, const cf* ec, BIdx bec, cx<TZ>* zo, BIdx bzo, int nb, hipStream_t s);
 
 // ---- slab factorization and sweep stages (slab.hip) ------------------------
 struct SlabDev {
@@ -192,9 +192,10 @@ void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t 
 int batch_dot_blocks(size_t n, int nb);
 void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BIdx bw, size_t n, cd* partial,
                       int nblocks, cd* out, size_t ldo, int nb, hipStream_t s);
-// w_z -= (or +=) sum_j h[z ldh + j] V_zj
-void launch_bmultiaxpy(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw, size_t n,
-                       int sub, int nb, hipStream_t s);
+// w_z -= (or +=) sum_j h[z ldh + j] V_zj (V complex128 or complex64)
+template <class TV>
+void launch_bmultiaxpy(const cx<TV>* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw,
+                       size_t n, int sub, int nb, hipStream_t s);
 // the same with nrm2[z ldo] = ||w_z||^2 after the update (partial: nb nblocks)
 void launch_bmultiaxpy_norm(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* h, size_t ldh, cd* w, BIdx bw,
                             size_t n, cd* partial, int nblocks, cd* nrm2, size_t ldo, int nb, hipStream_t s);

@@ -191,10 +191,10 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
   }
 }
 
-template <int NU, class TR>
+template <int NU, class TR, class TZ>
 __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr, double w, const cx<TR>* __restrict__ r,
                                                      BIdx br, const cf* __restrict__ xin, BIdx bxin,
-                                                     const cf* __restrict__ ec, BIdx bec, cd* __restrict__ zo,
+                                                     const cf* __restrict__ ec, BIdx bec, cx<TZ>* __restrict__ zo,
                                                      BIdx bzo) {
   using S = SmoothTile<NU>;
   constexpr int EY = S::EY, NE = S::NE, H = S::H;
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
     cur = nxt;
     nxt = t;
   }
-  // the last step on the tile, written in double
+  // the last step on the tile, written out in TZ
   for (int idx = threadIdx.x; idx < kTX * kTY; idx += blockDim.x) {
     const int ti = H + idx / kTY, tk = H + idx % kTY;
     const int i = i0 + ti, k = k0 + tk;
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
     const cf a = apply5<EY>(ax, cur, e, ti, tk, c11s[e], i > 1, i < n1, k > 1, k < n2);
     cf out = cur[e];
     cfma(out, dws[e], rr[e] - a);
-    zo[(size_t)(i - 1) * n2 + (k - 1)] = cvt<double>(out);
+    zo[(size_t)(i - 1) * n2 + (k - 1)] = cvt<TZ>(out);
   }
 }
 
@@ -285,31 +285,40 @@ void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BId
   }
 }
 
-template <class TR>
+template <class TR, class TZ>
 void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cx<TR>* r, BIdx br,
-                        const cf* xin, BIdx bxin, const cf* ec, BIdx bec, cd* zo, BIdx bzo, int nb, hipStream_t s) {
+                        const cf* xin, BIdx bxin, const cf* ec, BIdx bec, cx<TZ>* zo, BIdx bzo, int nb, hipStream_t s) {
   if (nb < 1) return;
   const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
   switch (nu) {
     case 1:
-      hipLaunchKernelGGL((k_smooth_post<1, TR>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      hipLaunchKernelGGL((k_smooth_post<1, TR, TZ>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
+                         bzo);
       break;
     case 2:
-      hipLaunchKernelGGL((k_smooth_post<2, TR>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      hipLaunchKernelGGL((k_smooth_post<2, TR, TZ>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
+                         bzo);
       break;
     default:
-      hipLaunchKernelGGL((k_smooth_post<3, TR>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo, bzo);
+      hipLaunchKernelGGL((k_smooth_post<3, TR, TZ>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
+                         bzo);
       break;
   }
 }
 
 #define INST(TR)                                                                                                \
   template void launch_smooth_pre<TR>(const LevelDev&, int, double, const cx<TR>*, BIdx, cf*, BIdx, cf*, BIdx,  \
-                                      int, hipStream_t);                                                        \
-  template void launch_smooth_post<TR>(const LevelDev&, const TransferDev&, int, double, const cx<TR>*, BIdx,   \
-                                       const cf*, BIdx, const cf*, BIdx, cd*, BIdx, int, hipStream_t);
+                                      int, hipStream_t);
 INST(double)
 INST(float)
+#undef INST
+#define INST(TR, TZ)                                                                                               \
+  template void launch_smooth_post<TR, TZ>(const LevelDev&, const TransferDev&, int, double, const cx<TR>*, BIdx, \
+                                           const cf*, BIdx, const cf*, BIdx, cx<TZ>*, BIdx, int, hipStream_t);
+INST(double, double)
+INST(double, float)
+INST(float, double)
+INST(float, float)
 #undef INST
 
 }  // namespace hsp

@@ -161,6 +161,7 @@ INST(float, float, double, double)
 INST(double, float, float, double)
 INST(float, float, float, double)
 INST(double, double, float, double)
+INST(double, double, float, float)
 #undef INST
 
 }  // namespace hsp
