@@ -32,11 +32,21 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# HBM traffic of the batched stage kernels, measured with rocprofv3 counters
-# (FETCH_SIZE and WRITE_SIZE runs, scaled by the same counters on a copy of
-# known size); valid only for the kernel sources it was taken on
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_bstage_layered1023_64src.md")
-STAGE_SOURCES = ["batch.hip", "sweep_dev.h", "internal.h", "common.h"]
+# HBM traffic of the roofline kernels, measured with rocprofv3 counters
+# (a FETCH_SIZE and a WRITE_SIZE run, scaled by the same counters on a copy of
+# known size); a record is valid only for the kernel sources it was taken on
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_layered1023_64src.md")
+KERNEL_SOURCES = {
+    "stage": ["batch.hip", "sweep_dev.h", "internal.h", "common.h"],
+    "project": ["blas.hip", "internal.h", "common.h"],
+}
+# kernel names in the counter files: the batched stage (three launches per
+# stage, for the tile in use) and the projection pass of the complex64 basis
+KERNEL_PATTERNS = {
+    "stage": r"k_bstage_(fwd|mid|bwd)<float, (\d+), (\d+)",
+    "project": r"k_bmultidot2<float>",
+}
+CLASSES = ("stage", "smooth", "coarse", "transfer", "krylov", "project")
 COPY_BYTES = 256 << 20
 
 METRIC = "dof·iter/s and solve time to 1e-6 rel. residual: FP32-batched vs plain FP64"
@@ -44,29 +54,33 @@ UNIT = "dof·iter/s"
 HBM_PEAK_GBS = 8000.0
 
 
-def stage_sources_digest():
+def sources_digest(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in STAGE_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1412_0464_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(tile, nsrc):
-    """Measured HBM bytes per batched stage from the counter record, or None
-    when there is none for this tile and batch size or the stage kernels
-    changed since it was taken."""
+def recorded_traffic(kernel, tile, nsrc):
+    """Measured HBM bytes per launch (per stage for "stage") from the counter
+    record, or None when there is none for this kernel, tile and batch size
+    or the kernel's sources changed since it was taken."""
     import re
     try:
         with open(TRAFFIC_RECORD) as fh:
             txt = fh.read()
     except OSError:
         return None
-    m = re.search(r"traffic-record: bytes_per_stage=(\S+) tile=(\d+) sources=(\d+) digest=(\w+)", txt)
-    if not m or int(m.group(2)) != tile or int(m.group(3)) != nsrc or m.group(4) != stage_sources_digest():
-        return None
-    return float(m.group(1))
+    for m in re.finditer(r"traffic-record: kernel=(\w+) bytes_per_launch=(\S+) tile=(\d+) sources=(\d+) "
+                         r"digest=(\w+)", txt):
+        if m.group(1) != kernel or int(m.group(4)) != nsrc or m.group(5) != sources_digest(kernel):
+            continue
+        if kernel == "stage" and int(m.group(3)) != tile:
+            continue
+        return float(m.group(2))
+    return None
 
 
 def copy_calibration():
@@ -85,7 +99,8 @@ def copy_calibration():
 def reduce_counters(fetch_csv, write_csv, tile, nsrc):
     """Per-kernel averages of the rocprofv3 counter files of a FETCH_SIZE run
     and a WRITE_SIZE run (KiB per dispatch), the copy scale factors, and the
-    traffic record of the batched stage for ``tile``."""
+    traffic records of the batched stage (per stage, for ``tile``) and of the
+    projection pass (per launch)."""
     import csv
     import re
     from collections import defaultdict
@@ -99,7 +114,7 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc):
                 disp[name].add(row["Dispatch_Id"])
         return {k: (len(disp[k]), tot[k]) for k in tot}
 
-    out = {}
+    per = {"stage": {}, "project": {}}
     for label, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         d = load_csv(path)
         print(f"{label} (KiB per dispatch)")
@@ -110,19 +125,26 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc):
             raise SystemExit(f"{path}: no copy calibration kernel")
         copy_kib = copy[0][1] / copy[0][0]
         scale = (COPY_BYTES / 1024) / copy_kib
-        stage_kib, stages = 0.0, 0
+        print(f"  copy: {copy_kib:.1f} KiB per dispatch for {COPY_BYTES // 1024} KiB -> scale {scale:.4f}")
+        stage_kib, stages, proj_kib, projs = 0.0, 0, 0.0, 0
         for k, (n, v) in d.items():
-            m = re.search(r"k_bstage_(fwd|mid|bwd)<float, (\d+), (\d+)", k)
+            m = re.search(KERNEL_PATTERNS["stage"], k)
             if m and int(m.group(3)) == tile:
                 stage_kib += v
                 if m.group(1) == "fwd":
                     stages += n
-        print(f"  copy: {copy_kib:.1f} KiB per dispatch for {COPY_BYTES // 1024} KiB -> scale {scale:.4f}")
+            if re.search(KERNEL_PATTERNS["project"], k):
+                proj_kib += v
+                projs += n
         print(f"  stage (tile {tile}): {stages} stages, {stage_kib / max(stages, 1):.1f} KiB per stage raw")
-        out[label] = stage_kib / max(stages, 1) * 1024 * scale
-    tot = out["FETCH_SIZE"] + out["WRITE_SIZE"]
-    print(f"fetch {out['FETCH_SIZE']:.4e} B + write {out['WRITE_SIZE']:.4e} B per stage (scaled)")
-    print(f"traffic-record: bytes_per_stage={tot:.5e} tile={tile} sources={nsrc} digest={stage_sources_digest()}")
+        print(f"  projection: {projs} launches, {proj_kib / max(projs, 1):.1f} KiB per launch raw")
+        per["stage"][label] = stage_kib / max(stages, 1) * 1024 * scale
+        per["project"][label] = proj_kib / max(projs, 1) * 1024 * scale
+    for kernel, t in (("stage", tile), ("project", 0)):
+        f, w = per[kernel]["FETCH_SIZE"], per[kernel]["WRITE_SIZE"]
+        print(f"{kernel}: fetch {f:.4e} B + write {w:.4e} B per launch (scaled)")
+        print(f"traffic-record: kernel={kernel} bytes_per_launch={f + w:.5e} tile={t} sources={nsrc} "
+              f"digest={sources_digest(kernel)}")
 
 
 def config(name):
@@ -195,7 +217,7 @@ def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile
         # launch (the records add a little time, so they stay out of the
         # steps timed above)
         hs.profile(True)
-        for cls in ("stage", "smooth", "coarse", "transfer", "krylov"):
+        for cls in CLASSES:
             hs.profile_read(cls)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -203,7 +225,7 @@ def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile
             hs.solve_batch(B, tol=tol, maxit=200, restart=restart, tile=tile, out=U)
         torch.cuda.synchronize()
         res["profiled_solve_s"] = (time.perf_counter() - t1) / steps
-        res["classes"] = {cls: hs.profile_read(cls) for cls in ("stage", "smooth", "coarse", "transfer", "krylov")}
+        res["classes"] = {cls: hs.profile_read(cls) for cls in CLASSES}
         hs.profile(False)
     return res
 
@@ -285,12 +307,12 @@ def gpu_run(cfg, c, f, precision, steps, warmup, tol, profile=False):
     res = dict(setup_s=setup_s, solve_s=dt / steps, iters=its[-1], relres=rr, total_iters=sum(its), time_s=dt)
     if profile:
         hs.profile(True)
-        for cls in ("stage", "smooth", "coarse", "transfer", "krylov"):
+        for cls in CLASSES:
             hs.profile_read(cls)
         for _ in range(steps):
             hs.solve(b, tol=tol, maxit=200, out=u)
         torch.cuda.synchronize()
-        res["classes"] = {cls: hs.profile_read(cls) for cls in ("stage", "smooth", "coarse", "transfer", "krylov")}
+        res["classes"] = {cls: hs.profile_read(cls) for cls in CLASSES}
         hs.profile(False)
     res["u"] = u
     res["hs"] = hs
@@ -372,19 +394,27 @@ def main():
                    "solve_s_per_source": bat["solve_s"] / len(fs), "precision": "mixed",
                    "rhs_tile": bat["tile"]},
     }
-    # roofline of the dominant kernel class (the SubdomSolve stage, three
-    # dependent launches timed as one): algorithmic bytes per stage (factor
-    # blocks once, per-source vectors for every source) / average event time
+    # rooflines from the event-timed classes of the profiled repeat:
+    # algorithmic bytes per launch / average launch time.  The dominant single
+    # kernel is the FGMRES projection pass (k_bmultidot2: every basis vector
+    # and w once per Arnoldi step; its event pair also covers two small
+    # reductions); the SubdomSolve stage (three dependent launches timed as
+    # one) follows as roofline_stage.
     cls = bat["classes"]
-    st_ms, st_n, st_bytes = cls["stage"]
-    per_launch_bytes = st_bytes / max(st_n, 1)
-    per_launch_s = st_ms * 1e-3 / max(st_n, 1)
-    achieved = per_launch_bytes / per_launch_s / 1e9
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(bat["tile"], len(fs)),
-                       "kernel": "batched SubdomSolve stage (k_bstage_fwd + k_bstage_mid + k_bstage_bwd)",
-                       "launches": st_n, "avg_launch_us": per_launch_s * 1e6,
-                       "alg_bytes_per_launch": per_launch_bytes}
+
+    def roofline(name, kernel, traffic):
+        ms, n, by = cls[name]
+        per_launch_bytes = by / max(n, 1)
+        per_launch_s = ms * 1e-3 / max(n, 1)
+        achieved = per_launch_bytes / per_launch_s / 1e9 if n else 0.0
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel, "launches": n,
+                "avg_launch_us": per_launch_s * 1e6, "alg_bytes_per_launch": per_launch_bytes}
+
+    out["roofline"] = roofline("project", "FGMRES projection pass k_bmultidot2<float> (complex64 basis)",
+                               recorded_traffic("project", bat["tile"], len(fs)))
+    out["roofline_stage"] = roofline("stage", "batched SubdomSolve stage (k_bstage_fwd + k_bstage_mid + k_bstage_bwd)",
+                                     recorded_traffic("stage", bat["tile"], len(fs)))
     out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
     out["config"]["profiled_solve_s"] = bat["profiled_solve_s"]
     Ub = None if args.no_fp64 else bat["U"][0].cpu().numpy()

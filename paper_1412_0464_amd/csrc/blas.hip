@@ -217,12 +217,11 @@ __global__ void __launch_bounds__(256) k_bmultidot(const cd* __restrict__ V, siz
 #pragma unroll
       for (int q = 0; q < kDotTile; ++q) cfma(acc[q], conj(v[(size_t)q * ldj + i]), wi);
     }
-  } else {
+  } else {  // a partial tile: rows q >= jn repeat the last vector, never written out
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
       const cd wi = w[i];
 #pragma unroll
-      for (int q = 0; q < kDotTile; ++q)
-        if (q < jn) cfma(acc[q], conj(v[(size_t)q * ldj + i]), wi);
+      for (int q = 0; q < kDotTile; ++q) cfma(acc[q], conj(v[(size_t)(q < jn ? q : jn - 1) * ldj + i]), wi);
     }
   }
   const cd r = block_sum_arr<kDotTile>(acc, sh);
@@ -276,15 +275,20 @@ __global__ void __launch_bounds__(256) k_bmultidot2(const cx<TV>* __restrict__ V
 #pragma unroll
   for (int q = 0; q < 2 * kDotTile; ++q) acc[q] = mk<double>(0, 0);
   const size_t stride = (size_t)gridDim.x * blockDim.x;
+  // all loads of an element are unconditional (rows q >= jn repeat the last
+  // vector of the tile and are never written out), so that they are issued
+  // together rather than one branch at a time
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
     const cd ui = cvt<double>(u[i]), wi = w[i];
+    cx<TV> vq[kDotTile];
 #pragma unroll
-    for (int q = 0; q < kDotTile; ++q)
-      if (q < jn) {
-        const cd vj = conj(cvt<double>(v[(size_t)q * ldj + i]));
-        cfma(acc[q], vj, ui);
-        cfma(acc[kDotTile + q], vj, wi);
-      }
+    for (int q = 0; q < kDotTile; ++q) vq[q] = v[(size_t)(q < jn ? q : jn - 1) * ldj + i];
+#pragma unroll
+    for (int q = 0; q < kDotTile; ++q) {
+      const cd vj = conj(cvt<double>(vq[q]));
+      cfma(acc[q], vj, ui);
+      cfma(acc[kDotTile + q], vj, wi);
+    }
   }
   const cd r = block_sum_arr<2 * kDotTile>(acc, sh);
   const int t = threadIdx.x;
@@ -344,7 +348,19 @@ __global__ void __launch_bounds__(256) k_bdcgs_update(cx<TV>* __restrict__ V, si
   double nrm = 0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     cd t1 = mk<double>(0, 0), t2 = mk<double>(0, 0);
-    for (int j = 0; j < k; ++j) {
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {  // four loads in flight per step
+      cx<TV> vq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vq[q] = vz[(size_t)(j + q) * ldj + i];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const cd vj = cvt<double>(vq[q]);
+        cfma(t1, sv[j + q], vj);
+        cfma(t2, pv[j + q], vj);
+      }
+    }
+    for (; j < k; ++j) {
       const cd vj = cvt<double>(vz[(size_t)j * ldj + i]);
       cfma(t1, sv[j], vj);
       cfma(t2, pv[j], vj);

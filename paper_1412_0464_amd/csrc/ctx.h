@@ -80,9 +80,9 @@ struct Stage {
 struct Prof {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[HSP_PROF_NCLASS];
-  size_t used[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
-  double bytes[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
-  long long n[HSP_PROF_NCLASS] = {0, 0, 0, 0, 0};
+  size_t used[HSP_PROF_NCLASS] = {};
+  double bytes[HSP_PROF_NCLASS] = {};
+  long long n[HSP_PROF_NCLASS] = {};
 };
 
 }  // namespace hsp

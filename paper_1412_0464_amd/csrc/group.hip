@@ -783,6 +783,11 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           bw.ld = nf;
           bVb.ld = (size_t)(m + 1) * nf;
           bVb.map = act_d;
+          // algorithmic bytes (basis vectors in the basis precision): matvec
+          // z, k^2 read, w written; projection k+1 basis vectors (u_k in slot
+          // k) and w read; update k basis vectors, u_k and w read, v_k and
+          // u_{k+1} written
+          const double vb = G.mixed ? sizeof(cf) : sizeof(cd), na = nact[p];
           prof_begin(mb.C, HSP_PROF_KRYLOV, s);
           if (G.mixed)
             launch_stencil<double, float, double, double>(mb.C->fine, 0, mptr<cf>(mb, B.o_Z) + (size_t)k * nf,
@@ -790,24 +795,23 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           else
             launch_stencil<double, double, double, double>(mb.C->fine, 0, mptr<cd>(mb, B.o_Z) + (size_t)k * nf,
                                                            (const cd*)nullptr, w, 0.0, s, nact[p], bZk, BIdx{}, bw);
-          if (G.mixed) {
-            cf* V = mptr<cf>(mb, B.o_V);
-            launch_bdcgs_project<float>(V, nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff, nact[p], s);
-            launch_bdcgs_update<float>(V, nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk, hb + koff + 2,
-                                       nact[p], s);
-          } else {
-            cd* V = mptr<cd>(mb, B.o_V);
-            launch_bdcgs_project<double>(V, nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff, nact[p], s);
-            launch_bdcgs_update<double>(V, nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk, hb + koff + 2,
+          prof_end(mb.C, HSP_PROF_KRYLOV, s, na * nf * (vb + sizeof(cd) + sizeof(double)));
+          prof_begin(mb.C, HSP_PROF_PROJECT, s);
+          if (G.mixed)
+            launch_bdcgs_project<float>(mptr<cf>(mb, B.o_V), nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff,
                                         nact[p], s);
-          }
-          // matvec (z, k^2 read, w written); projection reads k+1 basis vectors
-          // and w; update reads k basis vectors, u_k and w and writes v_k,
-          // u_{k+1} (basis vectors in the basis precision)
-          const double vb = G.mixed ? sizeof(cf) : sizeof(cd);
-          prof_end(mb.C, HSP_PROF_KRYLOV, s,
-                   (double)nact[p] * ((double)nf * (vb + sizeof(cd) + sizeof(double)) +
-                                      (double)nf * (vb * (2.0 * k + 4.0) + 2.0 * sizeof(cd))));
+          else
+            launch_bdcgs_project<double>(mptr<cd>(mb, B.o_V), nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff,
+                                         nact[p], s);
+          prof_end(mb.C, HSP_PROF_PROJECT, s, na * nf * (vb * (k + 1.0) + sizeof(cd)));
+          prof_begin(mb.C, HSP_PROF_KRYLOV, s);
+          if (G.mixed)
+            launch_bdcgs_update<float>(mptr<cf>(mb, B.o_V), nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk,
+                                       hb + koff + 2, nact[p], s);
+          else
+            launch_bdcgs_update<double>(mptr<cd>(mb, B.o_V), nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk,
+                                        hb + koff + 2, nact[p], s);
+          prof_end(mb.C, HSP_PROF_KRYLOV, s, na * nf * (vb * (k + 3.0) + sizeof(cd)));
           HIPCHK(hipMemcpyAsync(ms[p].hh.data(), hb, (size_t)nact[p] * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
         }
         HIPCHK(hipGetLastError());
