@@ -199,6 +199,7 @@ __device__ __forceinline__ cd block_sum_arr(cd (&v)[NV], cd* sh) {
 // Basis vectors j0 .. j0+kDotTile-1 (blockIdx.y tile) against w: w is read
 // once per tile.
 constexpr int kDotTile = 8;
+constexpr int kUpdUnroll = 8;
 __global__ void __launch_bounds__(256) k_bmultidot(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
                                                    const cd* __restrict__ w, BIdx bw, size_t n,
                                                    cd* __restrict__ partial) {
@@ -249,7 +250,15 @@ __global__ void __launch_bounds__(256) k_bmultiaxpy(const cx<TV>* __restrict__ V
   w += bw.off(z);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     cd acc = mk<double>(0, 0);
-    for (int j = 0; j < cnt; ++j) cfma(acc, hz[j], cvt<double>(v[(size_t)j * ldj + i]));
+    int j = 0;
+    for (; j + kUpdUnroll <= cnt; j += kUpdUnroll) {  // kUpdUnroll loads in flight per step
+      cx<TV> vq[kUpdUnroll];
+#pragma unroll
+      for (int q = 0; q < kUpdUnroll; ++q) vq[q] = v[(size_t)(j + q) * ldj + i];
+#pragma unroll
+      for (int q = 0; q < kUpdUnroll; ++q) cfma(acc, hz[j + q], cvt<double>(vq[q]));
+    }
+    for (; j < cnt; ++j) cfma(acc, hz[j], cvt<double>(v[(size_t)j * ldj + i]));
     w[i] = sub ? (w[i] - acc) : (w[i] + acc);
   }
 }
@@ -349,12 +358,12 @@ __global__ void __launch_bounds__(256) k_bdcgs_update(cx<TV>* __restrict__ V, si
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     cd t1 = mk<double>(0, 0), t2 = mk<double>(0, 0);
     int j = 0;
-    for (; j + 4 <= k; j += 4) {  // four loads in flight per step
-      cx<TV> vq[4];
+    for (; j + kUpdUnroll <= k; j += kUpdUnroll) {  // kUpdUnroll loads in flight per step
+      cx<TV> vq[kUpdUnroll];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) vq[q] = vz[(size_t)(j + q) * ldj + i];
+      for (int q = 0; q < kUpdUnroll; ++q) vq[q] = vz[(size_t)(j + q) * ldj + i];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kUpdUnroll; ++q) {
         const cd vj = cvt<double>(vq[q]);
         cfma(t1, sv[j + q], vj);
         cfma(t2, pv[j + q], vj);
