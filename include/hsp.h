@@ -76,8 +76,9 @@ typedef struct hsp_options {
   double omega_jac; /* Jacobi weight                                           */
   int sweep;        /* HSP_SWEEP_X (SweepingPrecX) or HSP_SWEEP_UD            */
   int precision;    /* HSP_FP64: everything complex128.  HSP_MIXED: smoother,
-                       slab factors and sweeps complex64; FGMRES, its
-                       residual and the restriction / prolongation complex128 */
+                       slab factors and sweeps complex64; FGMRES arithmetic,
+                       its residual and the solution complex128 (the batched
+                       solvers store their Krylov vectors in complex64) */
   int restart;      /* FGMRES restart length (sizes the workspace)            */
   int chunk;        /* blocks per chunk of the parallel slab substitutions
                        (1..64); 0 selects about sqrt(n_t) for n_t tangential
@@ -245,12 +246,16 @@ hsp_status hsp_tune_batch(hsp_handle hd, int nrhs, int restart, void* ws_dev, si
  * iterations work on the remaining ones only.  The Arnoldi vectors are
  * orthogonalised by classical Gram-Schmidt with one reorthogonalisation,
  * the reorthogonalisation of each vector being carried out with the
- * projection of the next one (one pass over the basis for both).  b_j = 0
- * gives u_j = 0 with 0 iterations.  iters[nrhs] and relres[nrhs] (host
- * arrays, may be NULL) receive the iteration counts and true relative
- * residuals.  One host synchronisation per iteration.
- * Errors: HSP_EINVAL, HSP_ENOMEM, HSP_ENOCONV (some right-hand side reached
- * maxit; all u_j hold their last iterates). */
+ * projection of the next one (one pass over the basis for both).  With
+ * HSP_MIXED the Arnoldi and preconditioned vectors are stored in complex64
+ * (products, Hessenberg matrix, residuals and u_j in complex128); a right-
+ * hand side whose true residual misses tol after its estimate met it gets
+ * another restart cycle.  b_j = 0 gives u_j = 0 with 0 iterations.
+ * iters[nrhs] and relres[nrhs] (host arrays, may be NULL) receive the
+ * iteration counts and true relative residuals.  One host synchronisation
+ * per iteration.
+ * Errors: HSP_EINVAL, HSP_ENOMEM, HSP_ENOCONV (some right-hand side's true
+ * residual misses tol at maxit; all u_j hold their last iterates). */
 hsp_status hsp_solve_batch(hsp_handle hd, int nrhs, const void* b_dev, void* u_dev, double tol, int maxit,
                            int restart, int conj_transpose, int tile, void* ws_dev, size_t ws_bytes,
                            int* iters, double* relres, void* stream);
