@@ -5,15 +5,17 @@
 // step.
 //
 //   pre:  x_1 = w D^{-1} r, x_{s+1} = x_s + w D^{-1} (r - A x_s), s < nu;
-//         outputs x_nu and the fine residual r - A x_nu (complex128);
+//         outputs x_nu and the fine residual r - A x_nu (complex64);
 //   post: x_0 = x + P e_c (prolongation of the coarse correction), then nu
-//         steps; output x_nu in complex128.
+//         steps; output x_nu (complex64 or complex128).
 //
 // Complex64 smoother (the mixed-precision path): the coefficients are formed
-// in complex64 from complex64 row / column factors and k^2 (the diagonal and
-// w D^{-1} once per node, the off-diagonals per step); the residual and the
-// prolongation sums are in double, as in the separate kernels (stencil.hip,
-// transfer.hip).
+// in complex64 from complex64 row / column factors and k^2 (w D^{-1} once per
+// node and kept in LDS with r and the two iterates; the off-diagonals per
+// step).  A step is written (1 - w) x + (w D^{-1}) (r - (A - D) x), so the
+// diagonal itself is needed only for the residual, where it is recovered
+// from w D^{-1}.  The prolongation sums are in double, as in the separate
+// kernel (transfer.hip).
 #include "internal.h"
 
 namespace hsp {
@@ -59,26 +61,27 @@ __device__ __forceinline__ void load_axes(const LevelDev& L, int i0, int k0, int
 
 __device__ __forceinline__ cf keepf(bool ok, cf v) { return mk<float>(ok ? v.re : 0.f, ok ? v.im : 0.f); }
 
-// A cur at tile node (ti, tk) with the diagonal c11 (complex64).
+// Off-diagonal part of A cur at tile node (ti, tk) (complex64).
 template <int EY>
-__device__ __forceinline__ cf apply5(const Axes5& ax, const cf* cur, int e, int ti, int tk, cf c11, bool iw, bool ie,
-                                     bool ks, bool kn) {
+__device__ __forceinline__ cf offdiag5(const Axes5& ax, const cf* cur, int e, int ti, int tk, bool iw, bool ie,
+                                       bool ks, bool kn) {
   const cf ian = ax.rB[ti], ikn = ax.cB[tk];
   const cf cw = keepf(iw, -(ax.rAm[ti] * ikn)), ce = keepf(ie, -(ax.rAp[ti] * ikn));
   const cf cs = keepf(ks, -(ax.cAm[tk] * ian)), cn = keepf(kn, -(ax.cAp[tk] * ian));
   cf a = mk<float>(0, 0);
   cfma(a, cw, cur[e - EY]);
   cfma(a, cs, cur[e - 1]);
-  cfma(a, c11, cur[e]);
   cfma(a, cn, cur[e + 1]);
   cfma(a, ce, cur[e + EY]);
   return a;
 }
 
-// One Jacobi step on the region of halo hs: nxt = cur + (w D^{-1}) (r - A cur).
+// One Jacobi step on the region of halo hs: nxt = cur + (w D^{-1}) (r - A cur)
+// = (1 - w) cur + (w D^{-1}) (r - (A - D) cur), so that only w D^{-1} is kept
+// per node.
 template <int NU>
-__device__ __forceinline__ void jacobi_region(const LevelDev& L, int i0, int k0, int hs, const cf* cur, cf* nxt,
-                                              const cf* rr, const cf* c11s, const cf* dws, const Axes5& ax) {
+__device__ __forceinline__ void jacobi_region(const LevelDev& L, int i0, int k0, int hs, float omw, const cf* cur,
+                                              cf* nxt, const cf* rr, const cf* dws, const Axes5& ax) {
   using S = SmoothTile<NU>;
   const int RX = S::EX - 2 * hs, RY = S::EY - 2 * hs;
   for (int idx = threadIdx.x; idx < RX * RY; idx += blockDim.x) {
@@ -86,8 +89,8 @@ __device__ __forceinline__ void jacobi_region(const LevelDev& L, int i0, int k0,
     const int i = i0 + ti, k = k0 + tk;
     const int e = ti * S::EY + tk;
     const bool in = i >= 1 && i <= L.n1 && k >= 1 && k <= L.n2;
-    const cf a = apply5<S::EY>(ax, cur, e, ti, tk, c11s[e], i > 1, i < L.n1, k > 1, k < L.n2);
-    cf out = cur[e];
+    const cf a = offdiag5<S::EY>(ax, cur, e, ti, tk, i > 1, i < L.n1, k > 1, k < L.n2);
+    cf out = omw * cur[e];
     cfma(out, dws[e], rr[e] - a);
     nxt[e] = keepf(in, out);
   }
@@ -121,7 +124,7 @@ __device__ __forceinline__ void fetch_nodes(const LevelDev& L, int i0, int k0, c
 
 template <int NU, class TR>
 __device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, double w, const NodeLoads<NU, TR>& ld,
-                                            const Axes5& ax, cf* rr, cf* c11s, cf* dws) {
+                                            const Axes5& ax, cf* rr, cf* dws) {
   using S = SmoothTile<NU>;
   const cf wt = cvt<float>(mk<double>(w, 0.0));
   const float h2 = (float)L.h2;
@@ -137,7 +140,6 @@ __device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, d
     const cf cs = -(ax.cAm[tk] * ian), cn = -(ax.cAp[tk] * ian);
     const cf c11 = -(cw + ce + cs + cn) - (h2 * (float)ld.k2[q]) * (ian * ikn);
     rr[idx] = keepf(in, cvt<float>(ld.r[q]));
-    c11s[idx] = c11;
     dws[idx] = wt * cinv(c11);
   }
 }
@@ -147,11 +149,13 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
                                                     cf* __restrict__ xo, BIdx bxo, cf* __restrict__ res, BIdx bres) {
   using S = SmoothTile<NU>;
   constexpr int EY = S::EY, NE = S::NE, H = S::H;
-  __shared__ cf xa[NE], xb[NE], rr[NE], c11s[NE], dws[NE];
+  __shared__ cf xa[NE], xb[NE], rr[NE], dws[NE];
   __shared__ Axes5 ax;
   const int n1 = L.n1, n2 = L.n2;
   const int i0 = blockIdx.y * kTX + 1 - H, k0 = blockIdx.x * kTY + 1 - H;
   const int z = blockIdx.z;
+  const float omw = (float)(1.0 - w);
+  const cf wt = mk<float>((float)w, 0.f);
   r += br.off(z);
   xo += bxo.off(z);
   res += bres.off(z);
@@ -159,7 +163,7 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
   fetch_nodes<NU, TR>(L, i0, k0, r, ld);
   load_axes(L, i0, k0, S::EX, EY, ax);
   __syncthreads();
-  store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, c11s, dws);
+  store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, dws);
   __syncthreads();
   // x_1 = (w D^{-1}) r
   for (int idx = threadIdx.x; idx < NE; idx += blockDim.x) {
@@ -171,7 +175,7 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
   cf* cur = xa;
   cf* nxt = xb;
   for (int s = 2; s <= NU; ++s) {
-    jacobi_region<NU>(L, i0, k0, s - 1, cur, nxt, rr, c11s, dws, ax);
+    jacobi_region<NU>(L, i0, k0, s - 1, omw, cur, nxt, rr, dws, ax);
     __syncthreads();
     cf* t = cur;
     cur = nxt;
@@ -185,7 +189,10 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
     if (i > n1 || k > n2) continue;
     const int e = ti * EY + tk;
     const size_t g = (size_t)(i - 1) * n2 + (k - 1);
-    const cf a = apply5<EY>(ax, cur, e, ti, tk, c11s[e], i > 1, i < n1, k > 1, k < n2);
+    // the diagonal back from w D^{-1}
+    const cf c11 = wt * cinv(dws[e]);
+    cf a = offdiag5<EY>(ax, cur, e, ti, tk, i > 1, i < n1, k > 1, k < n2);
+    cfma(a, c11, cur[e]);
     xo[g] = cur[e];
     res[g] = rr[e] - a;
   }
@@ -198,11 +205,12 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
                                                      BIdx bzo) {
   using S = SmoothTile<NU>;
   constexpr int EY = S::EY, NE = S::NE, H = S::H;
-  __shared__ cf xa[NE], xb[NE], rr[NE], c11s[NE], dws[NE];
+  __shared__ cf xa[NE], xb[NE], rr[NE], dws[NE];
   __shared__ Axes5 ax;
   const int n1 = L.n1, n2 = L.n2;
   const int i0 = blockIdx.y * kTX + 1 - H, k0 = blockIdx.x * kTY + 1 - H;
   const int z = blockIdx.z;
+  const float omw = (float)(1.0 - w);
   r += br.off(z);
   xin += bxin.off(z);
   ec += bec.off(z);
@@ -212,8 +220,9 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
   // x_0 = x + P e_c (prolongation sums in double, as k_prolong_add); the
   // taps of all nodes of the thread are fetched first
   constexpr int NI = NodeLoads<NU, TR>::NI;
+  // (the tent weights are products of 1, 1/2 and 1/4: exact in float)
   cf x0[NI], v[NI][2][2];
-  double wgt[NI][2][2];
+  float wgt[NI][2][2];
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
     const int idx = min((int)threadIdx.x + 256 * q, NE - 1);
@@ -225,14 +234,14 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int ci = max(Tr.px[2 * ic + a], 0), ck = max(Tr.py[2 * kc + b], 0);
-        wgt[q][a][b] = Tr.pwx[2 * ic + a] * Tr.pwy[2 * kc + b];
+        wgt[q][a][b] = (float)(Tr.pwx[2 * ic + a] * Tr.pwy[2 * kc + b]);
         v[q][a][b] = ec[(size_t)ci * Tr.nc2 + ck];
       }
     x0[q] = xin[(size_t)ic * n2 + kc];
   }
   load_axes(L, i0, k0, S::EX, EY, ax);
   __syncthreads();
-  store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, c11s, dws);
+  store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, dws);
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
     const int idx = (int)threadIdx.x + 256 * q;
@@ -243,14 +252,14 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc += wgt[q][a][b] * cvt<double>(v[q][a][b]);
+      for (int b = 0; b < 2; ++b) acc += (double)wgt[q][a][b] * cvt<double>(v[q][a][b]);
     xa[idx] = keepf(in, cvt<float>(cvt<double>(x0[q]) + acc));
   }
   __syncthreads();
   cf* cur = xa;
   cf* nxt = xb;
   for (int s = 1; s < NU; ++s) {
-    jacobi_region<NU>(L, i0, k0, s, cur, nxt, rr, c11s, dws, ax);
+    jacobi_region<NU>(L, i0, k0, s, omw, cur, nxt, rr, dws, ax);
     __syncthreads();
     cf* t = cur;
     cur = nxt;
@@ -262,8 +271,8 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
     const int i = i0 + ti, k = k0 + tk;
     if (i > n1 || k > n2) continue;
     const int e = ti * EY + tk;
-    const cf a = apply5<EY>(ax, cur, e, ti, tk, c11s[e], i > 1, i < n1, k > 1, k < n2);
-    cf out = cur[e];
+    const cf a = offdiag5<EY>(ax, cur, e, ti, tk, i > 1, i < n1, k > 1, k < n2);
+    cf out = omw * cur[e];
     cfma(out, dws[e], rr[e] - a);
     zo[(size_t)(i - 1) * n2 + (k - 1)] = cvt<TZ>(out);
   }
