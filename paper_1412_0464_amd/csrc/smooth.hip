@@ -217,42 +217,62 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
   zo += bzo.off(z);
   NodeLoads<NU, TR> ld;
   fetch_nodes<NU, TR>(L, i0, k0, r, ld);
-  // x_0 = x + P e_c (prolongation sums in double, as k_prolong_add); the
-  // taps of all nodes of the thread are fetched first
+  // x_0 = x + P e_c (prolongation sums in double, as k_prolong_add).  The
+  // taps are separable (rows times columns): the row and column taps of the
+  // tile are staged in LDS with the axes, then every node issues its four
+  // coarse loads.  (The tent weights are 0, 1/2 and 1: exact in float.)
   constexpr int NI = NodeLoads<NU, TR>::NI;
-  // (the tent weights are products of 1, 1/2 and 1/4: exact in float)
-  cf x0[NI], v[NI][2][2];
-  float wgt[NI][2][2];
+  __shared__ int tpi[2][S::EX], tpk[2][EY];
+  __shared__ float twi[2][S::EX], twk[2][EY];
+  for (int t = threadIdx.x; t < S::EX + EY; t += blockDim.x) {
+    const bool row = t < S::EX;
+    const int tt = row ? t : t - S::EX;
+    const int g = row ? i0 + tt : k0 + tt;
+    const int ng = row ? n1 : n2;
+    const int gc = (g >= 1 && g <= ng) ? g - 1 : 0;  // 0-based fine index
+    const int* pi = row ? Tr.px : Tr.py;
+    const double* pw = row ? Tr.pwx : Tr.pwy;
 #pragma unroll
-  for (int q = 0; q < NI; ++q) {
-    const int idx = min((int)threadIdx.x + 256 * q, NE - 1);
-    const int i = i0 + idx / EY, k = k0 + idx % EY;
-    const bool in = i >= 1 && i <= n1 && k >= 1 && k <= n2;
-    const int ic = in ? i - 1 : 0, kc = in ? k - 1 : 0;  // 0-based fine indices
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int ci = max(Tr.px[2 * ic + a], 0), ck = max(Tr.py[2 * kc + b], 0);
-        wgt[q][a][b] = (float)(Tr.pwx[2 * ic + a] * Tr.pwy[2 * kc + b]);
-        v[q][a][b] = ec[(size_t)ci * Tr.nc2 + ck];
+    for (int a = 0; a < 2; ++a) {
+      const int ci = max(pi[2 * gc + a], 0);
+      const float wa = (float)pw[2 * gc + a];
+      if (row) {
+        tpi[a][tt] = ci;
+        twi[a][tt] = wa;
+      } else {
+        tpk[a][tt] = ci;
+        twk[a][tt] = wa;
       }
-    x0[q] = xin[(size_t)ic * n2 + kc];
+    }
   }
   load_axes(L, i0, k0, S::EX, EY, ax);
   __syncthreads();
+  cf x0[NI], v[NI][2][2];
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    const int idx = min((int)threadIdx.x + 256 * q, NE - 1);
+    const int ti = idx / EY, tk = idx - (idx / EY) * EY;
+    const int i = i0 + ti, k = k0 + tk;
+    const bool in = i >= 1 && i <= n1 && k >= 1 && k <= n2;
+    x0[q] = xin[in ? (size_t)(i - 1) * n2 + (k - 1) : 0];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) v[q][a][b] = ec[(size_t)tpi[a][ti] * Tr.nc2 + tpk[b][tk]];
+  }
   store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, dws);
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
     const int idx = (int)threadIdx.x + 256 * q;
     if (idx >= NE) break;
-    const int i = i0 + idx / EY, k = k0 + idx % EY;
+    const int ti = idx / EY, tk = idx - (idx / EY) * EY;
+    const int i = i0 + ti, k = k0 + tk;
     const bool in = i >= 1 && i <= n1 && k >= 1 && k <= n2;
     cd acc = mk<double>(0, 0);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc += (double)wgt[q][a][b] * cvt<double>(v[q][a][b]);
+      for (int b = 0; b < 2; ++b) acc += (double)(twi[a][ti] * twk[b][tk]) * cvt<double>(v[q][a][b]);
     xa[idx] = keepf(in, cvt<float>(cvt<double>(x0[q]) + acc));
   }
   __syncthreads();
