@@ -14,10 +14,12 @@ process (FGMRES + every preconditioner application), with the medium,
 factors and right-hand sides resident in HBM.  The metric is
 dof * iterations / solve time summed over the batch, with dof the interior
 nodes (absorbing layers excluded).  The reported value is the FP32-batched
-form (complex64 preconditioner, complex128 FGMRES, all sources in one
-batch); the plain FP64 form (complex128 throughout, one source at a time) is
-timed beside it at the same final residual, as is the single-source mixed
-form.
+form (complex64 smoother, slab factors and sweeps; complex128 Arnoldi
+basis, orthogonalisation, residual, coarse-grid correction and solution; all
+sources in one batch); the plain FP64 form (complex128 throughout, one source
+at a time) is timed beside it at the same final residual, as are the
+single-source mixed form and the batched form with the Arnoldi basis stored
+in complex64 as well (the opt-in krylov_fp32 option).
 """
 from __future__ import annotations
 
@@ -41,10 +43,11 @@ KERNEL_SOURCES = {
     "project": ["blas.hip", "internal.h", "common.h"],
 }
 # kernel names in the counter files: the batched stage (three launches per
-# stage, for the tile in use) and the projection pass of the complex64 basis
+# stage, for the tile in use) and the projection pass over the complex128
+# Arnoldi basis
 KERNEL_PATTERNS = {
     "stage": r"k_bstage_(fwd|mid|bwd)<float, (\d+), (\d+)",
-    "project": r"k_bmultidot2<float>",
+    "project": r"k_bmultidot2<double>",
 }
 CLASSES = ("stage", "smooth", "coarse", "transfer", "krylov", "project")
 COPY_BYTES = 256 << 20
@@ -181,9 +184,10 @@ def sources(cfg, shape, nsrc, seed=1412048):
     return out
 
 
-def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile=False, tile=0):
+def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile=False, tile=0, **opts):
     """Setup once, tune the right-hand-side tile (unless ``tile`` fixes it),
-    then time ``steps`` batched solves of all sources after ``warmup`` ones."""
+    then time ``steps`` batched solves of all sources after ``warmup`` ones.
+    ``opts`` are further solver options (krylov_fp32)."""
     import torch
     from paper_1412_0464_amd import Helmholtz
     dev = torch.device("cuda:0")
@@ -191,7 +195,8 @@ def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hs = Helmholtz(ct, cfg["omega"], cfg["h"], cfg["w"], cfg["J"], S_outer=cfg.get("S_outer", 0.0),
-                   c_pml=cfg.get("c_pml", 0.0), two_grid=cfg["two_grid"], precision=precision, restart=restart)
+                   c_pml=cfg.get("c_pml", 0.0), two_grid=cfg["two_grid"], precision=precision, restart=restart,
+                   **opts)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     B = torch.stack([hs.rhs(torch.tensor(f, dtype=torch.complex128, device=dev)) for f in fs])
@@ -350,6 +355,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-single", action="store_true", help="skip the single-source mixed run")
+    ap.add_argument("--no-krylov-fp32", action="store_true",
+                    help="skip the batched run with the Arnoldi basis in complex64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--c3", action="store_true", help="also time the batched multi-frequency group workload")
@@ -415,12 +422,22 @@ def main():
 
     out["roofline"] = roofline("stage", "batched SubdomSolve stage (k_bstage_fwd + k_bstage_mid + k_bstage_bwd)",
                                recorded_traffic("stage", bat["tile"], len(fs)))
-    out["roofline_project"] = roofline("project", "FGMRES projection pass k_bmultidot2<float> (complex64 basis)",
+    out["roofline_project"] = roofline("project", "FGMRES projection pass k_bmultidot2<double> (complex128 basis)",
                                        recorded_traffic("project", bat["tile"], len(fs)))
     out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
     out["config"]["profiled_solve_s"] = bat["profiled_solve_s"]
     Ub = None if args.no_fp64 else bat["U"][0].cpu().numpy()
+    bat_tile = bat["tile"]
     del bat
+    if not args.no_krylov_fp32:
+        bk = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, tile=bat_tile, krylov_fp32=True)
+        kits = bk["iters"]
+        print(f"[bench] batched mixed, complex64 basis: solve {bk['solve_s'] * 1e3:.1f} ms, iterations "
+              f"{min(kits)}..{max(kits)}, max relres {max(bk['relres']):.2e}", file=sys.stderr, flush=True)
+        out["batched_krylov_fp32"] = {"value": dof * bk["total_iters"] / bk["time_s"], "solve_s": bk["solve_s"],
+                                      "iterations_min": min(kits), "iterations_max": max(kits),
+                                      "relres_max": max(bk["relres"]), "rhs_tile": bk["tile"]}
+        del bk
     if not args.no_fp64:
         fp = gpu_run(cfg, c, fs[0], "fp64", args.steps, args.warmup, args.tol)
         print(f"[bench] plain fp64, one source: setup {fp['setup_s']:.3f} s, solve {fp['solve_s'] * 1e3:.2f} ms, "

@@ -76,18 +76,26 @@ typedef struct hsp_options {
   double omega_jac; /* Jacobi weight                                           */
   int sweep;        /* HSP_SWEEP_X (SweepingPrecX) or HSP_SWEEP_UD            */
   int precision;    /* HSP_FP64: everything complex128.  HSP_MIXED: smoother,
-                       slab factors and sweeps complex64; FGMRES arithmetic,
-                       its residual and the solution complex128 (the batched
-                       solvers store their Krylov vectors in complex64) */
+                       slab factors and sweeps complex64; the FGMRES Arnoldi
+                       orthogonalisation, its residual, the coarse-grid
+                       correction and the solution complex128 (the batched
+                       solvers store the preconditioned vectors in complex64,
+                       exact for a complex64 preconditioner)                  */
   int restart;      /* FGMRES restart length (sizes the workspace)            */
   int chunk;        /* blocks per chunk of the parallel slab substitutions
                        (1..64); 0 selects about sqrt(n_t) for n_t tangential
                        nodes.  Changes the evaluation order only.             */
+  int krylov_fp32;  /* HSP_MIXED only, opt-in (default 0): the batched solvers
+                       store the Arnoldi basis in complex64 as well (products
+                       and sums still in complex128; a right-hand side whose
+                       true residual misses tol gets another restart cycle).
+                       Halves the orthogonalisation traffic; the basis is then
+                       orthogonal to complex64 accuracy only.                 */
 } hsp_options;
 
 /* Fills *opt with: fine_stencil 5, two_grid 0, w_dd 4, S_dd 0 (= 5 w_dd),
  * nu 3, omega_jac 0.8 (Sec. 5, Table 2), sweep X, precision FP64, restart 40,
- * chunk 0 (automatic). */
+ * chunk 0 (automatic), krylov_fp32 0. */
 hsp_status hsp_default_options(hsp_options* opt);
 
 /* Bytes of device workspace that hsp_setup needs for this geometry, slab
@@ -247,10 +255,11 @@ hsp_status hsp_tune_batch(hsp_handle hd, int nrhs, int restart, void* ws_dev, si
  * orthogonalised by classical Gram-Schmidt with one reorthogonalisation,
  * the reorthogonalisation of each vector being carried out with the
  * projection of the next one (one pass over the basis for both).  With
- * HSP_MIXED the Arnoldi and preconditioned vectors are stored in complex64
- * (products, Hessenberg matrix, residuals and u_j in complex128); a right-
- * hand side whose true residual misses tol after its estimate met it gets
- * another restart cycle.  b_j = 0 gives u_j = 0 with 0 iterations.
+ * HSP_MIXED the preconditioned vectors are stored in complex64 and the
+ * Arnoldi basis, products, Hessenberg matrix, residuals and u_j in
+ * complex128; krylov_fp32 = 1 stores the Arnoldi basis in complex64 too.
+ * A right-hand side whose true residual misses tol after its estimate met
+ * it gets another restart cycle.  b_j = 0 gives u_j = 0 with 0 iterations.
  * iters[nrhs] and relres[nrhs] (host arrays, may be NULL) receive the
  * iteration counts and true relative residuals.  One host synchronisation
  * per iteration.

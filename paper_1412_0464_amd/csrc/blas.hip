@@ -356,27 +356,29 @@ __global__ void __launch_bounds__(256) k_bdcgs_update(cx<TV>* __restrict__ V, si
   w += bw.off(z);
   double nrm = 0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const cx<TV> ui = u[i];
+    const cd wi = w[i];
     cd t1 = mk<double>(0, 0), t2 = mk<double>(0, 0);
-    int j = 0;
-    for (; j + kUpdUnroll <= k; j += kUpdUnroll) {  // kUpdUnroll loads in flight per step
+    // kUpdUnroll loads in flight per round, the last round included: its
+    // indices are clamped to k - 1 and the coefficients past k are zero, so
+    // that no load waits behind a branch
+    for (int j = 0; j < k; j += kUpdUnroll) {
       cx<TV> vq[kUpdUnroll];
 #pragma unroll
-      for (int q = 0; q < kUpdUnroll; ++q) vq[q] = vz[(size_t)(j + q) * ldj + i];
+      for (int q = 0; q < kUpdUnroll; ++q) vq[q] = vz[(size_t)min(j + q, k - 1) * ldj + i];
 #pragma unroll
       for (int q = 0; q < kUpdUnroll; ++q) {
+        const bool in = j + q < k;
+        const int jq = min(j + q, k - 1);
+        const cd sq = in ? sv[jq] : mk<double>(0, 0), pq = in ? pv[jq] : mk<double>(0, 0);
         const cd vj = cvt<double>(vq[q]);
-        cfma(t1, sv[j + q], vj);
-        cfma(t2, pv[j + q], vj);
+        cfma(t1, sq, vj);
+        cfma(t2, pq, vj);
       }
     }
-    for (; j < k; ++j) {
-      const cd vj = cvt<double>(vz[(size_t)j * ldj + i]);
-      cfma(t1, sv[j], vj);
-      cfma(t2, pv[j], vj);
-    }
-    const cx<TV> vks = cvt<TV>(inu * (cvt<double>(u[i]) - t1));
+    const cx<TV> vks = cvt<TV>(inu * (cvt<double>(ui) - t1));
     u[i] = vks;
-    cd wn = w[i] - t2;
+    cd wn = wi - t2;
     cfma(wn, -hkk, cvt<double>(vks));
     const cx<TV> wns = cvt<TV>(wn);
     un[i] = wns;
@@ -460,7 +462,20 @@ void launch_multiaxpy(const cd* V, size_t ldv, int m, const cd* h, cd* w, size_t
 void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_normalize, dim3(nblk(n)), dim3(256), 0, s, w, nrm2, v, n);
 }
-int batch_dot_blocks(size_t n, int nb) { return nblk_batch(n, nb); }
+// Blocks per right-hand side of the batched reductions: about 8192 blocks in
+// total for the projection pass (times its tiles of basis vectors) and 16384
+// for the update pass, so that a launch is many rounds of resident blocks and
+// its last round is short, also when few right-hand sides are left.
+// The projection pass ends every block with a reduction of 2 kDotTile
+// sums, so its blocks keep at least 16 elements per thread.
+int batch_dot_blocks(size_t n, int nb) {
+  const size_t b = (n + 16 * 256 - 1) / (16 * 256), cap = (size_t)std::max(16, 8192 / std::max(nb, 1));
+  return (int)(b > cap ? cap : (b == 0 ? 1 : b));
+}
+int batch_upd_blocks(size_t n, int nb) {
+  const size_t b = (n + 255) / 256, cap = (size_t)std::max(32, 16384 / std::max(nb, 1));
+  return (int)(b > cap ? cap : (b == 0 ? 1 : b));
+}
 void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BIdx bw, size_t n, cd* partial,
                       int nblocks, cd* out, size_t ldo, int nb, hipStream_t s) {
   if (nb < 1 || cnt < 1) return;

@@ -41,7 +41,7 @@ struct BatchLayout {
   size_t total = 0;
 };
 
-BatchLayout batch_layout(const Plan& P, int R, int m) {
+BatchLayout batch_layout(const Plan& P, int R, int m, bool v32) {
   BatchLayout B;
   B.R = R;
   B.m = m;
@@ -62,10 +62,10 @@ BatchLayout batch_layout(const Plan& P, int R, int m) {
   B.o_ctr = c.take(2 * slots * sizeof(int));
   B.nblk = batch_dot_blocks(nf, R);
   B.hs = 2 * (size_t)(m + 2) + 2;
-  // Krylov basis V and preconditioned vectors Z in the precision of the
-  // preconditioner (complex64 for the mixed-precision solver); everything
-  // else of FGMRES in complex128
-  B.o_V = c.take((size_t)R * (m + 1) * nf * T);
+  // Krylov basis V in complex128 (complex64 with krylov_fp32) and the
+  // preconditioned vectors Z in the precision of the preconditioner (exact
+  // for its output); everything else of FGMRES in complex128
+  B.o_V = c.take((size_t)R * (m + 1) * nf * (v32 ? sizeof(cf) : sizeof(cd)));
   B.o_Z = c.take((size_t)R * m * nf * T);
   B.o_w = c.take(R * nf * sizeof(cd));
   B.o_bc = c.take(R * nf * sizeof(cd));
@@ -114,6 +114,7 @@ struct Group {
   int m = 0;
   int nsteps = 0;
   bool mixed = false;
+  bool v32 = false;  // complex64 Arnoldi basis (mixed precision with krylov_fp32)
   size_t o_segs = 0, total = 0;
   char* ws = nullptr;
   BSeg* segs_dev = nullptr;
@@ -145,15 +146,20 @@ hsp_status group_plan(int nprob, const hsp_handle* hds, const int* nrhs, int res
     if (!hds[p]) return fail(HSP_EINVAL, "null handle in group");
     if (nrhs[p] < 0) return fail(HSP_EINVAL, "nrhs must be >= 0");
     const bool mixed = hds[p]->opt.precision == HSP_MIXED;
-    if (p == 0) G.mixed = mixed;
-    if (mixed != G.mixed) return fail(HSP_EINVAL, "the problems of a group must share the precision");
+    const bool v32 = mixed && hds[p]->opt.krylov_fp32 != 0;
+    if (p == 0) {
+      G.mixed = mixed;
+      G.v32 = v32;
+    }
+    if (mixed != G.mixed || v32 != G.v32)
+      return fail(HSP_EINVAL, "the problems of a group must share the precision and the Krylov storage");
     for (int q = 0; q < p; ++q)
       if (hds[q] == hds[p]) return fail(HSP_EINVAL, "a handle appears twice in a group");
     Member mb;
     mb.C = hds[p];
     mb.R = nrhs[p];
     if (mb.R > 0) {
-      mb.B = batch_layout(mb.C->P, mb.R, restart);
+      mb.B = batch_layout(mb.C->P, mb.R, restart, G.v32);
       mb.ws_off = c.take(mb.B.total);
     }
     rmax = std::max(rmax, residual_index(mb.C));
@@ -274,7 +280,7 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
     cx<T>* xa = mptr<cx<T>>(mb, B.o_xa);
     cx<T>* xb = mptr<cx<T>>(mb, B.o_xb);
     if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
-      cf* res = mptr<cf>(mb, B.o_res);  // complex64 residual of the fused smoother
+      cd* res = mptr<cd>(mb, B.o_res);
       prof_begin(C, HSP_PROF_SMOOTH, s);
       if (io[p].r32)
         launch_smooth_pre<float>(C->fine, nu, wj, static_cast<const cf*>(io[p].r), io[p].br,
@@ -282,12 +288,13 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
       else
         launch_smooth_pre<double>(C->fine, nu, wj, static_cast<const cd*>(io[p].r), io[p].br,
                                   reinterpret_cast<cf*>(xa), bf, res, bf, na, s);
-      // r read, k^2 read, the last iterate and the residual written
+      // r read, k^2 read, the last iterate (complex64) and the residual
+      // (complex128) written
       const double rb = io[p].r32 ? sizeof(cf) : sizeof(cd);
-      prof_end(C, HSP_PROF_SMOOTH, s, (double)na * nf * (rb + sizeof(double) + 2.0 * sizeof(cf)));
+      prof_end(C, HSP_PROF_SMOOTH, s, (double)na * nf * (rb + sizeof(double) + sizeof(cf) + sizeof(cd)));
       prof_begin(C, HSP_PROF_TRANSFER, s);
-      launch_restrict<float, T>(C->tr, res, mptr<cx<T>>(mb, B.o_rc), s, na, bf, bdd);
-      prof_end(C, HSP_PROF_TRANSFER, s, (double)na * ((double)nf * sizeof(cf) + (double)nd * sizeof(cx<T>)));
+      launch_restrict<double, T>(C->tr, res, mptr<cx<T>>(mb, B.o_rc), s, na, bf, bdd);
+      prof_end(C, HSP_PROF_TRANSFER, s, (double)na * ((double)nf * sizeof(cd) + (double)nd * sizeof(cx<T>)));
       launch_zero<T>(mptr<cx<T>>(mb, B.o_ec), (size_t)na * nd, s);
       continue;
     }
@@ -702,7 +709,7 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
         // r = b - A x in complex128, its norm, v_0 = r / ||r|| in the basis precision
         launch_stencil<double, double, double, double>(mb.C->fine, 1, S.x, S.b, w, 0.0, s, na, bx, bx, bw);
         launch_bmultidot(w, 0, bw, 1, w, bw, nf, mptr<cd>(mb, B.o_part), B.nblk, hb + 2 * (m + 1), B.hs, na, s);
-        if (G.mixed)
+        if (G.v32)
           launch_bnormalize<float>(w, bw, hb + 2 * (m + 1), B.hs, mptr<cf>(mb, B.o_V), bV, nf, na, s);
         else
           launch_bnormalize<double>(w, bw, hb + 2 * (m + 1), B.hs, mptr<cd>(mb, B.o_V), bV, nf, na, s);
@@ -745,12 +752,13 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           io[p].br.map = act_d;
           io[p].bz.ld = (size_t)m * nf;
           io[p].bz.map = act_d;
-          // slot k of the basis (complex64 for the mixed-precision solver)
+          // slot k of the basis (complex64 with krylov_fp32) and of Z
+          // (complex64 for the mixed-precision solver)
           const size_t vk = graph ? 0 : (size_t)k * nf;
-          io[p].r32 = G.mixed ? 1 : 0;
-          io[p].r = G.mixed ? (const void*)(mptr<cf>(mb, mb.B.o_V) + vk) : (const void*)(mptr<cd>(mb, mb.B.o_V) + vk);
+          io[p].r32 = G.v32 ? 1 : 0;
+          io[p].r = G.v32 ? (const void*)(mptr<cf>(mb, mb.B.o_V) + vk) : (const void*)(mptr<cd>(mb, mb.B.o_V) + vk);
           io[p].z32 = G.mixed ? 1 : 0;
-        io[p].z = G.mixed ? (void*)(mptr<cf>(mb, mb.B.o_Z) + vk) : (void*)(mptr<cd>(mb, mb.B.o_Z) + vk);
+          io[p].z = G.mixed ? (void*)(mptr<cf>(mb, mb.B.o_Z) + vk) : (void*)(mptr<cd>(mb, mb.B.o_Z) + vk);
           if (graph) {
             long long* dyn = mptr<long long>(mb, mb.B.o_dyn);
             ms[p].dyn = (long long)k * (long long)nf;
@@ -787,7 +795,8 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           // z, k^2 read, w written; projection k+1 basis vectors (u_k in slot
           // k) and w read; update k basis vectors, u_k and w read, v_k and
           // u_{k+1} written
-          const double vb = G.mixed ? sizeof(cf) : sizeof(cd), na = nact[p];
+          const double vb = G.v32 ? sizeof(cf) : sizeof(cd), zb = G.mixed ? sizeof(cf) : sizeof(cd);
+          const double na = nact[p];
           prof_begin(mb.C, HSP_PROF_KRYLOV, s);
           if (G.mixed)
             launch_stencil<double, float, double, double>(mb.C->fine, 0, mptr<cf>(mb, B.o_Z) + (size_t)k * nf,
@@ -795,21 +804,27 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           else
             launch_stencil<double, double, double, double>(mb.C->fine, 0, mptr<cd>(mb, B.o_Z) + (size_t)k * nf,
                                                            (const cd*)nullptr, w, 0.0, s, nact[p], bZk, BIdx{}, bw);
-          prof_end(mb.C, HSP_PROF_KRYLOV, s, na * nf * (vb + sizeof(cd) + sizeof(double)));
+          prof_end(mb.C, HSP_PROF_KRYLOV, s, na * nf * (zb + sizeof(cd) + sizeof(double)));
+          // blocks per right-hand side for the active count; the partial
+          // buffer holds 2 (m+1) B.nblk entries for each of R right-hand
+          // sides, and both passes use at most B.nblk R / nact per active one
+          const int pcap = (int)std::max<long>(1, (long)B.nblk * mb.R / nact[p]);
+          const int nbp = std::min(batch_dot_blocks(nf, nact[p]), pcap);
+          const int nbu = std::min(batch_upd_blocks(nf, nact[p]), pcap);
           prof_begin(mb.C, HSP_PROF_PROJECT, s);
-          if (G.mixed)
-            launch_bdcgs_project<float>(mptr<cf>(mb, B.o_V), nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff,
+          if (G.v32)
+            launch_bdcgs_project<float>(mptr<cf>(mb, B.o_V), nf, bVb, k, w, bw, nf, part, nbp, hb, B.hs, koff,
                                         nact[p], s);
           else
-            launch_bdcgs_project<double>(mptr<cd>(mb, B.o_V), nf, bVb, k, w, bw, nf, part, B.nblk, hb, B.hs, koff,
+            launch_bdcgs_project<double>(mptr<cd>(mb, B.o_V), nf, bVb, k, w, bw, nf, part, nbp, hb, B.hs, koff,
                                          nact[p], s);
           prof_end(mb.C, HSP_PROF_PROJECT, s, na * nf * (vb * (k + 1.0) + sizeof(cd)));
           prof_begin(mb.C, HSP_PROF_KRYLOV, s);
-          if (G.mixed)
-            launch_bdcgs_update<float>(mptr<cf>(mb, B.o_V), nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk,
+          if (G.v32)
+            launch_bdcgs_update<float>(mptr<cf>(mb, B.o_V), nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, nbu,
                                        hb + koff + 2, nact[p], s);
           else
-            launch_bdcgs_update<double>(mptr<cd>(mb, B.o_V), nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, B.nblk,
+            launch_bdcgs_update<double>(mptr<cd>(mb, B.o_V), nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, nbu,
                                         hb + koff + 2, nact[p], s);
           prof_end(mb.C, HSP_PROF_KRYLOV, s, na * nf * (vb * (k + 3.0) + sizeof(cd)));
           HIPCHK(hipMemcpyAsync(ms[p].hh.data(), hb, (size_t)nact[p] * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
@@ -914,10 +929,10 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
   return HSP_OK;
 }
 
-// r32: the right-hand sides and results are complex64 (the Krylov vectors of
-// the mixed-precision solver), else complex128.
+// r32, z32: the right-hand sides / the results are complex64 (the Krylov
+// vectors of the mixed-precision solver), else complex128.
 hsp_status group_precond(Group& G, const void* const* r, void* const* z, int tile, int flags, hipStream_t s,
-                         int r32 = 0) {
+                         int r32 = 0, int z32 = 0) {
   const size_t nm = G.mem.size();
   std::vector<int> nact(nm);
   std::vector<PrecIO> io(nm);
@@ -930,7 +945,7 @@ hsp_status group_precond(Group& G, const void* const* r, void* const* z, int til
     io[p].r = r[p];
     io[p].r32 = r32;
     io[p].z = z[p];
-    io[p].z32 = r32;
+    io[p].z32 = z32;
     io[p].br.ld = nf;
     io[p].bz.ld = nf;
   }
@@ -1023,7 +1038,7 @@ hsp_status hsp_tune_batch(hsp_handle C, int nrhs, int restart, void* ws, size_t 
   void* z = mb.ws + mb.B.o_Z;
   launch_fill(w, (size_t)nrhs * nf, mk<double>(1.0, 0.0), s);
   const void* r = w;
-  if (G.mixed) {
+  if (G.v32) {
     cf* r32 = mptr<cf>(mb, mb.B.o_V);
     launch_convert<float, double>(w, r32, (size_t)nrhs * nf, 0, s);
     r = r32;
@@ -1042,11 +1057,11 @@ hsp_status hsp_tune_batch(hsp_handle C, int nrhs, int restart, void* ws, size_t 
   double best_ms = 1e300;
   hipError_t err = hipSuccess;
   for (int rb = 1; rb <= kMaxTile && err == hipSuccess && st == HSP_OK; rb *= 2) {
-    st = group_precond(G, rr, zz, rb, 0, s, G.mixed ? 1 : 0);  // warm-up
+    st = group_precond(G, rr, zz, rb, 0, s, G.v32 ? 1 : 0, G.mixed ? 1 : 0);  // warm-up
     if (st != HSP_OK) break;
     err = hipEventRecord(e0, s);
     for (int rep = 0; rep < 2 && err == hipSuccess && st == HSP_OK; ++rep)
-      st = group_precond(G, rr, zz, rb, 0, s, G.mixed ? 1 : 0);
+      st = group_precond(G, rr, zz, rb, 0, s, G.v32 ? 1 : 0, G.mixed ? 1 : 0);
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0;

@@ -82,6 +82,7 @@ hsp_status validate(const hsp_grid* g, int J, const hsp_options* o) {
   if (o->precision != HSP_FP64 && o->precision != HSP_MIXED) return fail(HSP_EINVAL, "bad precision");
   if (!std::isfinite(o->omega_jac)) return fail(HSP_EINVAL, "bad omega_jac");
   if (o->chunk < 0 || o->chunk > kMaxChunk) return fail(HSP_EINVAL, "chunk must be in 0..64");
+  if (o->krylov_fp32 != 0 && o->krylov_fp32 != 1) return fail(HSP_EINVAL, "krylov_fp32 must be 0 or 1");
   return HSP_OK;
 }
 
@@ -438,16 +439,16 @@ void run_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
   const size_t nc = (size_t)P.nc1 * P.nc2;
   if (std::is_same<T, float>::value && smooth_fused_ok(C->fine, nu)) {
     // each smoothing phase as one kernel (LDS tiles with a halo of nu nodes)
-    cf* res = C->at<float>(P.o_tgres);  // complex64 residual of the fused smoother
+    cd* res = C->at<double>(P.o_tgres);
     cx<T>* rc = C->at<T>(P.o_tgrc);
     cx<T>* ec = C->at<T>(P.o_tgec);
     prof_begin(C, HSP_PROF_SMOOTH, s);
     launch_smooth_pre(C->fine, nu, wj, r, BIdx{}, reinterpret_cast<cf*>(xa), BIdx{}, res, BIdx{}, 1, s);
-    // r, k^2 read; x_nu and the residual written
-    prof_end(C, HSP_PROF_SMOOTH, s, (double)nf * (sizeof(cd) + sizeof(double) + 2.0 * sizeof(cf)));
+    // r, k^2 read; x_nu (complex64) and the residual (complex128) written
+    prof_end(C, HSP_PROF_SMOOTH, s, (double)nf * (2.0 * sizeof(cd) + sizeof(double) + sizeof(cf)));
     prof_begin(C, HSP_PROF_TRANSFER, s);
-    launch_restrict<float, T>(C->tr, res, rc, s);
-    prof_end(C, HSP_PROF_TRANSFER, s, (double)nf * sizeof(cf) + (double)nc * sizeof(cx<T>));
+    launch_restrict<double, T>(C->tr, res, rc, s);
+    prof_end(C, HSP_PROF_TRANSFER, s, (double)nf * sizeof(cd) + (double)nc * sizeof(cx<T>));
     run_sweep<T>(C, rc, ec, s);
     prof_begin(C, HSP_PROF_SMOOTH, s);
     launch_smooth_post(C->fine, C->tr, nu, wj, r, BIdx{}, reinterpret_cast<const cf*>(xa), BIdx{},
@@ -564,6 +565,7 @@ hsp_status hsp_default_options(hsp_options* o) {
   o->precision = HSP_FP64;
   o->restart = 40;
   o->chunk = 0;
+  o->krylov_fp32 = 0;
   return HSP_OK;
 }
 

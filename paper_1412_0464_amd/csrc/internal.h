@@ -60,7 +60,7 @@ void launch_prolong_add(const TransferDev& T, const cx<Tc>* ec, cx<Tf>* xf, hipS
 bool smooth_fused_ok(const LevelDev& L, int nu);
 // (r is complex128 or complex64: TR = double or float)
 template <class TR>
-void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cf* res,
+void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cd* res,
                        BIdx bres, int nb, hipStream_t s);
 template <class TR, class TZ>
 void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double w, const cx<TR>* r, BIdx br,
@@ -190,6 +190,8 @@ void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t 
 // Batched forms over nb right-hand sides z (vector j of z: V + bv.off(z) + j ldj):
 // out[z ldo + j] = conj(V_zj) . w_z, j < cnt (partial: nb cnt nblocks entries)
 int batch_dot_blocks(size_t n, int nb);
+// blocks per right-hand side of launch_bdcgs_update (partial: nb nblocks)
+int batch_upd_blocks(size_t n, int nb);
 void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BIdx bw, size_t n, cd* partial,
                       int nblocks, cd* out, size_t ldo, int nb, hipStream_t s);
 // w_z -= (or +=) sum_j h[z ldh + j] V_zj (V complex128 or complex64)

@@ -5,7 +5,7 @@
 // step.
 //
 //   pre:  x_1 = w D^{-1} r, x_{s+1} = x_s + w D^{-1} (r - A x_s), s < nu;
-//         outputs x_nu and the fine residual r - A x_nu (complex64);
+//         outputs x_nu and the fine residual r - A x_nu (complex128);
 //   post: x_0 = x + P e_c (prolongation of the coarse correction), then nu
 //         steps; output x_nu (complex64 or complex128).
 //
@@ -13,9 +13,9 @@
 // in complex64 from complex64 row / column factors and k^2 (w D^{-1} once per
 // node and kept in LDS with r and the two iterates; the off-diagonals per
 // step).  A step is written (1 - w) x + (w D^{-1}) (r - (A - D) x), so the
-// diagonal itself is needed only for the residual, where it is recovered
-// from w D^{-1}.  The prolongation sums are in double, as in the separate
-// kernel (transfer.hip).
+// diagonal itself is not kept.  The residual that starts the coarse-grid
+// correction and the prolongation sums are in double, as in the separate
+// kernels (stencil.hip, transfer.hip).
 #include "internal.h"
 
 namespace hsp {
@@ -146,7 +146,7 @@ __device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, d
 
 template <int NU, class TR>
 __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const cx<TR>* __restrict__ r, BIdx br,
-                                                    cf* __restrict__ xo, BIdx bxo, cf* __restrict__ res, BIdx bres) {
+                                                    cf* __restrict__ xo, BIdx bxo, cd* __restrict__ res, BIdx bres) {
   using S = SmoothTile<NU>;
   constexpr int EY = S::EY, NE = S::NE, H = S::H;
   __shared__ cf xa[NE], xb[NE], rr[NE], dws[NE];
@@ -155,7 +155,6 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
   const int i0 = blockIdx.y * kTX + 1 - H, k0 = blockIdx.x * kTY + 1 - H;
   const int z = blockIdx.z;
   const float omw = (float)(1.0 - w);
-  const cf wt = mk<float>((float)w, 0.f);
   r += br.off(z);
   xo += bxo.off(z);
   res += bres.off(z);
@@ -181,20 +180,26 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
     cur = nxt;
     nxt = t;
   }
-  // x_nu and the residual r - A x_nu, in complex64 from the tile like the
-  // smoothing steps
+  // x_nu and the residual r - A x_nu in double (stencil_coefs arithmetic:
+  // the coarse-grid correction starts from a complex128 residual)
   for (int idx = threadIdx.x; idx < kTX * kTY; idx += blockDim.x) {
     const int ti = H + idx / kTY, tk = H + idx % kTY;
     const int i = i0 + ti, k = k0 + tk;
     if (i > n1 || k > n2) continue;
     const int e = ti * EY + tk;
     const size_t g = (size_t)(i - 1) * n2 + (k - 1);
-    // the diagonal back from w D^{-1}
-    const cf c11 = wt * cinv(dws[e]);
-    cf a = offdiag5<EY>(ax, cur, e, ti, tk, i > 1, i < n1, k > 1, k < n2);
-    cfma(a, c11, cur[e]);
+    const cd ian = L.xB[i], ikn = L.yB[k];
+    const cd cw = -(L.xA[i - 1] * ikn), ce = -(L.xA[i] * ikn);
+    const cd cs = -(L.yA[k - 1] * ian), cn = -(L.yA[k] * ian);
+    const cd c11 = -(cw + ce + cs + cn) - (L.h2 * L.k2[g]) * (ian * ikn);
+    cd a = mk<double>(0, 0);
+    if (i > 1) cfma(a, cw, cvt<double>(cur[e - EY]));
+    if (k > 1) cfma(a, cs, cvt<double>(cur[e - 1]));
+    cfma(a, c11, cvt<double>(cur[e]));
+    if (k < n2) cfma(a, cn, cvt<double>(cur[e + 1]));
+    if (i < n1) cfma(a, ce, cvt<double>(cur[e + EY]));
     xo[g] = cur[e];
-    res[g] = rr[e] - a;
+    res[g] = cvt<double>(r[g]) - a;
   }
 }
 
@@ -303,7 +308,7 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
 bool smooth_fused_ok(const LevelDev& L, int nu) { return L.kind == 5 && L.xmap == nullptr && nu >= 1 && nu <= 3; }
 
 template <class TR>
-void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cf* res,
+void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cd* res,
                        BIdx bres, int nb, hipStream_t s) {
   if (nb < 1) return;
   const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
@@ -336,7 +341,7 @@ void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double
 }
 
 #define INST(TR)                                                                                                \
-  template void launch_smooth_pre<TR>(const LevelDev&, int, double, const cx<TR>*, BIdx, cf*, BIdx, cf*, BIdx,  \
+  template void launch_smooth_pre<TR>(const LevelDev&, int, double, const cx<TR>*, BIdx, cf*, BIdx, cd*, BIdx,  \
                                       int, hipStream_t);
 INST(double)
 INST(float)

@@ -36,7 +36,7 @@ class HspOptions(ctypes.Structure):
     _fields_ = [("fine_stencil", ctypes.c_int), ("two_grid", ctypes.c_int), ("w_dd", ctypes.c_int),
                 ("S_dd", ctypes.c_double), ("nu", ctypes.c_int), ("omega_jac", ctypes.c_double),
                 ("sweep", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
-                ("chunk", ctypes.c_int)]
+                ("chunk", ctypes.c_int), ("krylov_fp32", ctypes.c_int)]
 
 
 class HspInfo(ctypes.Structure):
@@ -150,8 +150,10 @@ def make_options(**kw):
             v = SWEEP[v] if isinstance(v, str) else v
         if k == "precision":
             v = PRECISION[v] if isinstance(v, str) else v
-        if k == "two_grid":
+        if k in ("two_grid", "krylov_fp32"):
             v = int(bool(v))
+        if k not in dict(HspOptions._fields_):
+            raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
     return o
 
@@ -172,7 +174,8 @@ class Helmholtz:
     ``pml`` outer PML cells per side (int or pair); the interior node counts
             follow from c.shape - 2*pml.
     Options follow hsp_options (fine_stencil, two_grid, w_dd, S_dd, nu,
-    omega_jac, sweep 'x'/'ud', precision 'fp64'/'mixed', restart, chunk).
+    omega_jac, sweep 'x'/'ud', precision 'fp64'/'mixed', restart, chunk,
+    krylov_fp32).
     """
 
     def __init__(self, c, omega, h, pml, J, S_outer=0.0, c_pml=0.0, **opts):

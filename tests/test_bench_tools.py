@@ -19,7 +19,7 @@ FWD = "void hsp::(anonymous namespace)::k_bstage_fwd<float, 32, 4, 2>(hsp::BSeg 
 MID = "void hsp::(anonymous namespace)::k_bstage_mid<float, 32, 4, 2>(hsp::BSeg const*, int, int)"
 BWD = "void hsp::(anonymous namespace)::k_bstage_bwd<float, 32, 4>(hsp::BSeg const*, int, int)"
 FWD8 = "void hsp::(anonymous namespace)::k_bstage_fwd<float, 32, 8, 2>(hsp::BSeg const*, int, int)"
-PROJ = "void hsp::(anonymous namespace)::k_bmultidot2<float>(hsp::cx<float> const*, unsigned long, hsp::BIdx, int)"
+PROJ = "void hsp::(anonymous namespace)::k_bmultidot2<double>(hsp::cx<double> const*, unsigned long, hsp::BIdx, int)"
 
 
 def _write(path, counter, rows):

@@ -37,17 +37,17 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def _build(name, precision="fp64", chunk=0, restart=40):
+def _build(name, precision="fp64", chunk=0, restart=40, **extra):
     n1, n2, w, J, fine, tg, sweep, ppw = CASES[name]
     c = extend_into_pml(layered_medium_2d(n1, n2, 1412046, n_layers=7, corr_len=6.0), w)
     h = 0.02
     om = 2 * np.pi * 1.5 / (ppw * h)
-    print(f"[batch case {name} precision={precision} chunk={chunk} shape={c.shape}]", flush=True)
+    print(f"[batch case {name} precision={precision} chunk={chunk} {extra} shape={c.shape}]", flush=True)
     ref = Problem2D(c, om, h, w, S_outer=5.0 * w, J=J, w_dd=4, fine=fine, two_grid=tg, sweep=sweep)
     from paper_1412_0464_amd import Helmholtz
     hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, J, S_outer=5.0 * w,
                    fine_stencil=5 if fine == "fd5" else 9, two_grid=tg, sweep=sweep, precision=precision,
-                   chunk=chunk, restart=restart)
+                   chunk=chunk, restart=restart, **extra)
     return c, ref, hs
 
 
@@ -125,8 +125,12 @@ def test_batch_solve_fp64(name):
         assert _relerr(U[j], uo) < 1e-6, f"column {j}"
 
 
-def test_batch_solve_mixed_after_refinement():
-    c, ref, hs = _build("tg_x_j5", "mixed")
+@pytest.mark.parametrize("krylov_fp32", [False, True])
+def test_batch_solve_mixed_after_refinement(krylov_fp32):
+    """Mixed precision, with the Arnoldi basis in complex128 (default) or in
+    complex64 (krylov_fp32): refined to 1e-10 it reaches the direct solution;
+    at 1e-6 each column takes the oracle's iteration count within +-1."""
+    c, ref, hs = _build("tg_x_j5", "mixed", krylov_fp32=krylov_fp32)
     fs = _sources(c.shape, 0.02, 5)
     B = torch.stack([hs.rhs(_t(f)) for f in fs])
     U, its, rrs = hs.solve_batch(B, tol=1e-10, maxit=200)
@@ -223,9 +227,9 @@ def test_batch_invalid_arguments():
 GROUP = [("tg_x_j5", 3), ("tg_ud", 2), ("fd5_1lvl_x", 5), ("fe9_1lvl_x", 0)]
 
 
-def _group(precision):
+def _group(precision, **extra):
     from paper_1412_0464_amd import Group
-    built = [_build(name, precision) for name, _ in GROUP]
+    built = [_build(name, precision, **extra) for name, _ in GROUP]
     return built, Group([hs for _, _, hs in built], restart=40)
 
 
@@ -255,9 +259,10 @@ def test_group_graph_replays_match_eager():
             assert np.array_equal(got[p], eager[p]), f"replay {rep} problem {p}"
 
 
-@pytest.mark.parametrize("precision,graph", [("fp64", False), ("mixed", True)])
-def test_group_solve(precision, graph):
-    built, grp = _group(precision)
+@pytest.mark.parametrize("precision,graph,krylov_fp32", [("fp64", False, False), ("mixed", True, False),
+                                                         ("mixed", False, True)])
+def test_group_solve(precision, graph, krylov_fp32):
+    built, grp = _group(precision, krylov_fp32=krylov_fp32)
     fss = [_sources(c.shape, 0.02, k) if k else [] for (c, _, _), (_, k) in zip(built, GROUP)]
     Bs = [torch.stack([hs.rhs(_t(f)) for f in fs]) if fs else
           torch.zeros((0,) + tuple(c.shape), dtype=torch.complex128, device=_dev())
@@ -277,3 +282,14 @@ def test_group_solve(precision, graph):
                 assert _relerr(U[j], uo) < 1e-6
             else:
                 assert _relerr(U[j], ref.direct(f)) < 1e-4
+
+
+def test_group_rejects_mixed_basis_precisions():
+    """The members of a group share one Krylov layout: a group of problems
+    whose Arnoldi bases are stored in different precisions is refused."""
+    from paper_1412_0464_amd import Group
+    from paper_1412_0464_amd.hsp import HspError
+    _, _, h1 = _build("tg_x_j5", "mixed")
+    _, _, h2 = _build("tg_ud", "mixed", krylov_fp32=True)
+    with pytest.raises(HspError):
+        Group([h1, h2], restart=40).workspace([1, 1])
