@@ -41,15 +41,17 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_layered1023_64src.md")
 KERNEL_SOURCES = {
     "stage": ["batch.hip", "sweep_dev.h", "internal.h", "common.h"],
     "project": ["blas.hip", "internal.h", "common.h"],
+    "update": ["blas.hip", "internal.h", "common.h"],
 }
 # kernel names in the counter files: the batched stage (three launches per
-# stage, for the tile in use) and the projection pass over the complex128
-# Arnoldi basis
+# stage, for the tile in use) and the projection and update passes over the
+# complex128 Arnoldi basis
 KERNEL_PATTERNS = {
     "stage": r"k_bstage_(fwd|mid|bwd)<float, (\d+), (\d+)",
     "project": r"k_bmultidot2<double>",
+    "update": r"k_bdcgs_update<double>",
 }
-CLASSES = ("stage", "smooth", "coarse", "transfer", "krylov", "project")
+CLASSES = ("stage", "smooth", "coarse", "transfer", "krylov", "project", "update")
 COPY_BYTES = 256 << 20
 
 METRIC = "dof·iter/s and solve time to 1e-6 rel. residual: FP32-batched vs plain FP64"
@@ -103,7 +105,7 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc):
     """Per-kernel averages of the rocprofv3 counter files of a FETCH_SIZE run
     and a WRITE_SIZE run (KiB per dispatch), the copy scale factors, and the
     traffic records of the batched stage (per stage, for ``tile``) and of the
-    projection pass (per launch)."""
+    projection and update passes (per launch)."""
     import csv
     import re
     from collections import defaultdict
@@ -117,7 +119,7 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc):
                 disp[name].add(row["Dispatch_Id"])
         return {k: (len(disp[k]), tot[k]) for k in tot}
 
-    per = {"stage": {}, "project": {}}
+    per = {"stage": {}, "project": {}, "update": {}}
     for label, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         d = load_csv(path)
         print(f"{label} (KiB per dispatch)")
@@ -129,21 +131,24 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc):
         copy_kib = copy[0][1] / copy[0][0]
         scale = (COPY_BYTES / 1024) / copy_kib
         print(f"  copy: {copy_kib:.1f} KiB per dispatch for {COPY_BYTES // 1024} KiB -> scale {scale:.4f}")
-        stage_kib, stages, proj_kib, projs = 0.0, 0, 0.0, 0
+        stage_kib, stages = 0.0, 0
+        pass_kib, passes = {"project": 0.0, "update": 0.0}, {"project": 0, "update": 0}
         for k, (n, v) in d.items():
             m = re.search(KERNEL_PATTERNS["stage"], k)
             if m and int(m.group(3)) == tile:
                 stage_kib += v
                 if m.group(1) == "fwd":
                     stages += n
-            if re.search(KERNEL_PATTERNS["project"], k):
-                proj_kib += v
-                projs += n
+            for kern in pass_kib:
+                if re.search(KERNEL_PATTERNS[kern], k):
+                    pass_kib[kern] += v
+                    passes[kern] += n
         print(f"  stage (tile {tile}): {stages} stages, {stage_kib / max(stages, 1):.1f} KiB per stage raw")
-        print(f"  projection: {projs} launches, {proj_kib / max(projs, 1):.1f} KiB per launch raw")
         per["stage"][label] = stage_kib / max(stages, 1) * 1024 * scale
-        per["project"][label] = proj_kib / max(projs, 1) * 1024 * scale
-    for kernel, t in (("stage", tile), ("project", 0)):
+        for kern in pass_kib:
+            print(f"  {kern}: {passes[kern]} launches, {pass_kib[kern] / max(passes[kern], 1):.1f} KiB per launch raw")
+            per[kern][label] = pass_kib[kern] / max(passes[kern], 1) * 1024 * scale
+    for kernel, t in (("stage", tile), ("project", 0), ("update", 0)):
         f, w = per[kernel]["FETCH_SIZE"], per[kernel]["WRITE_SIZE"]
         print(f"{kernel}: fetch {f:.4e} B + write {w:.4e} B per launch (scaled)")
         print(f"traffic-record: kernel={kernel} bytes_per_launch={f + w:.5e} tile={t} sources={nsrc} "
@@ -403,12 +408,13 @@ def main():
     }
     # rooflines from the event-timed classes of the profiled repeat:
     # algorithmic bytes per launch / average launch time.  The dominant kernel
-    # class is the SubdomSolve stage (three dependent launches timed as one;
-    # k_bstage_mid and k_bstage_fwd are the two kernels with the largest total
-    # time); the FGMRES projection pass (k_bmultidot2: every basis vector and
-    # w once per Arnoldi step; its event pair also covers two small
-    # reductions), the largest of the HBM-bound kernels, follows as
-    # roofline_project.
+    # class is the SubdomSolve stage (three dependent launches timed as one,
+    # about 40 % of a solve); the two HBM-bound passes of the complex128
+    # Gram-Schmidt follow: the update pass (k_bdcgs_update: k basis vectors,
+    # u_k and w read, v_k and u_{k+1} written; the kernel with the largest
+    # total time) as roofline_update and the projection pass (k_bmultidot2:
+    # every basis vector and w once per Arnoldi step; its event pair also
+    # covers two small reductions) as roofline_project.
     cls = bat["classes"]
 
     def roofline(name, kernel, traffic):
@@ -424,6 +430,8 @@ def main():
                                recorded_traffic("stage", bat["tile"], len(fs)))
     out["roofline_project"] = roofline("project", "FGMRES projection pass k_bmultidot2<double> (complex128 basis)",
                                        recorded_traffic("project", bat["tile"], len(fs)))
+    out["roofline_update"] = roofline("update", "FGMRES update pass k_bdcgs_update<double> (complex128 basis)",
+                                      recorded_traffic("update", bat["tile"], len(fs)))
     out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
     out["config"]["profiled_solve_s"] = bat["profiled_solve_s"]
     Ub = None if args.no_fp64 else bat["U"][0].cpu().numpy()

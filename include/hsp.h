@@ -309,9 +309,10 @@ enum {
   HSP_PROF_COARSE = 2,    /* residual inside the sweep (DD level)           */
   HSP_PROF_TRANSFER = 3,  /* restriction and prolongation                   */
   HSP_PROF_KRYLOV = 4,    /* FGMRES matvec and Gram-Schmidt kernels (the     */
-                          /* batched projection pass excepted)              */
+                          /* batched projection and update passes excepted) */
   HSP_PROF_PROJECT = 5,   /* batched FGMRES projection pass (k_bmultidot2)   */
-  HSP_PROF_NCLASS = 6
+  HSP_PROF_UPDATE = 6,    /* batched FGMRES update pass (k_bdcgs_update)     */
+  HSP_PROF_NCLASS = 7
 };
 hsp_status hsp_profile_enable(hsp_handle hd, int on);
 hsp_status hsp_profile_read(hsp_handle hd, int cls, double* total_ms, long long* launches,

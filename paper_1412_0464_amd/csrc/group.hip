@@ -819,14 +819,14 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
             launch_bdcgs_project<double>(mptr<cd>(mb, B.o_V), nf, bVb, k, w, bw, nf, part, nbp, hb, B.hs, koff,
                                          nact[p], s);
           prof_end(mb.C, HSP_PROF_PROJECT, s, na * nf * (vb * (k + 1.0) + sizeof(cd)));
-          prof_begin(mb.C, HSP_PROF_KRYLOV, s);
+          prof_begin(mb.C, HSP_PROF_UPDATE, s);
           if (G.v32)
             launch_bdcgs_update<float>(mptr<cf>(mb, B.o_V), nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, nbu,
                                        hb + koff + 2, nact[p], s);
           else
             launch_bdcgs_update<double>(mptr<cd>(mb, B.o_V), nf, bVb, k, hb, B.hs, koff, w, bw, nf, part, nbu,
                                         hb + koff + 2, nact[p], s);
-          prof_end(mb.C, HSP_PROF_KRYLOV, s, na * nf * (vb * (k + 3.0) + sizeof(cd)));
+          prof_end(mb.C, HSP_PROF_UPDATE, s, na * nf * (vb * (k + 3.0) + sizeof(cd)));
           HIPCHK(hipMemcpyAsync(ms[p].hh.data(), hb, (size_t)nact[p] * B.hs * sizeof(cd), hipMemcpyDeviceToHost, s));
         }
         HIPCHK(hipGetLastError());

@@ -52,7 +52,7 @@ EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", 
            "hsp_tune_batch", "hsp_solve_batch", "hsp_group_workspace_size", "hsp_apply_precond_group",
            "hsp_solve_group"]
 GROUP_GRAPH = 1
-PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4, "project": 5}
+PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4, "project": 5, "update": 6}
 
 
 def library_path():

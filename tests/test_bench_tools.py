@@ -20,6 +20,7 @@ MID = "void hsp::(anonymous namespace)::k_bstage_mid<float, 32, 4, 2>(hsp::BSeg 
 BWD = "void hsp::(anonymous namespace)::k_bstage_bwd<float, 32, 4>(hsp::BSeg const*, int, int)"
 FWD8 = "void hsp::(anonymous namespace)::k_bstage_fwd<float, 32, 8, 2>(hsp::BSeg const*, int, int)"
 PROJ = "void hsp::(anonymous namespace)::k_bmultidot2<double>(hsp::cx<double> const*, unsigned long, hsp::BIdx, int)"
+UPD = "void hsp::(anonymous namespace)::k_bdcgs_update<double>(hsp::cx<double>*, unsigned long, hsp::BIdx, int)"
 
 
 def _write(path, counter, rows):
@@ -35,9 +36,9 @@ def test_reduce_counters(tmp_path, capsys):
     # the 256 MiB written; two stages at tile 4 and one at tile 8 (ignored)
     kib = bench.COPY_BYTES / 1024
     fetch = [(COPY, kib / 2), (FWD, 100.0), (MID, 50.0), (BWD, 25.0), (FWD, 300.0), (MID, 150.0), (BWD, 75.0),
-             (FWD8, 1e6), (PROJ, 1000.0), (PROJ, 3000.0)]
+             (FWD8, 1e6), (PROJ, 1000.0), (PROJ, 3000.0), (UPD, 500.0), (UPD, 700.0)]
     write = [(COPY, kib), (FWD, 10.0), (MID, 20.0), (BWD, 30.0), (FWD, 10.0), (MID, 20.0), (BWD, 30.0),
-             (FWD8, 1e6), (PROJ, 1.0), (PROJ, 1.0)]
+             (FWD8, 1e6), (PROJ, 1.0), (PROJ, 1.0), (UPD, 100.0), (UPD, 100.0)]
     _write(tmp_path / "f.csv", "FETCH_SIZE", fetch)
     _write(tmp_path / "w.csv", "WRITE_SIZE", write)
     bench.reduce_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), tile=4, nsrc=64)
@@ -55,6 +56,8 @@ def test_reduce_counters(tmp_path, capsys):
     proj = float(rec["project"]["bytes_per_launch"])
     assert proj == pytest.approx((4000 / 2 * 2 + 2 / 2) * 1024, rel=1e-5)
     assert rec["project"]["digest"] == bench.sources_digest("project")
+    upd = float(rec["update"]["bytes_per_launch"])
+    assert upd == pytest.approx((1200 / 2 * 2 + 200 / 2) * 1024, rel=1e-5)
 
 
 def test_reduce_counters_needs_copy(tmp_path):
@@ -85,7 +88,7 @@ def test_committed_records_parse():
     """The committed counter summary holds a record for each roofline kernel."""
     with open(bench.TRAFFIC_RECORD) as fh:
         txt = fh.read()
-    for kernel in ("stage", "project"):
+    for kernel in ("stage", "project", "update"):
         assert f"traffic-record: kernel={kernel} " in txt
 
 
