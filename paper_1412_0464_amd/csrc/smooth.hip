@@ -181,17 +181,22 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
     nxt = t;
   }
   // x_nu and the residual r - A x_nu in double (stencil_coefs arithmetic:
-  // the coarse-grid correction starts from a complex128 residual)
-  for (int idx = threadIdx.x; idx < kTX * kTY; idx += blockDim.x) {
-    const int ti = H + idx / kTY, tk = H + idx % kTY;
+  // the coarse-grid correction starts from a complex128 residual).  Each
+  // thread takes the interior nodes among the ones it fetched, so r and k^2
+  // come from its registers rather than a second read.
+#pragma unroll
+  for (int q = 0; q < NodeLoads<NU, TR>::NI; ++q) {
+    const int e = (int)threadIdx.x + 256 * q;
+    if (e >= NE) break;
+    const int ti = e / EY, tk = e - (e / EY) * EY;
+    if (ti < H || ti >= H + kTX || tk < H || tk >= H + kTY) continue;
     const int i = i0 + ti, k = k0 + tk;
     if (i > n1 || k > n2) continue;
-    const int e = ti * EY + tk;
     const size_t g = (size_t)(i - 1) * n2 + (k - 1);
     const cd ian = L.xB[i], ikn = L.yB[k];
     const cd cw = -(L.xA[i - 1] * ikn), ce = -(L.xA[i] * ikn);
     const cd cs = -(L.yA[k - 1] * ian), cn = -(L.yA[k] * ian);
-    const cd c11 = -(cw + ce + cs + cn) - (L.h2 * L.k2[g]) * (ian * ikn);
+    const cd c11 = -(cw + ce + cs + cn) - (L.h2 * ld.k2[q]) * (ian * ikn);
     cd a = mk<double>(0, 0);
     if (i > 1) cfma(a, cw, cvt<double>(cur[e - EY]));
     if (k > 1) cfma(a, cs, cvt<double>(cur[e - 1]));
@@ -199,7 +204,7 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
     if (k < n2) cfma(a, cn, cvt<double>(cur[e + 1]));
     if (i < n1) cfma(a, ce, cvt<double>(cur[e + EY]));
     xo[g] = cur[e];
-    res[g] = cvt<double>(r[g]) - a;
+    res[g] = cvt<double>(ld.r[q]) - a;
   }
 }
 
