@@ -24,6 +24,11 @@ namespace {
 
 constexpr int kTX = 16;  // tile rows (x)
 constexpr int kTY = 64;  // tile columns (y, the contiguous axis)
+// Threads per workgroup: the LDS tile allows three workgroups per CU, so the
+// pre-smoothing (few registers) runs 512 threads to keep more loads in
+// flight; the post-smoothing (prolongation taps in registers) runs 256.
+constexpr int kPreThreads = 512;
+constexpr int kPostThreads = 256;
 
 // Extended tile (tile + halo of NU nodes) of the complex64 smoother.
 template <int NU>
@@ -100,20 +105,20 @@ __device__ __forceinline__ void jacobi_region(const LevelDev& L, int i0, int k0,
 // (formed in complex64 from the row / column factors and k^2).  All global
 // loads of a thread are issued before any is used (one memory round trip for
 // the whole tile); the axes must already be in LDS.
-template <int NU, class TR>
+template <int NU, class TR, int NT>
 struct NodeLoads {
-  static constexpr int NI = (SmoothTile<NU>::NE + 255) / 256;
+  static constexpr int NI = (SmoothTile<NU>::NE + NT - 1) / NT;
   cx<TR> r[NI];
   double k2[NI];
 };
 
-template <int NU, class TR>
+template <int NU, class TR, int NT>
 __device__ __forceinline__ void fetch_nodes(const LevelDev& L, int i0, int k0, const cx<TR>* r,
-                                            NodeLoads<NU, TR>& ld) {
+                                            NodeLoads<NU, TR, NT>& ld) {
   using S = SmoothTile<NU>;
 #pragma unroll
-  for (int q = 0; q < NodeLoads<NU, TR>::NI; ++q) {
-    const int idx = min((int)threadIdx.x + 256 * q, S::NE - 1);
+  for (int q = 0; q < NodeLoads<NU, TR, NT>::NI; ++q) {
+    const int idx = min((int)threadIdx.x + NT * q, S::NE - 1);
     const int i = i0 + idx / S::EY, k = k0 + idx % S::EY;
     const bool in = i >= 1 && i <= L.n1 && k >= 1 && k <= L.n2;
     const size_t g = in ? (size_t)(i - 1) * L.n2 + (k - 1) : 0;
@@ -122,15 +127,15 @@ __device__ __forceinline__ void fetch_nodes(const LevelDev& L, int i0, int k0, c
   }
 }
 
-template <int NU, class TR>
-__device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, double w, const NodeLoads<NU, TR>& ld,
-                                            const Axes5& ax, cf* rr, cf* dws) {
+template <int NU, class TR, int NT>
+__device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, double w,
+                                            const NodeLoads<NU, TR, NT>& ld, const Axes5& ax, cf* rr, cf* dws) {
   using S = SmoothTile<NU>;
   const cf wt = cvt<float>(mk<double>(w, 0.0));
   const float h2 = (float)L.h2;
 #pragma unroll
-  for (int q = 0; q < NodeLoads<NU, TR>::NI; ++q) {
-    const int idx = (int)threadIdx.x + 256 * q;
+  for (int q = 0; q < NodeLoads<NU, TR, NT>::NI; ++q) {
+    const int idx = (int)threadIdx.x + NT * q;
     if (idx >= S::NE) break;
     const int ti = idx / S::EY, tk = idx % S::EY;
     const int i = i0 + ti, k = k0 + tk;
@@ -145,7 +150,7 @@ __device__ __forceinline__ void store_nodes(const LevelDev& L, int i0, int k0, d
 }
 
 template <int NU, class TR>
-__global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const cx<TR>* __restrict__ r, BIdx br,
+__global__ void __launch_bounds__(kPreThreads) k_smooth_pre(LevelDev L, double w, const cx<TR>* __restrict__ r, BIdx br,
                                                     cf* __restrict__ xo, BIdx bxo, cd* __restrict__ res, BIdx bres) {
   using S = SmoothTile<NU>;
   constexpr int EY = S::EY, NE = S::NE, H = S::H;
@@ -158,11 +163,12 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
   r += br.off(z);
   xo += bxo.off(z);
   res += bres.off(z);
-  NodeLoads<NU, TR> ld;
-  fetch_nodes<NU, TR>(L, i0, k0, r, ld);
+  constexpr int NT = kPreThreads;
+  NodeLoads<NU, TR, NT> ld;
+  fetch_nodes<NU, TR, NT>(L, i0, k0, r, ld);
   load_axes(L, i0, k0, S::EX, EY, ax);
   __syncthreads();
-  store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, dws);
+  store_nodes<NU, TR, NT>(L, i0, k0, w, ld, ax, rr, dws);
   __syncthreads();
   // x_1 = (w D^{-1}) r
   for (int idx = threadIdx.x; idx < NE; idx += blockDim.x) {
@@ -185,8 +191,8 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
   // thread takes the interior nodes among the ones it fetched, so r and k^2
   // come from its registers rather than a second read.
 #pragma unroll
-  for (int q = 0; q < NodeLoads<NU, TR>::NI; ++q) {
-    const int e = (int)threadIdx.x + 256 * q;
+  for (int q = 0; q < NodeLoads<NU, TR, NT>::NI; ++q) {
+    const int e = (int)threadIdx.x + NT * q;
     if (e >= NE) break;
     const int ti = e / EY, tk = e - (e / EY) * EY;
     if (ti < H || ti >= H + kTX || tk < H || tk >= H + kTY) continue;
@@ -209,7 +215,7 @@ __global__ void __launch_bounds__(256) k_smooth_pre(LevelDev L, double w, const 
 }
 
 template <int NU, class TR, class TZ>
-__global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr, double w, const cx<TR>* __restrict__ r,
+__global__ void __launch_bounds__(kPostThreads) k_smooth_post(LevelDev L, TransferDev Tr, double w, const cx<TR>* __restrict__ r,
                                                      BIdx br, const cf* __restrict__ xin, BIdx bxin,
                                                      const cf* __restrict__ ec, BIdx bec, cx<TZ>* __restrict__ zo,
                                                      BIdx bzo) {
@@ -225,13 +231,14 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
   xin += bxin.off(z);
   ec += bec.off(z);
   zo += bzo.off(z);
-  NodeLoads<NU, TR> ld;
-  fetch_nodes<NU, TR>(L, i0, k0, r, ld);
+  constexpr int NT = kPostThreads;
+  NodeLoads<NU, TR, NT> ld;
+  fetch_nodes<NU, TR, NT>(L, i0, k0, r, ld);
   // x_0 = x + P e_c (prolongation sums in double, as k_prolong_add).  The
   // taps are separable (rows times columns): the row and column taps of the
   // tile are staged in LDS with the axes, then every node issues its four
   // coarse loads.  (The tent weights are 0, 1/2 and 1: exact in float.)
-  constexpr int NI = NodeLoads<NU, TR>::NI;
+  constexpr int NI = NodeLoads<NU, TR, NT>::NI;
   __shared__ int tpi[2][S::EX], tpk[2][EY];
   __shared__ float twi[2][S::EX], twk[2][EY];
   for (int t = threadIdx.x; t < S::EX + EY; t += blockDim.x) {
@@ -260,7 +267,7 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
   cf x0[NI], v[NI][2][2];
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
-    const int idx = min((int)threadIdx.x + 256 * q, NE - 1);
+    const int idx = min((int)threadIdx.x + NT * q, NE - 1);
     const int ti = idx / EY, tk = idx - (idx / EY) * EY;
     const int i = i0 + ti, k = k0 + tk;
     const bool in = i >= 1 && i <= n1 && k >= 1 && k <= n2;
@@ -270,10 +277,10 @@ __global__ void __launch_bounds__(256) k_smooth_post(LevelDev L, TransferDev Tr,
 #pragma unroll
       for (int b = 0; b < 2; ++b) v[q][a][b] = ec[(size_t)tpi[a][ti] * Tr.nc2 + tpk[b][tk]];
   }
-  store_nodes<NU, TR>(L, i0, k0, w, ld, ax, rr, dws);
+  store_nodes<NU, TR, NT>(L, i0, k0, w, ld, ax, rr, dws);
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
-    const int idx = (int)threadIdx.x + 256 * q;
+    const int idx = (int)threadIdx.x + NT * q;
     if (idx >= NE) break;
     const int ti = idx / EY, tk = idx - (idx / EY) * EY;
     const int i = i0 + ti, k = k0 + tk;
@@ -318,9 +325,9 @@ void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BId
   if (nb < 1) return;
   const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
   switch (nu) {
-    case 1: hipLaunchKernelGGL((k_smooth_pre<1, TR>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
-    case 2: hipLaunchKernelGGL((k_smooth_pre<2, TR>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
-    default: hipLaunchKernelGGL((k_smooth_pre<3, TR>), grd, dim3(256), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+    case 1: hipLaunchKernelGGL((k_smooth_pre<1, TR>), grd, dim3(kPreThreads), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+    case 2: hipLaunchKernelGGL((k_smooth_pre<2, TR>), grd, dim3(kPreThreads), 0, s, L, w, r, br, xo, bxo, res, bres); break;
+    default: hipLaunchKernelGGL((k_smooth_pre<3, TR>), grd, dim3(kPreThreads), 0, s, L, w, r, br, xo, bxo, res, bres); break;
   }
 }
 
@@ -331,15 +338,15 @@ void launch_smooth_post(const LevelDev& L, const TransferDev& Tr, int nu, double
   const dim3 grd((L.n2 + kTY - 1) / kTY, (L.n1 + kTX - 1) / kTX, nb);
   switch (nu) {
     case 1:
-      hipLaunchKernelGGL((k_smooth_post<1, TR, TZ>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
+      hipLaunchKernelGGL((k_smooth_post<1, TR, TZ>), grd, dim3(kPostThreads), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
                          bzo);
       break;
     case 2:
-      hipLaunchKernelGGL((k_smooth_post<2, TR, TZ>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
+      hipLaunchKernelGGL((k_smooth_post<2, TR, TZ>), grd, dim3(kPostThreads), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
                          bzo);
       break;
     default:
-      hipLaunchKernelGGL((k_smooth_post<3, TR, TZ>), grd, dim3(256), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
+      hipLaunchKernelGGL((k_smooth_post<3, TR, TZ>), grd, dim3(kPostThreads), 0, s, L, Tr, w, r, br, xin, bxin, ec, bec, zo,
                          bzo);
       break;
   }
