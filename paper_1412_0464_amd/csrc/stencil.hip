@@ -133,6 +133,88 @@ __global__ void __launch_bounds__(256) k_stencil9(LevelDev L, int mode, const cx
   stencil_out<Ta, Tb, Ty>(mode, ax, xv[1][1], has_x, b, id, c[1][1], w, y);
 }
 
+// Both kinds for nb right-hand sides at once (blockIdx.z no longer selects
+// one): the coefficients of a node are formed once and applied to every
+// right-hand side in turn, so the batched kernel streams only the vectors
+// (the per-node coefficient arithmetic and the k^2 / cell data are not
+// repeated per right-hand side).  Same arithmetic, in the same order, as the
+// one-right-hand-side kernels above.
+template <int KIND, class Ta, class Tx, class Tb, class Ty>
+__global__ void __launch_bounds__(256) k_stencil_multi(LevelDev L, int mode, const cx<Tx>* __restrict__ x,
+                                                       const cx<Tb>* __restrict__ b, cx<Ty>* __restrict__ y,
+                                                       double w, BIdx bx, BIdx bb, BIdx by, int nb) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;  // y node 1..n2
+  const int i = blockIdx.y + 1;                             // x node 1..n1
+  const int n1 = L.n1, n2 = L.n2;
+  if (k > n2) return;
+  const bool has_x = x != nullptr;
+  const size_t id = (size_t)(i - 1) * n2 + (k - 1);
+  // coefficients (masked toward the boundary) and clamped neighbour indices
+  cd c[3][3];
+  if constexpr (KIND == 5) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) c[a][q] = mk<double>(0, 0);
+    const int row = L.xmap ? L.xmap[i - 1] : (i - 1);
+    const double k2 = L.k2[(size_t)row * n2 + (k - 1)];
+    const cd ian = L.xB[i], ikn = L.yB[k];
+    const cd cw = -(L.xA[i - 1] * ikn), ce = -(L.xA[i] * ikn);
+    const cd cs = -(L.yA[k - 1] * ian), cn = -(L.yA[k] * ian);
+    c[1][1] = -(cw + ce + cs + cn) - (L.h2 * k2) * (ian * ikn);
+    c[0][1] = keep(i > 1, cw);
+    c[2][1] = keep(i < n1, ce);
+    c[1][0] = keep(k > 1, cs);
+    c[1][2] = keep(k < n2, cn);
+  } else {
+    stencil_coefs(L, i, k, c);
+  }
+  cx<Ta> cc[3][3];
+  size_t nid[3][3];
+#pragma unroll
+  for (int di = -1; di <= 1; ++di)
+#pragma unroll
+    for (int dk = -1; dk <= 1; ++dk) {
+      int ii = i + di, kk = k + dk;
+      const bool ok = ii >= 1 && ii <= n1 && kk >= 1 && kk <= n2;
+      ii = ii < 1 ? 1 : (ii > n1 ? n1 : ii);
+      kk = kk < 1 ? 1 : (kk > n2 ? n2 : kk);
+      nid[di + 1][dk + 1] = (size_t)(ii - 1) * n2 + (kk - 1);
+      cc[di + 1][dk + 1] = cvt<Ta>(KIND == 5 ? c[di + 1][dk + 1] : keep(ok, c[di + 1][dk + 1]));
+    }
+#pragma unroll 2
+  for (int z = 0; z < nb; ++z) {
+    const cx<Tx>* xz = has_x ? x + bx.off(z) : x;
+    const cx<Tb>* bz = b != nullptr ? b + bb.off(z) : b;
+    cx<Ty>* yz = y + by.off(z);
+    cx<Ta> ax = mk<Ta>(0, 0), xc = mk<Ta>(0, 0);
+    if constexpr (KIND == 5) {
+      if (has_x) {
+        const cx<Ta> xw = ld<Ta>(xz, nid[0][1]), xs = ld<Ta>(xz, nid[1][0]);
+        xc = ld<Ta>(xz, id);
+        const cx<Ta> xn = ld<Ta>(xz, nid[1][2]), xe = ld<Ta>(xz, nid[2][1]);
+        cfma(ax, cc[0][1], xw);
+        cfma(ax, cc[1][0], xs);
+        cfma(ax, cc[1][1], xc);
+        cfma(ax, cc[1][2], xn);
+        cfma(ax, cc[2][1], xe);
+      }
+    } else {
+      cx<Ta> xv[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) xv[a][q] = has_x ? ld<Ta>(xz, nid[a][q]) : mk<Ta>(0, 0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) cfma(ax, cc[a][q], xv[a][q]);
+      xc = xv[1][1];
+    }
+    stencil_out<Ta, Tb, Ty>(mode, ax, xc, has_x, bz, id, c[1][1], w, yz);
+  }
+}
+
 }  // namespace
 
 template <class Ta, class Tx, class Tb, class Ty>
@@ -140,6 +222,14 @@ void launch_stencil(const LevelDev& L, int mode, const cx<Tx>* x, const cx<Tb>* 
                     double w, hipStream_t s, int nb, BIdx bx, BIdx bb, BIdx by) {
   if (nb < 1) return;
   dim3 blk(256);
+  if (nb > 1) {
+    const dim3 g2((L.n2 + 255) / 256, L.n1, 1);
+    if (L.kind == 5)
+      hipLaunchKernelGGL((k_stencil_multi<5, Ta, Tx, Tb, Ty>), g2, blk, 0, s, L, mode, x, b, y, w, bx, bb, by, nb);
+    else
+      hipLaunchKernelGGL((k_stencil_multi<9, Ta, Tx, Tb, Ty>), g2, blk, 0, s, L, mode, x, b, y, w, bx, bb, by, nb);
+    return;
+  }
   dim3 grd((L.n2 + 255) / 256, L.n1, nb);
   if (L.kind == 5)
     hipLaunchKernelGGL((k_stencil5<Ta, Tx, Tb, Ty>), grd, blk, 0, s, L, mode, x, b, y, w, bx, bb, by);
