@@ -133,12 +133,14 @@ __global__ void __launch_bounds__(256) k_stencil9(LevelDev L, int mode, const cx
   stencil_out<Ta, Tb, Ty>(mode, ax, xv[1][1], has_x, b, id, c[1][1], w, y);
 }
 
-// Both kinds for nb right-hand sides at once (blockIdx.z no longer selects
-// one): the coefficients of a node are formed once and applied to every
-// right-hand side in turn, so the batched kernel streams only the vectors
-// (the per-node coefficient arithmetic and the k^2 / cell data are not
-// repeated per right-hand side).  Same arithmetic, in the same order, as the
-// one-right-hand-side kernels above.
+// Both kinds for nb right-hand sides at once: blockIdx.z selects a group of
+// kStencilZ right-hand sides, the coefficients of a node are formed once per
+// group and applied to each right-hand side of the group in turn, so the
+// batched kernel mostly streams the vectors (the per-node coefficient
+// arithmetic and the k^2 / cell data are not repeated per right-hand side).
+// Same arithmetic, in the same order, as the one-right-hand-side kernels
+// above.
+constexpr int kStencilZ = 16;
 template <int KIND, class Ta, class Tx, class Tb, class Ty>
 __global__ void __launch_bounds__(256) k_stencil_multi(LevelDev L, int mode, const cx<Tx>* __restrict__ x,
                                                        const cx<Tb>* __restrict__ b, cx<Ty>* __restrict__ y,
@@ -182,8 +184,9 @@ __global__ void __launch_bounds__(256) k_stencil_multi(LevelDev L, int mode, con
       nid[di + 1][dk + 1] = (size_t)(ii - 1) * n2 + (kk - 1);
       cc[di + 1][dk + 1] = cvt<Ta>(KIND == 5 ? c[di + 1][dk + 1] : keep(ok, c[di + 1][dk + 1]));
     }
+  const int z0 = blockIdx.z * kStencilZ, z1 = min(nb, z0 + kStencilZ);
 #pragma unroll 2
-  for (int z = 0; z < nb; ++z) {
+  for (int z = z0; z < z1; ++z) {
     const cx<Tx>* xz = has_x ? x + bx.off(z) : x;
     const cx<Tb>* bz = b != nullptr ? b + bb.off(z) : b;
     cx<Ty>* yz = y + by.off(z);
@@ -223,7 +226,7 @@ void launch_stencil(const LevelDev& L, int mode, const cx<Tx>* x, const cx<Tb>* 
   if (nb < 1) return;
   dim3 blk(256);
   if (nb > 1) {
-    const dim3 g2((L.n2 + 255) / 256, L.n1, 1);
+    const dim3 g2((L.n2 + 255) / 256, L.n1, (nb + kStencilZ - 1) / kStencilZ);
     if (L.kind == 5)
       hipLaunchKernelGGL((k_stencil_multi<5, Ta, Tx, Tb, Ty>), g2, blk, 0, s, L, mode, x, b, y, w, bx, bb, by, nb);
     else

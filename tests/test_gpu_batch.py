@@ -90,6 +90,37 @@ def test_batch_precond_columns(name, precision, tol, tile):
         assert _relerr(Z[j], ref.precond(R[j].ravel())) < tol, f"column {j}"
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
+def test_batch_precond_columns_many(precision, tol):
+    """18 right-hand sides: the batched stencil launches take the sources in
+    groups (a full group and a ragged one), here in the coarse residual of
+    every sweep."""
+    c, ref, hs = _build("tg_x_j5", precision)
+    nrhs = 18
+    R = np.stack([random_rhs(c.shape, 340 + j) for j in range(nrhs)])
+    Z = hs.apply_precond_batch(_t(R), tile=4).cpu().numpy()
+    for j in range(nrhs):
+        assert _relerr(Z[j], ref.precond(R[j].ravel())) < tol, f"column {j}"
+
+
+def test_batch_solve_many_sources():
+    """18 sources (one of them zero) through the batched FGMRES: the
+    matvec and coarse-residual launches cover two groups of sources until
+    enough of them have converged."""
+    c, ref, hs = _build("tg_x_j5")
+    fs = _sources(c.shape, 0.02, 18)
+    B = torch.stack([hs.rhs(_t(f)) for f in fs])
+    U, its, rrs = hs.solve_batch(B, tol=1e-6, maxit=100)
+    U = U.cpu().numpy()
+    for j, f in enumerate(fs):
+        if not np.any(f):
+            assert its[j] == 0 and rrs[j] == 0 and not np.any(U[j])
+            continue
+        uo, ito, _, _ = ref.solve(f, tol=1e-6, maxit=100)
+        assert abs(its[j] - ito) <= 1 and rrs[j] <= 1e-6, f"column {j}: {its[j]} vs {ito}, {rrs[j]}"
+        assert _relerr(U[j], uo) < 1e-6, f"column {j}"
+
+
 @pytest.mark.parametrize("chunk", [7, 64])
 def test_batch_precond_chunk_geometry(chunk):
     c, ref, hs = _build("tg_x_j5", "fp64", chunk=chunk)
