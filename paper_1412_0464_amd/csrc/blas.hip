@@ -337,7 +337,16 @@ __global__ void k_bdcgs_coef(cd* __restrict__ hb, size_t ldh, int k, int off, in
 // u' = w - V p - h_kk v_k (the next once-projected vector) goes to slot k+1,
 // with the block partials of ||u'||^2.  Reads V (k vectors), u and w once.
 // With a complex64 basis, v_k and u' are rounded before they are used, so
-// that the recurrences see exactly the stored vectors.
+// that the recurrences see exactly the stored vectors.  Each thread takes
+// kUpdElems elements per iteration (blockDim apart) so that more loads are in
+// flight, and the two output vectors are written with non-temporal stores
+// (no reuse before they are streamed again).
+constexpr int kUpdElems = 2;
+template <class T>
+__device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v) {
+  __builtin_nontemporal_store(v.re, &p->re);
+  __builtin_nontemporal_store(v.im, &p->im);
+}
 template <class TV>
 __global__ void __launch_bounds__(256) k_bdcgs_update(cx<TV>* __restrict__ V, size_t ldj, BIdx bv, int k,
                                                       const cd* __restrict__ hb, size_t ldh, int off,
@@ -355,34 +364,54 @@ __global__ void __launch_bounds__(256) k_bdcgs_update(cx<TV>* __restrict__ V, si
   cx<TV>* un = vz + (size_t)(k + 1) * ldj;
   w += bw.off(z);
   double nrm = 0;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const cx<TV> ui = u[i];
-    const cd wi = w[i];
-    cd t1 = mk<double>(0, 0), t2 = mk<double>(0, 0);
-    // kUpdUnroll loads in flight per round, the last round included: its
+  constexpr int E = kUpdElems;
+  const size_t stride = (size_t)gridDim.x * blockDim.x * E;
+  for (size_t i0 = blockIdx.x * (size_t)blockDim.x * E + threadIdx.x; i0 < n; i0 += stride) {
+    size_t ii[E];
+    cx<TV> ui[E];
+    cd wi[E], t1[E], t2[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const size_t ie = i0 + (size_t)e * blockDim.x;
+      ii[e] = ie < n ? ie : n - 1;  // clamped: loads are unconditional
+      ui[e] = u[ii[e]];
+      wi[e] = w[ii[e]];
+      t1[e] = mk<double>(0, 0);
+      t2[e] = mk<double>(0, 0);
+    }
+    // kUpdUnroll basis vectors per round, the last round included: its
     // indices are clamped to k - 1 and the coefficients past k are zero, so
     // that no load waits behind a branch
     for (int j = 0; j < k; j += kUpdUnroll) {
-      cx<TV> vq[kUpdUnroll];
+      cx<TV> vq[E][kUpdUnroll];
 #pragma unroll
-      for (int q = 0; q < kUpdUnroll; ++q) vq[q] = vz[(size_t)min(j + q, k - 1) * ldj + i];
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int q = 0; q < kUpdUnroll; ++q) vq[e][q] = vz[(size_t)min(j + q, k - 1) * ldj + ii[e]];
 #pragma unroll
       for (int q = 0; q < kUpdUnroll; ++q) {
         const bool in = j + q < k;
         const int jq = min(j + q, k - 1);
         const cd sq = in ? sv[jq] : mk<double>(0, 0), pq = in ? pv[jq] : mk<double>(0, 0);
-        const cd vj = cvt<double>(vq[q]);
-        cfma(t1, sq, vj);
-        cfma(t2, pq, vj);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const cd vj = cvt<double>(vq[e][q]);
+          cfma(t1[e], sq, vj);
+          cfma(t2[e], pq, vj);
+        }
       }
     }
-    const cx<TV> vks = cvt<TV>(inu * (cvt<double>(ui) - t1));
-    u[i] = vks;
-    cd wn = wi - t2;
-    cfma(wn, -hkk, cvt<double>(vks));
-    const cx<TV> wns = cvt<TV>(wn);
-    un[i] = wns;
-    nrm += abs2(cvt<double>(wns));
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (i0 + (size_t)e * blockDim.x >= n) continue;
+      const cx<TV> vks = cvt<TV>(inu * (cvt<double>(ui[e]) - t1[e]));
+      cd wn = wi[e] - t2[e];
+      cfma(wn, -hkk, cvt<double>(vks));
+      const cx<TV> wns = cvt<TV>(wn);
+      store_nt(u + ii[e], vks);
+      store_nt(un + ii[e], wns);
+      nrm += abs2(cvt<double>(wns));
+    }
   }
   const cd r = block_sum(mk<double>(nrm, 0.0), sh);
   if (threadIdx.x == 0) partial[(size_t)z * gridDim.x + blockIdx.x] = r;
@@ -473,7 +502,8 @@ int batch_dot_blocks(size_t n, int nb) {
   return (int)(b > cap ? cap : (b == 0 ? 1 : b));
 }
 int batch_upd_blocks(size_t n, int nb) {
-  const size_t b = (n + 255) / 256, cap = (size_t)std::max(32, 16384 / std::max(nb, 1));
+  const size_t per = (size_t)256 * kUpdElems;
+  const size_t b = (n + per - 1) / per, cap = (size_t)std::max(32, 16384 / std::max(nb, 1));
   return (int)(b > cap ? cap : (b == 0 ? 1 : b));
 }
 void launch_bmultidot(const cd* V, size_t ldj, BIdx bv, int cnt, const cd* w, BIdx bw, size_t n, cd* partial,
