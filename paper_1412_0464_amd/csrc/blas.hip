@@ -200,6 +200,7 @@ __device__ __forceinline__ cd block_sum_arr(cd (&v)[NV], cd* sh) {
 // once per tile.
 constexpr int kDotTile = 8;
 constexpr int kUpdUnroll = 8;
+constexpr int kDotElems = 2;  // elements per thread and iteration of k_bmultidot2
 __global__ void __launch_bounds__(256) k_bmultidot(const cd* __restrict__ V, size_t ldj, BIdx bv, int cnt,
                                                    const cd* __restrict__ w, BIdx bw, size_t n,
                                                    cd* __restrict__ partial) {
@@ -283,21 +284,35 @@ __global__ void __launch_bounds__(256) k_bmultidot2(const cx<TV>* __restrict__ V
   cd acc[2 * kDotTile];
 #pragma unroll
   for (int q = 0; q < 2 * kDotTile; ++q) acc[q] = mk<double>(0, 0);
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  // all loads of an element are unconditional (rows q >= jn repeat the last
-  // vector of the tile and are never written out), so that they are issued
-  // together rather than one branch at a time
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
-    const cd ui = cvt<double>(u[i]), wi = w[i];
-    cx<TV> vq[kDotTile];
+  // kDotElems elements per thread and iteration (blockDim apart, the last
+  // clamped and weighted by zero); all loads of an iteration are
+  // unconditional (rows q >= jn repeat the last vector of the tile and are
+  // never written out), so that they are issued together rather than one
+  // branch at a time
+  constexpr int E = kDotElems;
+  const size_t stride = (size_t)gridDim.x * blockDim.x * E;
+  for (size_t i0 = blockIdx.x * (size_t)blockDim.x * E + threadIdx.x; i0 < n; i0 += stride) {
+    cd ui[E], wi[E];
+    cx<TV> vq[E][kDotTile];
 #pragma unroll
-    for (int q = 0; q < kDotTile; ++q) vq[q] = v[(size_t)(q < jn ? q : jn - 1) * ldj + i];
+    for (int e = 0; e < E; ++e) {
+      const size_t ie = i0 + (size_t)e * blockDim.x;
+      const bool ok = ie < n;
+      const size_t i = ok ? ie : n - 1;
+      const cd uv = cvt<double>(u[i]), wv = w[i];
+      ui[e] = mk<double>(ok ? uv.re : 0.0, ok ? uv.im : 0.0);
+      wi[e] = mk<double>(ok ? wv.re : 0.0, ok ? wv.im : 0.0);
 #pragma unroll
-    for (int q = 0; q < kDotTile; ++q) {
-      const cd vj = conj(cvt<double>(vq[q]));
-      cfma(acc[q], vj, ui);
-      cfma(acc[kDotTile + q], vj, wi);
+      for (int q = 0; q < kDotTile; ++q) vq[e][q] = v[(size_t)(q < jn ? q : jn - 1) * ldj + i];
     }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+      for (int q = 0; q < kDotTile; ++q) {
+        const cd vj = conj(cvt<double>(vq[e][q]));
+        cfma(acc[q], vj, ui[e]);
+        cfma(acc[kDotTile + q], vj, wi[e]);
+      }
   }
   const cd r = block_sum_arr<2 * kDotTile>(acc, sh);
   const int t = threadIdx.x;
@@ -499,6 +514,7 @@ void launch_normalize(const cd* w, const cd* nrm2, cd* v, size_t n, hipStream_t 
 // sums, so its blocks keep at least 16 elements per thread.
 int batch_dot_blocks(size_t n, int nb) {
   const size_t b = (n + 16 * 256 - 1) / (16 * 256), cap = (size_t)std::max(16, 8192 / std::max(nb, 1));
+  static_assert(kDotElems <= 16, "a projection block must hold at least one iteration per thread");
   return (int)(b > cap ? cap : (b == 0 ? 1 : b));
 }
 int batch_upd_blocks(size_t n, int nb) {
