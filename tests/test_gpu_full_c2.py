@@ -1,0 +1,124 @@
+"""Full-size checks of the benchmark workload against the oracle.
+
+The 2-D layered medium with 1023^2 interior nodes and 16 PML cells per side,
+8 points per wavelength, the two-grid sweeping preconditioner with J = 32
+coarse slabs, 64 point sources solved in one batch with a right-hand-side
+tile of 4: the launch configuration bench.py times.  The oracle cannot run
+the whole batch in seconds, so the checks use outputs it computes one by one
+and properties that hold at any size:
+
+* the fine operator on a random vector (one sparse product), 1e-12;
+* preconditioner columns of sampled right-hand sides, complex128 path
+  within 1e-10 and the complex64 path within 2e-5 (as at the small sizes;
+  measured 1.1e-6 here);
+* the batched mixed-precision FGMRES: the true residual of every source,
+  recomputed with the oracle's operator, meets the tolerance; sampled
+  sources take the oracle's FGMRES iteration count within +-1;
+* the single-source complex128 solve of a sampled source matches the
+  oracle's FGMRES solution within 1e-6.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import bench  # noqa: E402
+from oracle.problem import Problem2D  # noqa: E402
+from synth.media import random_rhs  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")]
+
+SAMPLED = (0, 37, 63)
+
+
+def _relerr(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cfg = bench.config("c2")
+    c = bench.medium(cfg)
+    fs = bench.sources(cfg, c.shape, 64)
+    print(f"[full size c2] {cfg['workload']}, {c.shape}, 64 sources: oracle setup", flush=True)
+    ref = Problem2D(c, cfg["omega"], cfg["h"], cfg["w"], J=cfg["J"], w_dd=4, two_grid=True)
+    return cfg, c, fs, ref
+
+
+def _helmholtz(cfg, c, precision):
+    from paper_1412_0464_amd import Helmholtz
+    return Helmholtz(torch.tensor(c, device=torch.device("cuda:0")), cfg["omega"], cfg["h"], cfg["w"], cfg["J"],
+                     two_grid=True, precision=precision, restart=40)
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.complex128, device=torch.device("cuda:0"))
+
+
+def test_c2_fine_operator(c2):
+    cfg, c, fs, ref = c2
+    hs = _helmholtz(cfg, c, "fp64")
+    try:
+        x = random_rhs(c.shape, 1412060)
+        y = hs.apply_operator(_t(x)).cpu().numpy().ravel()
+        assert _relerr(y, ref.matvec(x.ravel())) < 1e-12
+    finally:
+        hs.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
+def test_c2_batched_precond_sampled_columns(c2, precision, tol):
+    cfg, c, fs, ref = c2
+    hs = _helmholtz(cfg, c, precision)
+    try:
+        R = np.stack([random_rhs(c.shape, 1412100 + j) for j in range(64)])
+        print(f"[full size c2] batched preconditioner, {precision}, 64 columns, tile 4", flush=True)
+        Z = hs.apply_precond_batch(_t(R), tile=4).cpu().numpy()
+        for j in SAMPLED:
+            err = _relerr(Z[j], ref.precond(R[j].ravel()))
+            print(f"[full size c2] {precision} column {j}: rel err {err:.2e}", flush=True)
+            assert err < tol, f"column {j}: {err:.2e}"
+    finally:
+        hs.close()
+
+
+def test_c2_batched_mixed_solve(c2):
+    cfg, c, fs, ref = c2
+    hs = _helmholtz(cfg, c, "mixed")
+    try:
+        B = torch.stack([hs.rhs(_t(f)) for f in fs])
+        print("[full size c2] batched mixed solve, 64 sources, tile 4", flush=True)
+        U, its, rrs = hs.solve_batch(B, tol=1e-6, maxit=200, tile=4)
+        U = U.cpu().numpy()
+    finally:
+        hs.close()
+    # every source: the true residual, recomputed by the oracle's operator
+    for j, f in enumerate(fs):
+        b = ref.rhs(f)
+        rr = np.linalg.norm(b - ref.matvec(U[j].ravel())) / np.linalg.norm(b)
+        assert rr <= 1.001e-6 and abs(rr - rrs[j]) <= 1e-9, f"source {j}: {rr:.3e} (library {rrs[j]:.3e})"
+    # sampled sources: the oracle's FGMRES iteration count
+    for j in SAMPLED[:2]:
+        print(f"[full size c2] oracle FGMRES, source {j}", flush=True)
+        _, ito, _, _ = ref.solve(fs[j], tol=1e-6, maxit=200)
+        assert abs(its[j] - ito) <= 1, f"source {j}: {its[j]} vs {ito}"
+
+
+def test_c2_single_fp64_solve_matches_oracle(c2):
+    cfg, c, fs, ref = c2
+    j = SAMPLED[1]
+    hs = _helmholtz(cfg, c, "fp64")
+    try:
+        u, it, rr = hs.solve(hs.rhs(_t(fs[j])), tol=1e-6, maxit=200)
+        u = u.cpu().numpy()
+    finally:
+        hs.close()
+    print(f"[full size c2] oracle FGMRES, source {j}", flush=True)
+    uo, ito, _, _ = ref.solve(fs[j], tol=1e-6, maxit=200)
+    assert abs(it - ito) <= 1, f"{it} vs {ito}"
+    assert _relerr(u, uo) < 1e-6
