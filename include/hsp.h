@@ -85,7 +85,8 @@ typedef struct hsp_options {
   int chunk;        /* blocks per chunk of the parallel slab substitutions
                        (1..64); 0 selects about sqrt(n_t) for n_t tangential
                        nodes.  Changes the evaluation order only.             */
-  int krylov_fp32;  /* HSP_MIXED only, opt-in (default 0): the batched solvers
+  int krylov_fp32;  /* HSP_MIXED only (1 with HSP_FP64: HSP_EINVAL), opt-in
+                       (default 0): the batched solvers
                        store the Arnoldi basis in complex64 as well (products
                        and sums still in complex128; a right-hand side whose
                        true residual misses tol gets another restart cycle).

@@ -83,6 +83,8 @@ hsp_status validate(const hsp_grid* g, int J, const hsp_options* o) {
   if (!std::isfinite(o->omega_jac)) return fail(HSP_EINVAL, "bad omega_jac");
   if (o->chunk < 0 || o->chunk > kMaxChunk) return fail(HSP_EINVAL, "chunk must be in 0..64");
   if (o->krylov_fp32 != 0 && o->krylov_fp32 != 1) return fail(HSP_EINVAL, "krylov_fp32 must be 0 or 1");
+  if (o->krylov_fp32 && o->precision != HSP_MIXED)
+    return fail(HSP_EINVAL, "krylov_fp32 requires precision HSP_MIXED");
   return HSP_OK;
 }
 

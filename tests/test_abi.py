@@ -52,6 +52,7 @@ def test_workspace_size_valid_configs():
     (dict(h=-1.0), "h must"),
     (dict(nu=-1), "nu"),
     (dict(restart=0), "restart"),
+    (dict(krylov_fp32=True), "krylov_fp32"),            # complex64 basis without mixed precision
 ])
 def test_workspace_size_rejects_invalid(kw, msg):
     with pytest.raises(hsp.HspError) as e:
