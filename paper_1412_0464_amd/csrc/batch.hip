@@ -3,19 +3,27 @@
 // the factors of a slab are shared by every source).
 //
 // Work items are (task of the stage, chunk of the tangential axis, tile of
-// RB right-hand sides); every launch covers all of them, so one stage is
-// three launches whatever the number of right-hand sides.  Within a tile the
-// block substitutions act on nl x RB blocks:
+// RB right-hand sides); every launch covers all of them, so one stage is two
+// launches whatever the number of right-hand sides.  Within a tile the block
+// substitutions act on nl x RB blocks:
 //   forward   y_t = G_t (f_t - A_t y_{t-1})         (A_t: coupling to t-1),
 //   backward  x_t = y_t - E_t x_{t+1},
-// chunked exactly as in the single right-hand-side kernels (chunk-local chains
-// from zero, a chain over the chunk ends through the transfer matrices Y and
-// X, and a fix-up of every block).  The factor blocks of a chunk are read
+// chunked: each work item runs both chunk-local chains from zero, the forward
+// one on its right-hand side and the backward one on the forward result, so
+// that with c_{p-1} the true forward value at the end of the previous chunk
+// and d_{p+1} the true backward value at the start of the next one,
+//   x_t = x_t(local) + W_t c_{p-1} + X_t d_{p+1}
+// (W_t: the local backward chain applied to the forward transfer matrices
+// Y_t).  The last work item of a slot to arrive runs the chain over the chunk
+// ends (c through Y), corrects the chunk starts by W, and runs the chain over
+// the chunk starts (d through X); the second launch applies both terms to
+// every block and scatters.  The factor blocks of a chunk are read
 // once per tile; the tiles of one chunk are placed on the same XCD so that
 // they share its L2.
 //
 // Scratch per (task, tile) slot: y [n2][RB][nl] (right-hand side, then the
-// solution), chunk tips and heads [2][P][RB][nl], two arrival counters.
+// solution), chunk tips and heads [2][P][RB][nl], an arrival counter (of
+// two reserved).
 #include "internal.h"
 #include "sweep_dev.h"
 
@@ -226,6 +234,99 @@ __device__ __forceinline__ void bfixup(const GAS cx<T>* __restrict__ mat, GAS cx
   }
 }
 
+// rows_t += Mat1_t v1 + Mat2_t v2 for t in [s, e): both fix-ups of a block
+// in one pass, the rows of the two matrices fetched together (one memory
+// round trip per block of JB entries of both).
+template <class T, int RB>
+__device__ __forceinline__ void bfixup2(const GAS cx<T>* __restrict__ m1, const cx<T>* v1,
+                                        const GAS cx<T>* __restrict__ m2, const cx<T>* v2, GAS cx<T>* rows, int s,
+                                        int e, int nl) {
+  constexpr int JB = sizeof(T) == 4 ? 32 : 16;
+  const int cnt = e - s;
+  for (int idx = threadIdx.x; idx < cnt * nl; idx += blockDim.x) {
+    const int t = s + idx / nl, l = idx - (idx / nl) * nl;
+    const GAS cx<T>* mb1 = m1 + (size_t)t * nl * nl + l;
+    const GAS cx<T>* mb2 = m2 + (size_t)t * nl * nl + l;
+    GAS cx<T>* o = rows + (size_t)t * RB * nl + l;
+    cx<T> acc[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) acc[c] = o[(size_t)c * nl];
+    for (int j0 = 0; j0 < nl; j0 += JB) {
+      cx<T> mv1[JB], mv2[JB];
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        const int j = j0 + jj;
+        const int jc = j < nl ? j : nl - 1;
+        mv1[jj] = sel(j < nl, mb1[(size_t)jc * nl]);
+        mv2[jj] = sel(j < nl, mb2[(size_t)jc * nl]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        const int j = j0 + jj;
+        if (j < nl) {  // the same for every thread
+#pragma unroll
+          for (int c = 0; c < RB; ++c) {
+            cfma(acc[c], mv1[jj], v1[j * RB + c]);
+            cfma(acc[c], mv2[jj], v2[j * RB + c]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RB; ++c) o[(size_t)c * nl] = acc[c];
+  }
+}
+
+// Chunk starts corrected for the true forward values of the previous chunk:
+// heads_q += W_{s_q} tips_{q-1} for q = 1..P-1 (s_q = q m), by the whole
+// workgroup.  The tip vectors are staged in buf (cap complex values) for as
+// many chunks at a time as fit; one (chunk, row) pair per thread.
+template <class T, int RB>
+__device__ __forceinline__ void bheads_fix(const GAS cx<T>* __restrict__ W, GAS cx<T>* heads,
+                                           const GAS cx<T>* tips, int P, int m, int nl, cx<T>* buf, int cap) {
+  constexpr int JB = sizeof(T) == 4 ? 32 : 16;
+  const int per = RB * nl;
+  const int qg = cap / per > 0 ? cap / per : 1;
+  for (int q0 = 1; q0 < P; q0 += qg) {
+    const int q1 = min(P, q0 + qg);
+    for (int idx = threadIdx.x; idx < (q1 - q0) * per; idx += blockDim.x) {
+      const int qq = idx / per, rem = idx - qq * per;
+      const int c = rem / nl, j = rem - c * nl;
+      buf[qq * per + j * RB + c] = tips[((size_t)(q0 + qq - 1) * RB + c) * nl + j];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < (q1 - q0) * nl; idx += blockDim.x) {
+      const int qq = idx / nl, l = idx - qq * nl;
+      const GAS cx<T>* wr = W + (size_t)(q0 + qq) * m * nl * nl + l;
+      GAS cx<T>* o = heads + (size_t)(q0 + qq) * RB * nl + l;
+      const cx<T>* v = buf + qq * per;
+      cx<T> acc[RB];
+#pragma unroll
+      for (int c = 0; c < RB; ++c) acc[c] = o[(size_t)c * nl];
+      for (int j0 = 0; j0 < nl; j0 += JB) {
+        cx<T> mv[JB];
+#pragma unroll
+        for (int jj = 0; jj < JB; ++jj) {
+          const int j = j0 + jj;
+          const int jc = j < nl ? j : nl - 1;
+          mv[jj] = sel(j < nl, wr[(size_t)jc * nl]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < JB; ++jj) {
+          const int j = j0 + jj;
+          if (j < nl) {  // the same for every thread
+#pragma unroll
+            for (int c = 0; c < RB; ++c) cfma(acc[c], mv[jj], v[j * RB + c]);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < RB; ++c) o[(size_t)c * nl] = acc[c];
+    }
+    __syncthreads();
+  }
+}
+
 // Work item of block b: blocks are dealt to the 8 XCDs in turn, so block b
 // takes item (b mod 8) per + b / 8; the tiles of one (task, chunk) pair are
 // consecutive items and so share an XCD and its L2.  The segment is found by
@@ -372,62 +473,33 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
   __syncthreads();
   // chunk-local forward substitution y_t = G_t (f_t - A_t y_{t-1}) from zero
   bchain<T, NB, RB, D, true>(gp(F.G), (long)nl * nl, gp(F.A), y, s, 1, cnt, nl, T(1), q, ps);
+  GAS cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
     tips[((size_t)w.p * RB + c) * nl + l] = y[((size_t)(e - 1) * RB + c) * nl + l];
   }
-  if (P == 1) return;
-  if (!last_arrival(counters + 2 * slot, P)) return;
-  // true chunk-end values: tip_q = raw_q + Y_{e_q - 1} tip_{q-1}
-  bchain<T, NB, RB, D, false>(gp(F.Y) + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0, 1,
-                              P - 1, nl, T(1), q, ps);
-}
-
-template <class T, int NB, int RB, int D>
-__global__ void __launch_bounds__(256) k_bstage_mid(const BSeg* __restrict__ segs, int nseg, int nitems) {
-  __shared__ cx<T> q[NB * RB];
-  __shared__ cx<T> ps[256 * RB];
-  BWork w;
-  BSeg A;
-  if (!decode_work(segs, nseg, nitems, A, w)) return;
-  GAS cx<T>* __restrict__ scratch = gp(static_cast<cx<T>*>(A.scratch));
-  const cx<T>* __restrict__ factors = static_cast<const cx<T>*>(A.factors);
-  GAS cx<T>* __restrict__ red = gp(static_cast<cx<T>*>(A.red));
-  int* counters = A.counters;
-  const int P = A.P, m = A.m, n2 = A.G.n2;
-  const int slot = w.q * A.ntiles + w.tile;
-  const TaskDev tk = cload(A.tasks, w.q);
-  const SlabDev sd = cload(A.slabs, tk.slab);
-  const int nl = sd.nl;
-  const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
-  const SlabFac<T> F(factors + sd.fac_off, n2, nl);
-  GAS cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
-  GAS cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
-  GAS cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
-  if (w.p > 0) {
-    for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
-      const int c = idx / nl, l = idx - c * nl;
-      q[l * RB + c] = tips[((size_t)(w.p - 1) * RB + c) * nl + l];
-    }
-    __syncthreads();
-    bfixup<T, RB>(gp(F.Y), y, s, e, nl, q);
-    __syncthreads();
-  }
-  // chunk-local backward substitution x_t = y_t - E_t x_{t+1}
+  // chunk-local backward substitution x_t = y_t - E_t x_{t+1} on the local
+  // forward values (bchain starts with a barrier-separated read of its first
+  // input, so the tips above are read before y is overwritten)
   bchain<T, NB, RB, D, false>(gp(F.E), (long)nl * nl, nullptr, y, e - 1, -1, cnt, nl, T(-1), q, ps);
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
     heads[((size_t)w.p * RB + c) * nl + l] = y[((size_t)s * RB + c) * nl + l];
   }
   if (P == 1) return;
-  if (!last_arrival(counters + 2 * slot + 1, P)) return;
+  if (!last_arrival(counters + 2 * slot, P)) return;
+  // true chunk-end values: tip_q = raw_q + Y_{e_q - 1} tip_{q-1}
+  bchain<T, NB, RB, D, false>(gp(F.Y) + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0, 1,
+                              P - 1, nl, T(1), q, ps);
+  // chunk starts of the backward chains on the true forward values
+  bheads_fix<T, RB>(gp(F.W), heads, tips, P, m, nl, ps, 256 * RB);
   // true chunk-start values: head_q = raw_q + X_{s_q} head_{q+1}
   bchain<T, NB, RB, D, false>(gp(F.X), (long)m * nl * nl, nullptr, heads, P - 1, -1, P - 1, nl, T(1), q, ps);
 }
 
 template <class T, int NB, int RB>
 __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ segs, int nseg, int nitems) {
-  __shared__ cx<T> hv[NB * RB];
+  __shared__ cx<T> hv[NB * RB], cv[NB * RB];
   BWork w;
   BSeg A;
   if (!decode_work(segs, nseg, nitems, A, w)) return;
@@ -445,14 +517,23 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ seg
   const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
   const SlabFac<T> F(factors + sd.fac_off, n2, nl);
   GAS cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
-  const GAS cx<T>* heads = red + (size_t)slot * 2 * P * A.nl_max * RB + (size_t)P * A.nl_max * RB;
-  if (w.p < P - 1) {
+  const GAS cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
+  const GAS cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
+  // x_t += W_t c_{p-1} + X_t d_{p+1} (the true values at the neighbouring
+  // chunk ends; absent at the first and last chunk)
+  if (w.p > 0 || w.p < P - 1) {
     for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
       const int c = idx / nl, l = idx - c * nl;
-      hv[l * RB + c] = heads[((size_t)(w.p + 1) * RB + c) * nl + l];
+      if (w.p > 0) cv[l * RB + c] = tips[((size_t)(w.p - 1) * RB + c) * nl + l];
+      if (w.p < P - 1) hv[l * RB + c] = heads[((size_t)(w.p + 1) * RB + c) * nl + l];
     }
     __syncthreads();
-    bfixup<T, RB>(gp(F.X), y, s, e, nl, hv);
+    if (w.p > 0 && w.p < P - 1)
+      bfixup2<T, RB>(gp(F.W), cv, gp(F.X), hv, y, s, e, nl);
+    else if (w.p > 0)
+      bfixup<T, RB>(gp(F.W), y, s, e, nl, cv);
+    else
+      bfixup<T, RB>(gp(F.X), y, s, e, nl, hv);
     __syncthreads();
   }
   // u += J^T x over the task's layers, outgoing transmission layers; U
@@ -548,7 +629,6 @@ void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launc
 #define BLAUNCH(NB, RB, D)                                                                                \
   do {                                                                                                    \
     hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);      \
-    hipLaunchKernelGGL((k_bstage_mid<T, NB, RB, D>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);      \
     hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);         \
   } while (0)
   constexpr int D32 = sizeof(T) == 4 ? 2 : 2;

@@ -91,9 +91,12 @@ struct TaskDev {
 // Factor storage per slab (elements of cx<T>), column-major nl x nl blocks:
 // G_t, M_t = -G_t A_t, E_t, the chunk transfer matrices Y_t and X_t, each
 // [n2][nl][nl], then the couplings to the previous tangential node,
-// A_t[a][l] = coefficient of x_{t-1}[l+a-1] in row l, as [n2][3][nl].
+// A_t[a][l] = coefficient of x_{t-1}[l+a-1] in row l, as [n2][3][nl], then
+// W_t [n2][nl][nl]: the chunk-local backward substitution applied to Y
+// (the batched stages run the backward chains on the forward values before
+// the forward fix-up).
 inline size_t slab_factor_elems(int nl, int n2) {
-  return (size_t)5 * n2 * nl * nl + (size_t)3 * n2 * nl;
+  return (size_t)6 * n2 * nl * nl + (size_t)3 * n2 * nl;
 }
 
 // Factor block pointers of a slab.
@@ -105,6 +108,7 @@ struct SlabFac {
   const cx<T>* Y;
   const cx<T>* X;
   const cx<T>* A;
+  const cx<T>* W;
   __device__ SlabFac(const cx<T>* base, int n2, int nl) {
     const size_t sz = (size_t)n2 * nl * nl;
     G = base;
@@ -113,6 +117,7 @@ struct SlabFac {
     Y = base + 3 * sz;
     X = base + 4 * sz;
     A = base + 5 * sz;
+    W = A + (size_t)3 * n2 * nl;
   }
 };
 // Setup scratch per slab (complex double): G_t, E_t and the couplings A_t.

@@ -168,8 +168,10 @@ __device__ __forceinline__ void matmul_cm(const cd* A, const cd* B, cd* C, int n
 }
 
 // Per chunk (blockIdx.x) of a slab (blockIdx.y): M_t = -G_t A_t, the forward
-// transfer matrices Y_t = M_t Y_{t-1} (Y_s = M_s) and the backward transfer
-// matrices X_t = -E_t X_{t+1} (X_{e-1} = -E_{e-1}).  Products in double.
+// transfer matrices Y_t = M_t Y_{t-1} (Y_s = M_s), the backward transfer
+// matrices X_t = -E_t X_{t+1} (X_{e-1} = -E_{e-1}) and W_t = Y_t - E_t W_{t+1}
+// (W_{e-1} = Y_{e-1}), the chunk-local backward substitution of the columns
+// of Y.  Products in double (W from the stored Y).
 template <class T>
 __global__ void __launch_bounds__(256) k_chunk_transfer(const SlabDev* __restrict__ slabs, int n2, int m,
                                                         cx<T>* factors, const cd* setup, cd* tmp) {
@@ -184,6 +186,7 @@ __global__ void __launch_bounds__(256) k_chunk_transfer(const SlabDev* __restric
   cx<T>* Mm = factors + sd.fac_off + (size_t)n2 * nb;
   cx<T>* Ym = factors + sd.fac_off + 3 * (size_t)n2 * nb;
   cx<T>* Xm = factors + sd.fac_off + 4 * (size_t)n2 * nb;
+  cx<T>* Wm = factors + sd.fac_off + 5 * (size_t)n2 * nb + (size_t)3 * n2 * nl;
   cd* bufM = tmp + ((size_t)blockIdx.y * P + p) * 3 * kMaxSlabLayers * kMaxSlabLayers;
   cd* bufA = bufM + kMaxSlabLayers * kMaxSlabLayers;
   cd* bufB = bufA + kMaxSlabLayers * kMaxSlabLayers;
@@ -191,8 +194,10 @@ __global__ void __launch_bounds__(256) k_chunk_transfer(const SlabDev* __restric
   // their blocks are multiplied by zero in the chains over chunk ends and
   // must hold finite values.
   if (p == 0)
-    for (size_t idx = threadIdx.x; idx < (size_t)(e - s) * nb; idx += blockDim.x)
+    for (size_t idx = threadIdx.x; idx < (size_t)(e - s) * nb; idx += blockDim.x) {
       Ym[(size_t)s * nb + idx] = mk<T>(0, 0);
+      Wm[(size_t)s * nb + idx] = mk<T>(0, 0);
+    }
   if (p == P - 1)
     for (size_t idx = threadIdx.x; idx < (size_t)(e - s) * nb; idx += blockDim.x)
       Xm[(size_t)s * nb + idx] = mk<T>(0, 0);
@@ -236,6 +241,22 @@ __global__ void __launch_bounds__(256) k_chunk_transfer(const SlabDev* __restric
       for (int idx = threadIdx.x; idx < nl * nl; idx += blockDim.x) {
         Xm[(size_t)t * nb + idx] = cvt<T>(bufB[idx]);
         bufA[idx] = bufB[idx];
+      }
+      __syncthreads();
+    }
+  }
+  if (p > 0) {
+    for (int t = e - 1; t >= s; --t) {
+      if (t == e - 1) {
+        for (int idx = threadIdx.x; idx < nl * nl; idx += blockDim.x) bufB[idx] = mk<double>(0, 0);
+      } else {
+        matmul_cm(Ed + (size_t)t * nb, bufA, bufB, nl, -1.0);
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < nl * nl; idx += blockDim.x) {
+        const cd wv = bufB[idx] + cvt<double>(Ym[(size_t)t * nb + idx]);
+        Wm[(size_t)t * nb + idx] = cvt<T>(wv);
+        bufA[idx] = wv;
       }
       __syncthreads();
     }
