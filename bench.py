@@ -19,7 +19,12 @@ basis, orthogonalisation, residual, coarse-grid correction and solution; all
 sources in one batch); the plain FP64 form (complex128 throughout, one source
 at a time) is timed beside it at the same final residual, as are the
 single-source mixed form and the batched form with the Arnoldi basis stored
-in complex64 as well (the opt-in krylov_fp32 option).
+in complex64 as well (the opt-in krylov_fp32 option).  Each form runs with
+its own chunk length of the slab substitutions (an evaluation-order
+setting): 34 tangential blocks per chunk for the batched solves (fewer,
+longer chunks keep one workgroup per CU at 64 sources), the automatic
+choice (about the square root of the tangential nodes) for the
+single-source ones.
 """
 from __future__ import annotations
 
@@ -68,21 +73,22 @@ def sources_digest(kernel):
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, tile, nsrc):
+def recorded_traffic(kernel, tile, nsrc, chunk=0):
     """Measured HBM bytes per launch (per stage for "stage") from the counter
-    record, or None when there is none for this kernel, tile and batch size
-    or the kernel's sources changed since it was taken."""
+    record, or None when there is none for this kernel, tile, chunk length
+    and batch size or the kernel's sources changed since it was taken (tile
+    and chunk length matter for the stage only)."""
     import re
     try:
         with open(TRAFFIC_RECORD) as fh:
             txt = fh.read()
     except OSError:
         return None
-    for m in re.finditer(r"traffic-record: kernel=(\w+) bytes_per_launch=(\S+) tile=(\d+) sources=(\d+) "
-                         r"digest=(\w+)", txt):
-        if m.group(1) != kernel or int(m.group(4)) != nsrc or m.group(5) != sources_digest(kernel):
+    for m in re.finditer(r"traffic-record: kernel=(\w+) bytes_per_launch=(\S+) tile=(\d+) chunk=(\d+) "
+                         r"sources=(\d+) digest=(\w+)", txt):
+        if m.group(1) != kernel or int(m.group(5)) != nsrc or m.group(6) != sources_digest(kernel):
             continue
-        if kernel == "stage" and int(m.group(3)) != tile:
+        if kernel == "stage" and (int(m.group(3)) != tile or int(m.group(4)) != chunk):
             continue
         return float(m.group(2))
     return None
@@ -101,7 +107,7 @@ def copy_calibration():
     print(f"[bench] copy calibration: 3 x neg over {COPY_BYTES} bytes", file=sys.stderr, flush=True)
 
 
-def reduce_counters(fetch_csv, write_csv, tile, nsrc):
+def reduce_counters(fetch_csv, write_csv, tile, nsrc, chunk=0):
     """Per-kernel averages of the rocprofv3 counter files of a FETCH_SIZE run
     and a WRITE_SIZE run (KiB per dispatch), the copy scale factors, and the
     traffic records of the batched stage (per stage, for ``tile``) and of the
@@ -151,7 +157,8 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc):
     for kernel, t in (("stage", tile), ("project", 0), ("update", 0)):
         f, w = per[kernel]["FETCH_SIZE"], per[kernel]["WRITE_SIZE"]
         print(f"{kernel}: fetch {f:.4e} B + write {w:.4e} B per launch (scaled)")
-        print(f"traffic-record: kernel={kernel} bytes_per_launch={f + w:.5e} tile={t} sources={nsrc} "
+        ch = chunk if kernel == "stage" else 0
+        print(f"traffic-record: kernel={kernel} bytes_per_launch={f + w:.5e} tile={t} chunk={ch} sources={nsrc} "
               f"digest={sources_digest(kernel)}")
 
 
@@ -367,13 +374,16 @@ def main():
     ap.add_argument("--c3", action="store_true", help="also time the batched multi-frequency group workload")
     ap.add_argument("--c3-sources", type=int, default=64)
     ap.add_argument("--tile", type=int, default=0, help="right-hand-side tile (0: tuned)")
+    ap.add_argument("--chunk", type=int, default=34,
+                    help="tangential blocks per chunk of the slab substitutions in the batched solves "
+                         "(0: about sqrt of the tangential nodes, the single-source choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a streaming kernel of known size (for counter scaling)")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise rocprofv3 counter files of the batched stage and exit (no GPU)")
     args = ap.parse_args()
     if args.reduce_counters:
-        reduce_counters(*args.reduce_counters, tile=args.tile or 4, nsrc=args.sources)
+        reduce_counters(*args.reduce_counters, tile=args.tile or 4, nsrc=args.sources, chunk=args.chunk)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -389,7 +399,8 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
-    bat = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, profile=True, tile=args.tile)
+    bat = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, profile=True, tile=args.tile,
+                        chunk=args.chunk)
     its = bat["iters"]
     print(f"[bench] batched mixed: setup {bat['setup_s']:.3f} s, tile {bat['tile']}, solve {bat['solve_s'] * 1e3:.1f} ms "
           f"for {len(fs)} sources, iterations {min(its)}..{max(its)}, max relres {max(bat['relres']):.2e}",
@@ -404,7 +415,7 @@ def main():
                    "iterations_min": min(its), "iterations_max": max(its), "relres_max": max(bat["relres"]),
                    "setup_s": bat["setup_s"], "solve_s": bat["solve_s"],
                    "solve_s_per_source": bat["solve_s"] / len(fs), "precision": "mixed",
-                   "rhs_tile": bat["tile"]},
+                   "rhs_tile": bat["tile"], "chunk": args.chunk},
     }
     # rooflines from the event-timed classes of the profiled repeat:
     # algorithmic bytes per launch / average launch time.  The dominant kernel
@@ -427,7 +438,7 @@ def main():
                 "avg_launch_us": per_launch_s * 1e6, "alg_bytes_per_launch": per_launch_bytes}
 
     out["roofline"] = roofline("stage", "batched SubdomSolve stage (k_bstage_fwd + k_bstage_mid + k_bstage_bwd)",
-                               recorded_traffic("stage", bat["tile"], len(fs)))
+                               recorded_traffic("stage", bat["tile"], len(fs), args.chunk))
     out["roofline_project"] = roofline("project", "FGMRES projection pass k_bmultidot2<double> (complex128 basis)",
                                        recorded_traffic("project", bat["tile"], len(fs)))
     out["roofline_update"] = roofline("update", "FGMRES update pass k_bdcgs_update<double> (complex128 basis)",
@@ -438,7 +449,8 @@ def main():
     bat_tile = bat["tile"]
     del bat
     if not args.no_krylov_fp32:
-        bk = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, tile=bat_tile, krylov_fp32=True)
+        bk = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, tile=bat_tile, krylov_fp32=True,
+                           chunk=args.chunk)
         kits = bk["iters"]
         print(f"[bench] batched mixed, complex64 basis: solve {bk['solve_s'] * 1e3:.1f} ms, iterations "
               f"{min(kits)}..{max(kits)}, max relres {max(bk['relres']):.2e}", file=sys.stderr, flush=True)

@@ -41,7 +41,7 @@ def test_reduce_counters(tmp_path, capsys):
              (FWD8, 1e6), (PROJ, 1.0), (PROJ, 1.0), (UPD, 100.0), (UPD, 100.0)]
     _write(tmp_path / "f.csv", "FETCH_SIZE", fetch)
     _write(tmp_path / "w.csv", "WRITE_SIZE", write)
-    bench.reduce_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), tile=4, nsrc=64)
+    bench.reduce_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), tile=4, nsrc=64, chunk=34)
     out = capsys.readouterr().out
     rec = {}
     for line in out.splitlines():
@@ -51,7 +51,8 @@ def test_reduce_counters(tmp_path, capsys):
     # stage: fetch (700 KiB over 2 stages) x 2 + write (120 KiB over 2 stages) x 1
     stage = float(rec["stage"]["bytes_per_launch"])
     assert stage == pytest.approx((700 / 2 * 2 + 120 / 2) * 1024, rel=1e-5)
-    assert rec["stage"]["tile"] == "4" and rec["stage"]["sources"] == "64"
+    assert rec["stage"]["tile"] == "4" and rec["stage"]["sources"] == "64" and rec["stage"]["chunk"] == "34"
+    assert rec["project"]["chunk"] == "0"
     assert rec["stage"]["digest"] == bench.sources_digest("stage")
     proj = float(rec["project"]["bytes_per_launch"])
     assert proj == pytest.approx((4000 / 2 * 2 + 2 / 2) * 1024, rel=1e-5)
@@ -71,17 +72,19 @@ def test_recorded_traffic_validity(tmp_path, monkeypatch):
     rec = tmp_path / "traffic.md"
     ds, dp = bench.sources_digest("stage"), bench.sources_digest("project")
     rec.write_text("notes\n"
-                   f"traffic-record: kernel=stage bytes_per_launch=1.5e+08 tile=4 sources=64 digest={ds}\n"
-                   f"traffic-record: kernel=project bytes_per_launch=9.0e+09 tile=0 sources=64 digest={dp}\n")
+                   f"traffic-record: kernel=stage bytes_per_launch=1.5e+08 tile=4 chunk=34 sources=64 digest={ds}\n"
+                   f"traffic-record: kernel=project bytes_per_launch=9.0e+09 tile=0 chunk=0 sources=64 digest={dp}\n")
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(rec))
-    assert bench.recorded_traffic("stage", 4, 64) == 1.5e8
-    assert bench.recorded_traffic("stage", 8, 64) is None  # other tile
-    assert bench.recorded_traffic("stage", 4, 32) is None  # other batch size
-    assert bench.recorded_traffic("project", 8, 64) == 9.0e9  # the tile does not matter
-    rec.write_text(f"traffic-record: kernel=stage bytes_per_launch=1.5e+08 tile=4 sources=64 digest=0000{ds[4:]}\n")
-    assert bench.recorded_traffic("stage", 4, 64) is None  # kernel sources changed
+    assert bench.recorded_traffic("stage", 4, 64, 34) == 1.5e8
+    assert bench.recorded_traffic("stage", 8, 64, 34) is None  # other tile
+    assert bench.recorded_traffic("stage", 4, 64, 24) is None  # other chunk length
+    assert bench.recorded_traffic("stage", 4, 32, 34) is None  # other batch size
+    assert bench.recorded_traffic("project", 8, 64) == 9.0e9  # tile and chunk do not matter
+    rec.write_text(f"traffic-record: kernel=stage bytes_per_launch=1.5e+08 tile=4 chunk=34 sources=64 "
+                   f"digest=0000{ds[4:]}\n")
+    assert bench.recorded_traffic("stage", 4, 64, 34) is None  # kernel sources changed
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(tmp_path / "missing.md"))
-    assert bench.recorded_traffic("stage", 4, 64) is None
+    assert bench.recorded_traffic("stage", 4, 64, 34) is None
 
 
 def test_committed_records_parse():
