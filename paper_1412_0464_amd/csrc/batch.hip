@@ -60,15 +60,21 @@ __device__ __forceinline__ X cload(const X* p, int i) {
   return ((const CAS X*)p)[i];
 }
 
-// Thread layout of a 256-thread workgroup for slabs of up to NB layers.
-// Product phase: thread (l, g), l = tid % NB, owns row l and the CW columns
-// [g CW, (g+1) CW) of a block.  Reduction phase: thread (l, g) owns row l of
-// the right-hand sides g, g + NG, ... (RC of them).
-template <int NB, int RB>
+// Thread layout of a 256-thread workgroup for slabs of up to NC <= NB
+// layers, NB (32 or 64) the row lanes.  Product phase: thread (l, g),
+// l = tid % NB, owns row l and the CW columns [g CW, (g+1) CW) of a block, the
+// first NC columns split over the NG groups (NC < NB trims the work of slabs
+// that are thinner than NB).  Reduction phase: thread (l, g) owns row l of
+// the right-hand sides g, g + NG, ... (RC of them).  The product input q has
+// QN = max(NB, NG CW) rows, the rows from nl on kept zero.
+template <int NB, int RB, int NC = NB>
 struct BLay {
+  static_assert(NC <= NB && 64 % NB == 0, "row lanes must divide the wavefront");
   static constexpr int NT = 256;
   static constexpr int NG = NT / NB;
-  static constexpr int CW = NB / NG;
+  static constexpr int CW = (NC + NG - 1) / NG;
+  static constexpr int QR = NG * CW;
+  static constexpr int QN = QR > NB ? QR : NB;
   static constexpr int RC = (RB + NG - 1) / NG;
 };
 
@@ -91,12 +97,12 @@ __device__ __forceinline__ cx<T> shfl_down1(cx<T> v, int width) {
 // slices (and B, couplings) of the next D steps are held in a register ring;
 // loads are unconditional from clamped addresses.  LDS: q [NB][RB] holds the
 // product input, ps [NG][RB][NB] the partial products.
-template <class T, int NB, int RB, int D, bool GD>
+template <class T, int NB, int RB, int D, bool GD, int NC = NB>
 __device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long mstride,
                                        const GAS cx<T>* __restrict__ cpl, GAS cx<T>* rows, int first, int dir,
                                        int count, int nl, T sigma, cx<T>* q, cx<T>* ps) {
-  using LY = BLay<NB, RB>;
-  constexpr int NG = LY::NG, CW = LY::CW, RC = LY::RC;
+  using LY = BLay<NB, RB, NC>;
+  constexpr int NG = LY::NG, CW = LY::CW, RC = LY::RC, QR = LY::QR;
   if (count <= 0) return;
   const int tid = threadIdx.x;
   const int l = tid % NB, g = tid / NB;
@@ -133,13 +139,15 @@ __device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long m
   }
 #define BCH_STEP(k, d)                                                                           \
   {                                                                                              \
-    cx<T> part[RB];                                                                              \
-    _Pragma("unroll") for (int c = 0; c < RB; ++c) part[c] = mk<T>(0, 0);                        \
-    _Pragma("unroll") for (int cc = 0; cc < CW; ++cc) {                                          \
-      const cx<T>* qr = q + (g * CW + cc) * RB;                                                  \
-      _Pragma("unroll") for (int c = 0; c < RB; ++c) cfma(part[c], rm[d][cc], qr[c]);            \
+    {                                                                                            \
+      cx<T> part[RB];                                                                            \
+      _Pragma("unroll") for (int c = 0; c < RB; ++c) part[c] = mk<T>(0, 0);                      \
+      _Pragma("unroll") for (int cc = 0; cc < CW; ++cc) {                                        \
+        const cx<T>* qr = q + (g * CW + cc) * RB;                                                \
+        _Pragma("unroll") for (int c = 0; c < RB; ++c) cfma(part[c], rm[d][cc], qr[c]);          \
+      }                                                                                          \
+      _Pragma("unroll") for (int c = 0; c < RB; ++c) ps[(g * RB + c) * NB + l] = part[c];        \
     }                                                                                            \
-    _Pragma("unroll") for (int c = 0; c < RB; ++c) ps[(g * RB + c) * NB + l] = part[c];          \
     __syncthreads();                                                                             \
     const int rk = first + dir * (k);                                                            \
     _Pragma("unroll") for (int i = 0; i < RC; ++i) {                                             \
@@ -168,7 +176,11 @@ __device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long m
     }                                                                                            \
     __syncthreads();                                                                             \
   }
-  // first input: B_0 (GD) or zero
+  // first input: B_0 (GD) or zero; rows past NB of the product input (when
+  // NG CW > NB) stay zero for the whole chain
+  if constexpr (QR > NB) {
+    for (int idx = tid; idx < (QR - NB) * RB; idx += 256) q[NB * RB + idx] = mk<T>(0, 0);
+  }
 #pragma unroll
   for (int i = 0; i < RC; ++i) {
     const int c = g + NG * i;
@@ -376,9 +388,9 @@ struct IdxWalk {
   }
 };
 
-template <class T, int NB, int RB, int D>
+template <class T, int NB, int RB, int D, int NC>
 __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ segs, int nseg, int nitems) {
-  __shared__ cx<T> q[NB * RB];
+  __shared__ cx<T> q[BLay<NB, RB, NC>::QN * RB];
   __shared__ cx<T> ps[256 * RB];
   BWork w;
   BSeg A;
@@ -472,7 +484,7 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
   }
   __syncthreads();
   // chunk-local forward substitution y_t = G_t (f_t - A_t y_{t-1}) from zero
-  bchain<T, NB, RB, D, true>(gp(F.G), (long)nl * nl, gp(F.A), y, s, 1, cnt, nl, T(1), q, ps);
+  bchain<T, NB, RB, D, true, NC>(gp(F.G), (long)nl * nl, gp(F.A), y, s, 1, cnt, nl, T(1), q, ps);
   GAS cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
@@ -481,7 +493,7 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
   // chunk-local backward substitution x_t = y_t - E_t x_{t+1} on the local
   // forward values (bchain starts with a barrier-separated read of its first
   // input, so the tips above are read before y is overwritten)
-  bchain<T, NB, RB, D, false>(gp(F.E), (long)nl * nl, nullptr, y, e - 1, -1, cnt, nl, T(-1), q, ps);
+  bchain<T, NB, RB, D, false, NC>(gp(F.E), (long)nl * nl, nullptr, y, e - 1, -1, cnt, nl, T(-1), q, ps);
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
     heads[((size_t)w.p * RB + c) * nl + l] = y[((size_t)s * RB + c) * nl + l];
@@ -489,12 +501,13 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
   if (P == 1) return;
   if (!last_arrival(counters + 2 * slot, P)) return;
   // true chunk-end values: tip_q = raw_q + Y_{e_q - 1} tip_{q-1}
-  bchain<T, NB, RB, D, false>(gp(F.Y) + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0, 1,
-                              P - 1, nl, T(1), q, ps);
+  bchain<T, NB, RB, D, false, NC>(gp(F.Y) + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0,
+                                  1, P - 1, nl, T(1), q, ps);
   // chunk starts of the backward chains on the true forward values
   bheads_fix<T, RB>(gp(F.W), heads, tips, P, m, nl, ps, 256 * RB);
   // true chunk-start values: head_q = raw_q + X_{s_q} head_{q+1}
-  bchain<T, NB, RB, D, false>(gp(F.X), (long)m * nl * nl, nullptr, heads, P - 1, -1, P - 1, nl, T(1), q, ps);
+  bchain<T, NB, RB, D, false, NC>(gp(F.X), (long)m * nl * nl, nullptr, heads, P - 1, -1, P - 1, nl, T(1), q,
+                                  ps);
 }
 
 template <class T, int NB, int RB>
@@ -626,26 +639,30 @@ template <class T>
 void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launch, int rb, hipStream_t s) {
   if (nseg < 1 || nitems < 1) return;
   const dim3 grd(8 * ((nitems + 7) / 8));
-#define BLAUNCH(NB, RB, D)                                                                                \
+#define BLAUNCH(NB, RB, D, NC)                                                                            \
   do {                                                                                                    \
-    hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);      \
+    hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D, NC>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);  \
     hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);         \
   } while (0)
   constexpr int D32 = sizeof(T) == 4 ? 2 : 2;
   constexpr int D64 = sizeof(T) == 4 ? 2 : 1;
-#define BRB(NB, D)                      \
-  do {                                  \
-    switch (rb) {                       \
-      case 1: BLAUNCH(NB, 1, D); break; \
-      case 2: BLAUNCH(NB, 2, D); break; \
-      case 4: BLAUNCH(NB, 4, D); break; \
-      default: BLAUNCH(NB, 8, D); break; \
-    }                                   \
+#define BRB(NB, D, NC)                      \
+  do {                                      \
+    switch (rb) {                           \
+      case 1: BLAUNCH(NB, 1, D, NC); break; \
+      case 2: BLAUNCH(NB, 2, D, NC); break; \
+      case 4: BLAUNCH(NB, 4, D, NC); break; \
+      default: BLAUNCH(NB, 8, D, NC); break; \
+    }                                       \
   } while (0)
+  // thin slabs on 32 row lanes; thicker ones on 64, with the product columns
+  // trimmed to 40 where the slab allows it
   if (nl_launch <= 32)
-    BRB(32, D32);
+    BRB(32, D32, 32);
+  else if (nl_launch <= 40)
+    BRB(64, D64, 40);
   else
-    BRB(64, D64);
+    BRB(64, D64, 64);
 #undef BRB
 #undef BLAUNCH
 }
