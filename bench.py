@@ -48,11 +48,11 @@ KERNEL_SOURCES = {
     "project": ["blas.hip", "internal.h", "common.h"],
     "update": ["blas.hip", "internal.h", "common.h"],
 }
-# kernel names in the counter files: the batched stage (three launches per
+# kernel names in the counter files: the batched stage (two launches per
 # stage, for the tile in use) and the projection and update passes over the
 # complex128 Arnoldi basis
 KERNEL_PATTERNS = {
-    "stage": r"k_bstage_(fwd|mid|bwd)<float, (\d+), (\d+)",
+    "stage": r"k_bstage_(fwd|bwd)<float, (\d+), (\d+)",
     "project": r"k_bmultidot2<double>",
     "update": r"k_bdcgs_update<double>",
 }
@@ -419,7 +419,7 @@ def main():
     }
     # rooflines from the event-timed classes of the profiled repeat:
     # algorithmic bytes per launch / average launch time.  The dominant kernel
-    # class is the SubdomSolve stage (three dependent launches timed as one,
+    # class is the SubdomSolve stage (two dependent launches timed as one,
     # about 40 % of a solve); the two HBM-bound passes of the complex128
     # Gram-Schmidt follow: the update pass (k_bdcgs_update: k basis vectors,
     # u_k and w read, v_k and u_{k+1} written; the kernel with the largest
@@ -437,7 +437,7 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel, "launches": n,
                 "avg_launch_us": per_launch_s * 1e6, "alg_bytes_per_launch": per_launch_bytes}
 
-    out["roofline"] = roofline("stage", "batched SubdomSolve stage (k_bstage_fwd + k_bstage_mid + k_bstage_bwd)",
+    out["roofline"] = roofline("stage", "batched SubdomSolve stage (k_bstage_fwd + k_bstage_bwd)",
                                recorded_traffic("stage", bat["tile"], len(fs), args.chunk))
     out["roofline_project"] = roofline("project", "FGMRES projection pass k_bmultidot2<double> (complex128 basis)",
                                        recorded_traffic("project", bat["tile"], len(fs)))

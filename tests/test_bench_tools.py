@@ -15,10 +15,9 @@ HEADER = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id",
           "Accum_VGPR_Count", "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
 
 COPY = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel_cuda(at::TensorIteratorBase&)>"
-FWD = "void hsp::(anonymous namespace)::k_bstage_fwd<float, 32, 4, 2>(hsp::BSeg const*, int, int)"
-MID = "void hsp::(anonymous namespace)::k_bstage_mid<float, 32, 4, 2>(hsp::BSeg const*, int, int)"
+FWD = "void hsp::(anonymous namespace)::k_bstage_fwd<float, 32, 4, 2, 32>(hsp::BSeg const*, int, int)"
 BWD = "void hsp::(anonymous namespace)::k_bstage_bwd<float, 32, 4>(hsp::BSeg const*, int, int)"
-FWD8 = "void hsp::(anonymous namespace)::k_bstage_fwd<float, 32, 8, 2>(hsp::BSeg const*, int, int)"
+FWD8 = "void hsp::(anonymous namespace)::k_bstage_fwd<float, 32, 8, 2, 32>(hsp::BSeg const*, int, int)"
 PROJ = "void hsp::(anonymous namespace)::k_bmultidot2<double>(hsp::cx<double> const*, unsigned long, hsp::BIdx, int)"
 UPD = "void hsp::(anonymous namespace)::k_bdcgs_update<double>(hsp::cx<double>*, unsigned long, hsp::BIdx, int)"
 
@@ -35,9 +34,9 @@ def test_reduce_counters(tmp_path, capsys):
     # copy kernel: FETCH_SIZE sees half of the 256 MiB read, WRITE_SIZE all of
     # the 256 MiB written; two stages at tile 4 and one at tile 8 (ignored)
     kib = bench.COPY_BYTES / 1024
-    fetch = [(COPY, kib / 2), (FWD, 100.0), (MID, 50.0), (BWD, 25.0), (FWD, 300.0), (MID, 150.0), (BWD, 75.0),
+    fetch = [(COPY, kib / 2), (FWD, 150.0), (BWD, 25.0), (FWD, 450.0), (BWD, 75.0),
              (FWD8, 1e6), (PROJ, 1000.0), (PROJ, 3000.0), (UPD, 500.0), (UPD, 700.0)]
-    write = [(COPY, kib), (FWD, 10.0), (MID, 20.0), (BWD, 30.0), (FWD, 10.0), (MID, 20.0), (BWD, 30.0),
+    write = [(COPY, kib), (FWD, 30.0), (BWD, 30.0), (FWD, 30.0), (BWD, 30.0),
              (FWD8, 1e6), (PROJ, 1.0), (PROJ, 1.0), (UPD, 100.0), (UPD, 100.0)]
     _write(tmp_path / "f.csv", "FETCH_SIZE", fetch)
     _write(tmp_path / "w.csv", "WRITE_SIZE", write)
