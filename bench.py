@@ -259,7 +259,7 @@ def c3_run(steps, warmup, tol, nsrc=64, graph=False):
     16 PML cells), one frequency per grid (8-12 points per wavelength at
     1.5 km/s, higher frequencies on finer grids), nsrc point sources per
     grid; all 4 x nsrc right-hand sides solved to tol in one group (every
-    aligned sweep step is one launch triple over all grids)."""
+    aligned sweep step is one launch pair over all grids)."""
     import torch
     from paper_1412_0464_amd import Group, Helmholtz
     from synth.media import layered_medium_2d, extend_into_pml, resample_nodes

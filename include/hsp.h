@@ -274,7 +274,7 @@ hsp_status hsp_solve_batch(hsp_handle hd, int nrhs, const void* b_dev, void* u_d
  *      grid sizes; each set up with its own handle and workspace) solved
  *      together.  The sweep stages of all problems are aligned on the
  *      coarse residual of the sweep (Table 3) and each step of the aligned
- *      schedule is one set of three launches over the work items of every
+ *      schedule is one pair of launches over the work items of every
  *      problem.  All handles must share the precision; a handle may appear
  *      once.  Vectors: b_dev[p], u_dev[p] (or r_dev[p], z_dev[p]) hold
  *      nrhs[p] contiguous complex128 fine vectors of problem p (nrhs[p] = 0

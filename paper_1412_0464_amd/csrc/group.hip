@@ -8,7 +8,7 @@
 // workspace (per right-hand-side vectors, FGMRES bases, slab scratch).  The
 // stage lists of the members are aligned on the residual of the sweep (the
 // coarse residual between MidSolveIn and MidSolveOut, Table 3), and every
-// step of the aligned schedule is one launch triple over the work items of
+// step of the aligned schedule is one launch pair over the work items of
 // all members that have a slab stage at that step.  FGMRES runs one process
 // per right-hand side, all advanced in lock step with one host
 // synchronisation per iteration; converged right-hand sides leave the
@@ -249,7 +249,7 @@ X* mptr(const Member& mb, size_t o) {
 
 // One preconditioner application of every member with active right-hand
 // sides (the two-grid cycle of Sec. 4 or the plain sweep), all slab stages
-// of a step in one launch triple.  build_segments must have run for nact.
+// of a step in one launch pair.  build_segments must have run for nact.
 template <class T>
 void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector<PrecIO>& io, hipStream_t s) {
   const size_t nm = G.mem.size();
