@@ -491,8 +491,8 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
     tips[((size_t)w.p * RB + c) * nl + l] = y[((size_t)(e - 1) * RB + c) * nl + l];
   }
   // chunk-local backward substitution x_t = y_t - E_t x_{t+1} on the local
-  // forward values (bchain starts with a barrier-separated read of its first
-  // input, so the tips above are read before y is overwritten)
+  // forward values (bchain passes a barrier before its first write, so the
+  // tips above are read before y is overwritten)
   bchain<T, NB, RB, D, false, NC>(gp(F.E), (long)nl * nl, nullptr, y, e - 1, -1, cnt, nl, T(-1), q, ps);
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
