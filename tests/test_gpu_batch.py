@@ -28,6 +28,11 @@ CASES = {
     "fe9_1lvl_x": (47, 53, 5, 4, "fe9", False, "x", 10.0),
     "tg_ud": (79, 63, 8, 2, "fd5", True, "ud", 8.0),
     "tg_x_j5": (127, 95, 8, 5, "fd5", True, "x", 8.0),
+    # thicker slabs (38, 53 and 40 layers): the chain layouts on 64 row lanes
+    # with 40 and 64 product columns
+    "thick38_1lvl_x": (55, 41, 6, 2, "fd5", False, "x", 8.0),
+    "thick53_1lvl_x": (85, 41, 6, 2, "fd5", False, "x", 8.0),
+    "thick40_tg_x": (111, 47, 8, 2, "fd5", True, "x", 8.0),
 }
 
 
@@ -79,7 +84,9 @@ def _sources(shape, h, nsrc):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name,precision,tol", [
     ("fd5_1lvl_x", "fp64", 1e-10), ("fe9_1lvl_x", "fp64", 1e-10), ("tg_ud", "fp64", 1e-10),
-    ("tg_x_j5", "fp64", 1e-10), ("tg_x_j5", "mixed", 2e-5), ("fd5_1lvl_x", "mixed", 2e-5)])
+    ("tg_x_j5", "fp64", 1e-10), ("tg_x_j5", "mixed", 2e-5), ("fd5_1lvl_x", "mixed", 2e-5),
+    ("thick38_1lvl_x", "fp64", 1e-10), ("thick53_1lvl_x", "fp64", 1e-10), ("thick53_1lvl_x", "mixed", 2e-5),
+    ("thick40_tg_x", "fp64", 1e-10), ("thick40_tg_x", "mixed", 2e-5)])
 @pytest.mark.parametrize("tile", [1, 2, 4, 8])
 def test_batch_precond_columns(name, precision, tol, tile):
     c, ref, hs = _build(name, precision)
@@ -140,7 +147,7 @@ def test_batch_precond_single_column_equals_single_path():
     assert _relerr(zb, z1) < 2e-5
 
 
-@pytest.mark.parametrize("name", ["fd5_1lvl_x", "tg_x_j5", "tg_ud"])
+@pytest.mark.parametrize("name", ["fd5_1lvl_x", "tg_x_j5", "tg_ud", "thick53_1lvl_x", "thick40_tg_x"])
 def test_batch_solve_fp64(name):
     c, ref, hs = _build(name)
     fs = _sources(c.shape, 0.02, 6)
