@@ -35,6 +35,9 @@ CASES = {
     "tg_x": (63, 79, 8, 3, "fd5", True, "x", 8.0),
     "tg_ud": (79, 63, 8, 2, "fd5", True, "ud", 8.0),
     "tg_x_j5": (127, 95, 8, 5, "fd5", True, "x", 8.0),
+    # thicker slabs (53 and 40 layers): the chain kernels for thick slabs
+    "thick53_1lvl_x": (85, 41, 6, 2, "fd5", False, "x", 8.0),
+    "thick40_tg_x": (111, 47, 8, 2, "fd5", True, "x", 8.0),
 }
 
 
@@ -119,7 +122,8 @@ def test_transfers_and_smoother():
 
 @pytest.mark.parametrize("name,precision,tol", [
     ("fd5_1lvl_x", "fp64", 1e-10), ("fe9_1lvl_x", "fp64", 1e-10), ("tg_x_j5", "fp64", 1e-10),
-    ("tg_x_j5", "mixed", 2e-5)])
+    ("tg_x_j5", "mixed", 2e-5), ("thick53_1lvl_x", "fp64", 1e-10), ("thick53_1lvl_x", "mixed", 2e-5),
+    ("thick40_tg_x", "fp64", 1e-10)])
 def test_slab_solves(name, precision, tol):
     c, ref, hs = _build(name, precision)
     for j in range(hs.J):
