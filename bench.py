@@ -386,7 +386,7 @@ def main():
         reduce_counters(*args.reduce_counters, tile=args.tile or 4, nsrc=args.sources, chunk=args.chunk)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not a measured path", file=sys.stderr)
         sys.exit(2)
 
