@@ -3,9 +3,9 @@
 Element-wise comparisons on seeded inputs at sizes that span several
 threadblocks and ragged tails; full-size configuration-2 checks on sampled
 rows and on properties (true residual).  Tolerances: FP64 kernels 1e-12
-relative, FP64 composite maps 1e-10, complex64 maps 1e-5 (spec bar:
-solutions 1e-6 in FP64, 1e-4 in mixed precision after refinement, iteration
-counts within +-1).
+relative, FP64 composite maps 1e-10, complex64 maps 1e-5 (the acceptance
+bar for solves: 1e-6 in FP64, 1e-4 in mixed precision after refinement,
+iteration counts within +-1).
 """
 import numpy as np
 import pytest
