@@ -357,6 +357,13 @@ def cpu_baseline(cfg, c, f, iters, tol):
             "setup_s": t1 - t0, "s_per_iter": (t2 - t1) / max(it, 1)}
 
 
+def c3_report(args, graph):
+    r3 = c3_run(max(1, args.steps - 1), 1, args.tol, nsrc=args.c3_sources, graph=graph)
+    print(f"[bench] c3 group (graph={graph}): {r3['solve_s'] * 1e3:.1f} ms, {r3['value']:.3e} dof*iter/s",
+          file=sys.stderr, flush=True)
+    return r3
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,6 +380,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--c3", action="store_true", help="also time the batched multi-frequency group workload")
     ap.add_argument("--c3-sources", type=int, default=64)
+    ap.add_argument("--c3-only", action="store_true",
+                    help="time only the group workload (no config-2 runs, no CPU baseline)")
+    ap.add_argument("--c3-graph", choices=("both", "off", "on"), default="both",
+                    help="group solves eager (off), with the preconditioner captured in a graph (on), or both")
     ap.add_argument("--tile", type=int, default=0, help="right-hand-side tile (0: tuned)")
     ap.add_argument("--chunk", type=int, default=34,
                     help="tangential blocks per chunk of the slab substitutions in the batched solves "
@@ -389,6 +400,14 @@ def main():
         print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not a measured path", file=sys.stderr)
         sys.exit(2)
+
+    c3_graphs = {"both": (False, True), "off": (False,), "on": (True,)}[args.c3_graph]
+    if args.c3_only:
+        out = {}
+        for graph in c3_graphs:
+            out["c3_graph" if graph else "c3"] = c3_report(args, graph)
+        print(json.dumps(out))
+        return
 
     cfg = config(args.config)
     c = medium(cfg)
@@ -483,11 +502,8 @@ def main():
                                "kernel_ms_per_solve": {k: v[0] / args.steps for k, v in scl.items()}}
         del sm
     if args.c3:
-        for graph in (False, True):
-            r3 = c3_run(max(1, args.steps - 1), 1, args.tol, nsrc=args.c3_sources, graph=graph)
-            print(f"[bench] c3 group (graph={graph}): {r3['solve_s'] * 1e3:.1f} ms, {r3['value']:.3e} dof*iter/s",
-                  file=sys.stderr, flush=True)
-            out["c3_graph" if graph else "c3"] = r3
+        for graph in c3_graphs:
+            out["c3_graph" if graph else "c3"] = c3_report(args, graph)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, c, fs[0], args.cpu_iters, args.tol)
