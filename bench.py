@@ -47,6 +47,7 @@ KERNEL_SOURCES = {
     "stage": ["batch.hip", "sweep_dev.h", "internal.h", "common.h"],
     "project": ["blas.hip", "internal.h", "common.h"],
     "update": ["blas.hip", "internal.h", "common.h"],
+    "matvec": ["stencil.hip", "internal.h", "common.h"],
 }
 # kernel names in the counter files: the batched stage (two launches per
 # stage, for the tile in use) and the projection and update passes over the
@@ -55,6 +56,7 @@ KERNEL_PATTERNS = {
     "stage": r"k_bstage_(fwd|bwd)<float, (\d+), (\d+)",
     "project": r"k_bmultidot2<double>",
     "update": r"k_bdcgs_update<double>",
+    "matvec": r"k_stencil_multi<5, double, float, double, double>",
 }
 CLASSES = ("stage", "smooth", "coarse", "transfer", "krylov", "project", "update")
 COPY_BYTES = 256 << 20
@@ -110,8 +112,9 @@ def copy_calibration():
 def reduce_counters(fetch_csv, write_csv, tile, nsrc, chunk=0):
     """Per-kernel averages of the rocprofv3 counter files of a FETCH_SIZE run
     and a WRITE_SIZE run (KiB per dispatch), the copy scale factors, and the
-    traffic records of the batched stage (per stage, for ``tile``) and of the
-    projection and update passes (per launch)."""
+    traffic records of the batched stage (per stage, for ``tile``), of the
+    projection and update passes and of the batched FGMRES matvec (per
+    launch)."""
     import csv
     import re
     from collections import defaultdict
@@ -125,7 +128,7 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc, chunk=0):
                 disp[name].add(row["Dispatch_Id"])
         return {k: (len(disp[k]), tot[k]) for k in tot}
 
-    per = {"stage": {}, "project": {}, "update": {}}
+    per = {"stage": {}, "project": {}, "update": {}, "matvec": {}}
     for label, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         d = load_csv(path)
         print(f"{label} (KiB per dispatch)")
@@ -138,7 +141,8 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc, chunk=0):
         scale = (COPY_BYTES / 1024) / copy_kib
         print(f"  copy: {copy_kib:.1f} KiB per dispatch for {COPY_BYTES // 1024} KiB -> scale {scale:.4f}")
         stage_kib, stages = 0.0, 0
-        pass_kib, passes = {"project": 0.0, "update": 0.0}, {"project": 0, "update": 0}
+        pass_kib = {"project": 0.0, "update": 0.0, "matvec": 0.0}
+        passes = {"project": 0, "update": 0, "matvec": 0}
         for k, (n, v) in d.items():
             m = re.search(KERNEL_PATTERNS["stage"], k)
             if m and int(m.group(3)) == tile:
@@ -154,7 +158,7 @@ def reduce_counters(fetch_csv, write_csv, tile, nsrc, chunk=0):
         for kern in pass_kib:
             print(f"  {kern}: {passes[kern]} launches, {pass_kib[kern] / max(passes[kern], 1):.1f} KiB per launch raw")
             per[kern][label] = pass_kib[kern] / max(passes[kern], 1) * 1024 * scale
-    for kernel, t in (("stage", tile), ("project", 0), ("update", 0)):
+    for kernel, t in (("stage", tile), ("project", 0), ("update", 0), ("matvec", 0)):
         f, w = per[kernel]["FETCH_SIZE"], per[kernel]["WRITE_SIZE"]
         print(f"{kernel}: fetch {f:.4e} B + write {w:.4e} B per launch (scaled)")
         ch = chunk if kernel == "stage" else 0
@@ -444,7 +448,9 @@ def main():
     # u_k and w read, v_k and u_{k+1} written; the kernel with the largest
     # total time) as roofline_update and the projection pass (k_bmultidot2:
     # every basis vector and w once per Arnoldi step; its event pair also
-    # covers two small reductions) as roofline_project.
+    # covers two small reductions) as roofline_project.  roofline_matvec is the
+    # batched 5-point FGMRES matvec (k_stencil_multi: z read and w written per
+    # source, k^2 read once).
     cls = bat["classes"]
 
     def roofline(name, kernel, traffic):
@@ -462,6 +468,8 @@ def main():
                                        recorded_traffic("project", bat["tile"], len(fs)))
     out["roofline_update"] = roofline("update", "FGMRES update pass k_bdcgs_update<double> (complex128 basis)",
                                       recorded_traffic("update", bat["tile"], len(fs)))
+    out["roofline_matvec"] = roofline("krylov", "FGMRES matvec k_stencil_multi<5> (batched 5-point operator)",
+                                      recorded_traffic("matvec", bat["tile"], len(fs)))
     out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
     out["config"]["profiled_solve_s"] = bat["profiled_solve_s"]
     Ub = None if args.no_fp64 else bat["U"][0].cpu().numpy()

@@ -792,7 +792,9 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           bVb.ld = (size_t)(m + 1) * nf;
           bVb.map = act_d;
           // algorithmic bytes (basis vectors in the basis precision): matvec
-          // z, k^2 read, w written; projection k+1 basis vectors (u_k in slot
+          // z read and w written per source, k^2 read once (the batched
+          // stencil forms each node's coefficients once for a group of
+          // sources); projection k+1 basis vectors (u_k in slot
           // k) and w read; update k basis vectors, u_k and w read, v_k and
           // u_{k+1} written
           const double vb = G.v32 ? sizeof(cf) : sizeof(cd), zb = G.mixed ? sizeof(cf) : sizeof(cd);
@@ -804,7 +806,7 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
           else
             launch_stencil<double, double, double, double>(mb.C->fine, 0, mptr<cd>(mb, B.o_Z) + (size_t)k * nf,
                                                            (const cd*)nullptr, w, 0.0, s, nact[p], bZk, BIdx{}, bw);
-          prof_end(mb.C, HSP_PROF_KRYLOV, s, na * nf * (zb + sizeof(cd) + sizeof(double)));
+          prof_end(mb.C, HSP_PROF_KRYLOV, s, na * nf * (zb + sizeof(cd)) + (double)nf * sizeof(double));
           // blocks per right-hand side for the active count; the partial
           // buffer holds 2 (m+1) B.nblk entries for each of R right-hand
           // sides, and both passes use at most B.nblk R / nact per active one

@@ -141,12 +141,31 @@ __global__ void __launch_bounds__(256) k_stencil9(LevelDev L, int mode, const cx
 // Same arithmetic, in the same order, as the one-right-hand-side kernels
 // above.
 constexpr int kStencilZ = 16;
+// Workgroups are dealt to the eight XCDs in turn by their linear index, and
+// each XCD has an L2 of its own.  Rows i - 1, i, i + 1 of one group of right-
+// hand sides are gridDim.x linear indices apart, so in launch order they sit
+// on different XCDs and every row of x comes from HBM three times.  The
+// workgroups are renumbered so that XCD q takes one contiguous range of
+// (column block, row, group) tiles: a permutation of the grid, whatever the
+// dispatch order.
+__device__ __forceinline__ void xcd_tile(int& tx, int& ty, int& tz) {
+  constexpr unsigned kXcd = 8;
+  const unsigned gx = gridDim.x, gy = gridDim.y, T = gx * gy * gridDim.z;
+  const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned per = T / kXcd, rem = T % kXcd, q = lin % kXcd, slot = lin / kXcd;
+  const unsigned t = (q < rem ? q * (per + 1) : rem * (per + 1) + (q - rem) * per) + slot;
+  tx = (int)(t % gx);
+  ty = (int)((t / gx) % gy);
+  tz = (int)(t / (gx * gy));
+}
 template <int KIND, class Ta, class Tx, class Tb, class Ty>
 __global__ void __launch_bounds__(256) k_stencil_multi(LevelDev L, int mode, const cx<Tx>* __restrict__ x,
                                                        const cx<Tb>* __restrict__ b, cx<Ty>* __restrict__ y,
                                                        double w, BIdx bx, BIdx bb, BIdx by, int nb) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;  // y node 1..n2
-  const int i = blockIdx.y + 1;                             // x node 1..n1
+  int tx, ty, tz;
+  xcd_tile(tx, ty, tz);
+  const int k = tx * blockDim.x + threadIdx.x + 1;  // y node 1..n2
+  const int i = ty + 1;                             // x node 1..n1
   const int n1 = L.n1, n2 = L.n2;
   if (k > n2) return;
   const bool has_x = x != nullptr;
@@ -184,7 +203,7 @@ __global__ void __launch_bounds__(256) k_stencil_multi(LevelDev L, int mode, con
       nid[di + 1][dk + 1] = (size_t)(ii - 1) * n2 + (kk - 1);
       cc[di + 1][dk + 1] = cvt<Ta>(KIND == 5 ? c[di + 1][dk + 1] : keep(ok, c[di + 1][dk + 1]));
     }
-  const int z0 = blockIdx.z * kStencilZ, z1 = min(nb, z0 + kStencilZ);
+  const int z0 = tz * kStencilZ, z1 = min(nb, z0 + kStencilZ);
 #pragma unroll 2
   for (int z = z0; z < z1; ++z) {
     const cx<Tx>* xz = has_x ? x + bx.off(z) : x;

@@ -20,6 +20,10 @@ BWD = "void hsp::(anonymous namespace)::k_bstage_bwd<float, 32, 4>(hsp::BSeg con
 FWD8 = "void hsp::(anonymous namespace)::k_bstage_fwd<float, 32, 8, 2, 32>(hsp::BSeg const*, int, int)"
 PROJ = "void hsp::(anonymous namespace)::k_bmultidot2<double>(hsp::cx<double> const*, unsigned long, hsp::BIdx, int)"
 UPD = "void hsp::(anonymous namespace)::k_bdcgs_update<double>(hsp::cx<double>*, unsigned long, hsp::BIdx, int)"
+MV = ("void hsp::(anonymous namespace)::k_stencil_multi<5, double, float, double, double>"
+      "(hsp::LevelDev, int, hsp::cx<float> const*, hsp::cx<double> const*, hsp::cx<double>*)")
+RES = ("void hsp::(anonymous namespace)::k_stencil_multi<5, double, double, double, double>"
+       "(hsp::LevelDev, int, hsp::cx<double> const*, hsp::cx<double> const*, hsp::cx<double>*)")
 
 
 def _write(path, counter, rows):
@@ -35,9 +39,11 @@ def test_reduce_counters(tmp_path, capsys):
     # the 256 MiB written; two stages at tile 4 and one at tile 8 (ignored)
     kib = bench.COPY_BYTES / 1024
     fetch = [(COPY, kib / 2), (FWD, 150.0), (BWD, 25.0), (FWD, 450.0), (BWD, 75.0),
-             (FWD8, 1e6), (PROJ, 1000.0), (PROJ, 3000.0), (UPD, 500.0), (UPD, 700.0)]
+             (FWD8, 1e6), (PROJ, 1000.0), (PROJ, 3000.0), (UPD, 500.0), (UPD, 700.0),
+             (MV, 80.0), (MV, 120.0), (RES, 1e6)]
     write = [(COPY, kib), (FWD, 30.0), (BWD, 30.0), (FWD, 30.0), (BWD, 30.0),
-             (FWD8, 1e6), (PROJ, 1.0), (PROJ, 1.0), (UPD, 100.0), (UPD, 100.0)]
+             (FWD8, 1e6), (PROJ, 1.0), (PROJ, 1.0), (UPD, 100.0), (UPD, 100.0),
+             (MV, 50.0), (MV, 70.0), (RES, 1e6)]
     _write(tmp_path / "f.csv", "FETCH_SIZE", fetch)
     _write(tmp_path / "w.csv", "WRITE_SIZE", write)
     bench.reduce_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), tile=4, nsrc=64, chunk=34)
@@ -58,6 +64,10 @@ def test_reduce_counters(tmp_path, capsys):
     assert rec["project"]["digest"] == bench.sources_digest("project")
     upd = float(rec["update"]["bytes_per_launch"])
     assert upd == pytest.approx((1200 / 2 * 2 + 200 / 2) * 1024, rel=1e-5)
+    # the batched matvec only (not the true-residual launches of the same kernel)
+    mv = float(rec["matvec"]["bytes_per_launch"])
+    assert mv == pytest.approx((200 / 2 * 2 + 120 / 2) * 1024, rel=1e-5)
+    assert rec["matvec"]["digest"] == bench.sources_digest("matvec")
 
 
 def test_reduce_counters_needs_copy(tmp_path):
