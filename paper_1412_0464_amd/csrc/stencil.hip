@@ -143,11 +143,11 @@ __global__ void __launch_bounds__(256) k_stencil9(LevelDev L, int mode, const cx
 constexpr int kStencilZ = 16;
 // Workgroups are dealt to the eight XCDs in turn by their linear index, and
 // each XCD has an L2 of its own.  Rows i - 1, i, i + 1 of one group of right-
-// hand sides are gridDim.x linear indices apart, so in launch order they sit
-// on different XCDs and every row of x comes from HBM three times.  The
+// hand sides are several workgroups apart, so in launch order they sit on
+// different XCDs and every row of x comes from HBM three times.  The
 // workgroups are renumbered so that XCD q takes one contiguous range of
-// (column block, row, group) tiles: a permutation of the grid, whatever the
-// dispatch order.
+// (node block, group) tiles: a permutation of the grid, whatever the dispatch
+// order.
 __device__ __forceinline__ void xcd_tile(int& tx, int& ty, int& tz) {
   constexpr unsigned kXcd = 8;
   const unsigned gx = gridDim.x, gy = gridDim.y, T = gx * gy * gridDim.z;
@@ -162,14 +162,16 @@ template <int KIND, class Ta, class Tx, class Tb, class Ty>
 __global__ void __launch_bounds__(256) k_stencil_multi(LevelDev L, int mode, const cx<Tx>* __restrict__ x,
                                                        const cx<Tb>* __restrict__ b, cx<Ty>* __restrict__ y,
                                                        double w, BIdx bx, BIdx bb, BIdx by, int nb) {
+  // the nodes are numbered row by row and taken 256 at a time, so that no
+  // lanes idle at the end of each row
   int tx, ty, tz;
   xcd_tile(tx, ty, tz);
-  const int k = tx * blockDim.x + threadIdx.x + 1;  // y node 1..n2
-  const int i = ty + 1;                             // x node 1..n1
   const int n1 = L.n1, n2 = L.n2;
-  if (k > n2) return;
+  const size_t id = (size_t)tx * blockDim.x + threadIdx.x;
+  if (id >= (size_t)n1 * n2) return;
+  const int i = (int)(id / (unsigned)n2) + 1;        // x node 1..n1
+  const int k = (int)(id - (size_t)(i - 1) * n2) + 1;  // y node 1..n2
   const bool has_x = x != nullptr;
-  const size_t id = (size_t)(i - 1) * n2 + (k - 1);
   // coefficients (masked toward the boundary) and clamped neighbour indices
   cd c[3][3];
   if constexpr (KIND == 5) {
@@ -245,7 +247,8 @@ void launch_stencil(const LevelDev& L, int mode, const cx<Tx>* x, const cx<Tb>* 
   if (nb < 1) return;
   dim3 blk(256);
   if (nb > 1) {
-    const dim3 g2((L.n2 + 255) / 256, L.n1, (nb + kStencilZ - 1) / kStencilZ);
+    const size_t nodes = (size_t)L.n1 * L.n2;
+    const dim3 g2((unsigned)((nodes + 255) / 256), 1, (nb + kStencilZ - 1) / kStencilZ);
     if (L.kind == 5)
       hipLaunchKernelGGL((k_stencil_multi<5, Ta, Tx, Tb, Ty>), g2, blk, 0, s, L, mode, x, b, y, w, bx, bb, by, nb);
     else

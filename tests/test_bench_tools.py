@@ -100,7 +100,7 @@ def test_committed_records_parse():
     """The committed counter summary holds a record for each roofline kernel."""
     with open(bench.TRAFFIC_RECORD) as fh:
         txt = fh.read()
-    for kernel in ("stage", "project", "update"):
+    for kernel in ("stage", "project", "update", "matvec"):
         assert f"traffic-record: kernel={kernel} " in txt
 
 
