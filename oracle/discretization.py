@@ -282,3 +282,149 @@ def pad_nodes_edge(v_unknowns):
     """Extend unknown-node values (N1-1, N2-1) to all nodes (N1+1, N2+1) by
     copying the nearest unknown node (used for the medium only)."""
     return np.pad(v_unknowns, 1, mode="edge")
+
+
+# --------------------------------------------------------------------------
+# Three dimensions
+# --------------------------------------------------------------------------
+# Flat index of unknown (i, j, k) (x, y, z, 1-based): ((i-1) n2 + (j-1)) n3 + (k-1).
+# x is the sweep axis (slowest), z the fastest.
+
+# The 7-point scheme written in the 3-D family of App. A: all mass on the
+# centre (c1 = 1, c2 = c3 = 0) and no transverse mass spreading in the
+# stiffness (c4 = 1, c5 = 0).
+SEVEN_POINT_COEFS_3D = (1.0, 0.0, 0.0, 1.0, 0.0)
+
+
+def fd7_matrix(ax, ay, az, k2_nodes, omega):
+    """h^3 times the 3-D analogue of eq. define_pml_fd (standard second order
+    finite differences with PML, the paper's fine level in 3-D, Sec. 4):
+
+      sum over axes l of  (1/h^2) [-a_l(i-1/2) u(i-1) + (a_l(i-1/2) + a_l(i+1/2)) u(i)
+                                    - a_l(i+1/2) u(i+1)] / (product of the other two a at the node)
+      - k^2 u / (a_1 a_2 a_3)
+
+    with the 1-D second-order operator of Sec. 4 along each axis.
+    ``k2_nodes`` has shape (N1-1, N2-1, N3-1).  Requires a uniform spacing h."""
+    h = ax.widths()[0]
+    for a in (ax, ay, az):
+        assert np.allclose(a.widths(), h), "7-point FD needs a uniform mesh"
+    an = [a.alpha_nodes(omega) for a in (ax, ay, az)]
+    ah = [a.alpha_cells(omega) for a in (ax, ay, az)]
+    n = [ax.n_unknowns, ay.n_unknowns, az.n_unknowns]
+    I, Jg, K = np.meshgrid(*[np.arange(1, m + 1) for m in n], indexing="ij")
+    idx = ((I - 1) * n[1] + (Jg - 1)) * n[2] + (K - 1)
+    pos = (I, Jg, K)
+    # transverse node factors: 1 / (product of the alphas of the other axes)
+    tr = [1.0 / (an[1][Jg] * an[2][K]), 1.0 / (an[0][I] * an[2][K]), 1.0 / (an[0][I] * an[1][Jg])]
+    diag = -h * h * h * k2_nodes / (an[0][I] * an[1][Jg] * an[2][K])
+    rows, cols, vals = [], [], []
+    for l in range(3):
+        p = pos[l]
+        lo = -h * ah[l][p - 1] * tr[l]      # coefficient of u(p-1) (h^3 / h^2 = h)
+        hi = -h * ah[l][p] * tr[l]          # coefficient of u(p+1)
+        diag = diag - lo - hi
+        for d, v in ((-1, lo), (1, hi)):
+            q = [I, Jg, K]
+            q[l] = q[l] + d
+            m = (q[l] >= 1) & (q[l] <= n[l])
+            rows.append(idx[m])
+            cols.append((((q[0] - 1) * n[1] + (q[1] - 1)) * n[2] + (q[2] - 1))[m])
+            vals.append(v[m])
+    rows.append(idx.ravel())
+    cols.append(idx.ravel())
+    vals.append(diag.ravel())
+    N = n[0] * n[1] * n[2]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(N, N))
+
+
+def fd7_rhs_scale(ax, ay, az, omega):
+    """h^3 / (a1 a2 a3) at the unknown nodes: turns the physical source into
+    the right-hand side of the FE-scaled 3-D system."""
+    h = ax.widths()[0]
+    a = [v.alpha_nodes(omega)[1:-1] for v in (ax, ay, az)]
+    return h ** 3 / (a[0][:, None, None] * a[1][None, :, None] * a[2][None, None, :])
+
+
+def fe_constants_3d(c1, c2, c3, c4, c5):
+    """eq. def_IJ_opt: I_0 = c1/8, I_1 = c2/24, I_2 = c3/24,
+    I_3 = (1 - c1 - c2 - c3)/8; J_0 = c4/4, J_1 = c5/8, J_2 = (1 - c4 - c5)/4."""
+    return ((c1 / 8.0, c2 / 24.0, c3 / 24.0, (1.0 - c1 - c2 - c3) / 8.0),
+            (c4 / 4.0, c5 / 8.0, (1.0 - c4 - c5) / 4.0))
+
+
+def fe27_element_values(h1, h2, h3, a1, a2, a3, k2, c1, c2, c3, c4, c5):
+    """Cell contributions of eq. define_H_FE (H = -M_FE - sum_l D^(l) (x) N).
+
+    For two corners a, b of one cell with |a - b| = (d1, d2, d3), d in {0,1}:
+      e = s1 sgn(d1) J_{d2+d3} + s2 sgn(d2) J_{d1+d3} + s3 sgn(d3) J_{d1+d2} - m I_{d1+d2+d3}
+    with s1 = (a1/h1)(h2 h3/(a2 a3)) (the cell's share of D^(1) times its
+    share of N^(2,3)), s2, s3 alike, m = h1 h2 h3 k^2 / (a1 a2 a3) (the cell's
+    share of M_FE), sgn(0) = +1, sgn(1) = -1.  Returns a dict keyed by
+    (d1, d2, d3)."""
+    (I0, I1, I2, I3), (J0, J1, J2) = fe_constants_3d(c1, c2, c3, c4, c5)
+    Iv = (I0, I1, I2, I3)
+    Jv = (J0, J1, J2)
+    s = ((a1 / h1) * (h2 * h3 / (a2 * a3)),
+         (a2 / h2) * (h1 * h3 / (a1 * a3)),
+         (a3 / h3) * (h1 * h2 / (a1 * a2)))
+    m = h1 * h2 * h3 * k2 / (a1 * a2 * a3)
+    out = {}
+    for d1 in (0, 1):
+        for d2 in (0, 1):
+            for d3 in (0, 1):
+                d = (d1, d2, d3)
+                e = -m * Iv[d1 + d2 + d3]
+                for l in range(3):
+                    sg = -1.0 if d[l] else 1.0
+                    e = e + s[l] * sg * Jv[sum(d) - d[l]]
+                out[d] = e
+    return out
+
+
+def fe27_matrix(ax, ay, az, k2_cells, coefs, omega):
+    """Assemble the 3-D finite-element operator H_FE of eq. define_H_FE on the
+    rectilinear mesh ax x ay x az as a sum of cell element matrices.
+    ``k2_cells`` (N1, N2, N3) and ``coefs`` = (c1, ..., c5), each (N1, N2, N3),
+    are cellwise constant, and the alphas are taken at cell midpoints
+    (App. A, coarse level)."""
+    h = [a.widths() for a in (ax, ay, az)]
+    al = [a.alpha_cells(omega) for a in (ax, ay, az)]
+    Nc = [ax.n_cells, ay.n_cells, az.n_cells]
+    n = [m - 1 for m in Nc]
+    P, Q, R = np.meshgrid(*[np.arange(m) for m in Nc], indexing="ij")
+    e = fe27_element_values(h[0][P], h[1][Q], h[2][R], al[0][P], al[1][Q], al[2][R], k2_cells, *coefs)
+    corners = [(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+    rows, cols, vals = [], [], []
+
+    def flat(i, j, k):
+        return ((i - 1) * n[1] + (j - 1)) * n[2] + (k - 1)
+
+    def inside(i, j, k):
+        return (i >= 1) & (i <= n[0]) & (j >= 1) & (j <= n[1]) & (k >= 1) & (k <= n[2])
+
+    for ca in corners:
+        ia, ja, ka = P + ca[0], Q + ca[1], R + ca[2]
+        ma = inside(ia, ja, ka)
+        for cb in corners:
+            ib, jb, kb = P + cb[0], Q + cb[1], R + cb[2]
+            m = ma & inside(ib, jb, kb)
+            v = e[(abs(ca[0] - cb[0]), abs(ca[1] - cb[1]), abs(ca[2] - cb[2]))]
+            rows.append(flat(ia, ja, ka)[m])
+            cols.append(flat(ib, jb, kb)[m])
+            vals.append(np.broadcast_to(v, m.shape)[m])
+    N = n[0] * n[1] * n[2]
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+    A.sum_duplicates()
+    return A
+
+
+def cell_coefs_3d(k2_cells, h_nom, mode="opt"):
+    """Cellwise (c1, ..., c5): Table (b) at 1/G = h_nom k / (2 pi) per cell, or
+    the 7-point set (``mode='fd7'``)."""
+    if mode == "fd7":
+        one = np.ones_like(k2_cells)
+        return tuple(v * one for v in SEVEN_POINT_COEFS_3D)
+    inv_g = h_nom * np.sqrt(k2_cells) / (2.0 * np.pi)
+    return opt_coefs_3d(inv_g)
