@@ -61,6 +61,9 @@ KERNEL_PATTERNS = {
 CLASSES = ("stage", "smooth", "coarse", "transfer", "krylov", "project", "update")
 COPY_BYTES = 256 << 20
 
+# tangential blocks per chunk of the slab substitutions in the batched solves
+BATCH_CHUNK = 34
+
 METRIC = "dof·iter/s and solve time to 1e-6 rel. residual: FP32-batched vs plain FP64"
 UNIT = "dof·iter/s"
 HBM_PEAK_GBS = 8000.0
@@ -389,7 +392,7 @@ def main():
     ap.add_argument("--c3-graph", choices=("both", "off", "on"), default="both",
                     help="group solves eager (off), with the preconditioner captured in a graph (on), or both")
     ap.add_argument("--tile", type=int, default=0, help="right-hand-side tile (0: tuned)")
-    ap.add_argument("--chunk", type=int, default=34,
+    ap.add_argument("--chunk", type=int, default=BATCH_CHUNK,
                     help="tangential blocks per chunk of the slab substitutions in the batched solves "
                          "(0: about sqrt of the tangential nodes, the single-source choice)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -60,7 +60,7 @@ typedef struct hsp_grid {
   double c_pml;     /* PML reference speed c_pml; <= 0 selects mean(c)        */
 } hsp_grid;
 
-/* Method parameters (Sec. 4 and 5). */
+/* Method parameters (Sec. 4, Sec. 6.1). */
 typedef struct hsp_options {
   int fine_stencil; /* 5: the 5-point PML finite differences of eq.
                        define_pml_fd (the paper's fine level); 9: the
@@ -95,7 +95,7 @@ typedef struct hsp_options {
 } hsp_options;
 
 /* Fills *opt with: fine_stencil 5, two_grid 0, w_dd 4, S_dd 0 (= 5 w_dd),
- * nu 3, omega_jac 0.8 (Sec. 5, Table 2), sweep X, precision FP64, restart 40,
+ * nu 3, omega_jac 0.8 (Sec. 6.1, 2-D experiments), sweep X, precision FP64, restart 40,
  * chunk 0 (automatic), krylov_fp32 0. */
 hsp_status hsp_default_options(hsp_options* opt);
 
@@ -124,7 +124,8 @@ hsp_status hsp_workspace_size(const hsp_grid* grid, int J, const hsp_options* op
  * Errors: HSP_EINVAL (bad geometry, options, non-positive or non-finite c or
  * omega, cores thinner than 3 layers, DD-PML leaving the domain, odd interior
  * cell count with two_grid), HSP_ENOMEM (workspace too small),
- * HSP_ESINGULAR (a zero or non-finite pivot), HSP_EDEVICE.  Synchronises
+ * HSP_ESINGULAR (a zero or non-finite pivot, or Schur-complement growth
+ * beyond the limit of hsp_debug_set), HSP_EDEVICE.  Synchronises
  * the stream (it reads the medium statistics and the pivot status). */
 hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, int J,
                      const hsp_options* opt, void* ws_dev, size_t ws_bytes, void* stream,
@@ -146,7 +147,8 @@ hsp_status hsp_apply_operator(hsp_handle hd, const void* x_dev, void* y_dev, voi
 hsp_status hsp_apply_precond(hsp_handle hd, const void* r_dev, void* z_dev, void* stream);
 
 /* Solve A u = b for the FE-scaled right-hand side b (see hsp_rhs) with
- * right-preconditioned FGMRES (x0 = 0, restart from options), stopping when
+ * right-preconditioned FGMRES (x0 = 0, restart from options; the paper uses
+ * the two-grid cycle as a preconditioner for GMRES, Sec. 4), stopping when
  * ||b - A u||_2 <= tol ||b||_2 (Arnoldi estimate, then checked on the true
  * residual).  conj_transpose = 1 solves A^H u = b instead (A is complex
  * symmetric, so this is conj(A^{-1} conj(b))).  iters and relres (may be
@@ -173,8 +175,28 @@ typedef struct hsp_info {
   int max_slab_layers;
   int precision;
   int two_grid;
+  double pivot_growth;  /* largest growth factor max_t |S_t| / max_t |B_t|
+                           of the slab Schur complements (Sec. 5: block LU
+                           with pivoting inside each block only)           */
+  int dim;              /* 2 or 3                                          */
+  int n_fine_z;         /* 3-D: fine unknowns along z (0 in 2-D)            */
+  int n_coarse_z;       /* 3-D with two-grid: coarse unknowns along z       */
 } hsp_info;
 hsp_status hsp_get_info(hsp_handle hd, hsp_info* info);
+
+/* Debugging knobs (process-wide; they affect later hsp_setup calls), for
+ * testing the failure paths of the setup:
+ *   HSP_DEBUG_SINGULAR_SLAB  value = slab index j (0-based): the first block
+ *                            of slab j is replaced by zero, so hsp_setup
+ *                            returns HSP_ESINGULAR; -1 switches it off.
+ *   HSP_DEBUG_GROWTH_LIMIT   value > 0 replaces the growth limit of the slab
+ *                            factorization (default 0.01 / eps of the factor
+ *                            precision: hsp_setup returns HSP_ESINGULAR when
+ *                            the Schur complements grow beyond it); <= 0
+ *                            restores the default.
+ * Errors: HSP_EINVAL for an unknown knob. */
+enum { HSP_DEBUG_SINGULAR_SLAB = 0, HSP_DEBUG_GROWTH_LIMIT = 1 };
+hsp_status hsp_debug_set(int knob, double value);
 
 /* Partition (host arrays supplied by the caller): beta[0..J] (Sec. 2.2) and
  * the first / last global layer x0[j], x1[j] of slab j = 0..J-1. */
@@ -219,7 +241,7 @@ hsp_status hsp_gradient_accumulate(hsp_handle hd, const void* u_dev, const void*
 
 /* ---- Batched right-hand sides.  Many sources (or adjoint sources) of one
  *      medium and frequency share the setup: the slab factors serve every
- *      right-hand side, which is the multi-RHS pipelining of Sec. 4.  A
+ *      right-hand side, which is the multi-RHS pipelining of Sec. 5.  A
  *      batch is nrhs contiguous complex128 fine vectors, right-hand side j
  *      at offset j * (N1-1)(N2-1).  These calls need a second caller-owned
  *      device workspace, 256-byte aligned, which holds the per-right-hand-

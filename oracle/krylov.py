@@ -2,7 +2,7 @@
 
 The paper uses GMRES with the (linear) two-grid sweeping preconditioner
 (Sec. 1 and Sec. 4) and stops when the residual is reduced by 1e-6
-(Sec. 5).  Here: x0 = 0, modified Gram-Schmidt Arnoldi, Givens rotations,
+(Sec. 5, implementation).  Here: x0 = 0, modified Gram-Schmidt Arnoldi, Givens rotations,
 stop when the Arnoldi residual estimate <= tol * ||b||, restart after
 ``restart`` inner steps.  FGMRES stores z_j = M v_j and forms x = Z y; GMRES
 forms x = M (V y).  For a fixed linear M both give the same iterates.

@@ -14,6 +14,8 @@ is d - d_obs).
 
 Selecting receiver values and placing the adjoint sources are index
 operations on device tensors; all arithmetic runs in the library's kernels.
+Receiver indices must be distinct: placing the adjoint sources is a plain
+assignment, which would keep only one of two entries for a repeated node.
 """
 from __future__ import annotations
 
@@ -27,6 +29,9 @@ class HelmholtzMisfit(torch.autograd.Function):
     def forward(ctx, m, sources, receivers, omega, h, pml, J, c_pml, tol, opts):
         if not (c_pml and c_pml > 0):
             raise ValueError("an explicit c_pml > 0 is required (with mean(c) the PML would depend on m)")
+        receivers = torch.as_tensor(receivers)
+        if receivers.dim() != 1 or torch.unique(receivers).numel() != receivers.numel():
+            raise ValueError("receivers must be a 1-D set of distinct node indices")
         opts = dict(opts or {})
         opts.setdefault("fine_stencil", 5)
         c = torch.rsqrt(m.detach()).contiguous()

@@ -1,5 +1,5 @@
 // Batched SubdomSolve stages: the slab solves of one sweep stage applied to
-// many right-hand sides at once (the multi-RHS pipelining of Sec. 4, where
+// many right-hand sides at once (the multi-RHS pipelining of Sec. 5, where
 // the factors of a slab are shared by every source).
 //
 // Work items are (task of the stage, chunk of the tangential axis, tile of

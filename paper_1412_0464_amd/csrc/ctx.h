@@ -15,6 +15,17 @@ namespace hsp {
 // Records msg as the calling thread's last error and returns st.
 hsp_status fail(hsp_status st, const std::string& msg);
 
+// Debugging knobs of hsp_debug_set (process-wide).
+struct DebugKnobs {
+  int singular_slab = -1;     // slab whose first block is replaced by zero at setup
+  double growth_limit = 0.0;  // > 0: replaces the default growth limit
+};
+DebugKnobs& debug_knobs();
+// Growth limit for slab factors stored with tsize bytes per complex value:
+// the factorization is refused when fewer than two significant digits of the
+// factor precision would survive a growth of the Schur complements.
+double growth_limit(size_t tsize);
+
 #define HIPCHK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
@@ -25,6 +36,35 @@ hsp_status fail(hsp_status st, const std::string& msg);
 using cplx = std::complex<double>;
 
 inline cd to_cd(cplx z) { return mk<double>(z.real(), z.imag()); }
+
+// PML damping sigma(x): C (lo - x)^2 left of lo, C (x - hi)^2 right of hi.
+struct Sigma {
+  double lo = 0, hi = 0, C = 0;
+  bool left = false, right = false;
+  double operator()(double x) const {
+    double s = 0;
+    if (left && x < lo) s = C * (lo - x) * (lo - x);
+    if (right && x > hi) s = C * (x - hi) * (x - hi);
+    return s;
+  }
+};
+
+inline cplx alpha_of(double sigma, double omega) { return 1.0 / cplx(1.0, sigma / omega); }
+
+// One axis of a level: node coordinates and the outer PML.
+struct AxisH {
+  std::vector<double> x;  // nodes 0..N
+  Sigma sig;
+  double h_nom = 0;
+  int n() const { return (int)x.size() - 2; }  // unknowns
+};
+
+// Partition beta_0..beta_J of n1 layers: outer-PML layers join the first and
+// last cores, interior layers split evenly.
+std::vector<int> partition(int n1, int w_outer, int J);
+// PML-aware coarsening of an axis with N cells and w PML cells per side: the
+// fine node of every coarse node (ifp) and which coarse cells are refined.
+void coarse_map(int N, int w, std::vector<int>& ifp, std::vector<char>& ref);
 
 inline hipStream_t S_(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -57,7 +97,7 @@ struct Plan {
   size_t o_cxA, o_cxB, o_cyA, o_cyB, o_ck2c, o_ccoef;
   size_t o_avgx0, o_avgwx, o_avgy0, o_avgwy;
   size_t o_rx, o_rwx, o_ry, o_rwy, o_px, o_pwx, o_py, o_pwy;
-  size_t o_slabs, o_slabA, o_slabB, o_xmap, o_fac, o_facscr, o_status, o_tasks, o_tcoef;
+  size_t o_slabs, o_slabA, o_slabB, o_xmap, o_fac, o_facscr, o_status, o_growth, o_tasks, o_tcoef;
   size_t o_swf, o_swg, o_swu, o_swB, o_swscr;
   size_t o_tgx0, o_tgx1, o_tgres, o_tgrc, o_tgec, o_cvin, o_cvout;
   size_t o_V, o_Z, o_w, o_part, o_hbuf, o_stats, o_bconj;
@@ -87,8 +127,14 @@ struct Prof {
 
 }  // namespace hsp
 
+namespace hsp {
+struct D3Ctx;  // the three-dimensional path (hsp3d.hip)
+void destroy_d3(D3Ctx* d);
+}  // namespace hsp
+
 struct hsp_ctx {
   hsp::Plan P;
+  hsp::D3Ctx* d3 = nullptr;  // set for dim = 3
   hsp_grid grid;
   hsp_options opt;
   int J = 0;
@@ -104,9 +150,11 @@ struct hsp_ctx {
   void* factors = nullptr;
   const hsp::cd* tcoef = nullptr;  // transmission coefficients per task (batched stages)
   hsp::Prof prof;
+  double growth = 0;   // largest growth factor of the slab factorization
   int tuned_rb = 0;    // right-hand-side tile chosen by hsp_tune_batch (0: none)
   int tuned_nact = 0;  // batch size it was chosen for
   ~hsp_ctx() {
+    if (d3) hsp::destroy_d3(d3);
     for (int c = 0; c < HSP_PROF_NCLASS; ++c)
       for (auto& e : prof.ev[c]) {
         (void)hipEventDestroy(e.first);
@@ -129,5 +177,25 @@ namespace hsp {
 // (no-ops unless timing is enabled on the handle).
 void prof_begin(hsp_ctx* C, int cls, hipStream_t s);
 void prof_end(hsp_ctx* C, int cls, hipStream_t s, double bytes);
+
+// Task list and stages of the sweep of Table 3 (X or UD) from the partition
+// in C->P (beta, bt, x0, x1) and C->J, C->opt.sweep.
+void build_schedule(hsp_ctx* C);
+
+// ---- the three-dimensional path (hsp3d.hip) --------------------------------
+hsp_status d3_workspace_size(const hsp_grid* g, int J, const hsp_options* o, size_t* bytes);
+hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* g, int J, const hsp_options* o, void* ws,
+                    size_t ws_bytes, hipStream_t s, hsp_ctx** out);
+void d3_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s);
+// fine operator: y = A x (mode 0) or y = b - A x (mode 1), complex128
+void d3_fine_apply(hsp_ctx* C, int mode, const cd* x, const cd* b, cd* y, hipStream_t s);
+hsp_status d3_rhs(hsp_ctx* C, const cd* f, cd* b, hipStream_t s);
+hsp_status d3_apply_level_operator(hsp_ctx* C, int level, const cd* x, cd* y, hipStream_t s);
+hsp_status d3_restrict(hsp_ctx* C, const cd* rf, cd* rc, hipStream_t s);
+hsp_status d3_prolong_add(hsp_ctx* C, const cd* ec, cd* xf, hipStream_t s);
+hsp_status d3_smooth(hsp_ctx* C, const cd* r, cd* x, int steps, hipStream_t s);
+hsp_status d3_sweep(hsp_ctx* C, const cd* f, cd* u, hipStream_t s);
+hsp_status d3_slab_solve(hsp_ctx* C, int j, const cd* b, cd* x, hipStream_t s);
+void d3_info(const hsp_ctx* C, hsp_info* info);
 
 }  // namespace hsp

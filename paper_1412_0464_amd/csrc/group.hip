@@ -1,5 +1,5 @@
 // Many right-hand sides of one or several problems (media / frequencies)
-// solved together: the multi-RHS pipelining of Sec. 4, where the slab
+// solved together: the multi-RHS pipelining of Sec. 5, where the slab
 // factors of a problem serve all of its sources, extended to several
 // problems whose sweep stages share launches.
 //
@@ -144,6 +144,7 @@ hsp_status group_plan(int nprob, const hsp_handle* hds, const int* nrhs, int res
   int rmax = 0;
   for (int p = 0; p < nprob; ++p) {
     if (!hds[p]) return fail(HSP_EINVAL, "null handle in group");
+    if (hds[p]->d3) return fail(HSP_EINVAL, "batched and grouped solves are implemented for 2-D problems");
     if (nrhs[p] < 0) return fail(HSP_EINVAL, "nrhs must be >= 0");
     const bool mixed = hds[p]->opt.precision == HSP_MIXED;
     const bool v32 = mixed && hds[p]->opt.krylov_fp32 != 0;
@@ -516,9 +517,17 @@ hsp_status check_ws(const Group& G, void* ws, size_t bytes) {
   return HSP_OK;
 }
 
-hsp_status zero_counters(const Group& G, hipStream_t s) {
-  for (const Member& mb : G.mem)
-    if (mb.R > 0) HIPCHK(hipMemsetAsync(mptr<int>(mb, mb.B.o_ctr), 0, 2 * batch_slots(mb.R) * sizeof(int), s));
+// The arrival counters of the stage launches start at zero.  by_kernel: clear
+// them with a fill kernel instead of hipMemsetAsync.
+hsp_status zero_counters(const Group& G, hipStream_t s, bool by_kernel = false) {
+  for (const Member& mb : G.mem) {
+    if (mb.R <= 0) continue;
+    const size_t n = 2 * batch_slots(mb.R);  // even: cleared as n/2 complex64 zeros
+    if (by_kernel)
+      launch_zero<float>(mptr<cf>(mb, mb.B.o_ctr), n / 2, s);
+    else
+      HIPCHK(hipMemsetAsync(mptr<int>(mb, mb.B.o_ctr), 0, n * sizeof(int), s));
+  }
   return HSP_OK;
 }
 
@@ -934,7 +943,7 @@ hsp_status group_solve(Group& G, const void* const* b_in, void* const* u_out, do
 // r32, z32: the right-hand sides / the results are complex64 (the Krylov
 // vectors of the mixed-precision solver), else complex128.
 hsp_status group_precond(Group& G, const void* const* r, void* const* z, int tile, int flags, hipStream_t s,
-                         int r32 = 0, int z32 = 0) {
+                         int r32 = 0, int z32 = 0, bool zero_by_kernel = false) {
   const size_t nm = G.mem.size();
   std::vector<int> nact(nm);
   std::vector<PrecIO> io(nm);
@@ -951,7 +960,7 @@ hsp_status group_precond(Group& G, const void* const* r, void* const* z, int til
     io[p].br.ld = nf;
     io[p].bz.ld = nf;
   }
-  hsp_status st = zero_counters(G, s);
+  hsp_status st = zero_counters(G, s, zero_by_kernel);
   if (st != HSP_OK) return st;
   st = build_segments(G, nact, tile ? tile : default_tile(G, nact), s);
   if (st != HSP_OK) return st;

@@ -1,0 +1,785 @@
+// Host side of the three-dimensional path: workspace planning, setup (PML
+// profiles, PML-aware coarse mesh, coarse optimized 27-point FE medium,
+// slab partition along x, slab operators with DD-PML and k continuation,
+// dense-block factorization of every slab), the sweep of Table 3, the
+// two-grid cycle of Sec. 4 and the component entry points.  The FGMRES of
+// hsp_solve is shared with the 2-D path.
+//
+// Precision: slab factors, sweeps and smoothing in complex64 (the blocks are
+// factored on the FP32 matrix cores), the fine residual, restriction input,
+// FGMRES and solution in complex128 (HSP_MIXED; HSP_FP64 is refused in 3-D).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+#include "d3.h"
+
+namespace hsp {
+
+struct D3Ctx {
+  int m[3] = {0, 0, 0}, N[3] = {0, 0, 0};  // fine unknowns / cells per axis
+  int two_grid = 0, fine_kind = 7;
+  int mc[3] = {0, 0, 0};                   // coarse unknowns
+  int dm[3] = {0, 0, 0};                   // DD-level unknowns
+  std::vector<int> ifp[3];
+  std::vector<char> ref[3];
+  d3::Level3 fine{}, coarse{}, dd{};
+  d3::Transfer3 tr{};
+  std::vector<d3::Slab3> slabs_host;
+  d3::Slab3* slabs_dev = nullptr;
+  std::vector<int> nls;
+  int n_max = 0, nl_max = 0;
+  cf* factors = nullptr;
+  std::vector<double> stage_bytes;  // algorithmic bytes per stage
+  // workspace offsets
+  size_t o_fA[3], o_fB[3], o_ib[3], o_k2n, o_fk2c, o_fcoef;
+  size_t o_cA[3], o_cB[3], o_ck2c, o_ccoef;
+  size_t o_avx[3], o_avw[3];
+  size_t o_r[3], o_rw[3], o_p[3], o_pw[3];
+  size_t o_slabA, o_slabB, o_xmap, o_slabs, o_fac, o_setup, o_status, o_growth, o_tasks;
+  size_t o_swf, o_swg, o_swu, o_bufs, o_fs, o_ys;
+  size_t o_tgx0, o_tgx1, o_tgres, o_tgrc, o_tgec, o_cvin, o_cvout;
+  size_t n_slabA = 0, n_xmap = 0, n_fac = 0, n_tasks = 0;
+  size_t nf() const { return (size_t)m[0] * m[1] * m[2]; }
+  size_t nd() const { return (size_t)dm[0] * dm[1] * dm[2]; }
+};
+
+void destroy_d3(D3Ctx* d) { delete d; }
+
+namespace {
+
+constexpr int kMaxBlock3 = 1536;  // unknowns per y-plane of a slab (panel rows: 1024 in registers, 512 in LDS)
+
+inline size_t blk_elems(int n) { return (size_t)2 * n * n + (size_t)n * (n + (n & 1)); }
+
+hsp_status validate3(const hsp_grid* g, int J, const hsp_options* o) {
+  if (!g || !o) return fail(HSP_EINVAL, "null grid or options");
+  for (int a = 0; a < 3; ++a) {
+    if (g->n[a] < 1) return fail(HSP_EINVAL, "n must be >= 1");
+    if (g->pml[a] < 0) return fail(HSP_EINVAL, "pml must be >= 0");
+  }
+  if (!(g->h > 0) || !std::isfinite(g->h)) return fail(HSP_EINVAL, "h must be positive and finite");
+  if (J < 1) return fail(HSP_EINVAL, "J must be >= 1");
+  if (o->w_dd < 1) return fail(HSP_EINVAL, "w_dd must be >= 1");
+  if (o->nu < 0) return fail(HSP_EINVAL, "nu must be >= 0");
+  if (o->restart < 1) return fail(HSP_EINVAL, "restart must be >= 1");
+  if (o->fine_stencil != 7 && o->fine_stencil != 27)
+    return fail(HSP_EINVAL, "fine_stencil must be 7 or 27 in three dimensions");
+  if (o->sweep != HSP_SWEEP_X && o->sweep != HSP_SWEEP_UD) return fail(HSP_EINVAL, "bad sweep");
+  if (o->precision != HSP_MIXED)
+    return fail(HSP_EINVAL, "the 3-D path factors its slabs in complex64: precision must be HSP_MIXED");
+  if (o->krylov_fp32 != 0) return fail(HSP_EINVAL, "krylov_fp32 applies to the 2-D batched solvers only");
+  if (!std::isfinite(o->omega_jac)) return fail(HSP_EINVAL, "bad omega_jac");
+  return HSP_OK;
+}
+
+// Sizes and the workspace layout (fills the FGMRES part of C->P as well).
+hsp_status plan3(const hsp_grid* g, int J, const hsp_options* o, D3Ctx& D, Plan& P, size_t* total) {
+  hsp_status st = validate3(g, J, o);
+  if (st != HSP_OK) return st;
+  for (int a = 0; a < 3; ++a) {
+    D.N[a] = g->n[a] + 1 + 2 * g->pml[a];
+    D.m[a] = D.N[a] - 1;
+  }
+  D.two_grid = o->two_grid ? 1 : 0;
+  D.fine_kind = o->fine_stencil;
+  if (D.two_grid) {
+    for (int a = 0; a < 3; ++a) {
+      if ((D.N[a] - 2 * g->pml[a]) % 2 != 0 || D.N[a] - 2 * g->pml[a] < 2)
+        return fail(HSP_EINVAL, "two-grid needs an even, positive interior cell count per axis");
+      coarse_map(D.N[a], g->pml[a], D.ifp[a], D.ref[a]);
+      D.mc[a] = (int)D.ifp[a].size() - 2;
+      D.dm[a] = D.mc[a];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) D.dm[a] = D.m[a];
+  }
+  const int w_outer = g->pml[0];
+  if (D.dm[0] - 2 * w_outer < J) return fail(HSP_EINVAL, "too many slabs for the interior layers");
+  P.beta = partition(D.dm[0], w_outer, J);
+  P.bt = P.beta;
+  for (int j = 1; j < J; ++j) P.bt[j] = P.beta[j] - 1;
+  P.x0.resize(J);
+  P.x1.resize(J);
+  D.nls.resize(J);
+  D.nl_max = 0;
+  D.n_max = 0;
+  for (int j = 1; j <= J; ++j) {
+    if (P.beta[j] - P.beta[j - 1] < 3) return fail(HSP_EINVAL, "a core is thinner than 3 layers");
+    P.x0[j - 1] = (j == 1) ? 1 : P.beta[j - 1] - o->w_dd;
+    P.x1[j - 1] = (j == J) ? D.dm[0] : P.beta[j] + o->w_dd;
+    if (P.x0[j - 1] < 1 || P.x1[j - 1] > D.dm[0]) return fail(HSP_EINVAL, "DD-PML layers leave the domain");
+    const int nl = P.x1[j - 1] - P.x0[j - 1] + 1;
+    D.nls[j - 1] = nl;
+    D.nl_max = std::max(D.nl_max, nl);
+    D.n_max = std::max(D.n_max, nl * D.dm[2]);
+  }
+  if (D.n_max > kMaxBlock3)
+    return fail(HSP_EINVAL, "slab planes of " + std::to_string(D.n_max) + " unknowns exceed " +
+                                std::to_string(kMaxBlock3) + ": use more slabs or a smaller z extent");
+  P.nl_max = D.nl_max;
+  P.two_grid = D.two_grid;
+  P.tsize = sizeof(cf);
+  P.m = o->restart;
+  P.nf1 = D.m[0];
+  P.nf2 = D.m[1] * D.m[2];
+  P.dd_n1 = D.dm[0];
+  P.dd_n2 = D.dm[1] * D.dm[2];
+
+  Carver c;
+  const size_t nf = D.nf(), nd = D.nd();
+  for (int a = 0; a < 3; ++a) {
+    D.o_fA[a] = c.take((D.N[a] + 1) * sizeof(cd));
+    D.o_fB[a] = c.take((D.N[a] + 1) * sizeof(cd));
+    D.o_ib[a] = c.take((D.N[a] + 1) * sizeof(cd));
+  }
+  D.o_k2n = c.take(nf * sizeof(double));
+  const size_t nfc = (size_t)D.N[0] * D.N[1] * D.N[2];
+  if (D.fine_kind == 27) {
+    D.o_fk2c = c.take(nfc * sizeof(double));
+    D.o_fcoef = c.take(nfc * 5 * sizeof(double));
+  }
+  int nav[3];
+  for (int a = 0; a < 3; ++a) nav[a] = std::max(D.N[a], D.mc[a] + 1);
+  for (int a = 0; a < 3; ++a) {
+    D.o_avx[a] = c.take(nav[a] * sizeof(int));
+    D.o_avw[a] = c.take((size_t)nav[a] * 3 * sizeof(double));
+  }
+  if (D.two_grid) {
+    const size_t ncc = (size_t)(D.mc[0] + 1) * (D.mc[1] + 1) * (D.mc[2] + 1);
+    for (int a = 0; a < 3; ++a) {
+      D.o_cA[a] = c.take((D.mc[a] + 1) * sizeof(cd));
+      D.o_cB[a] = c.take((D.mc[a] + 1) * sizeof(cd));
+      D.o_r[a] = c.take((size_t)D.mc[a] * 3 * sizeof(int));
+      D.o_rw[a] = c.take((size_t)D.mc[a] * 3 * sizeof(double));
+      D.o_p[a] = c.take((size_t)D.m[a] * 2 * sizeof(int));
+      D.o_pw[a] = c.take((size_t)D.m[a] * 2 * sizeof(double));
+    }
+    D.o_ck2c = c.take(ncc * sizeof(double));
+    D.o_ccoef = c.take(ncc * 5 * sizeof(double));
+  }
+  D.n_slabA = D.n_xmap = D.n_fac = 0;
+  for (int j = 0; j < J; ++j) {
+    D.n_slabA += D.nls[j] + 2;
+    D.n_xmap += D.nls[j] + 1;
+    D.n_fac += blk_elems(D.nls[j] * D.dm[2]) * D.dm[1];
+  }
+  D.o_slabA = c.take(D.n_slabA * sizeof(cd));
+  D.o_slabB = c.take(D.n_slabA * sizeof(cd));
+  D.o_xmap = c.take(D.n_xmap * sizeof(int));
+  D.o_slabs = c.take(J * sizeof(d3::Slab3));
+  D.o_fac = c.take(D.n_fac * sizeof(cf));
+  D.o_setup = c.take(d3::setup3_scratch_bytes(J, D.n_max));
+  D.o_status = c.take(64);
+  D.o_growth = c.take((size_t)J * sizeof(double));
+  D.n_tasks = 2 * (size_t)J + 8;
+  D.o_tasks = c.take(D.n_tasks * sizeof(TaskDev));
+  const size_t pl = (size_t)D.dm[1] * D.dm[2];
+  const size_t slot = (size_t)D.dm[1] * (D.n_max + (D.n_max & 1));
+  D.o_swf = c.take(nd * sizeof(cf));
+  D.o_swg = c.take(nd * sizeof(cf));
+  D.o_swu = c.take(nd * sizeof(cf));
+  D.o_bufs = c.take(4 * pl * sizeof(cf));
+  D.o_fs = c.take(2 * slot * sizeof(cf));
+  D.o_ys = c.take(2 * slot * sizeof(cf));
+  D.o_tgx0 = c.take(nf * sizeof(cf));
+  D.o_tgx1 = c.take(nf * sizeof(cf));
+  if (D.two_grid) {
+    D.o_tgres = c.take(nf * sizeof(cd));
+    D.o_tgrc = c.take(nd * sizeof(cf));
+    D.o_tgec = c.take(nd * sizeof(cf));
+  }
+  D.o_cvin = c.take(std::max(nf, nd) * sizeof(cd));
+  D.o_cvout = c.take(std::max(nf, nd) * sizeof(cd));
+  // FGMRES of hsp_solve
+  P.o_V = c.take((size_t)(2 * P.m + 1) * nf * sizeof(cd));
+  P.o_Z = P.o_V + (size_t)(P.m + 1) * nf * sizeof(cd);
+  P.o_w = c.take(nf * sizeof(cd));
+  P.o_bconj = c.take(nf * sizeof(cd));
+  P.o_part = c.take((size_t)kPartBlocks * (P.m + 2) * sizeof(cd));
+  P.o_hbuf = c.take((size_t)(2 * (P.m + 2) + 2) * sizeof(cd));
+  P.o_stats = c.take(8 * sizeof(double));
+  P.total = c.off + 256;
+  *total = P.total;
+  return HSP_OK;
+}
+
+// Per-axis arrays of a level (see Level3): kind 7 at half nodes and nodes,
+// kind 27 per cell.
+void axis_arrays3(const AxisH& ax, int kind, double omega, std::vector<cd>& A, std::vector<cd>& B) {
+  const int N = (int)ax.x.size() - 1;
+  if (kind == 7) {
+    A.resize(N);
+    B.resize(N + 1);
+    for (int p = 0; p < N; ++p) A[p] = to_cd(alpha_of(ax.sig(0.5 * (ax.x[p] + ax.x[p + 1])), omega));
+    for (int i = 0; i <= N; ++i) B[i] = to_cd(1.0 / alpha_of(ax.sig(ax.x[i]), omega));
+  } else {
+    A.resize(N);
+    B.resize(N);
+    for (int p = 0; p < N; ++p) {
+      const double hp = ax.x[p + 1] - ax.x[p];
+      const cplx al = alpha_of(ax.sig(0.5 * (ax.x[p] + ax.x[p + 1])), omega);
+      A[p] = to_cd(al / hp);
+      B[p] = to_cd(hp / al);
+    }
+  }
+}
+
+// Restriction maps: coarse unknown I gathers fine unknowns with weights
+// 1 (its own node) and 1/2 (the midpoints of its refined cells).
+void restrict_maps(const std::vector<int>& ifp, const std::vector<char>& ref, int nc, std::vector<int>& ri,
+                   std::vector<double>& rw) {
+  ri.assign(3 * nc, -1);
+  rw.assign(3 * nc, 0.0);
+  for (int I = 1; I <= nc; ++I) {
+    const int F = ifp[I];
+    int q = 0;
+    ri[3 * (I - 1) + q] = F - 1, rw[3 * (I - 1) + q] = 1.0, ++q;
+    if (ref[I - 1]) ri[3 * (I - 1) + q] = F - 2, rw[3 * (I - 1) + q] = 0.5, ++q;
+    if (ref[I]) ri[3 * (I - 1) + q] = F, rw[3 * (I - 1) + q] = 0.5, ++q;
+  }
+}
+
+// Prolongation maps: tent interpolation, no coarsening in the PML cells.
+void prolong_maps(const std::vector<int>& ifp, const std::vector<char>& ref, int nf_, std::vector<int>& pi,
+                  std::vector<double>& pw) {
+  pi.assign(2 * nf_, -1);
+  pw.assign(2 * nf_, 0.0);
+  const int Nc = (int)ifp.size() - 1;
+  for (int I = 0; I <= Nc; ++I) {
+    const int F = ifp[I];
+    if (F >= 1 && F <= nf_ && I >= 1 && I <= Nc - 1) pi[2 * (F - 1)] = I - 1, pw[2 * (F - 1)] = 1.0;
+    if (I < Nc && ref[I]) {
+      const int f = F + 1;
+      int q = 0;
+      if (I >= 1) pi[2 * (f - 1) + q] = I - 1, pw[2 * (f - 1) + q] = 0.5, ++q;
+      if (I + 1 <= Nc - 1) pi[2 * (f - 1) + q] = I, pw[2 * (f - 1) + q] = 0.5, ++q;
+    }
+  }
+}
+
+void run_sweep3(hsp_ctx* C, const cf* f, cf* u, hipStream_t s) {
+  D3Ctx& D = *C->d3;
+  const size_t nd = D.nd();
+  cf* g = C->at<float>(D.o_swg);
+  launch_zero<float>(u, nd, s);
+  for (size_t k = 0; k < C->stages.size(); ++k) {
+    const Stage& st = C->stages[k];
+    if (st.residual) {
+      prof_begin(C, HSP_PROF_COARSE, s);
+      d3::launch_stencil3<float, float, float, float>(D.dd, 1, u, f, g, 0.0, s);
+      prof_end(C, HSP_PROF_COARSE, s, (double)nd * 3.0 * sizeof(cf));
+      continue;
+    }
+    d3::Stage3 S;
+    S.tasks = C->tasks_dev + st.first;
+    S.slabs = D.slabs_dev;
+    S.G = D.dd;
+    S.ntasks = st.ntasks;
+    S.n_max = D.n_max;
+    S.nl_max = D.nl_max;
+    S.f = f;
+    S.g = g;
+    S.u = u;
+    S.bufs = C->at<float>(D.o_bufs);
+    S.fs = C->at<float>(D.o_fs);
+    S.ys = C->at<float>(D.o_ys);
+    S.factors = D.factors;
+    prof_begin(C, HSP_PROF_STAGE, s);
+    d3::launch_stage3(S, s);
+    prof_end(C, HSP_PROF_STAGE, s, D.stage_bytes[k]);
+  }
+}
+
+}  // namespace
+
+hsp_status d3_workspace_size(const hsp_grid* g, int J, const hsp_options* o, size_t* bytes) {
+  D3Ctx D;
+  Plan P;
+  return plan3(g, J, o, D, P, bytes);
+}
+
+hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int J, const hsp_options* opt,
+                    void* ws_dev, size_t ws_bytes, hipStream_t s, hsp_ctx** out) {
+  hsp_ctx* C = new hsp_ctx();
+  C->d3 = new D3Ctx();
+  D3Ctx& D = *C->d3;
+  Plan& P = C->P;
+  size_t total = 0;
+  hsp_status st = plan3(grid, J, opt, D, P, &total);
+  auto cleanup = [&](hsp_status e) {
+    delete C;
+    return e;
+  };
+  if (st != HSP_OK) return cleanup(st);
+  if (ws_bytes < total) return cleanup(fail(HSP_ENOMEM, "workspace too small: need " + std::to_string(total) + " bytes"));
+  C->grid = *grid;
+  C->opt = *opt;
+  C->J = J;
+  C->omega = omega;
+  C->h = grid->h;
+  C->ws = reinterpret_cast<char*>(ws_dev);
+#define CHK(expr)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return cleanup(fail(HSP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+  const size_t nf = D.nf();
+  double stats[4];
+  launch_stats(c_dev, nf, C->raw<double>(P.o_stats), s);
+  CHK(hipGetLastError());
+  CHK(hipMemcpyAsync(stats, C->raw<double>(P.o_stats), 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  CHK(hipStreamSynchronize(s));
+  if (stats[3] > 0) return cleanup(fail(HSP_EINVAL, "c has non-positive or non-finite values"));
+  C->c_pml = (grid->c_pml > 0) ? grid->c_pml : stats[0] / (double)nf;
+  const double S_o = (grid->S_outer > 0) ? grid->S_outer : 5.0 * grid->pml[0];
+  const double S_dd = (opt->S_dd > 0) ? opt->S_dd : 5.0 * opt->w_dd;
+  const double h = grid->h;
+
+  std::vector<hipError_t> errs;
+  std::vector<std::vector<char>> keep;  // host buffers alive until the final sync
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    keep.emplace_back((const char*)src, (const char*)src + bytes);
+    errs.push_back(hipMemcpyAsync(C->ws + off, keep.back().data(), bytes, hipMemcpyHostToDevice, s));
+  };
+
+  // fine axes and level
+  AxisH fa[3];
+  for (int a = 0; a < 3; ++a) {
+    AxisH& ax = fa[a];
+    const int N = D.N[a], w = grid->pml[a];
+    ax.x.resize(N + 1);
+    for (int i = 0; i <= N; ++i) ax.x[i] = i * h;
+    ax.h_nom = h;
+    if (w > 0) {
+      ax.sig.left = ax.sig.right = true;
+      ax.sig.lo = w * h;
+      ax.sig.hi = (N - w) * h;
+      const double d = w * h;
+      ax.sig.C = S_o * C->c_pml / (d * d * d);
+    }
+    std::vector<cd> A, B;
+    axis_arrays3(ax, D.fine_kind, omega, A, B);
+    up(D.o_fA[a], A.data(), A.size() * sizeof(cd));
+    up(D.o_fB[a], B.data(), B.size() * sizeof(cd));
+    std::vector<cd> ib(N + 1);
+    for (int i = 0; i <= N; ++i) ib[i] = to_cd(1.0 / alpha_of(ax.sig(ax.x[i]), omega));
+    up(D.o_ib[a], ib.data(), ib.size() * sizeof(cd));
+  }
+  launch_k2_nodes(c_dev, nf, omega, C->raw<double>(D.o_k2n), s);
+  D.fine.kind = D.fine_kind;
+  for (int a = 0; a < 3; ++a) {
+    D.fine.A[a] = C->at<double>(D.o_fA[a]);
+    D.fine.B[a] = C->at<double>(D.o_fB[a]);
+  }
+  D.fine.m1 = D.m[0];
+  D.fine.m2 = D.m[1];
+  D.fine.m3 = D.m[2];
+  D.fine.hs = h;
+  D.fine.xmap = nullptr;
+  auto upload_avg = [&](int a, const std::vector<int>& x0, const std::vector<double>& w) {
+    up(D.o_avx[a], x0.data(), x0.size() * sizeof(int));
+    up(D.o_avw[a], w.data(), w.size() * sizeof(double));
+  };
+  auto avg_ptrs = [&](const int* (&x0)[3], const double* (&w)[3]) {
+    for (int a = 0; a < 3; ++a) {
+      x0[a] = C->raw<int>(D.o_avx[a]);
+      w[a] = C->raw<double>(D.o_avw[a]);
+    }
+  };
+  if (D.fine_kind == 7) {
+    D.fine.k2 = C->raw<double>(D.o_k2n);
+    D.fine.coef = nullptr;
+  } else {
+    // cell k^2 = mean of the 8 corner nodes; Table (b) at the fine 1/G
+    for (int a = 0; a < 3; ++a) {
+      std::vector<int> x0(D.N[a]);
+      std::vector<double> w(3 * D.N[a], 0.0);
+      for (int p = 0; p < D.N[a]; ++p) x0[p] = p, w[3 * p] = w[3 * p + 1] = 0.5;
+      upload_avg(a, x0, w);
+    }
+    const int* x0p[3];
+    const double* wp[3];
+    avg_ptrs(x0p, wp);
+    d3::launch_cell_average3(C->raw<double>(D.o_k2n), D.m, x0p, wp, D.N, C->raw<double>(D.o_fk2c), s);
+    d3::launch_cell_coefs3(C->raw<double>(D.o_fk2c), (size_t)D.N[0] * D.N[1] * D.N[2], h,
+                           C->raw<double>(D.o_fcoef), s);
+    D.fine.k2 = C->raw<double>(D.o_fk2c);
+    D.fine.coef = C->raw<double>(D.o_fcoef);
+    CHK(hipStreamSynchronize(s));  // the averaging arrays are reused below
+  }
+
+  // DD level
+  AxisH da[3];
+  if (D.two_grid) {
+    int ncell[3];
+    for (int a = 0; a < 3; ++a) {
+      da[a].x.resize(D.ifp[a].size());
+      for (size_t i = 0; i < D.ifp[a].size(); ++i) da[a].x[i] = fa[a].x[D.ifp[a][i]];
+      da[a].sig = fa[a].sig;
+      da[a].h_nom = 2.0 * h;
+      std::vector<cd> A, B;
+      axis_arrays3(da[a], 27, omega, A, B);
+      up(D.o_cA[a], A.data(), A.size() * sizeof(cd));
+      up(D.o_cB[a], B.data(), B.size() * sizeof(cd));
+      // coarse cell k^2: (1/2, 1/2) on unrefined, (1/4, 1/2, 1/4) on refined cells
+      ncell[a] = D.mc[a] + 1;
+      std::vector<int> x0(ncell[a]);
+      std::vector<double> w(3 * ncell[a], 0.0);
+      for (int p = 0; p < ncell[a]; ++p) {
+        x0[p] = D.ifp[a][p];
+        if (D.ref[a][p]) {
+          w[3 * p] = 0.25;
+          w[3 * p + 1] = 0.5;
+          w[3 * p + 2] = 0.25;
+        } else {
+          w[3 * p] = w[3 * p + 1] = 0.5;
+        }
+      }
+      upload_avg(a, x0, w);
+      std::vector<int> ri;
+      std::vector<double> rw;
+      restrict_maps(D.ifp[a], D.ref[a], D.mc[a], ri, rw);
+      up(D.o_r[a], ri.data(), ri.size() * sizeof(int));
+      up(D.o_rw[a], rw.data(), rw.size() * sizeof(double));
+      prolong_maps(D.ifp[a], D.ref[a], D.m[a], ri, rw);
+      up(D.o_p[a], ri.data(), ri.size() * sizeof(int));
+      up(D.o_pw[a], rw.data(), rw.size() * sizeof(double));
+    }
+    const int* x0p[3];
+    const double* wp[3];
+    avg_ptrs(x0p, wp);
+    d3::launch_cell_average3(C->raw<double>(D.o_k2n), D.m, x0p, wp, ncell, C->raw<double>(D.o_ck2c), s);
+    d3::launch_cell_coefs3(C->raw<double>(D.o_ck2c), (size_t)ncell[0] * ncell[1] * ncell[2], 2.0 * h,
+                           C->raw<double>(D.o_ccoef), s);
+    D.coarse.kind = 27;
+    for (int a = 0; a < 3; ++a) {
+      D.coarse.A[a] = C->at<double>(D.o_cA[a]);
+      D.coarse.B[a] = C->at<double>(D.o_cB[a]);
+      D.tr.nf[a] = D.m[a];
+      D.tr.nc[a] = D.mc[a];
+      D.tr.r[a] = C->raw<int>(D.o_r[a]);
+      D.tr.rw[a] = C->raw<double>(D.o_rw[a]);
+      D.tr.p[a] = C->raw<int>(D.o_p[a]);
+      D.tr.pw[a] = C->raw<double>(D.o_pw[a]);
+    }
+    D.coarse.m1 = D.mc[0];
+    D.coarse.m2 = D.mc[1];
+    D.coarse.m3 = D.mc[2];
+    D.coarse.hs = 0;
+    D.coarse.k2 = C->raw<double>(D.o_ck2c);
+    D.coarse.coef = C->raw<double>(D.o_ccoef);
+    D.coarse.xmap = nullptr;
+    D.dd = D.coarse;
+  } else {
+    for (int a = 0; a < 3; ++a) da[a] = fa[a];
+    D.dd = D.fine;
+  }
+
+  // slabs along x on the DD level
+  {
+    const auto& be = P.beta;
+    const int kind = D.dd.kind;
+    const double d = opt->w_dd * da[0].h_nom;
+    const double Cdd = S_dd * C->c_pml / (d * d * d);
+    std::vector<cd> SA(D.n_slabA, mk<double>(0, 0)), SB(D.n_slabA, mk<double>(0, 0));
+    std::vector<int> XM(D.n_xmap, 0);
+    size_t oA = 0, oM = 0, oF = 0;
+    D.slabs_host.resize(J);
+    const int ncell = D.dm[0] + 1;
+    const AxisH& dx = da[0];
+    for (int j = 1; j <= J; ++j) {
+      const int x0 = P.x0[j - 1], x1 = P.x1[j - 1], nl = x1 - x0 + 1;
+      const Sigma gs = dx.sig;
+      const bool hasL = j > 1, hasR = j < J;
+      const double bl = hasL ? 0.5 * (dx.x[be[j - 1] - 1] + dx.x[be[j - 1]]) : 0.0;
+      const double br = hasR ? 0.5 * (dx.x[be[j]] + dx.x[be[j] + 1]) : 0.0;
+      auto sig = [&](double x) {
+        if (hasL && x < bl) return Cdd * (bl - x) * (bl - x);
+        if (hasR && x > br) return Cdd * (x - br) * (x - br);
+        return gs(x);
+      };
+      auto gxn = [&](int lnode) { return dx.x[x0 - 1 + lnode]; };
+      if (kind == 7) {
+        for (int p = 0; p <= nl; ++p) SA[oA + p] = to_cd(alpha_of(sig(0.5 * (gxn(p) + gxn(p + 1))), omega));
+        for (int i = 0; i <= nl + 1; ++i) SB[oA + i] = to_cd(1.0 / alpha_of(sig(gxn(i)), omega));
+        const int lo = hasL ? be[j - 1] : 1, hi = hasR ? be[j] : D.dm[0];
+        for (int l = 0; l < nl; ++l) XM[oM + l] = std::min(std::max(x0 + l, lo), hi) - 1;
+      } else {
+        for (int p = 0; p <= nl; ++p) {
+          const double hp = gxn(p + 1) - gxn(p);
+          const cplx al = alpha_of(sig(0.5 * (gxn(p) + gxn(p + 1))), omega);
+          SA[oA + p] = to_cd(al / hp);
+          SB[oA + p] = to_cd(hp / al);
+        }
+        const int lo = hasL ? be[j - 1] - 1 : 0, hi = hasR ? be[j] : ncell - 1;
+        for (int p = 0; p <= nl; ++p) XM[oM + p] = std::min(std::max(x0 - 1 + p, lo), hi);
+      }
+      d3::Slab3 sd;
+      sd.x0 = x0;
+      sd.nl = nl;
+      sd.n = nl * D.dm[2];
+      sd.op = D.dd;
+      sd.op.m1 = nl;
+      sd.op.A[0] = C->at<double>(D.o_slabA) + oA;
+      sd.op.B[0] = C->at<double>(D.o_slabB) + oA;
+      sd.op.xmap = C->raw<int>(D.o_xmap) + oM;
+      sd.fac_off = oF;
+      D.slabs_host[j - 1] = sd;
+      oA += nl + 2;
+      oM += nl + 1;
+      oF += blk_elems(sd.n) * D.dm[1];
+    }
+    up(D.o_slabA, SA.data(), SA.size() * sizeof(cd));
+    up(D.o_slabB, SB.data(), SB.size() * sizeof(cd));
+    up(D.o_xmap, XM.data(), XM.size() * sizeof(int));
+    up(D.o_slabs, D.slabs_host.data(), J * sizeof(d3::Slab3));
+    D.slabs_dev = C->raw<d3::Slab3>(D.o_slabs);
+    D.factors = C->at<float>(D.o_fac);
+  }
+  build_schedule(C);
+  if (C->tasks_host.size() + 1 > D.n_tasks) return cleanup(fail(HSP_EINVAL, "internal: schedule too long"));
+  up(D.o_tasks, C->tasks_host.data(), C->tasks_host.size() * sizeof(TaskDev));
+  C->tasks_dev = C->raw<TaskDev>(D.o_tasks);
+  // algorithmic bytes per stage: the factor blocks W_t and E_t once, the
+  // gathered right-hand side, the u read-modify-write and the transmission
+  // layers (complex64)
+  D.stage_bytes.assign(C->stages.size(), 0.0);
+  for (size_t k = 0; k < C->stages.size(); ++k) {
+    const Stage& sg = C->stages[k];
+    double b = 0;
+    for (int q = 0; q < sg.ntasks; ++q) {
+      const TaskDev& t = C->tasks_host[sg.first + q];
+      const double n = (double)D.nls[t.slab] * D.dm[2], pl = (double)D.dm[1] * D.dm[2];
+      b += D.dm[1] * 3.0 * n * n * sizeof(cf);
+      b += pl * ((t.b - t.a) + 2.0 * (t.bt - t.at) + 2.0 * (t.t1 + t.t2 + t.t3 + t.t4)) * sizeof(cf);
+    }
+    D.stage_bytes[k] = b;
+  }
+  for (hipError_t e : errs)
+    if (e != hipSuccess) return cleanup(fail(HSP_EDEVICE, std::string("upload: ") + hipGetErrorString(e)));
+
+  // factorization of every slab
+  d3::Setup3 Su;
+  Su.slabs = D.slabs_dev;
+  Su.nslabs = J;
+  Su.n_max = D.n_max;
+  Su.m2 = D.dm[1];
+  Su.factors = D.factors;
+  {
+    Carver sc;
+    const size_t nm = (size_t)D.n_max;
+    char* base = C->ws + D.o_setup;
+    Su.S = reinterpret_cast<cf*>(base + sc.take((size_t)J * nm * nm * sizeof(cf)));
+    Su.coef = reinterpret_cast<cf*>(base + sc.take((size_t)J * nm * 27 * sizeof(cf)));
+    Su.brow = reinterpret_cast<cf*>(base + sc.take((size_t)J * 32 * nm * sizeof(cf)));
+    Su.piv = reinterpret_cast<int*>(base + sc.take((size_t)J * nm * sizeof(int)));
+    Su.col = reinterpret_cast<int*>(base + sc.take((size_t)J * nm * sizeof(int)));
+    Su.gmax = reinterpret_cast<double*>(base + sc.take((size_t)J * 2 * sizeof(double)));
+    if (sc.off > d3::setup3_scratch_bytes(J, D.n_max)) return cleanup(fail(HSP_EINVAL, "internal: setup scratch"));
+  }
+  Su.status = C->raw<int>(D.o_status);
+  Su.dbg_singular = debug_knobs().singular_slab;
+  CHK(hipMemsetAsync(Su.status, 0, sizeof(int), s));
+  CHK(hipMemsetAsync(Su.gmax, 0, (size_t)J * 2 * sizeof(double), s));
+  d3::launch_factor3(Su, s);
+  double* growth = C->raw<double>(D.o_growth);
+  d3::finish_growth3(Su, growth, s);
+  CHK(hipGetLastError());
+  int hstat = 0;
+  std::vector<double> hg(J);
+  CHK(hipMemcpyAsync(&hstat, Su.status, sizeof(int), hipMemcpyDeviceToHost, s));
+  CHK(hipMemcpyAsync(hg.data(), growth, J * sizeof(double), hipMemcpyDeviceToHost, s));
+  CHK(hipStreamSynchronize(s));
+  if (hstat != 0) return cleanup(fail(HSP_ESINGULAR, "zero or non-finite pivot in a slab factorization"));
+  C->growth = *std::max_element(hg.begin(), hg.end());
+  if (!(C->growth <= growth_limit(sizeof(cf))))
+    return cleanup(fail(HSP_ESINGULAR, "growth factor " + std::to_string(C->growth) +
+                                           " of the slab Schur complements exceeds the limit " +
+                                           std::to_string(growth_limit(sizeof(cf)))));
+#undef CHK
+  *out = C;
+  return HSP_OK;
+}
+
+void d3_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
+  D3Ctx& D = *C->d3;
+  const size_t nf = D.nf(), nd = D.nd();
+  if (!D.two_grid) {
+    cf* fin = C->at<float>(D.o_swf);
+    cf* uo = C->at<float>(D.o_tgx0);
+    launch_convert<float, double>(r, fin, nf, 0, s);
+    run_sweep3(C, fin, uo, s);
+    launch_convert<double, float>(uo, z, nf, 0, s);
+    return;
+  }
+  const double wj = C->opt.omega_jac;
+  const int nu = C->opt.nu;
+  cf* xa = C->at<float>(D.o_tgx0);
+  cf* xb = C->at<float>(D.o_tgx1);
+  // bytes of one smoothing step: r (complex128), x read and written, k^2
+  const double jb = (double)nf * (sizeof(cd) + 2.0 * sizeof(cf) + sizeof(double));
+  prof_begin(C, HSP_PROF_SMOOTH, s);
+  if (nu > 0) {
+    d3::launch_stencil3<float, float, double, float>(D.fine, 2, (const cf*)nullptr, r, xa, wj, s);
+    for (int k = 1; k < nu; ++k) {
+      d3::launch_stencil3<float, float, double, float>(D.fine, 2, xa, r, xb, wj, s);
+      std::swap(xa, xb);
+    }
+  } else {
+    launch_zero<float>(xa, nf, s);
+  }
+  // coarse-grid correction: r_c = P^T (r - A x) from the complex128 residual
+  cd* res = C->at<double>(D.o_tgres);
+  d3::launch_stencil3<double, float, double, double>(D.fine, 1, xa, r, res, 0.0, s);
+  prof_end(C, HSP_PROF_SMOOTH, s, nu * jb + (double)nf * (2.0 * sizeof(cd) + sizeof(cf) + sizeof(double)));
+  cf* rc = C->at<float>(D.o_tgrc);
+  cf* ec = C->at<float>(D.o_tgec);
+  prof_begin(C, HSP_PROF_TRANSFER, s);
+  d3::launch_restrict3<double, float>(D.tr, res, rc, s);
+  prof_end(C, HSP_PROF_TRANSFER, s, (double)nf * sizeof(cd) + (double)nd * sizeof(cf));
+  run_sweep3(C, rc, ec, s);
+  prof_begin(C, HSP_PROF_TRANSFER, s);
+  d3::launch_prolong_add3<float, float>(D.tr, ec, xa, s);
+  prof_end(C, HSP_PROF_TRANSFER, s, (double)nd * sizeof(cf) + 2.0 * nf * sizeof(cf));
+  if (nu == 0) {
+    launch_convert<double, float>(xa, z, nf, 0, s);
+    return;
+  }
+  prof_begin(C, HSP_PROF_SMOOTH, s);
+  for (int k = 0; k < nu; ++k) {
+    if (k == nu - 1) {
+      d3::launch_stencil3<float, float, double, double>(D.fine, 2, xa, r, z, wj, s);
+    } else {
+      d3::launch_stencil3<float, float, double, float>(D.fine, 2, xa, r, xb, wj, s);
+      std::swap(xa, xb);
+    }
+  }
+  prof_end(C, HSP_PROF_SMOOTH, s, nu * jb);
+}
+
+void d3_fine_apply(hsp_ctx* C, int mode, const cd* x, const cd* b, cd* y, hipStream_t s) {
+  d3::launch_stencil3<double, double, double, double>(C->d3->fine, mode, x, b, y, 0.0, s);
+}
+
+hsp_status d3_rhs(hsp_ctx* C, const cd* f, cd* b, hipStream_t s) {
+  D3Ctx& D = *C->d3;
+  d3::launch_rhs3(D.m[0], D.m[1], D.m[2], C->h * C->h * C->h, C->at<double>(D.o_ib[0]), C->at<double>(D.o_ib[1]),
+                  C->at<double>(D.o_ib[2]), f, b, s);
+  HIPCHK(hipGetLastError());
+  return HSP_OK;
+}
+
+hsp_status d3_apply_level_operator(hsp_ctx* C, int level, const cd* x, cd* y, hipStream_t s) {
+  D3Ctx& D = *C->d3;
+  if (level == 0) {
+    d3::launch_stencil3<double, double, double, double>(D.fine, 0, x, nullptr, y, 0.0, s);
+  } else if (level == 1 && D.two_grid) {
+    // the coarse operator in the precision of its use inside the sweep
+    const size_t n = D.nd();
+    cf* xin = C->at<float>(D.o_cvin);
+    cf* yo = C->at<float>(D.o_cvout);
+    launch_convert<float, double>(x, xin, n, 0, s);
+    d3::launch_stencil3<float, float, float, float>(D.coarse, 0, xin, (const cf*)nullptr, yo, 0.0, s);
+    launch_convert<double, float>(yo, y, n, 0, s);
+  } else {
+    return fail(HSP_EINVAL, "no such level");
+  }
+  HIPCHK(hipGetLastError());
+  return HSP_OK;
+}
+
+hsp_status d3_restrict(hsp_ctx* C, const cd* rf, cd* rc, hipStream_t s) {
+  if (!C->d3->two_grid) return fail(HSP_EINVAL, "no coarse level");
+  d3::launch_restrict3<double, double>(C->d3->tr, rf, rc, s);
+  HIPCHK(hipGetLastError());
+  return HSP_OK;
+}
+
+hsp_status d3_prolong_add(hsp_ctx* C, const cd* ec, cd* xf, hipStream_t s) {
+  if (!C->d3->two_grid) return fail(HSP_EINVAL, "no coarse level");
+  d3::launch_prolong_add3<double, double>(C->d3->tr, ec, xf, s);
+  HIPCHK(hipGetLastError());
+  return HSP_OK;
+}
+
+hsp_status d3_smooth(hsp_ctx* C, const cd* r, cd* x, int steps, hipStream_t s) {
+  D3Ctx& D = *C->d3;
+  const double wj = C->opt.omega_jac;
+  cd* tmp = C->at<double>(D.o_cvin);
+  cd* bufs[2] = {x, tmp};
+  int cur = (steps % 2 == 1) ? 0 : 1;
+  d3::launch_stencil3<double, double, double, double>(D.fine, 2, (const cd*)nullptr, r, bufs[cur], wj, s);
+  for (int k = 1; k < steps; ++k) {
+    d3::launch_stencil3<double, double, double, double>(D.fine, 2, bufs[cur], r, bufs[1 - cur], wj, s);
+    cur = 1 - cur;
+  }
+  HIPCHK(hipGetLastError());
+  return HSP_OK;
+}
+
+hsp_status d3_sweep(hsp_ctx* C, const cd* f, cd* u, hipStream_t s) {
+  D3Ctx& D = *C->d3;
+  const size_t nd = D.nd();
+  cf* fin = C->at<float>(D.o_swf);
+  cf* uo = C->at<float>(D.o_swu);
+  launch_convert<float, double>(f, fin, nd, 0, s);
+  run_sweep3(C, fin, uo, s);
+  launch_convert<double, float>(uo, u, nd, 0, s);
+  HIPCHK(hipGetLastError());
+  return HSP_OK;
+}
+
+hsp_status d3_slab_solve(hsp_ctx* C, int j, const cd* b, cd* x, hipStream_t s) {
+  D3Ctx& D = *C->d3;
+  const size_t n = (size_t)D.nls[j] * D.dm[1] * D.dm[2];
+  TaskDev t;
+  std::memset(&t, 0, sizeof(t));
+  t.slab = j;
+  t.mode = 1;
+  TaskDev* td = C->tasks_dev + (D.n_tasks - 1);
+  HIPCHK(hipMemcpyAsync(td, &t, sizeof(t), hipMemcpyHostToDevice, s));
+  cf* fin = C->at<float>(D.o_swf);
+  cf* uo = C->at<float>(D.o_swu);
+  launch_convert<float, double>(b, fin, n, 0, s);
+  d3::Stage3 S;
+  S.tasks = td;
+  S.slabs = D.slabs_dev;
+  S.G = D.dd;
+  S.ntasks = 1;
+  S.n_max = D.n_max;
+  S.nl_max = D.nl_max;
+  S.f = fin;
+  S.g = fin;
+  S.u = uo;
+  S.bufs = C->at<float>(D.o_bufs);
+  S.fs = C->at<float>(D.o_fs);
+  S.ys = C->at<float>(D.o_ys);
+  S.factors = D.factors;
+  d3::launch_stage3(S, s);
+  launch_convert<double, float>(uo, x, n, 0, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));  // the task descriptor is host stack memory
+  return HSP_OK;
+}
+
+void d3_info(const hsp_ctx* C, hsp_info* info) {
+  const D3Ctx& D = *C->d3;
+  info->n_fine[0] = D.m[0];
+  info->n_fine[1] = D.m[1];
+  info->n_fine_z = D.m[2];
+  info->n_coarse[0] = D.two_grid ? D.mc[0] : 0;
+  info->n_coarse[1] = D.two_grid ? D.mc[1] : 0;
+  info->n_coarse_z = D.two_grid ? D.mc[2] : 0;
+  info->J = C->J;
+  info->max_slab_layers = D.nl_max;
+  info->precision = C->opt.precision;
+  info->two_grid = D.two_grid;
+  info->pivot_growth = C->growth;
+  info->dim = 3;
+}
+
+}  // namespace hsp

@@ -20,28 +20,6 @@ namespace {
 
 thread_local std::string g_err = "no error";
 
-// PML damping sigma(x): C (lo - x)^2 left of lo, C (x - hi)^2 right of hi.
-struct Sigma {
-  double lo = 0, hi = 0, C = 0;
-  bool left = false, right = false;
-  double operator()(double x) const {
-    double s = 0;
-    if (left && x < lo) s = C * (lo - x) * (lo - x);
-    if (right && x > hi) s = C * (x - hi) * (x - hi);
-    return s;
-  }
-};
-
-inline cplx alpha_of(double sigma, double omega) { return 1.0 / cplx(1.0, sigma / omega); }
-
-// One axis of a level: node coordinates and the outer PML.
-struct AxisH {
-  std::vector<double> x;  // nodes 0..N
-  Sigma sig;
-  double h_nom = 0;
-  int n() const { return (int)x.size() - 2; }  // unknowns
-};
-
 // Per-axis level arrays (see LevelDev in common.h).
 void axis_arrays(const AxisH& ax, int kind, double omega, const std::vector<double>* sig_override_x,
                  std::vector<cd>& A, std::vector<cd>& B) {
@@ -88,6 +66,10 @@ hsp_status validate(const hsp_grid* g, int J, const hsp_options* o) {
   return HSP_OK;
 }
 
+}  // namespace
+
+namespace hsp {
+
 // Partition beta_0..beta_J of n1 layers: outer-PML layers join the first and
 // last cores, interior layers split evenly (integer arithmetic).
 std::vector<int> partition(int n1, int w_outer, int J) {
@@ -108,6 +90,10 @@ void coarse_map(int N, int w, std::vector<int>& ifp, std::vector<char>& ref) {
   ref.resize(ifp.size() - 1);
   for (size_t p = 0; p + 1 < ifp.size(); ++p) ref[p] = (ifp[p + 1] - ifp[p]) == 2;
 }
+
+}  // namespace hsp
+
+namespace {
 
 hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   hsp_status st = validate(g, J, o);
@@ -225,6 +211,7 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   P.o_fac = c.take(P.n_fac * P.tsize);
   P.o_facscr = c.take((size_t)J * kMaxSlabLayers * kMaxSlabLayers * sizeof(cd));
   P.o_status = c.take(64);
+  P.o_growth = c.take((size_t)J * sizeof(double));
   P.n_tasks = 2 * (size_t)J + 8;
   P.o_tasks = c.take(P.n_tasks * sizeof(TaskDev));
   P.o_tcoef = c.take(P.n_tasks * trans_coef_elems(P.dd_n2) * sizeof(cd));
@@ -267,7 +254,7 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
 }  // namespace
 
 
-namespace {
+namespace hsp {
 
 // ---------------------------------------------------------------------------
 // Sweep schedules (Table 3)
@@ -393,6 +380,10 @@ void build_schedule(hsp_ctx* C) {
   }
 }
 
+}  // namespace hsp
+
+namespace {
+
 // ---------------------------------------------------------------------------
 // Sweep, two-grid cycle and preconditioner
 // ---------------------------------------------------------------------------
@@ -504,6 +495,10 @@ void run_precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
 }
 
 void precond(hsp_ctx* C, const cd* r, cd* z, hipStream_t s) {
+  if (C->d3) {
+    d3_precond(C, r, z, s);
+    return;
+  }
   if (C->opt.precision == HSP_MIXED)
     run_precond<float>(C, r, z, s);
   else
@@ -520,6 +515,17 @@ namespace hsp {
 hsp_status fail(hsp_status st, const std::string& msg) {
   g_err = msg;
   return st;
+}
+
+DebugKnobs& debug_knobs() {
+  static DebugKnobs k;
+  return k;
+}
+
+double growth_limit(size_t tsize) {
+  if (debug_knobs().growth_limit > 0) return debug_knobs().growth_limit;
+  const double eps = tsize == sizeof(cf) ? 1.1920929e-7 : 2.220446049250313e-16;
+  return 0.01 / eps;
 }
 
 void prof_begin(hsp_ctx* C, int cls, hipStream_t s) {
@@ -573,6 +579,7 @@ hsp_status hsp_default_options(hsp_options* o) {
 
 hsp_status hsp_workspace_size(const hsp_grid* grid, int J, const hsp_options* opt, size_t* bytes) {
   if (!bytes) return fail(HSP_EINVAL, "null bytes");
+  if (grid && grid->dim == 3) return d3_workspace_size(grid, J, opt, bytes);
   Plan P;
   hsp_status st = make_plan(grid, J, opt, P);
   if (st != HSP_OK) return st;
@@ -587,6 +594,11 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
   if (!c_dev || !ws_dev) return fail(HSP_EINVAL, "null device pointer");
   if (!(omega > 0) || !std::isfinite(omega)) return fail(HSP_EINVAL, "omega must be positive and finite");
   if (((uintptr_t)ws_dev) & 255) return fail(HSP_EINVAL, "workspace must be 256-byte aligned");
+  if (grid && grid->dim == 3) {
+    hsp_status st3 = d3_setup(c_dev, omega, grid, J, opt, ws_dev, ws_bytes, S_(stream), out);
+    if (st3 == HSP_OK) g_err = "no error";
+    return st3;
+  }
   hsp_ctx* C = new hsp_ctx();
   hsp_status st = make_plan(grid, J, opt, C->P);
   if (st != HSP_OK) {
@@ -893,17 +905,28 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
   int* status = C->raw<int>(P.o_status);
   CHK(hipMemsetAsync(status, 0, sizeof(int), s));
   CHK(hipMemsetAsync(C->raw<int>(P.o_ctr), 0, 64 * sizeof(int), s));
+  double* growth = C->raw<double>(P.o_growth);
+  const int dbg = debug_knobs().singular_slab;
   if (P.tsize == sizeof(cf))
     launch_factor<float>(C->slabs_dev, J, P.nl_max, P.dd_n2, P.chunk, P.nchunk, reinterpret_cast<cf*>(C->factors),
-                         C->at<double>(P.o_setup), C->at<double>(P.o_facscr), C->at<double>(P.o_ttmp), status, s);
+                         C->at<double>(P.o_setup), C->at<double>(P.o_facscr), C->at<double>(P.o_ttmp), status,
+                         growth, dbg, s);
   else
     launch_factor<double>(C->slabs_dev, J, P.nl_max, P.dd_n2, P.chunk, P.nchunk, reinterpret_cast<cd*>(C->factors),
-                          C->at<double>(P.o_setup), C->at<double>(P.o_facscr), C->at<double>(P.o_ttmp), status, s);
+                          C->at<double>(P.o_setup), C->at<double>(P.o_facscr), C->at<double>(P.o_ttmp), status,
+                          growth, dbg, s);
   CHK(hipGetLastError());
   int hstat = 0;
+  std::vector<double> hgrowth(J);
   CHK(hipMemcpyAsync(&hstat, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  CHK(hipMemcpyAsync(hgrowth.data(), growth, J * sizeof(double), hipMemcpyDeviceToHost, s));
   CHK(hipStreamSynchronize(s));
   if (hstat != 0) return cleanup(fail(HSP_ESINGULAR, "zero or non-finite pivot in a slab factorization"));
+  C->growth = *std::max_element(hgrowth.begin(), hgrowth.end());
+  if (!(C->growth <= growth_limit(P.tsize)))
+    return cleanup(fail(HSP_ESINGULAR, "growth factor " + std::to_string(C->growth) +
+                                           " of the slab Schur complements exceeds the limit " +
+                                           std::to_string(growth_limit(P.tsize))));
 #undef CHK
   *out = C;
   g_err = "no error";
@@ -917,6 +940,13 @@ hsp_status hsp_destroy(hsp_handle hd) {
 
 hsp_status hsp_get_info(hsp_handle C, hsp_info* info) {
   if (!C || !info) return fail(HSP_EINVAL, "null argument");
+  if (C->d3) {
+    d3_info(C, info);
+    return HSP_OK;
+  }
+  info->dim = 2;
+  info->n_fine_z = 0;
+  info->n_coarse_z = 0;
   info->n_fine[0] = C->P.nf1;
   info->n_fine[1] = C->P.nf2;
   info->n_coarse[0] = C->P.two_grid ? C->P.nc1 : 0;
@@ -925,7 +955,21 @@ hsp_status hsp_get_info(hsp_handle C, hsp_info* info) {
   info->max_slab_layers = C->P.nl_max;
   info->precision = C->opt.precision;
   info->two_grid = C->P.two_grid;
+  info->pivot_growth = C->growth;
   return HSP_OK;
+}
+
+hsp_status hsp_debug_set(int knob, double value) {
+  switch (knob) {
+    case HSP_DEBUG_SINGULAR_SLAB:
+      debug_knobs().singular_slab = (int)value;
+      return HSP_OK;
+    case HSP_DEBUG_GROWTH_LIMIT:
+      debug_knobs().growth_limit = value;
+      return HSP_OK;
+    default:
+      return fail(HSP_EINVAL, "unknown debug knob");
+  }
 }
 
 hsp_status hsp_get_partition(hsp_handle C, int* beta, int* x0, int* x1) {
@@ -941,6 +985,7 @@ hsp_status hsp_get_partition(hsp_handle C, int* beta, int* x0, int* x1) {
 
 hsp_status hsp_rhs(hsp_handle C, const void* f, void* b, void* stream) {
   if (!C || !f || !b) return fail(HSP_EINVAL, "null argument");
+  if (C->d3) return d3_rhs(C, (const cd*)f, (cd*)b, S_(stream));
   launch_scale_rhs_arrays(C->P.nf1, C->P.nf2, C->h * C->h, C->at<double>(C->P.o_ixn), C->at<double>(C->P.o_iyn),
                           (const cd*)f, (cd*)b, S_(stream));
   HIPCHK(hipGetLastError());
@@ -949,6 +994,11 @@ hsp_status hsp_rhs(hsp_handle C, const void* f, void* b, void* stream) {
 
 hsp_status hsp_apply_operator(hsp_handle C, const void* x, void* y, void* stream) {
   if (!C || !x || !y || x == y) return fail(HSP_EINVAL, "null or aliased argument");
+  if (C->d3) {
+    d3_fine_apply(C, 0, (const cd*)x, nullptr, (cd*)y, S_(stream));
+    HIPCHK(hipGetLastError());
+    return HSP_OK;
+  }
   launch_stencil<double, double, double, double>(C->fine, 0, (const cd*)x, (const cd*)nullptr, (cd*)y, 0.0,
                                                  S_(stream));
   HIPCHK(hipGetLastError());
@@ -957,6 +1007,7 @@ hsp_status hsp_apply_operator(hsp_handle C, const void* x, void* y, void* stream
 
 hsp_status hsp_apply_level_operator(hsp_handle C, int level, const void* x, void* y, void* stream) {
   if (!C || !x || !y || x == y) return fail(HSP_EINVAL, "null or aliased argument");
+  if (C->d3) return d3_apply_level_operator(C, level, (const cd*)x, (cd*)y, S_(stream));
   if (level != 0 && !(level == 1 && C->P.two_grid)) return fail(HSP_EINVAL, "no such level");
   const LevelDev& L = level == 0 ? C->fine : C->coarse;
   hipStream_t s = S_(stream);
@@ -976,6 +1027,7 @@ hsp_status hsp_apply_level_operator(hsp_handle C, int level, const void* x, void
 
 hsp_status hsp_restrict(hsp_handle C, const void* rf, void* rc, void* stream) {
   if (!C || !rf || !rc) return fail(HSP_EINVAL, "null argument");
+  if (C->d3) return d3_restrict(C, (const cd*)rf, (cd*)rc, S_(stream));
   if (!C->P.two_grid) return fail(HSP_EINVAL, "no coarse level");
   launch_restrict<double, double>(C->tr, (const cd*)rf, (cd*)rc, S_(stream));
   HIPCHK(hipGetLastError());
@@ -984,6 +1036,7 @@ hsp_status hsp_restrict(hsp_handle C, const void* rf, void* rc, void* stream) {
 
 hsp_status hsp_prolong_add(hsp_handle C, const void* ec, void* xf, void* stream) {
   if (!C || !ec || !xf) return fail(HSP_EINVAL, "null argument");
+  if (C->d3) return d3_prolong_add(C, (const cd*)ec, (cd*)xf, S_(stream));
   if (!C->P.two_grid) return fail(HSP_EINVAL, "no coarse level");
   launch_prolong_add<double, double>(C->tr, (const cd*)ec, (cd*)xf, S_(stream));
   HIPCHK(hipGetLastError());
@@ -992,6 +1045,7 @@ hsp_status hsp_prolong_add(hsp_handle C, const void* ec, void* xf, void* stream)
 
 hsp_status hsp_smooth(hsp_handle C, const void* r, void* x, int steps, void* stream) {
   if (!C || !r || !x || r == x || steps < 1) return fail(HSP_EINVAL, "bad argument");
+  if (C->d3) return d3_smooth(C, (const cd*)r, (cd*)x, steps, S_(stream));
   hipStream_t s = S_(stream);
   const double wj = C->opt.omega_jac;
   cd* tmp = C->at<double>(C->P.o_cvin);
@@ -1009,6 +1063,7 @@ hsp_status hsp_smooth(hsp_handle C, const void* r, void* x, int steps, void* str
 
 hsp_status hsp_sweep(hsp_handle C, const void* f, void* u, void* stream) {
   if (!C || !f || !u || f == u) return fail(HSP_EINVAL, "null or aliased argument");
+  if (C->d3) return d3_sweep(C, (const cd*)f, (cd*)u, S_(stream));
   hipStream_t s = S_(stream);
   const size_t nd = (size_t)C->P.dd_n1 * C->P.dd_n2;
   if (C->opt.precision == HSP_FP64) {
@@ -1029,6 +1084,7 @@ hsp_status hsp_sweep(hsp_handle C, const void* f, void* u, void* stream) {
 hsp_status hsp_slab_solve(hsp_handle C, int j, const void* b, void* x, void* stream) {
   if (!C || !b || !x || b == x) return fail(HSP_EINVAL, "null or aliased argument");
   if (j < 0 || j >= C->J) return fail(HSP_EINVAL, "slab index out of range");
+  if (C->d3) return d3_slab_solve(C, j, (const cd*)b, (cd*)x, S_(stream));
   hipStream_t s = S_(stream);
   const Plan& P = C->P;
   const int nl = P.x1[j] - P.x0[j] + 1;
@@ -1064,6 +1120,7 @@ hsp_status hsp_slab_solve(hsp_handle C, int j, const void* b, void* x, void* str
 
 hsp_status hsp_gradient_accumulate(hsp_handle C, const void* u, const void* lam, double* g, void* stream) {
   if (!C || !u || !lam || !g) return fail(HSP_EINVAL, "null argument");
+  if (C->d3) return fail(HSP_EINVAL, "the gradient is implemented for 2-D problems");
   if (C->opt.fine_stencil != 5) return fail(HSP_EINVAL, "the gradient is implemented for the 5-point fine operator");
   if (!(C->grid.c_pml > 0)) return fail(HSP_EINVAL, "the gradient needs an explicit c_pml (not mean(c))");
   launch_grad_m(C->P.nf1, C->P.nf2, C->h * C->h * C->omega * C->omega, C->at<double>(C->P.o_ixn),
@@ -1127,6 +1184,13 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
     b = bc;
   }
   const LevelDev& A = C->fine;
+  // fine operator: y = A x (mode 0) or y = b - A x (mode 1)
+  auto fine_op = [&](int mode, const cd* xx, const cd* bb, cd* yy) {
+    if (C->d3)
+      d3_fine_apply(C, mode, xx, bb, yy, s);
+    else
+      launch_stencil<double, double, double, double>(A, mode, xx, bb, yy, 0.0, s);
+  };
   // conj(vecs_j) . vv for j < cnt into out[j] (w read once per tile of basis vectors)
   auto dotn = [&](const cd* vecs, int cnt, const cd* vv, cd* out) {
     launch_bmultidot(vecs, n, BIdx{}, cnt, vv, BIdx{}, n, part, kPartBlocks, out, 1, 1, s);
@@ -1150,7 +1214,7 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
   bool done = false;
   while (it < maxit && !done) {
     // r = b - A x into V_0
-    launch_stencil<double, double, double, double>(A, 1, x, b, V, 0.0, s);
+    fine_op(1, x, b, V);
     dotn(V, 1, V, hb + 2 * (m + 1));
     HIPCHK(hipMemcpyAsync(&hn, hb + 2 * (m + 1), sizeof(cd), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1166,7 +1230,7 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
       cd* zk = Z + (size_t)k * n;
       precond(C, vk, zk, s);
       prof_begin(C, HSP_PROF_KRYLOV, s);
-      launch_stencil<double, double, double, double>(A, 0, zk, (const cd*)nullptr, w, 0.0, s);
+      fine_op(0, zk, nullptr, w);
       // classical Gram-Schmidt, twice
       dotn(V, k + 1, w, hb);
       launch_multiaxpy(V, n, k + 1, hb, w, n, 1, s);
@@ -1227,7 +1291,7 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
     HIPCHK(hipStreamSynchronize(s));
   }
   // true residual
-  launch_stencil<double, double, double, double>(A, 1, x, b, w, 0.0, s);
+  fine_op(1, x, b, w);
   dotn(w, 1, w, hb + 2 * (m + 1));
   HIPCHK(hipMemcpyAsync(&hn, hb + 2 * (m + 1), sizeof(cd), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

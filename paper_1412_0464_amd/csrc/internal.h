@@ -129,7 +129,8 @@ constexpr size_t kTransferTmpElems = (size_t)3 * kMaxSlabLayers * kMaxSlabLayers
 
 template <class T>
 void launch_factor(const SlabDev* slabs_dev, int nslabs, int nl_max, int n2, int m, int P,
-                   cx<T>* factors, cd* setup, cd* scratchE, cd* tmp, int* status, hipStream_t s);
+                   cx<T>* factors, cd* setup, cd* scratchE, cd* tmp, int* status, double* growth, int dbg_singular,
+                  hipStream_t s);
 
 // One SubdomSolve stage (ntasks slabs at once), as three launches over
 // (P chunks) x (ntasks).  red: per task 2 P nl_max complex (chunk tips and

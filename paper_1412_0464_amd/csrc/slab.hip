@@ -7,7 +7,10 @@
 //   S_0 = B_0,  S_t = B_t - A_t E_{t-1},  G_t = S_t^{-1},  E_t = G_t C_t.
 // S_t is inverted in LDS by Gauss-Jordan with partial (row) pivoting; the
 // pivot row is found by a wavefront max-reduction.  All slabs are factored in
-// one launch (one workgroup per slab).
+// one launch (one workgroup per slab).  Pivoting stays inside each block, so
+// the Schur complements S_t are not protected against growth: every slab
+// reports its growth factor max_t |S_t|_max / max_t |B_t|_max, which the
+// host compares with a limit (the factor loses about log10(growth) digits).
 //
 // The substitutions of this factorization are evaluated in parallel along t.
 // Forward: y_t = G_t (f_t - A_t y_{t-1}) = c_t + M_t y_{t-1} with
@@ -20,6 +23,8 @@
 // exact arithmetic this is the sequential substitution of the same factors.
 // All blocks are stored column major (a thread owning output row l reads
 // them coalesced).
+#include <algorithm>
+
 #include "internal.h"
 #include "sweep_dev.h"
 
@@ -29,7 +34,8 @@ namespace {
 
 template <class T>
 __global__ void __launch_bounds__(256) k_factor(const SlabDev* __restrict__ slabs, int n2, cx<T>* factors,
-                                                cd* setup, cd* scratchE, int* status) {
+                                                cd* setup, cd* scratchE, int* status, double* growth,
+                                                int dbg_singular) {
   extern __shared__ cd smem[];
   const SlabDev sd = slabs[blockIdx.x];
   const int nl = sd.nl;
@@ -48,6 +54,9 @@ __global__ void __launch_bounds__(256) k_factor(const SlabDev* __restrict__ slab
   cd* Ad = Ed + (size_t)n2 * nb;           // couplings A_t, [t][3][nl]
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) sh_bad = 0;
+  double mxB = 0.0, mxS = 0.0;  // largest |entry|^2 of the blocks B_t and of the Schur complements S_t
+  // debugging aid: the first block of slab dbg_singular is replaced by zero
+  const bool zero_block = (int)blockIdx.x == dbg_singular;
 
   for (int t = 0; t < n2; ++t) {
     for (int i = tid; i < nl; i += nt) {
@@ -56,7 +65,10 @@ __global__ void __launch_bounds__(256) k_factor(const SlabDev* __restrict__ slab
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
 #pragma unroll
-        for (int b = 0; b < 3; ++b) cfs[i * 9 + a * 3 + b] = c[a][b];
+        for (int b = 0; b < 3; ++b) {
+          cfs[i * 9 + a * 3 + b] = c[a][b];
+          if (b == 1) mxB = fmax(mxB, abs2(c[a][b]));
+        }
         Ad[((size_t)t * 3 + a) * nl + i] = c[a][0];
         Am[((size_t)t * 3 + a) * nl + i] = cvt<T>(c[a][0]);
       }
@@ -75,6 +87,8 @@ __global__ void __launch_bounds__(256) k_factor(const SlabDev* __restrict__ slab
           s -= cfs[i * 9 + a * 3 + 0] * Ep[m * nl + j];
         }
       }
+      if (zero_block && t == 0) s = mk<double>(0, 0);
+      mxS = fmax(mxS, abs2(s));
       S[idx] = s;
     }
     __syncthreads();
@@ -155,6 +169,20 @@ __global__ void __launch_bounds__(256) k_factor(const SlabDev* __restrict__ slab
     __syncthreads();
   }
   if (tid == 0 && sh_bad) atomicOr(status, 1);
+  // growth factor of this slab
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(S);
+  red[tid] = mxB;
+  red[nt + tid] = mxS;
+  __syncthreads();
+  for (int off = nt / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      red[tid] = fmax(red[tid], red[tid + off]);
+      red[nt + tid] = fmax(red[nt + tid], red[nt + tid + off]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) growth[blockIdx.x] = red[0] > 0.0 ? sqrt(red[nt] / red[0]) : 0.0;
 }
 
 // C = sign * A B for column-major nl x nl matrices in double (setup only).
@@ -614,9 +642,13 @@ __global__ void __launch_bounds__(NT) k_stage_bwd(const TaskDev* __restrict__ ta
 
 template <class T>
 void launch_factor(const SlabDev* slabs_dev, int nslabs, int nl_max, int n2, int m, int P, cx<T>* factors,
-                   cd* setup, cd* scratchE, cd* tmp, int* status, hipStream_t s) {
-  const size_t shm = ((size_t)nl_max * nl_max + 10 * (size_t)nl_max) * sizeof(cd);
-  hipLaunchKernelGGL((k_factor<T>), dim3(nslabs), dim3(256), shm, s, slabs_dev, n2, factors, setup, scratchE, status);
+                   cd* setup, cd* scratchE, cd* tmp, int* status, double* growth, int dbg_singular,
+                   hipStream_t s) {
+  // LDS: S, the row coefficients and one column; at least 2 x 256 doubles
+  // for the growth reduction, which reuses S
+  const size_t shm = std::max(((size_t)nl_max * nl_max + 10 * (size_t)nl_max) * sizeof(cd), 512 * sizeof(double));
+  hipLaunchKernelGGL((k_factor<T>), dim3(nslabs), dim3(256), shm, s, slabs_dev, n2, factors, setup, scratchE, status,
+                     growth, dbg_singular);
   hipLaunchKernelGGL((k_chunk_transfer<T>), dim3(P, nslabs), dim3(256), 0, s, slabs_dev, n2, m, factors,
                      (const cd*)setup, tmp);
 }
@@ -653,8 +685,10 @@ void launch_stage(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev
 #undef LAUNCH3
 }
 
-template void launch_factor<double>(const SlabDev*, int, int, int, int, int, cd*, cd*, cd*, cd*, int*, hipStream_t);
-template void launch_factor<float>(const SlabDev*, int, int, int, int, int, cf*, cd*, cd*, cd*, int*, hipStream_t);
+template void launch_factor<double>(const SlabDev*, int, int, int, int, int, cd*, cd*, cd*, cd*, int*, double*, int,
+                                    hipStream_t);
+template void launch_factor<float>(const SlabDev*, int, int, int, int, int, cf*, cd*, cd*, cd*, int*, double*, int,
+                                   hipStream_t);
 template void launch_stage<double>(const TaskDev*, int, const SlabDev*, const LevelDev&, const cd*, const cd*, cd*,
                                    cd*, cd*, const cd*, int, int, int, int, cd*, int*, hipStream_t);
 template void launch_stage<float>(const TaskDev*, int, const SlabDev*, const LevelDev&, const cf*, const cf*, cf*,

@@ -41,7 +41,9 @@ class HspOptions(ctypes.Structure):
 
 class HspInfo(ctypes.Structure):
     _fields_ = [("n_fine", ctypes.c_int * 2), ("n_coarse", ctypes.c_int * 2), ("J", ctypes.c_int),
-                ("max_slab_layers", ctypes.c_int), ("precision", ctypes.c_int), ("two_grid", ctypes.c_int)]
+                ("max_slab_layers", ctypes.c_int), ("precision", ctypes.c_int), ("two_grid", ctypes.c_int),
+                ("pivot_growth", ctypes.c_double), ("dim", ctypes.c_int), ("n_fine_z", ctypes.c_int),
+                ("n_coarse_z", ctypes.c_int)]
 
 
 EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", "hsp_apply_operator",
@@ -50,7 +52,8 @@ EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", 
            "hsp_smooth", "hsp_sweep", "hsp_slab_solve", "hsp_profile_enable", "hsp_profile_read",
            "hsp_gradient_accumulate", "hsp_batch_workspace_size", "hsp_apply_precond_batch",
            "hsp_tune_batch", "hsp_solve_batch", "hsp_group_workspace_size", "hsp_apply_precond_group",
-           "hsp_solve_group"]
+           "hsp_solve_group", "hsp_debug_set"]
+DEBUG_KNOBS = {"singular_slab": 0, "growth_limit": 1}
 GROUP_GRAPH = 1
 PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4, "project": 5, "update": 6}
 
@@ -99,6 +102,7 @@ def load():
                                     ctypes.POINTER(P), I, I, P, S, P],
         "hsp_solve_group": [I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(P), D, I,
                             I, I, I, I, P, S, ctypes.POINTER(I), ctypes.POINTER(D), P],
+        "hsp_debug_set": [I, D],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -108,6 +112,13 @@ def load():
     lib.hsp_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
+
+
+def debug_set(knob, value):
+    """Set a process-wide debugging knob of the setup (hsp_debug_set):
+    ``singular_slab`` (slab index, -1 off) or ``growth_limit`` (> 0, or <= 0
+    for the default)."""
+    _check(load().hsp_debug_set(DEBUG_KNOBS[knob] if isinstance(knob, str) else int(knob), float(value)))
 
 
 def _check(st):
@@ -132,11 +143,16 @@ def _vec(t, shape, name):
 
 
 def make_grid(n, h, pml, S_outer=0.0, c_pml=0.0):
+    """hsp_grid for 2 (len(n) == 2) or 3 dimensions."""
     g = HspGrid()
-    g.dim = 2
-    g.n[0], g.n[1], g.n[2] = int(n[0]), int(n[1]), 0
+    d = len(n)
+    if d not in (2, 3) or len(pml) != d:
+        raise ValueError("n and pml must both have 2 or 3 entries")
+    g.dim = d
+    for a in range(3):
+        g.n[a] = int(n[a]) if a < d else 0
+        g.pml[a] = int(pml[a]) if a < d else 0
     g.h = float(h)
-    g.pml[0], g.pml[1], g.pml[2] = int(pml[0]), int(pml[1]), 0
     g.S_outer = float(S_outer)
     g.c_pml = float(c_pml)
     return g
@@ -170,20 +186,30 @@ class Helmholtz:
     """One medium and frequency: hsp_setup on construction, hsp_destroy on close.
 
     ``c``   contiguous float64 CUDA tensor of wave speeds at all unknown nodes
-            (PML nodes included), shape (N1-1, N2-1).
-    ``pml`` outer PML cells per side (int or pair); the interior node counts
-            follow from c.shape - 2*pml.
+            (PML nodes included), shape (N1-1, N2-1) in 2-D or
+            (N1-1, N2-1, N3-1) in 3-D.
+    ``pml`` outer PML cells per side (int, or one per axis); the interior node
+            counts follow from c.shape - 2*pml.
     Options follow hsp_options (fine_stencil, two_grid, w_dd, S_dd, nu,
     omega_jac, sweep 'x'/'ud', precision 'fp64'/'mixed', restart, chunk,
-    krylov_fp32).
+    krylov_fp32).  In 3-D the defaults are those of the paper's 3-D
+    experiments (Sec. 6.2): fine_stencil 7, w_dd 3, omega_jac 0.6, and the
+    complex64 slab factors of precision 'mixed'.
     """
 
     def __init__(self, c, omega, h, pml, J, S_outer=0.0, c_pml=0.0, **opts):
         lib = load()
-        if not (c.is_cuda and c.dtype == torch.float64 and c.is_contiguous() and c.dim() == 2):
-            raise ValueError("c must be a contiguous 2-D float64 CUDA tensor")
-        pml = (pml, pml) if isinstance(pml, int) else tuple(pml)
-        n = (c.shape[0] - 2 * pml[0], c.shape[1] - 2 * pml[1])
+        if not (c.is_cuda and c.dtype == torch.float64 and c.is_contiguous() and c.dim() in (2, 3)):
+            raise ValueError("c must be a contiguous 2-D or 3-D float64 CUDA tensor")
+        d = c.dim()
+        if d == 3:
+            opts.setdefault("fine_stencil", 7)
+            opts.setdefault("w_dd", 3)
+            opts.setdefault("omega_jac", 0.6)
+            opts.setdefault("precision", "mixed")
+        pml = (pml,) * d if isinstance(pml, int) else tuple(pml)
+        n = tuple(c.shape[a] - 2 * pml[a] for a in range(d))
+        self.dim = d
         self.shape = tuple(c.shape)
         self.grid = make_grid(n, h, pml, S_outer, c_pml)
         self.opts = make_options(**opts)
@@ -197,10 +223,15 @@ class Helmholtz:
         self.handle = hd
         inf = HspInfo()
         _check(lib.hsp_get_info(self.handle, ctypes.byref(inf)))
-        self.n_fine = tuple(inf.n_fine)
-        self.n_coarse = tuple(inf.n_coarse)
+        if d == 3:
+            self.n_fine = (inf.n_fine[0], inf.n_fine[1], inf.n_fine_z)
+            self.n_coarse = (inf.n_coarse[0], inf.n_coarse[1], inf.n_coarse_z)
+        else:
+            self.n_fine = tuple(inf.n_fine)
+            self.n_coarse = tuple(inf.n_coarse)
         self.max_slab_layers = inf.max_slab_layers
         self.two_grid = bool(inf.two_grid)
+        self.pivot_growth = inf.pivot_growth
         beta = (ctypes.c_int * (self.J + 1))()
         x0 = (ctypes.c_int * self.J)()
         x1 = (ctypes.c_int * self.J)()
@@ -275,7 +306,7 @@ class Helmholtz:
 
     def slab_solve(self, j, b):
         nl = self.x1[j] - self.x0[j] + 1
-        shape = (nl, self.dd_shape[1])
+        shape = (nl,) + tuple(self.dd_shape[1:])
         _vec(b, shape, "b")
         x = self._new(shape)
         _check(load().hsp_slab_solve(self.handle, int(j), _ptr(b), _ptr(x), _stream()))

@@ -72,3 +72,30 @@ def test_null_arguments_rejected_without_device():
     assert lib.hsp_setup(None, 1.0, ctypes.byref(g), 2, ctypes.byref(o), None, 0, None,
                          ctypes.byref(out)) == hsp.HSP_EINVAL
     assert b"null" in lib.hsp_last_error()
+
+
+def _ws3(n=(17, 8, 9), h=0.05, pml=(3, 3, 3), J=3, **kw):
+    kw.setdefault("fine_stencil", 7)
+    kw.setdefault("precision", "mixed")
+    return hsp.workspace_size(n, h, pml, J, **kw)
+
+
+def test_workspace_size_3d():
+    assert _ws3() > 0
+    assert _ws3(two_grid=True, n=(25, 9, 11), pml=(4, 4, 4)) > 0
+    assert _ws3(fine_stencil=27) > _ws3()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(precision="fp64"), "HSP_MIXED"),                 # 3-D factors are complex64
+    (dict(fine_stencil=5), "7 or 27"),
+    (dict(two_grid=True, n=(17, 8, 9)), "even"),
+    (dict(J=9), "thinner than 3"),
+    (dict(n=(40, 8, 300), J=1), "exceed"),                 # slab planes beyond the panel kernel
+    (dict(krylov_fp32=True), "krylov_fp32"),
+])
+def test_workspace_size_3d_rejects_invalid(kw, msg):
+    with pytest.raises(hsp.HspError) as e:
+        _ws3(**kw)
+    assert e.value.status == hsp.HSP_EINVAL
+    assert msg in str(e.value)

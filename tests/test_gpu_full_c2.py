@@ -3,7 +3,8 @@
 The 2-D layered medium with 1023^2 interior nodes and 16 PML cells per side,
 8 points per wavelength, the two-grid sweeping preconditioner with J = 32
 coarse slabs, 64 point sources solved in one batch with a right-hand-side
-tile of 4: the launch configuration bench.py times.  The oracle cannot run
+tile of 4 and 34 tangential blocks per chunk of the slab substitutions: the
+launch configuration bench.py times.  The oracle cannot run
 the whole batch in seconds, so the checks use outputs it computes one by one
 and properties that hold at any size:
 
@@ -50,10 +51,10 @@ def c2():
     return cfg, c, fs, ref
 
 
-def _helmholtz(cfg, c, precision):
+def _helmholtz(cfg, c, precision, chunk=0):
     from paper_1412_0464_amd import Helmholtz
     return Helmholtz(torch.tensor(c, device=torch.device("cuda:0")), cfg["omega"], cfg["h"], cfg["w"], cfg["J"],
-                     two_grid=True, precision=precision, restart=40)
+                     two_grid=True, precision=precision, restart=40, chunk=chunk)
 
 
 def _t(a):
@@ -74,10 +75,11 @@ def test_c2_fine_operator(c2):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
 def test_c2_batched_precond_sampled_columns(c2, precision, tol):
     cfg, c, fs, ref = c2
-    hs = _helmholtz(cfg, c, precision)
+    hs = _helmholtz(cfg, c, precision, chunk=bench.BATCH_CHUNK)
     try:
         R = np.stack([random_rhs(c.shape, 1412100 + j) for j in range(64)])
-        print(f"[full size c2] batched preconditioner, {precision}, 64 columns, tile 4", flush=True)
+        print(f"[full size c2] batched preconditioner, {precision}, 64 columns, tile 4, chunk {bench.BATCH_CHUNK}",
+              flush=True)
         Z = hs.apply_precond_batch(_t(R), tile=4).cpu().numpy()
         for j in SAMPLED:
             err = _relerr(Z[j], ref.precond(R[j].ravel()))
@@ -89,10 +91,10 @@ def test_c2_batched_precond_sampled_columns(c2, precision, tol):
 
 def test_c2_batched_mixed_solve(c2):
     cfg, c, fs, ref = c2
-    hs = _helmholtz(cfg, c, "mixed")
+    hs = _helmholtz(cfg, c, "mixed", chunk=bench.BATCH_CHUNK)
     try:
         B = torch.stack([hs.rhs(_t(f)) for f in fs])
-        print("[full size c2] batched mixed solve, 64 sources, tile 4", flush=True)
+        print(f"[full size c2] batched mixed solve, 64 sources, tile 4, chunk {bench.BATCH_CHUNK}", flush=True)
         U, its, rrs = hs.solve_batch(B, tol=1e-6, maxit=200, tile=4)
         U = U.cpu().numpy()
     finally:

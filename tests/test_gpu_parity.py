@@ -293,3 +293,79 @@ def test_precond_smoothing_variants(fine, nu, precision, tol):
     Z = hs.apply_precond_batch(_t(R), tile=2).cpu().numpy()
     for j in range(3):
         assert _relerr(Z[j], ref.precond(R[j].ravel())) < tol
+
+
+# ---------------------------------------------------------------------------
+# failure paths through the C ABI (Sec. 5: block LU with pivoting inside
+# each block; FGMRES that stops at maxit)
+# ---------------------------------------------------------------------------
+def _small_problem():
+    n1, n2, w = 47, 39, 5
+    c = extend_into_pml(layered_medium_2d(n1, n2, 1412046, n_layers=7, corr_len=6.0), w)
+    h = 0.02
+    return c, 2 * np.pi * 1.5 / (8.0 * h), h, w
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_singular_slab_block_gives_esingular(precision):
+    from paper_1412_0464_amd import Helmholtz, HspError, hsp
+    c, om, h, w = _small_problem()
+    print(f"[failure path: singular first block of slab 1, {precision}]", flush=True)
+    hsp.debug_set("singular_slab", 1)
+    try:
+        with pytest.raises(HspError) as e:
+            Helmholtz(torch.tensor(c, device=_dev()), om, h, w, 3, precision=precision)
+        assert e.value.status == hsp.HSP_ESINGULAR
+        assert "pivot" in str(e.value)
+    finally:
+        hsp.debug_set("singular_slab", -1)
+    hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, 3, precision=precision)
+    print(f"[pivot growth {hs.pivot_growth:.4f}]", flush=True)
+    assert 0.0 < hs.pivot_growth < 1e3
+    hs.close()
+
+
+def test_pivot_growth_guard():
+    """The setup refuses factors whose Schur complements grew beyond the
+    limit (here set below the growth measured for this medium)."""
+    from paper_1412_0464_amd import Helmholtz, HspError, hsp
+    c, om, h, w = _small_problem()
+    hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, 3, precision="mixed")
+    g = hs.pivot_growth
+    hs.close()
+    print(f"[failure path: growth limit below the measured growth {g:.3f}]", flush=True)
+    hsp.debug_set("growth_limit", 0.5 * g)
+    try:
+        with pytest.raises(HspError) as e:
+            Helmholtz(torch.tensor(c, device=_dev()), om, h, w, 3, precision="mixed")
+        assert e.value.status == hsp.HSP_ESINGULAR and "growth" in str(e.value)
+    finally:
+        hsp.debug_set("growth_limit", 0.0)
+
+
+def test_maxit_gives_enoconv_with_last_iterate():
+    from paper_1412_0464_amd import Helmholtz, HspError, hsp
+    c, om, h, w = _small_problem()
+    ref = Problem2D(c, om, h, w, S_outer=5.0 * w, J=3, w_dd=4)
+    f = point_source(c.shape, (c.shape[0] // 2, c.shape[1] // 2), h)
+    print("[failure path: maxit = 1, single and batched]", flush=True)
+    hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, 3, S_outer=5.0 * w)
+    try:
+        b = hs.rhs(_t(f))
+        with pytest.raises(HspError) as e:
+            hs.solve(b, tol=1e-10, maxit=1)
+        assert e.value.status == hsp.HSP_ENOCONV
+        u, it, rr = hs.solve(b, tol=1e-10, maxit=1, raise_on_noconv=False)
+        assert it == 1 and rr > 1e-10
+        # the returned iterate is the oracle's first FGMRES iterate
+        uo, ito, _, _ = ref.solve(f, tol=1e-10, maxit=1)
+        assert ito == 1 and _relerr(u.cpu().numpy(), uo) < 1e-10
+        B = torch.stack([b, b])
+        with pytest.raises(HspError) as e:
+            hs.solve_batch(B, tol=1e-10, maxit=1)
+        assert e.value.status == hsp.HSP_ENOCONV
+        U, its, rrs = hs.solve_batch(B, tol=1e-10, maxit=1, raise_on_noconv=False)
+        assert its == [1, 1] and min(rrs) > 1e-10
+        assert _relerr(U[1].cpu().numpy(), uo) < 1e-10
+    finally:
+        hs.close()

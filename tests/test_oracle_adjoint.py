@@ -60,3 +60,15 @@ def test_adjoint_gradient_matches_torch_autograd():
     Lo, go, _ = ADJ.misfit_gradient(m, om, h, w, 5.0 * w, 2.5, src, rec, d_obs)
     assert abs(L.item() - Lo) <= 1e-10 * Lo
     assert np.abs(mt.grad.numpy() - go.ravel()).max() <= 1e-9 * np.abs(go).max()
+
+
+def test_library_misfit_rejects_repeated_receivers():
+    """The library's adjoint places the adjoint sources by assignment, so a
+    repeated receiver node would drop one of its two misfit terms; the
+    forward pass refuses such receiver sets before any device work."""
+    from paper_1412_0464_amd.adjoint import misfit
+    m = torch.ones((9, 9), dtype=torch.float64)
+    src = torch.zeros((1, 9, 9), dtype=torch.complex128)
+    rec = torch.tensor([3, 4, 4])
+    with pytest.raises(ValueError, match="distinct"):
+        misfit(m, src, rec, torch.zeros((1, 3), dtype=torch.complex128), 10.0, 0.1, 2, 1, 1.0)
