@@ -262,6 +262,22 @@ hsp_status hsp_batch_workspace_size(hsp_handle hd, int nrhs, int restart, size_t
 hsp_status hsp_apply_precond_batch(hsp_handle hd, int nrhs, const void* r_dev, void* z_dev, int tile,
                                    void* ws_dev, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * map as hsp_apply_precond_batch (same kernels, same evaluation order for
+ * the same tile, so bitwise the same z), with the batch workspace taken from
+ * a fixed device array inside the library instead of a caller workspace.
+ * Calls no allocating routine.  The array holds 256 MiB per GPU (written to
+ * *scratch_bytes if not NULL); it is reserved on every GPU the library runs
+ * on until the process ends, and it is shared by all calls on that GPU:
+ * calls that overlap on one GPU (other streams or host threads) race and must
+ * be serialised by the caller.  Every call clears what must start at zero.
+ * Errors: HSP_EINVAL (bad tile, null or aliased vectors), HSP_ENOMEM (the
+ * batch needs more than the fixed scratch: hsp_batch_workspace_size(hd,
+ * nrhs, 1) must not exceed it), HSP_EDEVICE. */
+hsp_status hsp_apply_precond_batch_noalloc(hsp_handle hd, int nrhs, const void* r_dev, void* z_dev, int tile,
+                                           size_t* scratch_bytes, void* stream);
+
 /* Times one batched preconditioner application for every tile and keeps the
  * fastest for batches of nrhs right-hand sides (used when tile = 0).  Writes
  * into the batch workspace (sized for nrhs, restart).  tile_out and ms_out

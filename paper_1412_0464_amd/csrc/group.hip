@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -974,6 +975,35 @@ hsp_status group_precond(Group& G, const void* const* r, void* const* z, int til
   return HSP_OK;
 }
 
+// ---- fixed device scratch of hsp_apply_precond_batch_noalloc --------------
+// One copy of this array lives on every GPU the library runs on, from the
+// first use until the process ends.  Host code never passes the symbol
+// itself to a kernel: it is a host-side stand-in, and the device address of
+// each GPU's copy comes from hipGetSymbolAddress with that GPU current.
+constexpr size_t kNoallocScratchBytes = (size_t)256 << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch (looked up once per device).
+hsp_status noalloc_scratch(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HSP_EDEVICE, "device index out of range for the fixed scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(HSP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HSP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1029,6 +1059,28 @@ hsp_status hsp_apply_precond_batch(hsp_handle C, int nrhs, const void* r, void* 
   hsp_status st = check_tile(tile);
   if (st != HSP_OK || nrhs == 0) return st;
   return hsp_apply_precond_group(1, &C, &nrhs, &r, &z, tile, 0, ws, ws_bytes, stream);
+}
+
+hsp_status hsp_apply_precond_batch_noalloc(hsp_handle C, int nrhs, const void* r, void* z, int tile,
+                                           size_t* scratch_bytes, void* stream) {
+  if (!C) return fail(HSP_EINVAL, "null handle");
+  if (nrhs < 0) return fail(HSP_EINVAL, "nrhs must be >= 0");
+  hsp_status st = check_tile(tile);
+  if (st != HSP_OK) return st;
+  if (scratch_bytes) *scratch_bytes = kNoallocScratchBytes;
+  if (nrhs == 0) return HSP_OK;
+  if (!r || !z || r == z) return fail(HSP_EINVAL, "null or aliased vectors");
+  Group G;
+  if ((st = group_plan(1, &C, &nrhs, 1, G)) != HSP_OK) return st;
+  if (G.total > kNoallocScratchBytes)
+    return fail(HSP_ENOMEM, "batch needs " + std::to_string(G.total) + " bytes of scratch, more than the fixed " +
+                                std::to_string(kNoallocScratchBytes) + " bytes: use fewer right-hand sides");
+  void* ws = nullptr;
+  if ((st = noalloc_scratch(&ws)) != HSP_OK) return st;
+  group_bind(G, ws);
+  const void* rr[1] = {r};
+  void* zz[1] = {z};
+  return group_precond(G, rr, zz, tile, 0, S_(stream), 0, 0, /*zero_by_kernel=*/true);
 }
 
 hsp_status hsp_tune_batch(hsp_handle C, int nrhs, int restart, void* ws, size_t ws_bytes, int* tile_out,

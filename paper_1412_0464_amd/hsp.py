@@ -52,7 +52,7 @@ EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", 
            "hsp_smooth", "hsp_sweep", "hsp_slab_solve", "hsp_profile_enable", "hsp_profile_read",
            "hsp_gradient_accumulate", "hsp_batch_workspace_size", "hsp_apply_precond_batch",
            "hsp_tune_batch", "hsp_solve_batch", "hsp_group_workspace_size", "hsp_apply_precond_group",
-           "hsp_solve_group", "hsp_debug_set"]
+           "hsp_solve_group", "hsp_debug_set", "hsp_apply_precond_batch_noalloc"]
 DEBUG_KNOBS = {"singular_slab": 0, "growth_limit": 1}
 GROUP_GRAPH = 1
 PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4, "project": 5, "update": 6}
@@ -103,6 +103,7 @@ def load():
         "hsp_solve_group": [I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(P), D, I,
                             I, I, I, I, P, S, ctypes.POINTER(I), ctypes.POINTER(D), P],
         "hsp_debug_set": [I, D],
+        "hsp_apply_precond_batch_noalloc": [P, I, P, P, I, ctypes.POINTER(S), P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -383,6 +384,16 @@ class Helmholtz:
         ws = self._bws if key is not None and key[0] == nrhs else self.batch_workspace(nrhs, 1)
         _check(load().hsp_apply_precond_batch(self.handle, int(nrhs), _ptr(r), _ptr(z), int(tile), _ptr(ws),
                                               ws.numel(), _stream()))
+        return z
+
+    def apply_precond_batch_noalloc(self, r, tile=1, out=None):
+        """As apply_precond_batch, with the library's fixed device scratch
+        instead of a workspace (hsp_apply_precond_batch_noalloc).  ``out``
+        lets the caller avoid any allocation as well."""
+        self._batch(r, "r")
+        z = torch.empty_like(r) if out is None else self._batch(out, "out")
+        _check(load().hsp_apply_precond_batch_noalloc(self.handle, int(r.shape[0]), _ptr(r), _ptr(z), int(tile), None,
+                                                      _stream()))
         return z
 
     def tune_batch(self, nrhs, restart=None):
