@@ -301,6 +301,79 @@ def c3_run(steps, warmup, tol, nsrc=64, graph=False):
             "graph": bool(graph)}
 
 
+def c4_config():
+    """The 3-D workload: a seeded smooth random medium (linear depth trend
+    1.5 -> 4.5 km/s times 1 + 5 % Gaussian random field, correlation length
+    10 cells) on 127^3 interior nodes + 8 PML cells per side, h = 20 m,
+    10 points per wavelength at 1.5 km/s (7.5 Hz), two-grid sweeping
+    preconditioner with the 7-point fine level and the optimized 27-point
+    FE coarse level (79^3), X-sweep over J = 16 coarse slabs of 4 layers
+    plus 3 DD-PML layers per side, nu = 3, omega_jac = 0.6."""
+    n, w, h, ppw, J = 127, 8, 0.02, 10.0, 16
+    return dict(n=n, w=w, h=h, omega=2 * np.pi * 1.5 / (ppw * h), J=J, w_dd=3, omega_jac=0.6,
+                workload="3D smooth random 127^3 + 8 PML, 10 ppw, TGSP (7-pt fine, opt 27-pt FE coarse 79^3), "
+                         "X-sweep J=16, w_dd=3, point source")
+
+
+def c4_medium(cfg, seed=1412047):
+    from synth.media import smooth_medium_3d
+    n, w = cfg["n"], cfg["w"]
+    return np.pad(smooth_medium_3d(n, n, n, seed, corr_len=10.0), w, mode="edge")
+
+
+def c4_run(steps, warmup, tol, profile=True):
+    """Setup (timed alone), then ``steps`` solves of a point source at the
+    centre to ``tol``; optionally a profiled repeat with event pairs around
+    every kernel class."""
+    import torch
+    from paper_1412_0464_amd import Helmholtz
+    from synth.media import point_source
+    cfg = c4_config()
+    dev = torch.device("cuda:0")
+    c = c4_medium(cfg)
+    ct = torch.tensor(c, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs = Helmholtz(ct, cfg["omega"], cfg["h"], cfg["w"], cfg["J"], two_grid=True, w_dd=cfg["w_dd"],
+                   omega_jac=cfg["omega_jac"], restart=60)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] c4 setup {setup_s:.3f} s, pivot growth {hs.pivot_growth:.3f}", file=sys.stderr, flush=True)
+    f = point_source(c.shape, tuple(s // 2 for s in c.shape), cfg["h"])
+    b = hs.rhs(torch.tensor(f, dtype=torch.complex128, device=dev))
+    u = torch.empty_like(b)
+    for _ in range(warmup):
+        hs.solve(b, tol=tol, maxit=200, out=u)
+    torch.cuda.synchronize()
+    its = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, it, rr = hs.solve(b, tol=tol, maxit=200, out=u)
+        its += it
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dof = cfg["n"] ** 3
+    out = {"workload": cfg["workload"], "value": dof * its / dt, "unit": UNIT, "solve_s": dt / steps,
+           "setup_s": setup_s, "iterations": it, "relres": rr, "dof_interior": dof, "unknowns": int(c.size),
+           "pivot_growth": hs.pivot_growth, "precision": "mixed (complex64 factors on FP32 MFMA, complex128 FGMRES)"}
+    if profile:
+        hs.profile(True)
+        for cls in CLASSES:
+            hs.profile_read(cls)
+        for _ in range(steps):
+            hs.solve(b, tol=tol, maxit=200, out=u)
+        torch.cuda.synchronize()
+        cl = {cls: hs.profile_read(cls) for cls in CLASSES}
+        hs.profile(False)
+        out["kernel_ms_per_solve"] = {k: v[0] / steps for k, v in cl.items()}
+        ms, n, by = cl["stage"]
+        out["stage"] = {"launch_groups": n, "avg_us": ms * 1e3 / max(n, 1), "alg_bytes_per_stage": by / max(n, 1),
+                        "achieved_gbs": (by / max(n, 1)) / (ms * 1e-3 / max(n, 1)) / 1e9 if n else 0.0}
+    out["u"] = u
+    out["hs"] = hs
+    return out
+
+
 def gpu_run(cfg, c, f, precision, steps, warmup, tol, profile=False):
     """Setup once, then time ``steps`` complete solves after ``warmup`` ones.
     With ``profile`` the same solves are repeated with the library bracketing
@@ -389,6 +462,7 @@ def main():
     ap.add_argument("--c3-sources", type=int, default=64)
     ap.add_argument("--c3-only", action="store_true",
                     help="time only the group workload (no config-2 runs, no CPU baseline)")
+    ap.add_argument("--c4-only", action="store_true", help="time only the 3-D workload")
     ap.add_argument("--c3-graph", choices=("both", "off", "on"), default="both",
                     help="group solves eager (off), with the preconditioner captured in a graph (on), or both")
     ap.add_argument("--tile", type=int, default=0, help="right-hand-side tile (0: tuned)")
@@ -409,6 +483,14 @@ def main():
         sys.exit(2)
 
     c3_graphs = {"both": (False, True), "off": (False,), "on": (True,)}[args.c3_graph]
+    if args.c4_only:
+        r4 = c4_run(args.steps, args.warmup, args.tol)
+        r4.pop("u")
+        r4.pop("hs")
+        print(f"[bench] c4: setup {r4['setup_s']:.2f} s, solve {r4['solve_s'] * 1e3:.1f} ms, {r4['iterations']} "
+              f"iterations, {r4['value']:.3e} dof*iter/s", file=sys.stderr, flush=True)
+        print(json.dumps({"c4": r4}))
+        return
     if args.c3_only:
         out = {}
         for graph in c3_graphs:

@@ -197,5 +197,7 @@ hsp_status d3_smooth(hsp_ctx* C, const cd* r, cd* x, int steps, hipStream_t s);
 hsp_status d3_sweep(hsp_ctx* C, const cd* f, cd* u, hipStream_t s);
 hsp_status d3_slab_solve(hsp_ctx* C, int j, const cd* b, cd* x, hipStream_t s);
 void d3_info(const hsp_ctx* C, hsp_info* info);
+// Reports a failed stage launch since the last check.
+hsp_status d3_check(hsp_ctx* C);
 
 }  // namespace hsp

@@ -202,7 +202,8 @@ struct Stage3 {
   cf* ys;
   const cf* factors;
 };
-void launch_stage3(const Stage3& st, hipStream_t s);
+// Enqueues the stage (one launch per block step); returns the launch status.
+hipError_t launch_stage3(const Stage3& st, hipStream_t s);
 
 }  // namespace d3
 }  // namespace hsp

@@ -34,6 +34,7 @@ struct D3Ctx {
   int n_max = 0, nl_max = 0;
   cf* factors = nullptr;
   std::vector<double> stage_bytes;  // algorithmic bytes per stage
+  hipError_t launch_err = hipSuccess;  // first failed launch of a stage (reported by the next call)
   // workspace offsets
   size_t o_fA[3], o_fB[3], o_ib[3], o_k2n, o_fk2c, o_fcoef;
   size_t o_cA[3], o_cB[3], o_ck2c, o_ccoef;
@@ -52,6 +53,9 @@ void destroy_d3(D3Ctx* d) { delete d; }
 namespace {
 
 constexpr int kMaxBlock3 = 1536;  // unknowns per y-plane of a slab (panel rows: 1024 in registers, 512 in LDS)
+// zeroed tail of the factor array: the substitutions read whole 128-entry
+// groups per lane, past the end of the last row
+constexpr size_t kFacTail = 128 * 24;
 
 inline size_t blk_elems(int n) { return (size_t)2 * n * n + (size_t)n * (n + (n & 1)); }
 
@@ -171,7 +175,7 @@ hsp_status plan3(const hsp_grid* g, int J, const hsp_options* o, D3Ctx& D, Plan&
   D.o_slabB = c.take(D.n_slabA * sizeof(cd));
   D.o_xmap = c.take(D.n_xmap * sizeof(int));
   D.o_slabs = c.take(J * sizeof(d3::Slab3));
-  D.o_fac = c.take(D.n_fac * sizeof(cf));
+  D.o_fac = c.take((D.n_fac + kFacTail) * sizeof(cf));
   D.o_setup = c.take(d3::setup3_scratch_bytes(J, D.n_max));
   D.o_status = c.take(64);
   D.o_growth = c.take((size_t)J * sizeof(double));
@@ -289,7 +293,8 @@ void run_sweep3(hsp_ctx* C, const cf* f, cf* u, hipStream_t s) {
     S.ys = C->at<float>(D.o_ys);
     S.factors = D.factors;
     prof_begin(C, HSP_PROF_STAGE, s);
-    d3::launch_stage3(S, s);
+    const hipError_t e = d3::launch_stage3(S, s);
+    if (e != hipSuccess && D.launch_err == hipSuccess) D.launch_err = e;
     prof_end(C, HSP_PROF_STAGE, s, D.stage_bytes[k]);
   }
 }
@@ -584,6 +589,8 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
   Su.status = C->raw<int>(D.o_status);
   Su.dbg_singular = debug_knobs().singular_slab;
   CHK(hipMemsetAsync(Su.status, 0, sizeof(int), s));
+  // every factor entry (row padding and the tail included) starts at zero
+  CHK(hipMemsetAsync(D.factors, 0, (D.n_fac + kFacTail) * sizeof(cf), s));
   CHK(hipMemsetAsync(Su.gmax, 0, (size_t)J * 2 * sizeof(double), s));
   d3::launch_factor3(Su, s);
   double* growth = C->raw<double>(D.o_growth);
@@ -730,7 +737,7 @@ hsp_status d3_sweep(hsp_ctx* C, const cd* f, cd* u, hipStream_t s) {
   run_sweep3(C, fin, uo, s);
   launch_convert<double, float>(uo, u, nd, 0, s);
   HIPCHK(hipGetLastError());
-  return HSP_OK;
+  return d3_check(C);
 }
 
 hsp_status d3_slab_solve(hsp_ctx* C, int j, const cd* b, cd* x, hipStream_t s) {
@@ -759,10 +766,21 @@ hsp_status d3_slab_solve(hsp_ctx* C, int j, const cd* b, cd* x, hipStream_t s) {
   S.fs = C->at<float>(D.o_fs);
   S.ys = C->at<float>(D.o_ys);
   S.factors = D.factors;
-  d3::launch_stage3(S, s);
+  const hipError_t e = d3::launch_stage3(S, s);
+  if (e != hipSuccess) return fail(HSP_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
   launch_convert<double, float>(uo, x, n, 0, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));  // the task descriptor is host stack memory
+  return HSP_OK;
+}
+
+hsp_status d3_check(hsp_ctx* C) {
+  D3Ctx& D = *C->d3;
+  if (D.launch_err != hipSuccess) {
+    const hipError_t e = D.launch_err;
+    D.launch_err = hipSuccess;
+    return fail(HSP_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
+  }
   return HSP_OK;
 }
 

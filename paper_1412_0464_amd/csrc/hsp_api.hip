@@ -1160,6 +1160,7 @@ hsp_status hsp_apply_precond(hsp_handle C, const void* r, void* z, void* stream)
   if (!C || !r || !z || r == z) return fail(HSP_EINVAL, "null or aliased argument");
   precond(C, (const cd*)r, (cd*)z, S_(stream));
   HIPCHK(hipGetLastError());
+  if (C->d3) return d3_check(C);
   return HSP_OK;
 }
 
@@ -1298,6 +1299,10 @@ hsp_status hsp_solve(hsp_handle C, const void* b_in, void* u_out, double tol, in
   const double rr = std::sqrt(std::max(hn.re, 0.0)) / bnorm;
   if (conj_transpose) launch_convert<double, double>(x, x, n, 1, s);
   HIPCHK(hipGetLastError());
+  if (C->d3) {
+    const hsp_status st3 = d3_check(C);
+    if (st3 != HSP_OK) return st3;
+  }
   if (iters) *iters = it;
   if (relres) *relres = rr;
   if (!done && rr > tol) return fail(HSP_ENOCONV, "maxit reached before the tolerance");

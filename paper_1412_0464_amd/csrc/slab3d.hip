@@ -37,6 +37,7 @@ constexpr int kNB = 32;        // panel width
 constexpr int kPanelT = 1024;  // threads of the panel kernel
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 inline int nblk(size_t n, int t = 256) { return (int)std::min<size_t>((n + t - 1) / t, (size_t)1 << 20); }
 
@@ -491,83 +492,92 @@ __global__ void __launch_bounds__(256) k3s_prep(Stage3 st) {
   st.fs[(size_t)blockIdx.y * m2 * padded(st.n_max) + (size_t)t * padded(st.n_max) + q] = cvt<float>(v);
 }
 
-// Dense matrix-vector products of one block step for every task.  The input
-// vector (length nin) is staged in LDS; each wavefront forms two rows, its
-// lanes reading consecutive pairs of complex entries of a row.
-template <bool FWD>
-__global__ void __launch_bounds__(256) k3s_step(Stage3 st, int t) {
-  const TaskDev tk = st.tasks[blockIdx.y];
-  const Slab3 sl = st.slabs[tk.slab];
-  const int n = sl.n, m2 = st.G.m2;
-  const int i0 = blockIdx.x * 8;
-  if (i0 >= n) return;
-  if (!FWD && t == m2 - 1) return;  // x_{m2-1} = y_{m2-1}
-  const int ldv = padded(st.n_max);
-  const cf* fs = st.fs + (size_t)blockIdx.y * m2 * ldv;
-  cf* ys = st.ys + (size_t)blockIdx.y * m2 * ldv;
-  __shared__ __align__(16) cf vin[2 * 2048 + 4];
-  const int tid = threadIdx.x;
-  int nin;
-  const cf* Wr;
-  size_t ldw;
-  if (FWD) {
-    // [f_t ; y_{t-1}] against [G_t | M_t]
-    const int pn = padded(n);
-    nin = t > 0 ? 2 * n : n;
-    for (int e = tid; e < n; e += 256) {
-      vin[e] = fs[(size_t)t * ldv + e];
-      if (t > 0) vin[n + e] = ys[(size_t)(t - 1) * ldv + e];
-    }
-    (void)pn;
-    Wr = Wblk(st.factors, sl, t);
-    ldw = (size_t)2 * n;
-  } else {
-    nin = n;
-    for (int e = tid; e < n; e += 256) vin[e] = ys[(size_t)(t + 1) * ldv + e];
-    Wr = Wblk(st.factors, sl, t) + (size_t)2 * n * n;
-    ldw = padded(n);
-  }
-  if (tid < 4) vin[nin + tid] = mk<float>(0, 0);
-  __syncthreads();
-  const int lane = tid & 63, wv = tid >> 6;
-  const int r0 = i0 + 2 * wv;
-  float ar0 = 0, ai0 = 0, ar1 = 0, ai1 = 0;
-  const bool ok0 = r0 < n, ok1 = r0 + 1 < n;
-  const float4* w0 = reinterpret_cast<const float4*>(Wr + (size_t)(ok0 ? r0 : 0) * ldw);
-  const float4* w1 = reinterpret_cast<const float4*>(Wr + (size_t)(ok1 ? r0 + 1 : 0) * ldw);
-  const float4* vv = reinterpret_cast<const float4*>(vin);
-  const int npair = (nin + 1) / 2;  // the row start is 16-byte aligned; an odd tail reads a zero
-  for (int c = lane; c < npair; c += 64) {
-    const float4 x = vv[c];
-    if (ok0) {
-      const float4 a = w0[c];
-      ar0 += a.x * x.x - a.y * x.y + a.z * x.z - a.w * x.w;
-      ai0 += a.x * x.y + a.y * x.x + a.z * x.w + a.w * x.z;
-    }
-    if (ok1) {
-      const float4 a = w1[c];
-      ar1 += a.x * x.x - a.y * x.y + a.z * x.z - a.w * x.w;
-      ai1 += a.x * x.y + a.y * x.x + a.z * x.w + a.w * x.z;
+// One block step of the substitutions of every task (one launch per step:
+// the steps depend on each other through the whole vector y_{t-1} or
+// x_{t+1}).  Each wavefront forms one row, four rows per workgroup; every
+// lane issues all of its loads of the row (pairs of complex entries, 16
+// bytes each) at once, before the input vector is staged in LDS, so that a
+// step keeps its whole factor block in flight.
+//   forward  (FWD): y_t = [G_t | M_t] [f_t ; y_{t-1}]
+//   backward:       x_t = y_t - E_t x_{t+1}   (in place over y_t)
+constexpr int kRowsPerBlock = 4;
+
+// Pairs c < npair of the row (pair c = entries 2c, 2c + 1; an odd row
+// length reads one entry past the row, which meets a zero of the staged
+// input vector).
+template <int NP>
+__device__ __forceinline__ void load_row(floatx4 (&a)[NP], const cf* row, int npair, int lane) {
+  const floatx4* w = reinterpret_cast<const floatx4*>(row) + lane;
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+    a[k] = (lane + 64 * k < npair) ? __builtin_nontemporal_load(w + 64 * k) : floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+template <int NP>
+__device__ __forceinline__ cf row_dot(const floatx4 (&a)[NP], const cf* vin, int npair, int lane) {
+  const floatx4* vv = reinterpret_cast<const floatx4*>(vin) + lane;
+  float ar = 0, ai = 0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    if (lane + 64 * k < npair) {
+      const floatx4 x = vv[64 * k];
+      ar += a[k].x * x.x - a[k].y * x.y + a[k].z * x.z - a[k].w * x.w;
+      ai += a[k].x * x.y + a[k].y * x.x + a[k].z * x.w + a[k].w * x.z;
     }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    ar0 += __shfl_xor(ar0, off, 64);
-    ai0 += __shfl_xor(ai0, off, 64);
-    ar1 += __shfl_xor(ar1, off, 64);
-    ai1 += __shfl_xor(ai1, off, 64);
+    ar += __shfl_xor(ar, off, 64);
+    ai += __shfl_xor(ai, off, 64);
   }
-  if (lane < 2) {
-    const int r = r0 + lane;
-    if (r < n) {
-      const float ar = lane ? ar1 : ar0, ai = lane ? ai1 : ai0;
-      cf* y = ys + (size_t)t * ldv + r;
-      if (FWD) {
-        *y = mk<float>(ar, ai);
-      } else {
-        const cf o = *y;
-        *y = mk<float>(o.re - ar, o.im - ai);
-      }
+  return mk<float>(ar, ai);
+}
+
+// NP: pairs of complex entries per lane and row (rows of up to 128 NP
+// entries: [G_t | M_t] has 2n, E_t has n).
+template <bool FWD, int NP>
+__global__ void __launch_bounds__(256) k3s_step(Stage3 st, int t) {
+  const TaskDev tk = st.tasks[blockIdx.y];
+  const Slab3 sl = st.slabs[tk.slab];
+  const int n = sl.n, m2 = st.G.m2;
+  const int i0 = blockIdx.x * kRowsPerBlock;
+  if (i0 >= n) return;
+  const int ldv = padded(st.n_max);
+  const cf* fs = st.fs + (size_t)blockIdx.y * m2 * ldv;
+  cf* ys = st.ys + (size_t)blockIdx.y * m2 * ldv;
+  __shared__ __align__(16) cf vin[128 * NP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = i0 + wv;
+  const bool ok = r < n;
+  const int rr = ok ? r : 0;
+  floatx4 a[NP];
+  const int nin = (FWD && t > 0) ? 2 * n : n;
+  const int npair = (nin + 1) / 2;
+  if (FWD)
+    load_row(a, Wblk(st.factors, sl, t) + (size_t)rr * 2 * n, npair, lane);
+  else
+    load_row(a, Wblk(st.factors, sl, t) + (size_t)2 * n * n + (size_t)rr * padded(n), npair, lane);
+  for (int e = tid; e < 2 * npair; e += 256) {
+    cf v = mk<float>(0, 0);
+    if (FWD) {
+      if (e < n)
+        v = fs[(size_t)t * ldv + e];
+      else if (e < 2 * n && t > 0)
+        v = ys[(size_t)(t - 1) * ldv + e - n];
+    } else if (e < n) {
+      v = ys[(size_t)(t + 1) * ldv + e];
+    }
+    vin[e] = v;
+  }
+  __syncthreads();
+  const cf d = row_dot(a, vin, npair, lane);
+  if (lane == 0 && ok) {
+    cf* y = ys + (size_t)t * ldv + r;
+    if (FWD) {
+      *y = d;
+    } else {
+      const cf o = *y;
+      *y = mk<float>(o.re - d.re, o.im - d.im);
     }
   }
 }
@@ -636,16 +646,38 @@ void finish_growth3(const Setup3& Su, double* growth, hipStream_t s) {
   hipLaunchKernelGGL(k3_growth, dim3((Su.nslabs + 63) / 64), dim3(64), 0, s, Su, growth);
 }
 
-void launch_stage3(const Stage3& st, hipStream_t s) {
-  if (st.ntasks < 1) return;
+hipError_t launch_stage3(const Stage3& st, hipStream_t s) {
+  if (st.ntasks < 1) return hipSuccess;
   const size_t cnt = (size_t)st.G.m2 * st.n_max;
   const int m2 = st.G.m2;
   hipLaunchKernelGGL(k3s_prep, dim3(nblk(cnt), st.ntasks), dim3(256), 0, s, st);
-  const int rb = (st.n_max + 7) / 8;
-  for (int t = 0; t < m2; ++t) hipLaunchKernelGGL(k3s_step<true>, dim3(rb, st.ntasks), dim3(256), 0, s, st, t);
-  for (int t = m2 - 2; t >= 0; --t) hipLaunchKernelGGL(k3s_step<false>, dim3(rb, st.ntasks), dim3(256), 0, s, st, t);
+  const dim3 grd((st.n_max + kRowsPerBlock - 1) / kRowsPerBlock, st.ntasks);
+  // pairs per lane: n_max (forward rows of 2 n_max entries), n_max / 2 (backward)
+  const int npf = (st.n_max + 63) / 64, npb = (st.n_max + 127) / 128;
+#define FWD_STEPS(NP)                                                                                 \
+  for (int t = 0; t < m2; ++t) hipLaunchKernelGGL((k3s_step<true, NP>), grd, dim3(256), 0, s, st, t)
+#define BWD_STEPS(NP)                     \
+  for (int t = m2 - 2; t >= 0; --t) hipLaunchKernelGGL((k3s_step<false, NP>), grd, dim3(256), 0, s, st, t)
+  if (npf <= 8)
+    FWD_STEPS(8);
+  else if (npf <= 16)
+    FWD_STEPS(16);
+  else if (npf <= 20)
+    FWD_STEPS(20);
+  else
+    FWD_STEPS(24);
+  if (npb <= 4)
+    BWD_STEPS(4);
+  else if (npb <= 8)
+    BWD_STEPS(8);
+  else
+    BWD_STEPS(12);
+#undef FWD_STEPS
+#undef BWD_STEPS
   hipLaunchKernelGGL(k3s_fin, dim3(nblk(cnt), st.ntasks), dim3(256), 0, s, st);
+  return hipGetLastError();
 }
+
 
 }  // namespace d3
 }  // namespace hsp
