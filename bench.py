@@ -260,30 +260,40 @@ def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile
 C3_GRIDS = [(255, 12.0, 8), (511, 10.0, 16), (767, 9.0, 24), (1023, 8.0, 32)]
 
 
-def c3_run(steps, warmup, tol, nsrc=64, graph=False):
-    """The batched multi-frequency workload: one seeded layered medium on a
-    10.24 km square sampled on four grids (255^2 .. 1023^2 interior nodes +
-    16 PML cells), one frequency per grid (8-12 points per wavelength at
-    1.5 km/s, higher frequencies on finer grids), nsrc point sources per
-    grid; all 4 x nsrc right-hand sides solved to tol in one group (every
-    aligned sweep step is one launch pair over all grids)."""
-    import torch
-    from paper_1412_0464_amd import Group, Helmholtz
+def c3_inputs(nsrc=64):
+    """The batched multi-frequency workload's inputs: one seeded layered
+    medium on a 10.24 km square sampled on four grids (255^2 .. 1023^2
+    interior nodes + 16 PML cells), one frequency per grid (8-12 points per
+    wavelength at 1.5 km/s, higher frequencies on finer grids), nsrc point
+    sources per grid at seeded interior positions.  Returns a list of dicts
+    (n, w, h, omega, J, c, sources)."""
     from synth.media import layered_medium_2d, extend_into_pml, resample_nodes
-    dev = torch.device("cuda:0")
     L, w = 10.24, 16
     base = layered_medium_2d(1023, 1023, 1412046)
-    probs, Bs, dofs = [], [], []
+    out = []
     for n, ppw, J in C3_GRIDS:
         h = L / (n + 1)
         c = extend_into_pml(resample_nodes(base, n), w)
         om = 2 * np.pi * 1.5 / (ppw * h)
-        hs = Helmholtz(torch.tensor(c, device=dev), om, h, w, J, two_grid=True, precision="mixed", restart=40)
-        cfg = dict(w=w, h=h)
-        fs = sources(cfg, c.shape, nsrc, seed=1412049 + n)
-        Bs.append(torch.stack([hs.rhs(torch.tensor(f, dtype=torch.complex128, device=dev)) for f in fs]))
+        fs = sources(dict(w=w, h=h), c.shape, nsrc, seed=1412049 + n)
+        out.append(dict(n=n, w=w, h=h, omega=om, J=J, ppw=ppw, c=c, sources=fs))
+    return out
+
+
+def c3_run(steps, warmup, tol, nsrc=64, graph=False):
+    """All 4 x nsrc right-hand sides of c3_inputs solved to tol in one group
+    (every aligned sweep step is one launch pair over all grids)."""
+    import torch
+    from paper_1412_0464_amd import Group, Helmholtz
+    dev = torch.device("cuda:0")
+    probs, Bs, dofs = [], [], []
+    for q in c3_inputs(nsrc):
+        hs = Helmholtz(torch.tensor(q["c"], device=dev), q["omega"], q["h"], q["w"], q["J"], two_grid=True,
+                       precision="mixed", restart=40)
+        Bs.append(torch.stack([hs.rhs(torch.tensor(f, dtype=torch.complex128, device=dev)) for f in q["sources"]]))
         probs.append(hs)
-        dofs.append(n * n)
+        dofs.append(q["n"] * q["n"])
+    w = 16
     grp = Group(probs, restart=40)
     for _ in range(warmup):
         grp.solve(Bs, tol=tol, maxit=200, graph=graph)
@@ -416,25 +426,76 @@ def gpu_run(cfg, c, f, precision, steps, warmup, tol, profile=False):
     return res
 
 
+def _host_info():
+    """Host facts for the CPU baseline: logical CPUs, the CPUs this process
+    may run on, the CPU model and the BLAS thread pools."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        info["blas_threads"] = {d.get("internal_api", "?"): d.get("num_threads") for d in threadpool_info()}
+    except Exception:  # noqa: BLE001 - informational only
+        pass
+    return info
+
+
 def cpu_baseline(cfg, c, f, iters, tol):
     """The CPU reference implementation (oracle), untuned, on a bounded
     sample of the same workload: its full setup, then ``iters`` FGMRES
-    iterations of the same solve.  Single-threaded (SciPy sparse kernels and
-    SuperLU are; BLAS is pinned to one thread)."""
-    from threadpoolctl import threadpool_limits
+    iterations of the same solve.  The thread pools are left at their
+    defaults; SciPy's sparse products and SuperLU run on one thread, so the
+    threads actually used are measured as CPU time / wall time."""
     from oracle.problem import Problem2D
     dof = cfg["n"] ** 2
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        P = Problem2D(c, cfg["omega"], cfg["h"], cfg["w"], S_outer=cfg.get("S_outer"), c_pml=cfg.get("c_pml"),
-                      J=cfg["J"], w_dd=4, two_grid=cfg["two_grid"])
-        t1 = time.perf_counter()
-        _, it, hist, _ = P.solve(f, tol=tol, maxit=iters)
-        t2 = time.perf_counter()
-    return {"value": dof * it / (t2 - t1), "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"full setup ({t1 - t0:.1f} s) + {it} FGMRES iterations of the same solve "
-                      f"({t2 - t1:.1f} s); value = interior dof x iterations / iteration time",
-            "setup_s": t1 - t0, "s_per_iter": (t2 - t1) / max(it, 1)}
+    c0 = time.process_time()
+    t0 = time.perf_counter()
+    P = Problem2D(c, cfg["omega"], cfg["h"], cfg["w"], S_outer=cfg.get("S_outer"), c_pml=cfg.get("c_pml"),
+                  J=cfg["J"], w_dd=4, two_grid=cfg["two_grid"])
+    t1 = time.perf_counter()
+    c1 = time.process_time()
+    _, it, hist, _ = P.solve(f, tol=tol, maxit=iters)
+    t2 = time.perf_counter()
+    c2 = time.process_time()
+    used = (c2 - c1) / max(t2 - t1, 1e-9)
+    out = {"value": dof * it / (t2 - t1), "unit": UNIT, "cores": max(1, int(round(used))), "kind": "oracle",
+           "sample": f"full setup ({t1 - t0:.1f} s) + {it} FGMRES iterations of the same solve "
+                     f"({t2 - t1:.1f} s); value = interior dof x iterations / iteration time",
+           "setup_s": t1 - t0, "s_per_iter": (t2 - t1) / max(it, 1),
+           "threads_used_cpu_over_wall": {"setup": (c1 - c0) / max(t1 - t0, 1e-9), "iterations": used}}
+    out.update(_host_info())
+    return out
+
+
+def oracle_check(cfg, c, fs, U, sampled):
+    """Relative L2 error of sampled GPU solutions (batched, mixed precision)
+    against the oracle's direct solution of the same FP64 system (sparse LU
+    of the fine operator), computed outside the timed region."""
+    import scipy.sparse.linalg as spla
+    from oracle import discretization as D
+    N = cfg["n"] + 1 + 2 * cfg["w"]
+    cp = float(c.mean()) if not cfg.get("c_pml") else cfg["c_pml"]
+    S_o = cfg.get("S_outer") or 5.0 * cfg["w"]
+    ax = D.uniform_axis(N, cfg["h"], cfg["w"], S_o, cp)
+    t0 = time.perf_counter()
+    lu = spla.splu(D.fd5_matrix(ax, ax, cfg["omega"] ** 2 / c ** 2, cfg["omega"]).tocsc())
+    scale = D.fd5_rhs_scale(ax, ax, cfg["omega"])
+    errs = {}
+    for j in sampled:
+        x = lu.solve((scale * fs[j]).ravel())
+        errs[str(j)] = float(np.linalg.norm(U[j].ravel() - x) / np.linalg.norm(x))
+    return {"kind": "oracle direct solve (SuperLU of the FP64 fine operator)", "sources": list(sampled),
+            "rel_l2_error": errs, "max_rel_l2_error": max(errs.values()), "oracle_s": time.perf_counter() - t0}
 
 
 def c3_report(args, graph):
@@ -458,7 +519,12 @@ def main():
                     help="skip the batched run with the Arnoldi basis in complex64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
-    ap.add_argument("--c3", action="store_true", help="also time the batched multi-frequency group workload")
+    ap.add_argument("--no-c3", action="store_true", help="skip the batched multi-frequency group workload")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 3-D workload")
+    ap.add_argument("--no-fp64-batched", action="store_true",
+                    help="skip the plain FP64 batched run (same batch, restart, tile and chunk)")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the error of sampled solutions against the oracle's direct solve")
     ap.add_argument("--c3-sources", type=int, default=64)
     ap.add_argument("--c3-only", action="store_true",
                     help="time only the group workload (no config-2 runs, no CPU baseline)")
@@ -557,7 +623,8 @@ def main():
                                       recorded_traffic("matvec", bat["tile"], len(fs)))
     out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
     out["config"]["profiled_solve_s"] = bat["profiled_solve_s"]
-    Ub = None if args.no_fp64 else bat["U"][0].cpu().numpy()
+    samp = [0, len(fs) // 2, len(fs) - 1]
+    Ub = {j: bat["U"][j].cpu().numpy() for j in samp}
     bat_tile = bat["tile"]
     del bat
     if not args.no_krylov_fp32:
@@ -570,6 +637,16 @@ def main():
                                       "iterations_min": min(kits), "iterations_max": max(kits),
                                       "relres_max": max(bk["relres"]), "rhs_tile": bk["tile"]}
         del bk
+    if not args.no_fp64_batched:
+        bf = gpu_run_batch(cfg, c, fs, "fp64", args.steps, args.warmup, args.tol, tile=bat_tile, chunk=args.chunk)
+        fits = bf["iters"]
+        print(f"[bench] batched fp64: solve {bf['solve_s'] * 1e3:.1f} ms, iterations {min(fits)}..{max(fits)}, "
+              f"max relres {max(bf['relres']):.2e}", file=sys.stderr, flush=True)
+        out["fp64_batched"] = {"value": dof * bf["total_iters"] / bf["time_s"], "solve_s": bf["solve_s"],
+                               "setup_s": bf["setup_s"], "iterations_min": min(fits), "iterations_max": max(fits),
+                               "relres_max": max(bf["relres"]), "rhs_tile": bf["tile"], "chunk": args.chunk,
+                               "speedup_mixed_over_fp64_same_batch": bf["solve_s"] / out["config"]["solve_s"]}
+        del bf
     if not args.no_fp64:
         fp = gpu_run(cfg, c, fs[0], "fp64", args.steps, args.warmup, args.tol)
         print(f"[bench] plain fp64, one source: setup {fp['setup_s']:.3f} s, solve {fp['solve_s'] * 1e3:.2f} ms, "
@@ -577,9 +654,7 @@ def main():
         uf = fp["u"].cpu().numpy()
         out["fp64"] = {"value": dof * fp["total_iters"] / fp["time_s"], "solve_s": fp["solve_s"],
                        "setup_s": fp["setup_s"], "iterations": fp["iters"], "relres": fp["relres"],
-                       "batched_mixed_vs_fp64_rel_l2_source0": float(np.linalg.norm(Ub - uf) / np.linalg.norm(uf)),
-                       "speedup_batched_mixed_over_fp64_per_source":
-                           fp["solve_s"] / out["config"]["solve_s_per_source"]}
+                       "batched_mixed_vs_fp64_rel_l2_source0": float(np.linalg.norm(Ub[0] - uf) / np.linalg.norm(uf))}
         del fp
     if not args.no_single:
         sm = gpu_run(cfg, c, fs[0], "mixed", args.steps, args.warmup, args.tol, profile=True)
@@ -593,13 +668,26 @@ def main():
                                "stage_frac_hbm": (s_b / max(s_n, 1)) / (s_ms * 1e-3 / max(s_n, 1)) / 1e9
                                / HBM_PEAK_GBS,
                                "kernel_ms_per_solve": {k: v[0] / args.steps for k, v in scl.items()}}
+        if "fp64" in out:
+            out["fp64"]["speedup_single_mixed_over_fp64"] = out["fp64"]["solve_s"] / sm["solve_s"]
         del sm
-    if args.c3:
+    if not args.no_c3:
         for graph in c3_graphs:
             out["c3_graph" if graph else "c3"] = c3_report(args, graph)
+    if not args.no_c4:
+        r4 = c4_run(args.steps, args.warmup, args.tol)
+        r4.pop("u")
+        r4.pop("hs")
+        print(f"[bench] c4: setup {r4['setup_s']:.2f} s, solve {r4['solve_s'] * 1e3:.1f} ms, {r4['iterations']} "
+              f"iterations, {r4['value']:.3e} dof*iter/s", file=sys.stderr, flush=True)
+        out["c4"] = r4
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, c, fs[0], args.cpu_iters, args.tol)
+        if Ub is not None and not args.no_oracle_check:
+            print("[bench] sampled batched solutions against the oracle's direct solve ...", file=sys.stderr,
+                  flush=True)
+            out["cpu_baseline"]["oracle_check"] = oracle_check(cfg, c, fs, Ub, [0, len(fs) // 2, len(fs) - 1])
     print(json.dumps(out))
 
 
