@@ -175,6 +175,58 @@ class SweepDD:
         self.forward_sweep(u, g, jm + 1, J, Bf)
         return u
 
+    def nx_cells(self, ncell):
+        """Groups of the partial sweeps (Sec. 2.2, SweepingPrecNX): boundary
+        subdomains j_cell,m = round(m (J + 1) / N_cell) for 0 < m < N_cell,
+        with j_cell,0 = 0 and j_cell,N_cell = J + 1 (the paper writes -1 for
+        j_cell,0, which would start the first sweep at subdomain 0; read as
+        0), and the centre j_mid,m = floor((j_cell,m-1 + j_cell,m + 1) / 2)
+        of the subdomains strictly between two boundaries.  N_cell = 1 gives
+        the X-sweep's j_mid.  Every group needs at least one subdomain."""
+        J, N = self.J, ncell
+        if N < 1 or 2 * N - 1 > J:
+            raise ValueError("NX-sweep needs 1 <= N_cell and 2 N_cell - 1 <= J")
+        jc = [0] + [(m * (J + 1) + N // 2) // N for m in range(1, N)] + [J + 1]
+        if any(jc[m] - jc[m - 1] < 2 for m in range(1, N + 1)):
+            raise ValueError("a group of the NX-sweep has no subdomain")
+        jm = [None] + [(jc[m - 1] + jc[m] + 1) // 2 for m in range(1, N + 1)]
+        return jc, jm
+
+    def apply_nx(self, f, ncell):
+        """SweepingPrecNX: X-sweeps over N_cell groups of subdomains, coupled
+        through the boundary subdomains between the groups.  The groups are
+        independent within each half (the partial sweeps are meant to run in
+        parallel), so the order taken is: the boundary subdomains'
+        MidSolveOut, the sweeps of every group and its MidSolveIn; the
+        residual; every group's MidSolveOut and outward sweeps; then the
+        boundary subdomains' MidSolveIn, which needs the sweeps of both
+        neighbouring groups.  Buffer B_{2m-1} carries the forward data of
+        group m, B_{2m} its backward data."""
+        f = f.reshape(self.n1, self.n2)
+        u = np.zeros_like(f, dtype=complex)
+        jc, jm = self.nx_cells(ncell)
+        N = ncell
+        fwd_in = [None] * (N + 2)   # B_{2m-1} entering group m from the left
+        bwd_in = [None] * (N + 2)   # B_{2m} entering group m from the right
+        for m in range(1, N):       # boundary subdomains, first half
+            fo, bo = self.mid_solve_out(u, f, jc[m])
+            fwd_in[m + 1] = fo
+            bwd_in[m] = bo
+        for m in range(1, N + 1):
+            B1 = self.forward_sweep(u, f, jc[m - 1] + 1, jm[m] - 1, fwd_in[m])
+            B2 = self.backward_sweep(u, f, jc[m] - 1, jm[m] + 1, bwd_in[m])
+            self.mid_solve_in(u, f, jm[m], B1, B2)
+        g = self.residual(f, u)
+        left_of = [None] * (N + 2)  # forward data arriving at boundary j_cell,m
+        right_of = [None] * (N + 2)  # backward data arriving at boundary j_cell,m
+        for m in range(1, N + 1):
+            fo, bo = self.mid_solve_out(u, g, jm[m])
+            right_of[m - 1] = self.backward_sweep(u, g, jm[m] - 1, jc[m - 1] + 1, bo)
+            left_of[m] = self.forward_sweep(u, g, jm[m] + 1, jc[m] - 1, fo)
+        for m in range(1, N):       # boundary subdomains, second half
+            self.mid_solve_in(u, g, jc[m], left_of[m], right_of[m])
+        return u
+
     # ---- written layer ranges (for the partition check) -------------------
     def written_ranges(self, kind):
         """Layer ranges (a~+1..b~) written by each solve of one preconditioner

@@ -100,7 +100,7 @@ def make_sweep(level, J, w, strength, c_pml, w_outer):
 class Problem2D:
     def __init__(self, c, omega, h, w_outer, S_outer=None, c_pml=None, J=4, w_dd=4,
                  S_dd=None, fine="fd5", two_grid=False, nu=3, omega_jac=0.8,
-                 sweep="x", coarse="sweep"):
+                 sweep="x", coarse="sweep", ncell=2):
         c = np.asarray(c, dtype=float)
         wx, wy = (w_outer, w_outer) if np.isscalar(w_outer) else tuple(w_outer)
         N1, N2 = c.shape[0] + 1, c.shape[1] + 1
@@ -135,14 +135,26 @@ class Problem2D:
                 self.dd = None
             else:
                 self.dd = make_sweep(self.coarse, J, w_dd, S_dd, self.c_pml, wx)
-                csolve = self.dd.apply_x if sweep == "x" else self.dd.apply_ud
+                csolve = self._sweep_map(sweep, ncell)
             self.tg = TG.TwoGrid(self.A, P, Ac, lambda r: csolve(r).ravel(), nu, omega_jac)
             self.precond = self.tg.apply
         else:
             self.coarse = None
             self.dd = make_sweep(self.fine, J, w_dd, S_dd, self.c_pml, wx)
-            ap = self.dd.apply_x if sweep == "x" else self.dd.apply_ud
+            ap = self._sweep_map(sweep, ncell)
             self.precond = lambda r: ap(r).ravel()
+
+    def _sweep_map(self, sweep, ncell):
+        """The sweep of Table 3: 'x' (SweepingPrecX), 'ud' (SweepingPrecUD)
+        or 'nx' (SweepingPrecNX over ncell groups)."""
+        if sweep == "x":
+            return self.dd.apply_x
+        if sweep == "ud":
+            return self.dd.apply_ud
+        if sweep == "nx":
+            self.dd.nx_cells(ncell)  # validates the groups
+            return lambda f: self.dd.apply_nx(f, ncell)
+        raise ValueError(f"unknown sweep {sweep}")
 
     def rhs(self, f):
         return (self.rhs_scale * np.asarray(f).reshape(self.shape)).ravel()
