@@ -45,7 +45,7 @@ typedef enum {
   HSP_EDEVICE = -5     /* a HIP runtime call failed                        */
 } hsp_status;
 
-enum { HSP_SWEEP_X = 0, HSP_SWEEP_UD = 1 };
+enum { HSP_SWEEP_X = 0, HSP_SWEEP_UD = 1, HSP_SWEEP_NX = 2 };
 enum { HSP_FP64 = 0, HSP_MIXED = 1 };
 
 typedef struct hsp_ctx* hsp_handle;
@@ -74,7 +74,11 @@ typedef struct hsp_options {
   double S_dd;      /* DD-PML strength; <= 0 selects 5 * w_dd                  */
   int nu;           /* omega-Jacobi pre- and post-smoothing steps             */
   double omega_jac; /* Jacobi weight                                           */
-  int sweep;        /* HSP_SWEEP_X (SweepingPrecX) or HSP_SWEEP_UD            */
+  int sweep;        /* HSP_SWEEP_X (SweepingPrecX), HSP_SWEEP_UD
+                       (SweepingPrecUD) or HSP_SWEEP_NX (SweepingPrecNX:
+                       partial X-sweeps over ncell groups of slabs coupled
+                       through the boundary slabs between them; the groups'
+                       sweeps share every stage launch)                       */
   int precision;    /* HSP_FP64: everything complex128.  HSP_MIXED: smoother,
                        slab factors and sweeps complex64; the FGMRES Arnoldi
                        orthogonalisation, its residual, the coarse-grid
@@ -92,11 +96,17 @@ typedef struct hsp_options {
                        true residual misses tol gets another restart cycle).
                        Halves the orthogonalisation traffic; the basis is then
                        orthogonal to complex64 accuracy only.                 */
+  int ncell;        /* HSP_SWEEP_NX: number of groups N_cell (1..16; 1 is the
+                       X-sweep).  Boundary slabs j_cell,m = round(m (J+1) /
+                       N_cell), 0 < m < N_cell, group centres j_mid,m =
+                       floor((j_cell,m-1 + j_cell,m + 1) / 2) with j_cell,0 =
+                       0 and j_cell,N_cell = J + 1; every group needs a slab
+                       (HSP_EINVAL otherwise).  Ignored by the other sweeps. */
 } hsp_options;
 
 /* Fills *opt with: fine_stencil 5, two_grid 0, w_dd 4, S_dd 0 (= 5 w_dd),
  * nu 3, omega_jac 0.8 (Sec. 6.1, 2-D experiments), sweep X, precision FP64, restart 40,
- * chunk 0 (automatic), krylov_fp32 0. */
+ * chunk 0 (automatic), krylov_fp32 0, ncell 2. */
 hsp_status hsp_default_options(hsp_options* opt);
 
 /* Bytes of device workspace that hsp_setup needs for this geometry, slab

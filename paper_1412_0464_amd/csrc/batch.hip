@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
       cx<T> v = mk<T>(0, 0);
       if (c < nr) {
         if (tk.a < gl && gl <= tk.b) v = src[(size_t)(r0 + c) * A.ld + (size_t)(gl - 1) * n2 + t];
-        const GAS cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
+        const GAS cx<T>* bz = bufs + (size_t)(r0 + c) * A.nbuf * 2 * n2;
         cd acc = mk<double>(0, 0);
         for (int k2 = k; k2 < 4; ++k2) {
           if (slot_gl(k2) != gl) continue;
@@ -579,7 +579,7 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ seg
       const int gl = sd.x0 + ll;
       const cx<T> x = xv[q];
       if (tk.at < gl && gl <= tk.bt) u[uid[q]] = uv[q] + x;
-      GAS cx<T>* bz = bufs + (size_t)(r0 + c) * 4 * n2;
+      GAS cx<T>* bz = bufs + (size_t)(r0 + c) * A.nbuf * 2 * n2;
       if (tk.t2) {
         GAS cx<T>* Bo = bz + (size_t)tk.bout_f * 2 * n2;
         if (gl == tk.beta_out) Bo[t] = x;

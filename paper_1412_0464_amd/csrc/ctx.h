@@ -90,6 +90,7 @@ struct Plan {
   std::vector<int> beta, bt, x0, x1;
   int nl_max = 0;
   int chunk = 0, nchunk = 0;              // parallel substitution: chunk length m, count P
+  int nbuf = 2, maxtask = 2;              // transmission buffers; most slab solves in one stage
   size_t tsize = 16;                      // bytes per preconditioner complex
   int m = 0;                              // FGMRES restart
   // workspace offsets
@@ -178,9 +179,15 @@ namespace hsp {
 void prof_begin(hsp_ctx* C, int cls, hipStream_t s);
 void prof_end(hsp_ctx* C, int cls, hipStream_t s, double bytes);
 
-// Task list and stages of the sweep of Table 3 (X or UD) from the partition
-// in C->P (beta, bt, x0, x1) and C->J, C->opt.sweep.
+// Task list and stages of the sweep of Table 3 (X, UD or NX) from the
+// partition in C->P (beta, bt, x0, x1) and C->J, C->opt.sweep, C->opt.ncell.
 void build_schedule(hsp_ctx* C);
+// Groups of the NX-sweep: jc[0..N] (jc[0] = 0, jc[N] = J + 1) and the centres
+// jm[1..N] (jm[0] unused); HSP_EINVAL when a group would hold no slab.
+hsp_status nx_cells(int J, int N, std::vector<int>& jc, std::vector<int>& jm);
+// Transmission buffers and the largest number of slab solves in one stage of
+// the sweep selected by the options (HSP_EINVAL for a bad NX grouping).
+hsp_status sweep_shape(int J, const hsp_options* o, int* nbuf, int* maxtask);
 
 // ---- the three-dimensional path (hsp3d.hip) --------------------------------
 hsp_status d3_workspace_size(const hsp_grid* g, int J, const hsp_options* o, size_t* bytes);

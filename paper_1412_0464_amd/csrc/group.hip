@@ -30,8 +30,9 @@ namespace {
 
 constexpr int kMaxTile = 8;
 
-// (task, tile) slots of a stage, times the tile: >= 2 ceil(R/rb) rb for every rb <= 8
-inline size_t batch_slots(int R) { return 2 * (size_t)(R + kMaxTile - 1); }
+// (task, tile) slots of a stage, times the tile: >= maxtask ceil(R/rb) rb for
+// every rb <= 8 (maxtask: the most slab solves in one stage of the sweep)
+inline size_t batch_slots(int R, int maxtask) { return (size_t)maxtask * (size_t)(R + kMaxTile - 1); }
 
 // Layout of one member's slice of a group workspace.
 struct BatchLayout {
@@ -48,7 +49,7 @@ BatchLayout batch_layout(const Plan& P, int R, int m, bool v32) {
   B.m = m;
   Carver c;
   const size_t nf = (size_t)P.nf1 * P.nf2, nd = (size_t)P.dd_n1 * P.dd_n2, T = P.tsize;
-  const size_t slots = batch_slots(R);
+  const size_t slots = batch_slots(R, P.maxtask);
   B.o_xa = c.take(R * nf * T);
   B.o_xb = c.take(R * nf * T);
   B.o_res = c.take(P.two_grid ? R * nf * sizeof(cd) : 0);
@@ -57,7 +58,7 @@ BatchLayout batch_layout(const Plan& P, int R, int m, bool v32) {
   B.o_swf = c.take(R * nd * T);
   B.o_swg = c.take(R * nd * T);
   B.o_swu = c.take(R * nd * T);
-  B.o_swB = c.take(R * 4 * (size_t)P.dd_n2 * T);
+  B.o_swB = c.take(R * (size_t)P.nbuf * 2 * (size_t)P.dd_n2 * T);
   B.o_scr = c.take(slots * P.dd_n2 * P.nl_max * T);
   B.o_red = c.take(slots * 2 * P.nchunk * P.nl_max * T);
   B.o_ctr = c.take(2 * slots * sizeof(int));
@@ -232,6 +233,7 @@ hsp_status build_segments(Group& G, const std::vector<int>& nact, int rb, hipStr
       q.m = P.chunk;
       q.P = P.nchunk;
       q.item0 = S.nitems;
+      q.nbuf = P.nbuf;
       S.nitems += q.ntasks * q.P * q.ntiles;
       S.nl = std::max(S.nl, sg.nl);
       G.segs_host.push_back(q);
@@ -523,7 +525,7 @@ hsp_status check_ws(const Group& G, void* ws, size_t bytes) {
 hsp_status zero_counters(const Group& G, hipStream_t s, bool by_kernel = false) {
   for (const Member& mb : G.mem) {
     if (mb.R <= 0) continue;
-    const size_t n = 2 * batch_slots(mb.R);  // even: cleared as n/2 complex64 zeros
+    const size_t n = 2 * batch_slots(mb.R, mb.C->P.maxtask);  // even: cleared as n/2 complex64 zeros
     if (by_kernel)
       launch_zero<float>(mptr<cf>(mb, mb.B.o_ctr), n / 2, s);
     else

@@ -72,7 +72,8 @@ hsp_status validate3(const hsp_grid* g, int J, const hsp_options* o) {
   if (o->restart < 1) return fail(HSP_EINVAL, "restart must be >= 1");
   if (o->fine_stencil != 7 && o->fine_stencil != 27)
     return fail(HSP_EINVAL, "fine_stencil must be 7 or 27 in three dimensions");
-  if (o->sweep != HSP_SWEEP_X && o->sweep != HSP_SWEEP_UD) return fail(HSP_EINVAL, "bad sweep");
+  if (o->sweep != HSP_SWEEP_X && o->sweep != HSP_SWEEP_UD && o->sweep != HSP_SWEEP_NX)
+    return fail(HSP_EINVAL, "bad sweep");
   if (o->precision != HSP_MIXED)
     return fail(HSP_EINVAL, "the 3-D path factors its slabs in complex64: precision must be HSP_MIXED");
   if (o->krylov_fp32 != 0) return fail(HSP_EINVAL, "krylov_fp32 applies to the 2-D batched solvers only");
@@ -124,6 +125,8 @@ hsp_status plan3(const hsp_grid* g, int J, const hsp_options* o, D3Ctx& D, Plan&
   if (D.n_max > kMaxBlock3)
     return fail(HSP_EINVAL, "slab planes of " + std::to_string(D.n_max) + " unknowns exceed " +
                                 std::to_string(kMaxBlock3) + ": use more slabs or a smaller z extent");
+  st = sweep_shape(J, o, &P.nbuf, &P.maxtask);
+  if (st != HSP_OK) return st;
   P.nl_max = D.nl_max;
   P.two_grid = D.two_grid;
   P.tsize = sizeof(cf);
@@ -186,9 +189,9 @@ hsp_status plan3(const hsp_grid* g, int J, const hsp_options* o, D3Ctx& D, Plan&
   D.o_swf = c.take(nd * sizeof(cf));
   D.o_swg = c.take(nd * sizeof(cf));
   D.o_swu = c.take(nd * sizeof(cf));
-  D.o_bufs = c.take(4 * pl * sizeof(cf));
-  D.o_fs = c.take(2 * slot * sizeof(cf));
-  D.o_ys = c.take(2 * slot * sizeof(cf));
+  D.o_bufs = c.take((size_t)P.nbuf * 2 * pl * sizeof(cf));
+  D.o_fs = c.take((size_t)P.maxtask * slot * sizeof(cf));
+  D.o_ys = c.take((size_t)P.maxtask * slot * sizeof(cf));
   D.o_tgx0 = c.take(nf * sizeof(cf));
   D.o_tgx1 = c.take(nf * sizeof(cf));
   if (D.two_grid) {

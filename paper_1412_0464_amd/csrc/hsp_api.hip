@@ -56,7 +56,8 @@ hsp_status validate(const hsp_grid* g, int J, const hsp_options* o) {
   if (o->nu < 0) return fail(HSP_EINVAL, "nu must be >= 0");
   if (o->restart < 1) return fail(HSP_EINVAL, "restart must be >= 1");
   if (o->fine_stencil != 5 && o->fine_stencil != 9) return fail(HSP_EINVAL, "fine_stencil must be 5 or 9");
-  if (o->sweep != HSP_SWEEP_X && o->sweep != HSP_SWEEP_UD) return fail(HSP_EINVAL, "bad sweep");
+  if (o->sweep != HSP_SWEEP_X && o->sweep != HSP_SWEEP_UD && o->sweep != HSP_SWEEP_NX)
+    return fail(HSP_EINVAL, "bad sweep");
   if (o->precision != HSP_FP64 && o->precision != HSP_MIXED) return fail(HSP_EINVAL, "bad precision");
   if (!std::isfinite(o->omega_jac)) return fail(HSP_EINVAL, "bad omega_jac");
   if (o->chunk < 0 || o->chunk > kMaxChunk) return fail(HSP_EINVAL, "chunk must be in 0..64");
@@ -79,6 +80,32 @@ std::vector<int> partition(int n1, int w_outer, int J) {
   for (int j = 1; j < J; ++j) b[j] = w_outer + (int)(((long long)j * n_int + J / 2) / J);
   b[J] = n1;
   return b;
+}
+
+hsp_status nx_cells(int J, int N, std::vector<int>& jc, std::vector<int>& jm) {
+  if (N < 1 || N > 16) return fail(HSP_EINVAL, "ncell must be in 1..16");
+  if (2 * N - 1 > J) return fail(HSP_EINVAL, "the NX-sweep needs J >= 2 ncell - 1 slabs");
+  jc.assign(N + 1, 0);
+  jm.assign(N + 1, 0);
+  jc[N] = J + 1;
+  for (int m = 1; m < N; ++m) jc[m] = (m * (J + 1) + N / 2) / N;
+  for (int m = 1; m <= N; ++m) {
+    if (jc[m] - jc[m - 1] < 2) return fail(HSP_EINVAL, "a group of the NX-sweep holds no slab");
+    jm[m] = (jc[m - 1] + jc[m] + 1) / 2;
+  }
+  return HSP_OK;
+}
+
+hsp_status sweep_shape(int J, const hsp_options* o, int* nbuf, int* maxtask) {
+  *nbuf = 2;
+  *maxtask = 2;
+  if (o->sweep != HSP_SWEEP_NX) return HSP_OK;
+  std::vector<int> jc, jm;
+  hsp_status st = nx_cells(J, o->ncell, jc, jm);
+  if (st != HSP_OK) return st;
+  *nbuf = std::max(2, 2 * o->ncell);
+  *maxtask = std::max(2, 2 * o->ncell);
+  return HSP_OK;
 }
 
 void coarse_map(int N, int w, std::vector<int>& ifp, std::vector<char>& ref) {
@@ -152,6 +179,8 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   }
   P.chunk = std::min(P.chunk, P.dd_n2);
   P.nchunk = (P.dd_n2 + P.chunk - 1) / P.chunk;
+  st = sweep_shape(J, o, &P.nbuf, &P.maxtask);
+  if (st != HSP_OK) return st;
 
   // ---- workspace layout
   Carver c;
@@ -202,7 +231,7 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
     P.n_xmap += (size_t)(nl + 1);
     P.n_fac += slab_factor_elems(nl, P.dd_n2);
   }
-  P.o_red = c.take((size_t)2 * 2 * P.nchunk * P.nl_max * P.tsize);
+  P.o_red = c.take((size_t)P.maxtask * 2 * P.nchunk * P.nl_max * P.tsize);
   P.o_ctr = c.take(64 * sizeof(int));
   P.o_slabs = c.take(J * sizeof(SlabDev));
   P.o_slabA = c.take(P.n_slabA * sizeof(cd));
@@ -219,8 +248,8 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   P.o_swf = c.take(nd * P.tsize);
   P.o_swg = c.take(nd * P.tsize);
   P.o_swu = c.take(nd * P.tsize);
-  P.o_swB = c.take((size_t)2 * 2 * P.dd_n2 * P.tsize);
-  P.o_swscr = c.take((size_t)2 * P.dd_n2 * P.nl_max * P.tsize);
+  P.o_swB = c.take((size_t)P.nbuf * 2 * P.dd_n2 * P.tsize);
+  P.o_swscr = c.take((size_t)P.maxtask * P.dd_n2 * P.nl_max * P.tsize);
   // two-grid vectors
   P.o_tgx0 = c.take(nf * P.tsize);
   P.o_tgx1 = c.take(nf * P.tsize);
@@ -268,7 +297,7 @@ void build_schedule(hsp_ctx* C) {
   std::vector<Stage>& S = C->stages;
   T.clear();
   S.clear();
-  bool written[2] = {false, false};
+  std::vector<char> written(std::max(2, P.nbuf), 0);
   auto blank = [](int j) {
     TaskDev t;
     std::memset(&t, 0, sizeof(t));
@@ -320,6 +349,90 @@ void build_schedule(hsp_ctx* C) {
     if (t.t2) written[t.bout_f] = true;
     if (t.t4) written[t.bout_b] = true;
   };
+  // MidSolveIn / MidSolveOut of Table 2 on slab j (buffers: forward and
+  // backward data in, or forward and backward data out)
+  auto midin = [&](int j, int src, int bf, int bb) {
+    TaskDev t = blank(j);
+    t.a = t.at = be[j - 1];
+    t.b = t.bt = bt[j];
+    t.t1 = (j > 1 && written[bf]) ? 1 : 0;
+    t.bin_f = bf;
+    t.beta_in = be[j - 1];
+    t.t3 = (j < J && written[bb]) ? 1 : 0;
+    t.bin_b = bb;
+    t.bt_in = bt[j];
+    t.src = src;
+    return t;
+  };
+  auto midout = [&](int j, int src, int bf, int bb) {
+    TaskDev t = blank(j);
+    t.a = t.at = bt[j - 1];
+    t.b = t.bt = be[j];
+    t.t2 = (j < J) ? 1 : 0;
+    t.bout_f = bf;
+    t.beta_out = be[j];
+    t.t4 = (j > 1) ? 1 : 0;
+    t.bout_b = bb;
+    t.bt_out = bt[j - 1];
+    t.src = src;
+    return t;
+  };
+  auto run_stage = [&](std::vector<TaskDev> ts) {
+    for (auto& t : ts) mark(t);
+    push_stage(ts);
+  };
+  if (C->opt.sweep == HSP_SWEEP_NX) {
+    // SweepingPrecNX: the X-sweeps of the N groups share every stage; the
+    // boundary slabs between the groups are solved first (on f) and last
+    // (on g).  Forward data of group m in buffer 2(m-1), backward data in
+    // 2(m-1)+1.
+    std::vector<int> jc, jm;
+    (void)nx_cells(J, C->opt.ncell, jc, jm);  // validated by the plan
+    const int N = C->opt.ncell;
+    auto BF = [](int m) { return 2 * (m - 1); };
+    auto BB = [](int m) { return 2 * (m - 1) + 1; };
+    {
+      std::vector<TaskDev> ts;
+      for (int m = 1; m < N; ++m) ts.push_back(midout(jc[m], 0, BF(m + 1), BB(m)));
+      run_stage(ts);
+    }
+    for (int st = 1;; ++st) {
+      std::vector<TaskDev> ts;
+      for (int m = 1; m <= N; ++m) {
+        if (jc[m - 1] + st <= jm[m] - 1) ts.push_back(fwd(jc[m - 1] + st, 0, BF(m)));
+        if (jc[m] - st >= jm[m] + 1) ts.push_back(bwd(jc[m] - st, 0, BB(m)));
+      }
+      if (ts.empty()) break;
+      run_stage(ts);
+    }
+    {
+      std::vector<TaskDev> ts;
+      for (int m = 1; m <= N; ++m) ts.push_back(midin(jm[m], 0, BF(m), BB(m)));
+      push_stage(ts);
+    }
+    S.push_back(Stage{1, 0, 0, 0, 0.0, 0.0});
+    std::fill(written.begin(), written.end(), 0);
+    {
+      std::vector<TaskDev> ts;
+      for (int m = 1; m <= N; ++m) ts.push_back(midout(jm[m], 1, BB(m), BF(m)));
+      run_stage(ts);
+    }
+    for (int st = 1;; ++st) {
+      std::vector<TaskDev> ts;
+      for (int m = 1; m <= N; ++m) {
+        if (jm[m] - st >= jc[m - 1] + 1) ts.push_back(bwd(jm[m] - st, 1, BF(m)));
+        if (jm[m] + st <= jc[m] - 1) ts.push_back(fwd(jm[m] + st, 1, BB(m)));
+      }
+      if (ts.empty()) break;
+      run_stage(ts);
+    }
+    {
+      std::vector<TaskDev> ts;
+      for (int m = 1; m < N; ++m) ts.push_back(midin(jc[m], 1, BB(m), BF(m + 1)));
+      push_stage(ts);
+    }
+    return;
+  }
   if (C->opt.sweep == HSP_SWEEP_UD) {
     for (int j = 1; j <= J; ++j) {
       TaskDev t = fwd(j, 0, 0);
@@ -356,7 +469,7 @@ void build_schedule(hsp_ctx* C) {
     push_stage({t});
   }
   S.push_back(Stage{1, 0, 0, 0, 0.0, 0.0});
-  written[0] = written[1] = false;
+  std::fill(written.begin(), written.end(), 0);
   {  // MidSolveOut: forward output -> buffer 1, backward output -> buffer 0
     TaskDev t = blank(jm);
     t.a = t.at = bt[jm - 1];
@@ -574,6 +687,7 @@ hsp_status hsp_default_options(hsp_options* o) {
   o->restart = 40;
   o->chunk = 0;
   o->krylov_fp32 = 0;
+  o->ncell = 2;
   return HSP_OK;
 }
 

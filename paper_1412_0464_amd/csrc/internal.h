@@ -144,10 +144,10 @@ void launch_stage(const TaskDev* tasks_dev, int ntasks, const SlabDev* slabs_dev
 // The same stage for many right-hand sides of several problems (batch.hip).
 // One segment per problem taking part in the launch: its tasks of this
 // stage, its level vectors f, g, u ([nact][ld], right-hand side z at offset
-// z ld, storage type of the launch), transmission buffers [nact][2][2][n2],
-// scratch 2 ceil(nact/rb) rb n2 nl_max, chunk tips / heads
-// 2 ceil(nact/rb) 2 P nl_max rb, counters 4 ceil(nact/rb) ints (zero
-// between launches).  Work items of a segment: (task, chunk, tile of rb
+// z ld, storage type of the launch), transmission buffers [nact][nbuf][2][n2],
+// scratch ntasks ceil(nact/rb) rb n2 nl_max, chunk tips / heads
+// ntasks ceil(nact/rb) 2 P nl_max rb, counters 2 ntasks ceil(nact/rb) ints
+// (zero between launches).  Work items of a segment: (task, chunk, tile of rb
 // right-hand sides); item0 is the segment's first item in the launch.
 struct BSeg {
   const TaskDev* tasks;
@@ -163,7 +163,7 @@ struct BSeg {
   int* counters;
   const cd* tcoef;  // transmission coefficients of the segment's first task
   size_t ld;
-  int ntasks, ntiles, nact, nl_max, m, P, item0, pad;
+  int ntasks, ntiles, nact, nl_max, m, P, item0, nbuf;  // nbuf: transmission buffers per right-hand side
 };
 // Incoming transmission terms of a task as a table, [4][n2][3] complex
 // double per task: slot k of the (up to) four incoming transmission layers

@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 _lib = None
 
 HSP_OK, HSP_EINVAL, HSP_ENOMEM, HSP_ESINGULAR, HSP_ENOCONV, HSP_EDEVICE = 0, -1, -2, -3, -4, -5
-SWEEP = {"x": 0, "ud": 1}
+SWEEP = {"x": 0, "ud": 1, "nx": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 
 
@@ -36,7 +36,7 @@ class HspOptions(ctypes.Structure):
     _fields_ = [("fine_stencil", ctypes.c_int), ("two_grid", ctypes.c_int), ("w_dd", ctypes.c_int),
                 ("S_dd", ctypes.c_double), ("nu", ctypes.c_int), ("omega_jac", ctypes.c_double),
                 ("sweep", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
-                ("chunk", ctypes.c_int), ("krylov_fp32", ctypes.c_int)]
+                ("chunk", ctypes.c_int), ("krylov_fp32", ctypes.c_int), ("ncell", ctypes.c_int)]
 
 
 class HspInfo(ctypes.Structure):
@@ -192,8 +192,8 @@ class Helmholtz:
     ``pml`` outer PML cells per side (int, or one per axis); the interior node
             counts follow from c.shape - 2*pml.
     Options follow hsp_options (fine_stencil, two_grid, w_dd, S_dd, nu,
-    omega_jac, sweep 'x'/'ud', precision 'fp64'/'mixed', restart, chunk,
-    krylov_fp32).  In 3-D the defaults are those of the paper's 3-D
+    omega_jac, sweep 'x'/'ud'/'nx', precision 'fp64'/'mixed', restart, chunk,
+    krylov_fp32, ncell).  In 3-D the defaults are those of the paper's 3-D
     experiments (Sec. 6.2): fine_stencil 7, w_dd 3, omega_jac 0.6, and the
     complex64 slab factors of precision 'mixed'.
     """
