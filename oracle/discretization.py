@@ -141,6 +141,27 @@ def outer_pml_sigma(x_lo, x_hi, width, strength, c_pml):
     return sig
 
 
+def sponge_profile(n_cells, h, width, beta_max):
+    """Sponge layers (Sec. 2.1): k is replaced by k (1 + i beta) with beta
+    continuous and quadratically increasing over ``width`` cells from each
+    end, beta = beta_max (dist / d)^2, d = width h.  Returns beta at the nodes
+    0..N of the axis (0 in the interior)."""
+    x = h * np.arange(n_cells + 1)
+    if width <= 0:
+        return np.zeros_like(x)
+    d = width * h
+    dist = np.maximum(np.maximum(d - x, x - (n_cells - width) * h), 0.0)
+    return beta_max * (dist / d) ** 2
+
+
+def sponge_beta_default(omega, c_ref, width, h):
+    """beta_max for which a wave crossing the layer once is damped by about
+    1e-2 (round trip 1e-4, the middle of the paper's 1e-2..1e-4): with
+    beta = beta_max (s/d)^2 the damping is exp(-k beta_max d / 3)."""
+    k = omega / c_ref
+    return 3.0 * np.log(100.0) / (k * width * h)
+
+
 def uniform_axis(n_cells, h, pml_cells, strength, c_pml):
     """Uniform axis with ``pml_cells`` outer PML cells on each side.  The PML
     onset is node ``pml_cells`` (and node N - pml_cells); d_pml = pml_cells*h."""
