@@ -58,6 +58,17 @@ typedef struct hsp_grid {
   int pml[3];       /* outer PML cells per side, per axis (>= 0)               */
   double S_outer;   /* outer PML strength S; <= 0 selects 5 * pml[0]           */
   double c_pml;     /* PML reference speed c_pml; <= 0 selects mean(c)        */
+  int sponge;       /* 0: the pml[a] outer cells are PML layers.  1 (2-D,
+                       fine_stencil 5): they are sponge layers instead
+                       (Sec. 2.1): no PML, k replaced by k (1 + i beta) with
+                       beta = beta_max (dist/d)^2 per axis (summed in the
+                       corners), beta_max = S_outer, or for S_outer <= 0 the
+                       value that damps a crossing wave by 1e-2 at c_pml
+                       (3 ln 100 / (k d), d the layer width).  With two_grid
+                       the coarse mesh then coarsens every cell (the two-grid
+                       method in absence of PML layers, Sec. 4: full
+                       weighting and linear interpolation), and the slab
+                       partition spreads over all layers.                   */
 } hsp_grid;
 
 /* Method parameters (Sec. 4, Sec. 6.1). */

@@ -163,6 +163,19 @@ __global__ void k_cell_coefs(const double* __restrict__ k2c, size_t n, double h_
   }
 }
 
+// Sponge layers (Sec. 2.1): k^2 -> k^2 (1 + i beta)^2 at the unknown nodes,
+// beta = bx[i] + by[k]; k2 holds the real part on return, k2i the imaginary.
+__global__ void k_sponge_k2(int n1, int n2, const double* __restrict__ bx, const double* __restrict__ by,
+                            double* __restrict__ k2, double* __restrict__ k2i) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= n2) return;
+  const size_t id = (size_t)i * n2 + k;
+  const double b = bx[i] + by[k], v = k2[id];
+  k2[id] = v * (1.0 - b * b);
+  k2i[id] = 2.0 * v * b;
+}
+
 __global__ void k_grad_m(int n1, int n2, double scale, const cd* __restrict__ ixn, const cd* __restrict__ iyn,
                          const cd* __restrict__ u, const cd* __restrict__ lam, double* __restrict__ g) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -600,6 +613,9 @@ void launch_cell_average(const double* k2n, int n1, int n2, const int* x0, const
                          const int* y0, const double* wy, int nc2, double* k2c, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_average, dim3((nc2 + 255) / 256, nc1), dim3(256), 0, s, k2n, n1, n2, x0, wx, y0, wy,
                      nc2, k2c);
+}
+void launch_sponge_k2(int n1, int n2, const double* bx, const double* by, double* k2, double* k2i, hipStream_t s) {
+  hipLaunchKernelGGL(k_sponge_k2, dim3((n2 + 255) / 256, n1), dim3(256), 0, s, n1, n2, bx, by, k2, k2i);
 }
 void launch_cell_coefs(const double* k2c, size_t ncell, double h_nom, double* coef, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_coefs, dim3(nblk(ncell)), dim3(256), 0, s, k2c, ncell, h_nom, coef);

@@ -88,6 +88,8 @@ using cf = cx<float>;
 // xmap (optional) maps the view's own x row (node i-1 for kind 5, cell p
 // for kind 9) to the row of k2 / coef; it lets a slab reuse the global
 // medium arrays with the k continuation of its added layers.
+// k2i (optional, same layout as k2): imaginary part of k^2 - the sponge
+// layers of Sec. 2.1 replace k by k (1 + i beta).
 // ---------------------------------------------------------------------------
 struct LevelDev {
   int kind;
@@ -100,7 +102,13 @@ struct LevelDev {
   const double* k2;
   const double* coef;
   const int* xmap;
+  const double* k2i;
 };
+
+// k^2 at entry idx of the medium arrays (complex inside sponge layers).
+__device__ __forceinline__ cd k2_at(const LevelDev& L, size_t idx) {
+  return mk<double>(L.k2[idx], L.k2i ? L.k2i[idx] : 0.0);
+}
 
 // Stencil coefficients of row (i, k) (1-based unknown node):
 // c[di+1][dk+1] multiplies u(i+di, k+dk).  Always computed in double.
@@ -111,7 +119,7 @@ __device__ __forceinline__ void stencil_coefs(const LevelDev& L, int i, int k, c
     for (int b = 0; b < 3; ++b) c[a][b] = mk<double>(0.0, 0.0);
   if (L.kind == 5) {
     const int row = L.xmap ? L.xmap[i - 1] : (i - 1);
-    const double k2 = L.k2[(size_t)row * L.n2 + (k - 1)];
+    const cd k2 = k2_at(L, (size_t)row * L.n2 + (k - 1));
     const cd ian = L.xB[i], ikn = L.yB[k];
     const cd w = -(L.xA[i - 1] * ikn), e = -(L.xA[i] * ikn);
     const cd s = -(L.yA[k - 1] * ian), n = -(L.yA[k] * ian);
@@ -131,7 +139,7 @@ __device__ __forceinline__ void stencil_coefs(const LevelDev& L, int i, int k, c
       const int ax = i - p, ay = k - q;          // corner of the node in the cell
       const int row = L.xmap ? L.xmap[p] : p;
       const size_t ci = (size_t)row * (L.n2 + 1) + q;
-      const double k2 = L.k2[ci];
+      const cd k2 = k2_at(L, ci);
       const double c1 = L.coef[3 * ci], c2 = L.coef[3 * ci + 1], c3 = L.coef[3 * ci + 2];
       const double I0 = 0.25 * c1, I1 = 0.125 * c2, I2 = 0.25 * (1.0 - c1 - c2);
       const double J0 = 0.5 * c3, J1 = 0.5 * (1.0 - c3);

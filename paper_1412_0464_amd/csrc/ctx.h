@@ -91,6 +91,8 @@ struct Plan {
   int nl_max = 0;
   int chunk = 0, nchunk = 0;              // parallel substitution: chunk length m, count P
   int nbuf = 2, maxtask = 2;              // transmission buffers; most slab solves in one stage
+  int sponge = 0;                         // outer layers are sponge layers (no PML)
+  size_t o_k2i = 0, o_bx = 0, o_by = 0, o_ck2ci = 0;  // sponge: imaginary k^2, beta per node
   size_t tsize = 16;                      // bytes per preconditioner complex
   int m = 0;                              // FGMRES restart
   // workspace offsets

@@ -78,6 +78,7 @@ hsp_status validate3(const hsp_grid* g, int J, const hsp_options* o) {
     return fail(HSP_EINVAL, "the 3-D path factors its slabs in complex64: precision must be HSP_MIXED");
   if (o->krylov_fp32 != 0) return fail(HSP_EINVAL, "krylov_fp32 applies to the 2-D batched solvers only");
   if (!std::isfinite(o->omega_jac)) return fail(HSP_EINVAL, "bad omega_jac");
+  if (g->sponge != 0) return fail(HSP_EINVAL, "sponge layers are implemented for 2-D problems");
   return HSP_OK;
 }
 

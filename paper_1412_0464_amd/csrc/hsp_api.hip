@@ -60,6 +60,8 @@ hsp_status validate(const hsp_grid* g, int J, const hsp_options* o) {
     return fail(HSP_EINVAL, "bad sweep");
   if (o->precision != HSP_FP64 && o->precision != HSP_MIXED) return fail(HSP_EINVAL, "bad precision");
   if (!std::isfinite(o->omega_jac)) return fail(HSP_EINVAL, "bad omega_jac");
+  if (g->sponge != 0 && g->sponge != 1) return fail(HSP_EINVAL, "sponge must be 0 or 1");
+  if (g->sponge && o->fine_stencil != 5) return fail(HSP_EINVAL, "sponge layers need fine_stencil 5");
   if (o->chunk < 0 || o->chunk > kMaxChunk) return fail(HSP_EINVAL, "chunk must be in 0..64");
   if (o->krylov_fp32 != 0 && o->krylov_fp32 != 1) return fail(HSP_EINVAL, "krylov_fp32 must be 0 or 1");
   if (o->krylov_fp32 && o->precision != HSP_MIXED)
@@ -134,14 +136,18 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   P.tsize = (o->precision == HSP_MIXED) ? sizeof(cf) : sizeof(cd);
   P.m = o->restart;
   int w_dd_outer;
+  P.sponge = g->sponge;
   if (P.two_grid) {
+    // cells that are not coarsened: the PML cells, none with sponge layers
+    const int cw[2] = {P.sponge ? 0 : g->pml[0], P.sponge ? 0 : g->pml[1]};
     for (int a = 0; a < 2; ++a) {
       const int N = a == 0 ? P.Nf1 : P.Nf2;
-      if ((N - 2 * g->pml[a]) % 2 != 0 || N - 2 * g->pml[a] < 2)
-        return fail(HSP_EINVAL, "two-grid needs an even, positive interior cell count per axis");
+      if ((N - 2 * cw[a]) % 2 != 0 || N - 2 * cw[a] < 2)
+        return fail(HSP_EINVAL, P.sponge ? "two-grid with sponge layers needs an even cell count per axis"
+                                         : "two-grid needs an even, positive interior cell count per axis");
     }
-    coarse_map(P.Nf1, g->pml[0], P.ifp1, P.ref1);
-    coarse_map(P.Nf2, g->pml[1], P.ifp2, P.ref2);
+    coarse_map(P.Nf1, cw[0], P.ifp1, P.ref1);
+    coarse_map(P.Nf2, cw[1], P.ifp2, P.ref2);
     P.nc1 = (int)P.ifp1.size() - 2;
     P.nc2 = (int)P.ifp2.size() - 2;
     P.dd_kind = 9;
@@ -152,7 +158,7 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
     P.dd_n1 = P.nf1;
     P.dd_n2 = P.nf2;
   }
-  w_dd_outer = g->pml[0];
+  w_dd_outer = P.sponge ? 0 : g->pml[0];  // sponge layers are ordinary layers of the partition
   if (P.dd_n1 - 2 * w_dd_outer < J) return fail(HSP_EINVAL, "too many slabs for the interior layers");
   P.beta = partition(P.dd_n1, w_dd_outer, J);
   P.bt = P.beta;
@@ -199,6 +205,11 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   }
   P.o_ixn = c.take((N1 + 1) * sizeof(cd));
   P.o_iyn = c.take((N2 + 1) * sizeof(cd));
+  if (P.sponge) {
+    P.o_k2i = c.take(nf * sizeof(double));
+    P.o_bx = c.take(P.nf1 * sizeof(double));
+    P.o_by = c.take(P.nf2 * sizeof(double));
+  }
   const int Nc1 = P.dd_n1 + 1, Nc2 = P.dd_n2 + 1;  // DD level cells
   if (P.two_grid) {
     P.o_cxA = c.take(Nc1 * sizeof(cd));
@@ -206,6 +217,7 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
     P.o_cyA = c.take(Nc2 * sizeof(cd));
     P.o_cyB = c.take(Nc2 * sizeof(cd));
     P.o_ck2c = c.take((size_t)Nc1 * Nc2 * sizeof(double));
+    if (P.sponge) P.o_ck2ci = c.take((size_t)Nc1 * Nc2 * sizeof(double));
     P.o_ccoef = c.take((size_t)Nc1 * Nc2 * 3 * sizeof(double));
     P.o_rx = c.take((size_t)P.nc1 * 3 * sizeof(int));
     P.o_rwx = c.take((size_t)P.nc1 * 3 * sizeof(double));
@@ -760,7 +772,7 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
     ax.x.resize(N + 1);
     for (int i = 0; i <= N; ++i) ax.x[i] = i * h;
     ax.h_nom = h;
-    if (w > 0) {
+    if (w > 0 && !P.sponge) {
       ax.sig.left = ax.sig.right = true;
       ax.sig.lo = w * h;
       ax.sig.hi = (N - w) * h;
@@ -794,6 +806,25 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
     up(P.o_iyn, iy.data(), iy.size() * sizeof(cd));
   }
   launch_k2_nodes(c_dev, nf, omega, C->raw<double>(P.o_k2n), s);
+  if (P.sponge) {
+    // beta per unknown node and axis: beta_max (dist / d)^2 inside the layers
+    auto beta_axis = [&](int N, int w, std::vector<double>& b) {
+      b.assign(N - 1, 0.0);
+      if (w <= 0) return;
+      const double d = w * h;
+      const double bmax = grid->S_outer > 0 ? grid->S_outer : 3.0 * std::log(100.0) / ((omega / C->c_pml) * d);
+      for (int i = 1; i < N; ++i) {
+        const double x = i * h;
+        const double dist = std::max(std::max(d - x, x - (N - w) * h), 0.0);
+        b[i - 1] = bmax * (dist / d) * (dist / d);
+      }
+    };
+    std::vector<double> bx, by;
+    beta_axis(P.Nf1, grid->pml[0], bx);
+    beta_axis(P.Nf2, grid->pml[1], by);
+    up(P.o_bx, bx.data(), bx.size() * sizeof(double));
+    up(P.o_by, by.data(), by.size() * sizeof(double));
+  }
   C->fine.kind = P.fine_kind;
   C->fine.n1 = P.nf1;
   C->fine.n2 = P.nf2;
@@ -803,6 +834,7 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
   C->fine.yA = C->at<double>(P.o_fyA);
   C->fine.yB = C->at<double>(P.o_fyB);
   C->fine.xmap = nullptr;
+  C->fine.k2i = nullptr;
   if (P.fine_kind == 5) {
     C->fine.k2 = C->raw<double>(P.o_k2n);
     C->fine.coef = nullptr;
@@ -870,6 +902,18 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
     launch_cell_average(C->raw<double>(P.o_k2n), P.nf1, P.nf2, C->raw<int>(P.o_avgx0), C->raw<double>(P.o_avgwx), Nc1,
                         C->raw<int>(P.o_avgy0), C->raw<double>(P.o_avgwy), Nc2, C->raw<double>(P.o_ck2c), s);
     launch_cell_coefs(C->raw<double>(P.o_ck2c), (size_t)Nc1 * Nc2, 2.0 * h, C->raw<double>(P.o_ccoef), s);
+    if (P.sponge) {
+      // the coefficients come from the real k^2; the operator takes the
+      // damped k^2 (1 + i beta)^2, averaged to the cells part by part
+      CHK(hipStreamSynchronize(s));  // beta arrays uploaded
+      launch_sponge_k2(P.nf1, P.nf2, C->raw<double>(P.o_bx), C->raw<double>(P.o_by), C->raw<double>(P.o_k2n),
+                       C->raw<double>(P.o_k2i), s);
+      launch_cell_average(C->raw<double>(P.o_k2n), P.nf1, P.nf2, C->raw<int>(P.o_avgx0), C->raw<double>(P.o_avgwx),
+                          Nc1, C->raw<int>(P.o_avgy0), C->raw<double>(P.o_avgwy), Nc2, C->raw<double>(P.o_ck2c), s);
+      launch_cell_average(C->raw<double>(P.o_k2i), P.nf1, P.nf2, C->raw<int>(P.o_avgx0), C->raw<double>(P.o_avgwx),
+                          Nc1, C->raw<int>(P.o_avgy0), C->raw<double>(P.o_avgwy), Nc2, C->raw<double>(P.o_ck2ci), s);
+      C->fine.k2i = C->raw<double>(P.o_k2i);
+    }
     C->coarse.kind = 9;
     C->coarse.n1 = P.nc1;
     C->coarse.n2 = P.nc2;
@@ -881,6 +925,7 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
     C->coarse.k2 = C->raw<double>(P.o_ck2c);
     C->coarse.coef = C->raw<double>(P.o_ccoef);
     C->coarse.xmap = nullptr;
+    C->coarse.k2i = P.sponge ? C->raw<double>(P.o_ck2ci) : nullptr;
     C->dd = C->coarse;
     // transfer maps
     auto rmaps = [](const std::vector<int>& ifp, const std::vector<char>& ref, int nc, std::vector<int>& ri,
@@ -938,6 +983,12 @@ hsp_status hsp_setup(const double* c_dev, double omega, const hsp_grid* grid, in
     C->tr.py = C->raw<int>(P.o_py);
     C->tr.pwy = C->raw<double>(P.o_pwy);
   } else {
+    if (P.sponge) {
+      CHK(hipStreamSynchronize(s));  // beta arrays uploaded
+      launch_sponge_k2(P.nf1, P.nf2, C->raw<double>(P.o_bx), C->raw<double>(P.o_by), C->raw<double>(P.o_k2n),
+                       C->raw<double>(P.o_k2i), s);
+      C->fine.k2i = C->raw<double>(P.o_k2i);
+    }
     dx = fx;
     dy = fy;
     C->dd = C->fine;
@@ -1235,6 +1286,7 @@ hsp_status hsp_slab_solve(hsp_handle C, int j, const void* b, void* x, void* str
 hsp_status hsp_gradient_accumulate(hsp_handle C, const void* u, const void* lam, double* g, void* stream) {
   if (!C || !u || !lam || !g) return fail(HSP_EINVAL, "null argument");
   if (C->d3) return fail(HSP_EINVAL, "the gradient is implemented for 2-D problems");
+  if (C->P.sponge) return fail(HSP_EINVAL, "the gradient is implemented for PML layers, not sponge layers");
   if (C->opt.fine_stencil != 5) return fail(HSP_EINVAL, "the gradient is implemented for the 5-point fine operator");
   if (!(C->grid.c_pml > 0)) return fail(HSP_EINVAL, "the gradient needs an explicit c_pml (not mean(c))");
   launch_grad_m(C->P.nf1, C->P.nf2, C->h * C->h * C->omega * C->omega, C->at<double>(C->P.o_ixn),

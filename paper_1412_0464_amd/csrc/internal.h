@@ -241,5 +241,8 @@ void launch_cell_average(const double* k2n, int n1, int n2, const int* x0, const
                          hipStream_t s);
 void launch_cell_coefs(const double* k2c, size_t ncell, double h_nom, double* coef,
                        hipStream_t s);
+// sponge layers: k2 -> real part of k2 (1 + i (bx[i] + by[k]))^2, k2i its
+// imaginary part, at the n1 x n2 unknown nodes
+void launch_sponge_k2(int n1, int n2, const double* bx, const double* by, double* k2, double* k2i, hipStream_t s);
 
 }  // namespace hsp

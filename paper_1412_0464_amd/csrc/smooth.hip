@@ -317,7 +317,10 @@ __global__ void __launch_bounds__(kPostThreads) k_smooth_post(LevelDev L, Transf
 
 }  // namespace
 
-bool smooth_fused_ok(const LevelDev& L, int nu) { return L.kind == 5 && L.xmap == nullptr && nu >= 1 && nu <= 3; }
+// (the fused kernels hold a real k^2 per node: no sponge layers)
+bool smooth_fused_ok(const LevelDev& L, int nu) {
+  return L.kind == 5 && L.xmap == nullptr && L.k2i == nullptr && nu >= 1 && nu <= 3;
+}
 
 template <class TR>
 void launch_smooth_pre(const LevelDev& L, int nu, double w, const cx<TR>* r, BIdx br, cf* xo, BIdx bxo, cd* res,

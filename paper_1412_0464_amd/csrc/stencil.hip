@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) k_stencil5(LevelDev L, int mode, const cx
     xe = ld<Ta>(x, ie);
   }
   const int row = L.xmap ? L.xmap[i - 1] : (i - 1);
-  const double k2 = L.k2[(size_t)row * n2 + (k - 1)];
+  const cd k2 = k2_at(L, (size_t)row * n2 + (k - 1));
   const cd ian = L.xB[i], ikn = L.yB[k];
   cd cw = -(L.xA[i - 1] * ikn), ce = -(L.xA[i] * ikn);
   cd cs = -(L.yA[k - 1] * ian), cn = -(L.yA[k] * ian);
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) k_stencil_multi(LevelDev L, int mode, con
 #pragma unroll
       for (int q = 0; q < 3; ++q) c[a][q] = mk<double>(0, 0);
     const int row = L.xmap ? L.xmap[i - 1] : (i - 1);
-    const double k2 = L.k2[(size_t)row * n2 + (k - 1)];
+    const cd k2 = k2_at(L, (size_t)row * n2 + (k - 1));
     const cd ian = L.xB[i], ikn = L.yB[k];
     const cd cw = -(L.xA[i - 1] * ikn), ce = -(L.xA[i] * ikn);
     const cd cs = -(L.yA[k - 1] * ian), cn = -(L.yA[k] * ian);

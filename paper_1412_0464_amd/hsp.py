@@ -29,7 +29,8 @@ class HspError(RuntimeError):
 
 class HspGrid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
-                ("pml", ctypes.c_int * 3), ("S_outer", ctypes.c_double), ("c_pml", ctypes.c_double)]
+                ("pml", ctypes.c_int * 3), ("S_outer", ctypes.c_double), ("c_pml", ctypes.c_double),
+                ("sponge", ctypes.c_int)]
 
 
 class HspOptions(ctypes.Structure):
@@ -143,8 +144,9 @@ def _vec(t, shape, name):
     return t
 
 
-def make_grid(n, h, pml, S_outer=0.0, c_pml=0.0):
-    """hsp_grid for 2 (len(n) == 2) or 3 dimensions."""
+def make_grid(n, h, pml, S_outer=0.0, c_pml=0.0, sponge=False):
+    """hsp_grid for 2 (len(n) == 2) or 3 dimensions; sponge=True makes the
+    outer layers sponge layers instead of PML."""
     g = HspGrid()
     d = len(n)
     if d not in (2, 3) or len(pml) != d:
@@ -156,6 +158,7 @@ def make_grid(n, h, pml, S_outer=0.0, c_pml=0.0):
     g.h = float(h)
     g.S_outer = float(S_outer)
     g.c_pml = float(c_pml)
+    g.sponge = int(bool(sponge))
     return g
 
 
@@ -190,7 +193,8 @@ class Helmholtz:
             (PML nodes included), shape (N1-1, N2-1) in 2-D or
             (N1-1, N2-1, N3-1) in 3-D.
     ``pml`` outer PML cells per side (int, or one per axis); the interior node
-            counts follow from c.shape - 2*pml.
+            counts follow from c.shape - 2*pml.  ``sponge=True``: these
+            cells are sponge layers instead (S_outer = beta at the edge).
     Options follow hsp_options (fine_stencil, two_grid, w_dd, S_dd, nu,
     omega_jac, sweep 'x'/'ud'/'nx', precision 'fp64'/'mixed', restart, chunk,
     krylov_fp32, ncell).  In 3-D the defaults are those of the paper's 3-D
@@ -198,7 +202,7 @@ class Helmholtz:
     complex64 slab factors of precision 'mixed'.
     """
 
-    def __init__(self, c, omega, h, pml, J, S_outer=0.0, c_pml=0.0, **opts):
+    def __init__(self, c, omega, h, pml, J, S_outer=0.0, c_pml=0.0, sponge=False, **opts):
         lib = load()
         if not (c.is_cuda and c.dtype == torch.float64 and c.is_contiguous() and c.dim() in (2, 3)):
             raise ValueError("c must be a contiguous 2-D or 3-D float64 CUDA tensor")
@@ -212,7 +216,7 @@ class Helmholtz:
         n = tuple(c.shape[a] - 2 * pml[a] for a in range(d))
         self.dim = d
         self.shape = tuple(c.shape)
-        self.grid = make_grid(n, h, pml, S_outer, c_pml)
+        self.grid = make_grid(n, h, pml, S_outer, c_pml, sponge)
         self.opts = make_options(**opts)
         self.J = int(J)
         S = ctypes.c_size_t()
