@@ -47,12 +47,13 @@ typedef enum {
 
 enum { HSP_SWEEP_X = 0, HSP_SWEEP_UD = 1, HSP_SWEEP_NX = 2 };
 enum { HSP_FP64 = 0, HSP_MIXED = 1 };
+enum { HSP_SLAB_AUTO = 0, HSP_SLAB_BLOCK = 1, HSP_SLAB_ND = 2 };
 
 typedef struct hsp_ctx* hsp_handle;
 
 /* Geometry of the fine mesh. */
 typedef struct hsp_grid {
-  int dim;          /* 2 (other values: HSP_EINVAL)                           */
+  int dim;          /* 2 or 3 (other values: HSP_EINVAL)                      */
   int n[3];         /* interior nodes per axis, x first                       */
   double h;         /* mesh spacing                                            */
   int pml[3];       /* outer PML cells per side, per axis (>= 0)               */
@@ -113,11 +114,26 @@ typedef struct hsp_options {
                        floor((j_cell,m-1 + j_cell,m + 1) / 2) with j_cell,0 =
                        0 and j_cell,N_cell = J + 1; every group needs a slab
                        (HSP_EINVAL otherwise).  Ignored by the other sweeps. */
+  int slab_factor;  /* factorization of the 3-D slabs (the paper uses a
+                       sparse multifrontal solver, Sec. 5):
+                       HSP_SLAB_BLOCK  block tridiagonal along y with dense
+                                       (n_l m3)^2 blocks, inverted on the
+                                       matrix cores; the substitutions take
+                                       one step per y-plane;
+                       HSP_SLAB_ND     nested dissection of the (y, z) plane
+                                       of the slab (multifrontal; dense fronts
+                                       eliminated on the matrix cores); the
+                                       substitutions take one step per level
+                                       of the dissection and about a third of
+                                       the factor bytes at 79^2 planes;
+                       HSP_SLAB_AUTO   nested dissection in 3-D.
+                       2-D slabs are always block tridiagonal (HSP_SLAB_ND:
+                       HSP_EINVAL).                                          */
 } hsp_options;
 
 /* Fills *opt with: fine_stencil 5, two_grid 0, w_dd 4, S_dd 0 (= 5 w_dd),
  * nu 3, omega_jac 0.8 (Sec. 6.1, 2-D experiments), sweep X, precision FP64, restart 40,
- * chunk 0 (automatic), krylov_fp32 0, ncell 2. */
+ * chunk 0 (automatic), krylov_fp32 0, ncell 2, slab_factor HSP_SLAB_AUTO. */
 hsp_status hsp_default_options(hsp_options* opt);
 
 /* Bytes of device workspace that hsp_setup needs for this geometry, slab
@@ -202,6 +218,7 @@ typedef struct hsp_info {
   int dim;              /* 2 or 3                                          */
   int n_fine_z;         /* 3-D: fine unknowns along z (0 in 2-D)            */
   int n_coarse_z;       /* 3-D with two-grid: coarse unknowns along z       */
+  int slab_factor;      /* HSP_SLAB_BLOCK or HSP_SLAB_ND (the one in use)   */
 } hsp_info;
 hsp_status hsp_get_info(hsp_handle hd, hsp_info* info);
 

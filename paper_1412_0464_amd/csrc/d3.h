@@ -10,6 +10,9 @@
 // values of the level vector.
 #pragma once
 
+#include <string>
+#include <vector>
+
 #include "common.h"
 #include "internal.h"
 
@@ -163,11 +166,35 @@ void launch_cell_average3(const double* k2n, const int m[3], const int* x0[3], c
 // cell coefficients c1..c5 of Table (b) at 1/G = h_nom k / (2 pi)
 void launch_cell_coefs3(const double* k2c, size_t ncell, double h_nom, double* coef, hipStream_t s);
 
+// ---- dense partial Gauss-Jordan elimination (slab3d.hip) -------------------
+// One job: the nf x nf complex64 matrix F (row stride ld) whose first s
+// columns are eliminated with partial pivoting among rows 0..s-1:
+//   [F11 F12; F21 F22]  ->  [F11^-1  F11^-1 F12; -F21 F11^-1  F22 - F21 F11^-1 F12]
+// (the row interchanges leave the first s columns permuted: column j of the
+// result is column col[j] of F after the elimination).  s = nf inverts F.
+// Scratch per job: piv, col (s ints), brow (32 x ld: pivot rows of the
+// current panel), spr (32 x 32: the scaled pivot row of every step of the
+// current panel, replayed on the rows >= s).
+struct GJob {
+  cf* F;
+  int nf, s, ld;
+  int* piv;
+  int* col;
+  cf* brow;
+  cf* spr;
+};
+// Eliminates the first s columns of every job of the device array (the
+// launches cover all jobs; s_max, b_max and nf_max bound s, nf - s and nf over
+// the jobs).  status[0] |= 1 for a zero or non-finite pivot.
+void launch_gauss_jordan(const GJob* jobs, int njobs, int s_max, int b_max, int nf_max, int* status, hipStream_t s);
+constexpr int kGJMaxPivots = 1536;  // s <= 1024 rows in registers + 512 in LDS
+
 // ---- slab factorization and stage (slab3d.hip) ----------------------------
 // Setup of all slabs, block by block along y (see slab3d.hip).  Scratch:
 // per slab n_max^2 complex64 (S), n_max 27 complex64 (block coefficients),
-// 32 n_max complex64 (pivot rows), n_max ints (pivots); status[0] |= 1 for
-// a zero or non-finite pivot; growth[slab] = max |S_t| / max |D_t|.
+// 32 n_max complex64 (pivot rows), 32 x 32 complex64 (panel steps), n_max
+// ints (pivots, column permutation), one GJob; status[0] |= 1 for a zero or
+// non-finite pivot; growth[slab] = max |S_t| / max |D_t|.
 struct Setup3 {
   const Slab3* slabs;  // device array
   int nslabs, n_max, m2;
@@ -175,15 +202,123 @@ struct Setup3 {
   cf* S;       // [slab][n_max][n_max]
   cf* coef;    // [slab][n_max][27]
   cf* brow;    // [slab][32][n_max]
+  cf* spr;     // [slab][32][32]
   int* piv;    // [slab][n_max]
   int* col;    // [slab][n_max]
+  GJob* jobs;  // [slab]
   double* gmax;  // [slab][2] running max |D|^2, |S|^2
   int* status;
   int dbg_singular;
 };
 size_t setup3_scratch_bytes(int nslabs, int n_max);
+// Fills the job table of Su (host array jobs_host, uploaded by the caller
+// to Su.jobs) for the slab sizes n[slab].
+void setup3_jobs(const Setup3& Su, const int* n, GJob* jobs_host);
 void launch_factor3(const Setup3& Su, hipStream_t s);
 void finish_growth3(const Setup3& Su, double* growth, hipStream_t s);
+
+// ---- nested-dissection slab factorization (nd3d.hip) ----------------------
+// The (y, z) plane of a slab is cut recursively by lines of nodes (the
+// longer side of a rectangle is halved; rectangles of at most kNDLeaf nodes
+// are leaves), every cut running through all n_l x-layers.  Each tree node
+// is a front: its separator (the cut line, or the whole leaf rectangle) and
+// its ring (the nodes of the ancestors' separators next to its rectangle:
+// the in-domain nodes of the one-node border around it).  With a stencil
+// that couples nodes at most one apart in y and z, the separator couples
+// only to its own region and to the ring, so eliminating the fronts from
+// the leaves up is block Gaussian elimination in a nested-dissection order
+// (multifrontal: the Schur complement of a front is added into its
+// parent's front).  Front variables: the separator's n_l ns unknowns
+// (x_l ns + point) first, then the ring's n_l nb (x_l nb + point).
+constexpr int kNDLeaf = 9;         // nodes per leaf rectangle (at most)
+constexpr int kNDMaxFront = 2048;  // unknowns per front
+
+struct NDGeom {       // one front of the plane (shared by all slabs)
+  int ns, nb;         // separator and ring nodes
+  int pt_off;         // pts[pt_off + P], P < ns + nb: plane index y m3 + z
+  int y0, z0, h, w;   // the front's rectangle
+  int lmap_off;       // lmap[lmap_off + (y - y0 + 1)(w + 2) + z - z0 + 1]: front point of node (y, z) or -1
+  int child[2];       // child fronts (-1: none)
+  int chmap_off[2];   // chmap[chmap_off[c] + P]: ring index in child c of front point P, or -1
+  int cmap_off;       // cmap[cmap_off + q]: parent front point of ring point q
+  int level;          // depth from the root (0)
+};
+
+// Per slab and front: factor offsets (complex64 elements) of
+//   GN = [F11^-1 ; -F21 F11^-1]   (nf x s, row stride s + (s & 1)) and
+//   E  = F11^-1 F12               (s x b, row stride b + (b & 1)),
+// the offset of the front's update vector (b entries) in a task's scratch,
+// and (setup only) its dense front matrix.
+struct NDFront {
+  size_t gn, e, u;
+  cf* F;
+};
+struct NDJob {
+  int slab, front;
+};
+
+// Device view of the plan for the stage kernels.  Items are (front, first
+// row) pairs, four rows per workgroup: forward items cover the nf rows of
+// GN, backward items the s rows of E (fronts with a ring); the tables give
+// (offset, count) per slab and level.
+struct NDSolve {
+  const NDGeom* geom;
+  const int* pts;
+  const int* chmap;
+  const NDFront* fr;  // [slab][front]
+  int nfronts, depth;
+  const int2* items;
+  const int* fwd_tab;  // [slab][level][2]
+  const int* bwd_tab;
+  cf* U;               // [task][u_stride]
+  size_t u_stride;
+};
+
+// Host plan of the dissection of an m2 x m3 plane.
+struct NDPlan {
+  int m2 = 0, m3 = 0, depth = 0;
+  std::vector<NDGeom> fronts;
+  std::vector<int> pts, lmap, chmap, cmap;
+  std::vector<std::vector<int>> levels;  // front indices per level (0: root)
+};
+// Builds the plan; returns false (with *why) if it breaks an invariant.
+bool nd_plan(int m2, int m3, NDPlan& P, std::string* why);
+
+// Sizes per slab of n_l layers.
+struct NDSizes {
+  size_t factor = 0;   // complex64 elements of GN and E over all fronts
+  size_t update = 0;   // complex64 elements of the update vectors
+  size_t rows = 0;     // forward items (workgroups) over all levels
+  int s_max = 0, b_max = 0, nf_max = 0;
+};
+NDSizes nd_sizes(const NDPlan& P, int nl);
+
+// Setup scratch of the multifrontal factorization, carved by the caller:
+// two level buffers of dense fronts (levels alternate), the Gauss-Jordan
+// scratch of the largest level, the job tables.
+struct NDSetup {
+  const Slab3* slabs;        // device
+  const NDGeom* geom;        // device
+  const int* pts;
+  const int* lmap;
+  const int* chmap;
+  const int* cmap;
+  NDFront* fr;               // device [slab][front]
+  int nslabs, nfronts, m2, m3;
+  cf* factors;
+  const NDJob* jobs;         // device, all levels
+  GJob* gjobs;               // device, all levels
+  double* gmax;              // [slab][2]: max |A|^2, max |F11|^2
+  int* status;
+  int dbg_slab, dbg_front;   // a separator block forced to zero (-1: off)
+};
+// Host description of the levels for the launches.
+struct NDLevelHost {
+  int first_job = 0, njobs = 0;  // into the job tables
+  int s_max = 0, b_max = 0, nf_max = 0;
+  int fwd_items = 0, bwd_items = 0;  // max over slabs (grid size)
+};
+void launch_factor_nd(const NDSetup& Su, const std::vector<NDLevelHost>& lv, hipStream_t s);
 
 // One SubdomSolve stage of the 3-D sweep: ntasks tasks, each a slab solve
 // (gather + transmission injection, block substitutions along y, scatter-
@@ -201,9 +336,18 @@ struct Stage3 {
   cf* fs;
   cf* ys;
   const cf* factors;
+  // nested-dissection factors: the substitutions of the stage run level by
+  // level through the fronts instead of block by block along y
+  const NDSolve* nd;                      // host pointer, or nullptr
+  const std::vector<NDLevelHost>* nd_lv;  // host
 };
-// Enqueues the stage (one launch per block step); returns the launch status.
+// Enqueues the stage (one launch per block step, or per level of the
+// dissection and direction); returns the launch status.
 hipError_t launch_stage3(const Stage3& st, hipStream_t s);
+// The level-synchronous substitutions of the nested-dissection factors
+// (forward: leaves to root, backward: root to leaves) on the slab-layout
+// right-hand sides of the stage (nd3d.hip).
+void launch_nd_solve(const Stage3& st, const NDSolve& nd, const std::vector<NDLevelHost>& lv, hipStream_t s);
 
 }  // namespace d3
 }  // namespace hsp

@@ -44,6 +44,17 @@ struct D3Ctx {
   size_t o_swf, o_swg, o_swu, o_bufs, o_fs, o_ys;
   size_t o_tgx0, o_tgx1, o_tgres, o_tgrc, o_tgec, o_cvin, o_cvout;
   size_t n_slabA = 0, n_xmap = 0, n_fac = 0, n_tasks = 0;
+  // nested-dissection factorization (slab_factor HSP_SLAB_ND)
+  int slab_factor = HSP_SLAB_BLOCK;
+  d3::NDPlan ndp;
+  std::vector<d3::NDSizes> ndz;        // per slab
+  std::vector<d3::NDLevelHost> ndlv;   // per level
+  d3::NDSolve nds{};
+  size_t nd_njobs = 0, nd_nitems = 0, nd_u_stride = 0;
+  size_t nd_buf[2] = {0, 0};           // complex64 elements of the two level buffers
+  size_t nd_piv = 0, nd_brow = 0, nd_spr = 0;  // Gauss-Jordan scratch of the largest level
+  size_t o_ndgeom = 0, o_ndpts = 0, o_ndlmap = 0, o_ndchmap = 0, o_ndcmap = 0, o_ndfr = 0, o_nditems = 0,
+         o_ndtab = 0, o_ndU = 0;
   size_t nf() const { return (size_t)m[0] * m[1] * m[2]; }
   size_t nd() const { return (size_t)dm[0] * dm[1] * dm[2]; }
 };
@@ -79,6 +90,70 @@ hsp_status validate3(const hsp_grid* g, int J, const hsp_options* o) {
   if (o->krylov_fp32 != 0) return fail(HSP_EINVAL, "krylov_fp32 applies to the 2-D batched solvers only");
   if (!std::isfinite(o->omega_jac)) return fail(HSP_EINVAL, "bad omega_jac");
   if (g->sponge != 0) return fail(HSP_EINVAL, "sponge layers are implemented for 2-D problems");
+  if (o->slab_factor != HSP_SLAB_AUTO && o->slab_factor != HSP_SLAB_BLOCK && o->slab_factor != HSP_SLAB_ND)
+    return fail(HSP_EINVAL, "bad slab_factor");
+  return HSP_OK;
+}
+
+// Bytes of the setup scratch of the nested-dissection factorization.
+size_t nd_setup_bytes(const D3Ctx& D, int J) {
+  return (D.nd_buf[0] + D.nd_buf[1] + D.nd_brow + D.nd_spr) * sizeof(cf) + 2 * D.nd_piv * sizeof(int) +
+         D.nd_njobs * (sizeof(d3::NDJob) + sizeof(d3::GJob)) + (size_t)J * 2 * sizeof(double) + 8 * 256;
+}
+
+// The dissection, the per-slab sizes, the level table and the scratch sizes.
+hsp_status plan_nd(D3Ctx& D, int J) {
+  std::string why;
+  if (!d3::nd_plan(D.dm[1], D.dm[2], D.ndp, &why)) return fail(HSP_EINVAL, "internal: " + why);
+  const d3::NDPlan& np = D.ndp;
+  D.ndz.resize(J);
+  D.n_fac = 0;
+  D.nd_u_stride = 0;
+  D.nd_nitems = 0;
+  for (int j = 0; j < J; ++j) {
+    D.ndz[j] = d3::nd_sizes(np, D.nls[j]);
+    const d3::NDSizes& z = D.ndz[j];
+    if (z.s_max > d3::kGJMaxPivots || z.nf_max > d3::kNDMaxFront)
+      return fail(HSP_EINVAL, "nested-dissection fronts of " + std::to_string(z.nf_max) + " unknowns (" +
+                                  std::to_string(z.s_max) + " pivots) exceed " + std::to_string(d3::kNDMaxFront) +
+                                  " (" + std::to_string(d3::kGJMaxPivots) + "): use more slabs or HSP_SLAB_BLOCK");
+    D.n_fac += z.factor;
+    D.nd_u_stride = std::max(D.nd_u_stride, z.update);
+  }
+  D.nd_u_stride = (D.nd_u_stride + 63) / 64 * 64;
+  D.ndlv.assign(np.depth, d3::NDLevelHost());
+  D.nd_njobs = 0;
+  D.nd_buf[0] = D.nd_buf[1] = 0;
+  D.nd_piv = D.nd_brow = D.nd_spr = 0;
+  for (int L = 0; L < np.depth; ++L) {
+    d3::NDLevelHost& l = D.ndlv[L];
+    l.first_job = (int)D.nd_njobs;
+    l.njobs = J * (int)np.levels[L].size();
+    D.nd_njobs += l.njobs;
+    size_t buf = 0, piv = 0, brow = 0;
+    for (int j = 0; j < J; ++j) {
+      int fi = 0, bi = 0;
+      for (int f : np.levels[L]) {
+        const d3::NDGeom& g = np.fronts[f];
+        const int s = g.ns * D.nls[j], b = g.nb * D.nls[j], nf = s + b;
+        l.s_max = std::max(l.s_max, s);
+        l.b_max = std::max(l.b_max, b);
+        l.nf_max = std::max(l.nf_max, nf);
+        buf += (size_t)nf * nf;
+        piv += s;
+        brow += (size_t)32 * nf;
+        fi += (nf + 3) / 4;
+        if (b > 0) bi += (s + 3) / 4;
+      }
+      l.fwd_items = std::max(l.fwd_items, fi);
+      l.bwd_items = std::max(l.bwd_items, bi);
+      D.nd_nitems += fi + bi;
+    }
+    D.nd_buf[L & 1] = std::max(D.nd_buf[L & 1], buf);
+    D.nd_piv = std::max(D.nd_piv, piv);
+    D.nd_brow = std::max(D.nd_brow, brow);
+    D.nd_spr = std::max(D.nd_spr, (size_t)l.njobs * 32 * 32);
+  }
   return HSP_OK;
 }
 
@@ -123,9 +198,14 @@ hsp_status plan3(const hsp_grid* g, int J, const hsp_options* o, D3Ctx& D, Plan&
     D.nl_max = std::max(D.nl_max, nl);
     D.n_max = std::max(D.n_max, nl * D.dm[2]);
   }
-  if (D.n_max > kMaxBlock3)
+  D.slab_factor = (o->slab_factor == HSP_SLAB_BLOCK) ? HSP_SLAB_BLOCK : HSP_SLAB_ND;
+  if (D.slab_factor == HSP_SLAB_BLOCK && D.n_max > kMaxBlock3)
     return fail(HSP_EINVAL, "slab planes of " + std::to_string(D.n_max) + " unknowns exceed " +
                                 std::to_string(kMaxBlock3) + ": use more slabs or a smaller z extent");
+  if (D.slab_factor == HSP_SLAB_ND) {
+    st = plan_nd(D, J);
+    if (st != HSP_OK) return st;
+  }
   st = sweep_shape(J, o, &P.nbuf, &P.maxtask);
   if (st != HSP_OK) return st;
   P.nl_max = D.nl_max;
@@ -169,18 +249,31 @@ hsp_status plan3(const hsp_grid* g, int J, const hsp_options* o, D3Ctx& D, Plan&
     D.o_ck2c = c.take(ncc * sizeof(double));
     D.o_ccoef = c.take(ncc * 5 * sizeof(double));
   }
-  D.n_slabA = D.n_xmap = D.n_fac = 0;
+  D.n_slabA = D.n_xmap = 0;
+  if (D.slab_factor == HSP_SLAB_BLOCK) D.n_fac = 0;
   for (int j = 0; j < J; ++j) {
     D.n_slabA += D.nls[j] + 2;
     D.n_xmap += D.nls[j] + 1;
-    D.n_fac += blk_elems(D.nls[j] * D.dm[2]) * D.dm[1];
+    if (D.slab_factor == HSP_SLAB_BLOCK) D.n_fac += blk_elems(D.nls[j] * D.dm[2]) * D.dm[1];
   }
   D.o_slabA = c.take(D.n_slabA * sizeof(cd));
   D.o_slabB = c.take(D.n_slabA * sizeof(cd));
   D.o_xmap = c.take(D.n_xmap * sizeof(int));
   D.o_slabs = c.take(J * sizeof(d3::Slab3));
   D.o_fac = c.take((D.n_fac + kFacTail) * sizeof(cf));
-  D.o_setup = c.take(d3::setup3_scratch_bytes(J, D.n_max));
+  D.o_setup = c.take(D.slab_factor == HSP_SLAB_ND ? nd_setup_bytes(D, J) : d3::setup3_scratch_bytes(J, D.n_max));
+  if (D.slab_factor == HSP_SLAB_ND) {
+    const d3::NDPlan& np = D.ndp;
+    D.o_ndgeom = c.take(np.fronts.size() * sizeof(d3::NDGeom));
+    D.o_ndpts = c.take(np.pts.size() * sizeof(int));
+    D.o_ndlmap = c.take(np.lmap.size() * sizeof(int));
+    D.o_ndchmap = c.take(std::max<size_t>(np.chmap.size(), 1) * sizeof(int));
+    D.o_ndcmap = c.take(std::max<size_t>(np.cmap.size(), 1) * sizeof(int));
+    D.o_ndfr = c.take((size_t)J * np.fronts.size() * sizeof(d3::NDFront));
+    D.o_nditems = c.take(std::max<size_t>(D.nd_nitems, 1) * sizeof(int2));
+    D.o_ndtab = c.take((size_t)J * np.depth * 4 * sizeof(int));
+    D.o_ndU = c.take((size_t)P.maxtask * D.nd_u_stride * sizeof(cf));
+  }
   D.o_status = c.take(64);
   D.o_growth = c.take((size_t)J * sizeof(double));
   D.n_tasks = 2 * (size_t)J + 8;
@@ -296,6 +389,8 @@ void run_sweep3(hsp_ctx* C, const cf* f, cf* u, hipStream_t s) {
     S.fs = C->at<float>(D.o_fs);
     S.ys = C->at<float>(D.o_ys);
     S.factors = D.factors;
+    S.nd = D.slab_factor == HSP_SLAB_ND ? &D.nds : nullptr;
+    S.nd_lv = &D.ndlv;
     prof_begin(C, HSP_PROF_STAGE, s);
     const hipError_t e = d3::launch_stage3(S, s);
     if (e != hipSuccess && D.launch_err == hipSuccess) D.launch_err = e;
@@ -563,7 +658,10 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
     for (int q = 0; q < sg.ntasks; ++q) {
       const TaskDev& t = C->tasks_host[sg.first + q];
       const double n = (double)D.nls[t.slab] * D.dm[2], pl = (double)D.dm[1] * D.dm[2];
-      b += D.dm[1] * 3.0 * n * n * sizeof(cf);
+      if (D.slab_factor == HSP_SLAB_ND)
+        b += (double)D.ndz[t.slab].factor * sizeof(cf);
+      else
+        b += D.dm[1] * 3.0 * n * n * sizeof(cf);
       b += pl * ((t.b - t.a) + 2.0 * (t.bt - t.at) + 2.0 * (t.t1 + t.t2 + t.t3 + t.t4)) * sizeof(cf);
     }
     D.stage_bytes[k] = b;
@@ -572,39 +670,191 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
     if (e != hipSuccess) return cleanup(fail(HSP_EDEVICE, std::string("upload: ") + hipGetErrorString(e)));
 
   // factorization of every slab
-  d3::Setup3 Su;
-  Su.slabs = D.slabs_dev;
-  Su.nslabs = J;
-  Su.n_max = D.n_max;
-  Su.m2 = D.dm[1];
-  Su.factors = D.factors;
-  {
-    Carver sc;
-    const size_t nm = (size_t)D.n_max;
-    char* base = C->ws + D.o_setup;
-    Su.S = reinterpret_cast<cf*>(base + sc.take((size_t)J * nm * nm * sizeof(cf)));
-    Su.coef = reinterpret_cast<cf*>(base + sc.take((size_t)J * nm * 27 * sizeof(cf)));
-    Su.brow = reinterpret_cast<cf*>(base + sc.take((size_t)J * 32 * nm * sizeof(cf)));
-    Su.piv = reinterpret_cast<int*>(base + sc.take((size_t)J * nm * sizeof(int)));
-    Su.col = reinterpret_cast<int*>(base + sc.take((size_t)J * nm * sizeof(int)));
-    Su.gmax = reinterpret_cast<double*>(base + sc.take((size_t)J * 2 * sizeof(double)));
-    if (sc.off > d3::setup3_scratch_bytes(J, D.n_max)) return cleanup(fail(HSP_EINVAL, "internal: setup scratch"));
-  }
-  Su.status = C->raw<int>(D.o_status);
-  Su.dbg_singular = debug_knobs().singular_slab;
-  CHK(hipMemsetAsync(Su.status, 0, sizeof(int), s));
-  // every factor entry (row padding and the tail included) starts at zero
-  CHK(hipMemsetAsync(D.factors, 0, (D.n_fac + kFacTail) * sizeof(cf), s));
-  CHK(hipMemsetAsync(Su.gmax, 0, (size_t)J * 2 * sizeof(double), s));
-  d3::launch_factor3(Su, s);
-  double* growth = C->raw<double>(D.o_growth);
-  d3::finish_growth3(Su, growth, s);
-  CHK(hipGetLastError());
-  int hstat = 0;
   std::vector<double> hg(J);
-  CHK(hipMemcpyAsync(&hstat, Su.status, sizeof(int), hipMemcpyDeviceToHost, s));
-  CHK(hipMemcpyAsync(hg.data(), growth, J * sizeof(double), hipMemcpyDeviceToHost, s));
-  CHK(hipStreamSynchronize(s));
+  int hstat = 0;
+  if (D.slab_factor == HSP_SLAB_ND) {
+    const d3::NDPlan& np = D.ndp;
+    const int nfr = (int)np.fronts.size();
+    up(D.o_ndgeom, np.fronts.data(), nfr * sizeof(d3::NDGeom));
+    up(D.o_ndpts, np.pts.data(), np.pts.size() * sizeof(int));
+    up(D.o_ndlmap, np.lmap.data(), np.lmap.size() * sizeof(int));
+    if (!np.chmap.empty()) up(D.o_ndchmap, np.chmap.data(), np.chmap.size() * sizeof(int));
+    if (!np.cmap.empty()) up(D.o_ndcmap, np.cmap.data(), np.cmap.size() * sizeof(int));
+    // setup scratch: two level buffers, Gauss-Jordan scratch, job tables, growth
+    Carver sc;
+    char* base = C->ws + D.o_setup;
+    cf* buf[2];
+    buf[0] = reinterpret_cast<cf*>(base + sc.take(D.nd_buf[0] * sizeof(cf)));
+    buf[1] = reinterpret_cast<cf*>(base + sc.take(D.nd_buf[1] * sizeof(cf)));
+    cf* brow = reinterpret_cast<cf*>(base + sc.take(D.nd_brow * sizeof(cf)));
+    cf* spr = reinterpret_cast<cf*>(base + sc.take(D.nd_spr * sizeof(cf)));
+    int* piv = reinterpret_cast<int*>(base + sc.take(D.nd_piv * sizeof(int)));
+    int* col = reinterpret_cast<int*>(base + sc.take(D.nd_piv * sizeof(int)));
+    d3::NDJob* jobs_dev = reinterpret_cast<d3::NDJob*>(base + sc.take(D.nd_njobs * sizeof(d3::NDJob)));
+    d3::GJob* gjobs_dev = reinterpret_cast<d3::GJob*>(base + sc.take(D.nd_njobs * sizeof(d3::GJob)));
+    double* gmax = reinterpret_cast<double*>(base + sc.take((size_t)J * 2 * sizeof(double)));
+    if (sc.off > nd_setup_bytes(D, J)) return cleanup(fail(HSP_EINVAL, "internal: nested-dissection scratch"));
+    // per slab and front: factor and update offsets, front matrices
+    std::vector<d3::NDFront> fr((size_t)J * nfr);
+    size_t ofac = 0;
+    for (int j = 0; j < J; ++j) {
+      size_t ou = 0;
+      for (int f = 0; f < nfr; ++f) {
+        const d3::NDGeom& g = np.fronts[f];
+        const size_t sv = (size_t)g.ns * D.nls[j], bv = (size_t)g.nb * D.nls[j];
+        d3::NDFront& e = fr[(size_t)j * nfr + f];
+        e.gn = ofac;
+        ofac += (sv + bv) * (sv + (sv & 1));
+        e.e = ofac;
+        ofac += sv * (bv + (bv & 1));
+        e.u = ou;
+        ou += bv;
+        e.F = nullptr;
+      }
+    }
+    if (ofac != D.n_fac) return cleanup(fail(HSP_EINVAL, "internal: nested-dissection factor size"));
+    // jobs level by level (slab-major within a level); front matrices in the
+    // buffer of the level's parity, Gauss-Jordan scratch reused per level
+    std::vector<d3::NDJob> jobs(D.nd_njobs);
+    std::vector<d3::GJob> gjobs(D.nd_njobs);
+    for (int L = 0; L < np.depth; ++L) {
+      size_t ob = 0, op = 0, obr = 0;
+      int q = D.ndlv[L].first_job;
+      for (int j = 0; j < J; ++j)
+        for (int f : np.levels[L]) {
+          const d3::NDGeom& g = np.fronts[f];
+          const int sv = g.ns * D.nls[j], nf = sv + g.nb * D.nls[j];
+          d3::NDFront& e = fr[(size_t)j * nfr + f];
+          e.F = buf[L & 1] + ob;
+          jobs[q] = {j, f};
+          d3::GJob& gj = gjobs[q];
+          gj.F = e.F;
+          gj.nf = nf;
+          gj.s = sv;
+          gj.ld = nf;
+          gj.piv = piv + op;
+          gj.col = col + op;
+          gj.brow = brow + obr;
+          gj.spr = spr + (size_t)(q - D.ndlv[L].first_job) * 32 * 32;
+          ob += (size_t)nf * nf;
+          op += sv;
+          obr += (size_t)32 * nf;
+          ++q;
+        }
+    }
+    up(D.o_ndfr, fr.data(), fr.size() * sizeof(d3::NDFront));
+    CHK(hipMemcpyAsync(jobs_dev, jobs.data(), jobs.size() * sizeof(d3::NDJob), hipMemcpyHostToDevice, s));
+    CHK(hipMemcpyAsync(gjobs_dev, gjobs.data(), gjobs.size() * sizeof(d3::GJob), hipMemcpyHostToDevice, s));
+    // substitution items: (front, first row) per slab and level, forward and backward
+    std::vector<int2> items;
+    items.reserve(D.nd_nitems);
+    std::vector<int> tab((size_t)J * np.depth * 4, 0);
+    for (int j = 0; j < J; ++j)
+      for (int L = 0; L < np.depth; ++L) {
+        int* ft = &tab[((size_t)j * np.depth + L) * 2];
+        int* bt = &tab[(size_t)J * np.depth * 2 + ((size_t)j * np.depth + L) * 2];
+        ft[0] = (int)items.size();
+        for (int f : np.levels[L]) {
+          const d3::NDGeom& g = np.fronts[f];
+          const int nf = (g.ns + g.nb) * D.nls[j];
+          for (int r0 = 0; r0 < nf; r0 += 4) items.push_back(make_int2(f, r0));
+        }
+        ft[1] = (int)items.size() - ft[0];
+        bt[0] = (int)items.size();
+        for (int f : np.levels[L]) {
+          const d3::NDGeom& g = np.fronts[f];
+          if (g.nb == 0) continue;
+          const int sv = g.ns * D.nls[j];
+          for (int r0 = 0; r0 < sv; r0 += 4) items.push_back(make_int2(f, r0));
+        }
+        bt[1] = (int)items.size() - bt[0];
+      }
+    if (items.size() != D.nd_nitems) return cleanup(fail(HSP_EINVAL, "internal: nested-dissection items"));
+    up(D.o_nditems, items.data(), items.size() * sizeof(int2));
+    up(D.o_ndtab, tab.data(), tab.size() * sizeof(int));
+    for (hipError_t e : errs)
+      if (e != hipSuccess) return cleanup(fail(HSP_EDEVICE, std::string("upload: ") + hipGetErrorString(e)));
+    d3::NDSetup Su;
+    Su.slabs = D.slabs_dev;
+    Su.geom = C->raw<d3::NDGeom>(D.o_ndgeom);
+    Su.pts = C->raw<int>(D.o_ndpts);
+    Su.lmap = C->raw<int>(D.o_ndlmap);
+    Su.chmap = C->raw<int>(D.o_ndchmap);
+    Su.cmap = C->raw<int>(D.o_ndcmap);
+    Su.fr = C->raw<d3::NDFront>(D.o_ndfr);
+    Su.nslabs = J;
+    Su.nfronts = nfr;
+    Su.m2 = D.dm[1];
+    Su.m3 = D.dm[2];
+    Su.factors = D.factors;
+    Su.jobs = jobs_dev;
+    Su.gjobs = gjobs_dev;
+    Su.gmax = gmax;
+    Su.status = C->raw<int>(D.o_status);
+    Su.dbg_slab = debug_knobs().singular_slab;
+    Su.dbg_front = np.levels.back()[0];
+    CHK(hipMemsetAsync(Su.status, 0, sizeof(int), s));
+    CHK(hipMemsetAsync(D.factors, 0, (D.n_fac + kFacTail) * sizeof(cf), s));
+    CHK(hipMemsetAsync(gmax, 0, (size_t)J * 2 * sizeof(double), s));
+    d3::launch_factor_nd(Su, D.ndlv, s);
+    CHK(hipGetLastError());
+    std::vector<double> gm(2 * J);
+    CHK(hipMemcpyAsync(&hstat, Su.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    CHK(hipMemcpyAsync(gm.data(), gmax, 2 * J * sizeof(double), hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+    for (int j = 0; j < J; ++j) hg[j] = gm[2 * j] > 0 ? std::sqrt(gm[2 * j + 1] / gm[2 * j]) : 0.0;
+    // device view for the stages
+    D.nds.geom = Su.geom;
+    D.nds.pts = Su.pts;
+    D.nds.chmap = Su.chmap;
+    D.nds.fr = Su.fr;
+    D.nds.nfronts = nfr;
+    D.nds.depth = np.depth;
+    D.nds.items = C->raw<int2>(D.o_nditems);
+    D.nds.fwd_tab = C->raw<int>(D.o_ndtab);
+    D.nds.bwd_tab = C->raw<int>(D.o_ndtab) + (size_t)J * np.depth * 2;
+    D.nds.U = C->at<float>(D.o_ndU);
+    D.nds.u_stride = D.nd_u_stride;
+  } else {
+    d3::Setup3 Su;
+    Su.slabs = D.slabs_dev;
+    Su.nslabs = J;
+    Su.n_max = D.n_max;
+    Su.m2 = D.dm[1];
+    Su.factors = D.factors;
+    {
+      Carver sc;
+      const size_t nm = (size_t)D.n_max;
+      char* base = C->ws + D.o_setup;
+      Su.S = reinterpret_cast<cf*>(base + sc.take((size_t)J * nm * nm * sizeof(cf)));
+      Su.coef = reinterpret_cast<cf*>(base + sc.take((size_t)J * nm * 27 * sizeof(cf)));
+      Su.brow = reinterpret_cast<cf*>(base + sc.take((size_t)J * 32 * nm * sizeof(cf)));
+      Su.spr = reinterpret_cast<cf*>(base + sc.take((size_t)J * 32 * 32 * sizeof(cf)));
+      Su.piv = reinterpret_cast<int*>(base + sc.take((size_t)J * nm * sizeof(int)));
+      Su.col = reinterpret_cast<int*>(base + sc.take((size_t)J * nm * sizeof(int)));
+      Su.jobs = reinterpret_cast<d3::GJob*>(base + sc.take((size_t)J * sizeof(d3::GJob)));
+      Su.gmax = reinterpret_cast<double*>(base + sc.take((size_t)J * 2 * sizeof(double)));
+      if (sc.off > d3::setup3_scratch_bytes(J, D.n_max)) return cleanup(fail(HSP_EINVAL, "internal: setup scratch"));
+    }
+    std::vector<int> slab_n(J);
+    for (int j = 0; j < J; ++j) slab_n[j] = D.slabs_host[j].n;
+    std::vector<d3::GJob> jobs(J);
+    d3::setup3_jobs(Su, slab_n.data(), jobs.data());
+    CHK(hipMemcpyAsync(Su.jobs, jobs.data(), J * sizeof(d3::GJob), hipMemcpyHostToDevice, s));
+    Su.status = C->raw<int>(D.o_status);
+    Su.dbg_singular = debug_knobs().singular_slab;
+    CHK(hipMemsetAsync(Su.status, 0, sizeof(int), s));
+    // every factor entry (row padding and the tail included) starts at zero
+    CHK(hipMemsetAsync(D.factors, 0, (D.n_fac + kFacTail) * sizeof(cf), s));
+    CHK(hipMemsetAsync(Su.gmax, 0, (size_t)J * 2 * sizeof(double), s));
+    d3::launch_factor3(Su, s);
+    double* growth = C->raw<double>(D.o_growth);
+    d3::finish_growth3(Su, growth, s);
+    CHK(hipGetLastError());
+    CHK(hipMemcpyAsync(&hstat, Su.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    CHK(hipMemcpyAsync(hg.data(), growth, J * sizeof(double), hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+  }
   if (hstat != 0) return cleanup(fail(HSP_ESINGULAR, "zero or non-finite pivot in a slab factorization"));
   C->growth = *std::max_element(hg.begin(), hg.end());
   if (!(C->growth <= growth_limit(sizeof(cf))))
@@ -770,6 +1020,8 @@ hsp_status d3_slab_solve(hsp_ctx* C, int j, const cd* b, cd* x, hipStream_t s) {
   S.fs = C->at<float>(D.o_fs);
   S.ys = C->at<float>(D.o_ys);
   S.factors = D.factors;
+  S.nd = D.slab_factor == HSP_SLAB_ND ? &D.nds : nullptr;
+  S.nd_lv = &D.ndlv;
   const hipError_t e = d3::launch_stage3(S, s);
   if (e != hipSuccess) return fail(HSP_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
   launch_convert<double, float>(uo, x, n, 0, s);
@@ -802,6 +1054,7 @@ void d3_info(const hsp_ctx* C, hsp_info* info) {
   info->two_grid = D.two_grid;
   info->pivot_growth = C->growth;
   info->dim = 3;
+  info->slab_factor = D.slab_factor;
 }
 
 }  // namespace hsp

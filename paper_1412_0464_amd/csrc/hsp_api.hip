@@ -66,6 +66,8 @@ hsp_status validate(const hsp_grid* g, int J, const hsp_options* o) {
   if (o->krylov_fp32 != 0 && o->krylov_fp32 != 1) return fail(HSP_EINVAL, "krylov_fp32 must be 0 or 1");
   if (o->krylov_fp32 && o->precision != HSP_MIXED)
     return fail(HSP_EINVAL, "krylov_fp32 requires precision HSP_MIXED");
+  if (o->slab_factor != HSP_SLAB_AUTO && o->slab_factor != HSP_SLAB_BLOCK)
+    return fail(HSP_EINVAL, "2-D slabs are block tridiagonal: slab_factor must be HSP_SLAB_AUTO or HSP_SLAB_BLOCK");
   return HSP_OK;
 }
 
@@ -700,6 +702,7 @@ hsp_status hsp_default_options(hsp_options* o) {
   o->chunk = 0;
   o->krylov_fp32 = 0;
   o->ncell = 2;
+  o->slab_factor = HSP_SLAB_AUTO;
   return HSP_OK;
 }
 
@@ -1121,6 +1124,7 @@ hsp_status hsp_get_info(hsp_handle C, hsp_info* info) {
   info->precision = C->opt.precision;
   info->two_grid = C->P.two_grid;
   info->pivot_growth = C->growth;
+  info->slab_factor = HSP_SLAB_BLOCK;
   return HSP_OK;
 }
 

@@ -136,10 +136,13 @@ __global__ void __launch_bounds__(256) k3_schur(Setup3 Su, int t) {
   block_max_into(mx, Su.gmax + 2 * blockIdx.y + 1);
 }
 
-// Gauss-Jordan elimination of the panel columns k0..k0+31 (all rows), one
-// workgroup per slab.  Row r < 1024 lives in the registers of thread r;
-// rows 1024.. (at most kPanelLds of them) in LDS, handled by thread r - 1024.
-constexpr int kPanelLds = 512;
+// ---- dense partial Gauss-Jordan elimination (GJob) -------------------------
+// Gauss-Jordan elimination of the panel columns k0..k0+31 over the rows
+// 0..s-1 of every job, one workgroup of T threads per job.  Row r < T lives
+// in the registers of thread r; with T = 1024, rows 1024.. (at most
+// kPanelLds of them) in LDS, handled by thread r - 1024.  The scaled pivot
+// row of every step goes to spr, for the rows >= s (kg_replay).
+constexpr int kPanelLds = kGJMaxPivots - kPanelT;
 
 __device__ __forceinline__ void pivot_better(float& best, int& bi, float v, int r) {
   if (v > best || (v == best && r < bi)) {
@@ -148,25 +151,27 @@ __device__ __forceinline__ void pivot_better(float& best, int& bi, float v, int 
   }
 }
 
-__global__ void __launch_bounds__(kPanelT) k3_panel(Setup3 Su, int k0) {
-  const Slab3 sl = Su.slabs[blockIdx.x];
-  const int n = sl.n;
+template <int T>
+__global__ void __launch_bounds__(T) kg_panel(const GJob* __restrict__ jobs, int k0, int* status) {
+  const GJob jb = jobs[blockIdx.x];
+  const int n = jb.s;
   if (k0 >= n) return;
   const int nbv = min(kNB, n - k0);
-  const int ld = Su.n_max;
-  cf* S = Su.S + (size_t)blockIdx.x * ld * ld;
+  const int ld = jb.ld;
+  cf* S = jb.F;
+  constexpr int kL = (T == kPanelT) ? kPanelLds : 1;  // rows held in LDS
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ cf prow[kNB], srow[kNB], spr[kNB];
-  __shared__ cf P2[kPanelLds][kNB + 1];
-  __shared__ float wbest[kPanelT / 64];
-  __shared__ int widx[kPanelT / 64];
+  __shared__ cf P2[kL][kNB + 1];
+  __shared__ float wbest[T / 64];
+  __shared__ int widx[T / 64];
   __shared__ int sh_p;
-  const int r1 = tid, r2 = kPanelT + tid;  // the thread's rows
-  const bool has1 = r1 < n, has2 = tid < kPanelLds && r2 < n;
+  const int r1 = tid, r2 = T + tid;  // the thread's rows
+  const bool has1 = r1 < n, has2 = T == kPanelT && tid < kPanelLds && r2 < n;
   cf P[kNB];
 #pragma unroll
   for (int c = 0; c < kNB; ++c) P[c] = (has1 && c < nbv) ? S[(size_t)r1 * ld + k0 + c] : mk<float>(0, 0);
-  if (tid < kPanelLds)
+  if (T == kPanelT && tid < kPanelLds)
     for (int c = 0; c < kNB; ++c) P2[tid][c] = (has2 && c < nbv) ? S[(size_t)r2 * ld + k0 + c] : mk<float>(0, 0);
   bool bad = false;
 #pragma clang loop unroll(full)
@@ -190,8 +195,8 @@ __global__ void __launch_bounds__(kPanelT) k3_panel(Setup3 Su, int k0) {
       }
       __syncthreads();
       if (tid < 64) {
-        float b2 = tid < kPanelT / 64 ? wbest[tid] : -1.0f;
-        int i2 = tid < kPanelT / 64 ? widx[tid] : n;
+        float b2 = tid < T / 64 ? wbest[tid] : -1.0f;
+        int i2 = tid < T / 64 ? widx[tid] : n;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
           const float ov = __shfl_xor(b2, off, 64);
@@ -204,7 +209,7 @@ __global__ void __launch_bounds__(kPanelT) k3_panel(Setup3 Su, int k0) {
             i2 = gc;
           }
           sh_p = i2;
-          Su.piv[(size_t)blockIdx.x * Su.n_max + gc] = i2;
+          jb.piv[gc] = i2;
         }
       }
       __syncthreads();
@@ -230,7 +235,9 @@ __global__ void __launch_bounds__(kPanelT) k3_panel(Setup3 Su, int k0) {
         const cf pv = prow[c];
         const float d = 1.0f / (pv.re * pv.re + pv.im * pv.im);
         const cf inv = mk<float>(pv.re * d, -pv.im * d);
-        spr[tid] = (tid == c) ? inv : prow[tid] * inv;
+        const cf v = (tid == c) ? inv : prow[tid] * inv;
+        spr[tid] = v;
+        jb.spr[c * kNB + tid] = v;
       }
       if (p != gc) {
         if (r1 == p) {
@@ -278,27 +285,59 @@ __global__ void __launch_bounds__(kPanelT) k3_panel(Setup3 Su, int k0) {
   }
   if (has2)
     for (int c = 0; c < nbv; ++c) S[(size_t)r2 * ld + k0 + c] = P2[tid][c];
-  if (bad) atomicOr(Su.status, 1);
+  if (bad) atomicOr(status, 1);
+}
+
+// The panel steps replayed on the rows s..nf-1 (never pivot candidates):
+// the same eliminations with the scaled pivot rows kg_panel recorded.
+__global__ void __launch_bounds__(256) kg_replay(const GJob* __restrict__ jobs, int k0) {
+  const GJob jb = jobs[blockIdx.y];
+  if (k0 >= jb.s) return;
+  const int nbv = min(kNB, jb.s - k0);
+  __shared__ cf sp[kNB][kNB];
+  for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+    const int c = e / kNB, q = e - (e / kNB) * kNB;
+    sp[c][q] = (c < nbv && q < nbv) ? jb.spr[e] : mk<float>(0, 0);
+  }
+  __syncthreads();
+  const int r = jb.s + blockIdx.x * 256 + threadIdx.x;
+  if (r >= jb.nf) return;
+  cf* row = jb.F + (size_t)r * jb.ld + k0;
+  cf P[kNB];
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) P[c] = c < nbv ? row[c] : mk<float>(0, 0);
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) {
+    if (c < nbv) {
+      const cf f = P[c];
+#pragma unroll
+      for (int q = 0; q < kNB; ++q) {
+        const cf base = (q == c) ? mk<float>(0, 0) : P[q];
+        const cf v = sp[c][q];
+        P[q] = mk<float>(base.re - (f.re * v.re - f.im * v.im), base.im - (f.re * v.im + f.im * v.re));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kNB; ++c)
+    if (c < nbv) row[c] = P[c];
 }
 
 // Row interchanges of the panel applied to the other columns, and the pivot
 // rows of those columns copied to brow[c][j] (zero in the panel columns).
-__global__ void __launch_bounds__(256) k3_swap(Setup3 Su, int k0) {
-  const Slab3 sl = Su.slabs[blockIdx.y];
-  const int n = sl.n;
-  if (k0 >= n) return;
+__global__ void __launch_bounds__(256) kg_swap(const GJob* __restrict__ jobs, int k0) {
+  const GJob jb = jobs[blockIdx.y];
+  if (k0 >= jb.s) return;
   const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  const int nbv = min(kNB, n - k0);
-  const int ld = Su.n_max;
-  cf* S = Su.S + (size_t)blockIdx.y * ld * ld;
-  cf* B = Su.brow + (size_t)blockIdx.y * kNB * ld;
-  const int* piv = Su.piv + (size_t)blockIdx.y * Su.n_max;
+  if (j >= jb.nf) return;
+  const int nbv = min(kNB, jb.s - k0);
+  const int ld = jb.ld;
+  cf* S = jb.F;
   const bool panel = j >= k0 && j < k0 + nbv;
   for (int c = 0; c < kNB; ++c) {
     cf v = mk<float>(0, 0);
     if (c < nbv && !panel) {
-      const int gc = k0 + c, p = piv[gc];
+      const int gc = k0 + c, p = jb.piv[gc];
       if (p != gc) {
         const cf a = S[(size_t)gc * ld + j];
         v = S[(size_t)p * ld + j];
@@ -308,24 +347,24 @@ __global__ void __launch_bounds__(256) k3_swap(Setup3 Su, int k0) {
         v = S[(size_t)gc * ld + j];
       }
     }
-    B[(size_t)c * ld + j] = v;
+    jb.brow[(size_t)c * ld + j] = v;
   }
 }
 
-// R <- R + P' B_K over the columns outside the panel, with the pivot rows
-// of R replaced (not incremented).  64 x 64 output tile per workgroup, a
-// 32 x 32 tile per wavefront on the FP32 matrix cores.
-__global__ void __launch_bounds__(256) k3_update(Setup3 Su, int k0, int tiles) {
-  const Slab3 sl = Su.slabs[blockIdx.y];
-  const int n = sl.n;
-  if (k0 >= n) return;
-  const int nbv = min(kNB, n - k0);
+// R <- R + P' B_K over the columns outside the panel (all nf rows), with
+// the pivot rows of R replaced (not incremented).  64 x 64 output tile per
+// workgroup, a 32 x 32 tile per wavefront on the FP32 matrix cores.
+__global__ void __launch_bounds__(256) kg_update(const GJob* __restrict__ jobs, int k0, int tiles) {
+  const GJob jb = jobs[blockIdx.y];
+  const int n = jb.nf;
+  if (k0 >= jb.s) return;
+  const int nbv = min(kNB, jb.s - k0);
   const int ti = blockIdx.x / tiles, tj = blockIdx.x - (blockIdx.x / tiles) * tiles;
   const int i0 = ti * 64, j0 = tj * 64;
   if (i0 >= n || j0 >= n) return;
-  const int ld = Su.n_max;
-  cf* S = Su.S + (size_t)blockIdx.y * ld * ld;
-  const cf* B = Su.brow + (size_t)blockIdx.y * kNB * ld;
+  const int ld = jb.ld;
+  cf* S = jb.F;
+  const cf* B = jb.brow;
   __shared__ cf sA[64][kNB + 1];
   __shared__ cf sB[kNB][64];
   const int tid = threadIdx.x;
@@ -373,23 +412,21 @@ __global__ void __launch_bounds__(256) k3_update(Setup3 Su, int k0, int tiles) {
   }
 }
 
-// Column permutation of the computed inverse: the row interchanges in
+// Column permutation of the eliminated columns: the row interchanges in
 // reverse order become column interchanges; col[j] = the column of the
-// eliminated matrix that is column j of S_t^{-1}.
-__global__ void __launch_bounds__(64) k3_colperm(Setup3 Su) {
-  const Slab3 sl = Su.slabs[blockIdx.x];
-  const int n = sl.n;
-  const int* piv = Su.piv + (size_t)blockIdx.x * Su.n_max;
-  int* col = Su.col + (size_t)blockIdx.x * Su.n_max;
-  for (int j = threadIdx.x; j < n; j += 64) col[j] = j;
+// eliminated matrix that is column j of F11^{-1}.
+__global__ void __launch_bounds__(64) kg_colperm(const GJob* __restrict__ jobs) {
+  const GJob jb = jobs[blockIdx.x];
+  const int n = jb.s;
+  for (int j = threadIdx.x; j < n; j += 64) jb.col[j] = j;
   __syncthreads();
   if (threadIdx.x == 0)
     for (int c = n - 1; c >= 0; --c) {
-      const int p = piv[c];
+      const int p = jb.piv[c];
       if (p != c) {
-        const int a = col[c];
-        col[c] = col[p];
-        col[p] = a;
+        const int a = jb.col[c];
+        jb.col[c] = jb.col[p];
+        jb.col[p] = a;
       }
     }
 }
@@ -618,26 +655,50 @@ __global__ void __launch_bounds__(256) k3s_fin(Stage3 st) {
 
 }  // namespace
 
+void launch_gauss_jordan(const GJob* jobs, int njobs, int s_max, int b_max, int nf_max, int* status,
+                         hipStream_t s) {
+  if (njobs < 1 || s_max < 1) return;
+  const int tiles = (nf_max + 63) / 64;
+  for (int k0 = 0; k0 < s_max; k0 += kNB) {
+    if (s_max > 256)
+      hipLaunchKernelGGL(kg_panel<kPanelT>, dim3(njobs), dim3(kPanelT), 0, s, jobs, k0, status);
+    else
+      hipLaunchKernelGGL(kg_panel<256>, dim3(njobs), dim3(256), 0, s, jobs, k0, status);
+    if (b_max > 0) hipLaunchKernelGGL(kg_replay, dim3((b_max + 255) / 256, njobs), dim3(256), 0, s, jobs, k0);
+    hipLaunchKernelGGL(kg_swap, dim3((nf_max + 255) / 256, njobs), dim3(256), 0, s, jobs, k0);
+    hipLaunchKernelGGL(kg_update, dim3(tiles * tiles, njobs), dim3(256), 0, s, jobs, k0, tiles);
+  }
+  hipLaunchKernelGGL(kg_colperm, dim3(njobs), dim3(64), 0, s, jobs);
+}
+
 size_t setup3_scratch_bytes(int nslabs, int n_max) {
   const size_t nm = (size_t)n_max;
-  // six arrays, each 256-byte aligned
-  return nslabs * (nm * nm * sizeof(cf) + nm * 27 * sizeof(cf) + kNB * nm * sizeof(cf) + 2 * nm * sizeof(int) +
-                   2 * sizeof(double)) + 6 * 256;
+  // eight arrays, each 256-byte aligned
+  return nslabs * (nm * nm * sizeof(cf) + nm * 27 * sizeof(cf) + kNB * nm * sizeof(cf) + kNB * kNB * sizeof(cf) +
+                   2 * nm * sizeof(int) + sizeof(GJob) + 2 * sizeof(double)) + 8 * 256;
+}
+
+void setup3_jobs(const Setup3& Su, const int* n, GJob* jobs) {
+  const size_t nm = (size_t)Su.n_max;
+  for (int sl = 0; sl < Su.nslabs; ++sl) {
+    GJob& jb = jobs[sl];
+    jb.F = Su.S + (size_t)sl * nm * nm;
+    jb.nf = jb.s = n[sl];
+    jb.ld = Su.n_max;
+    jb.piv = Su.piv + (size_t)sl * nm;
+    jb.col = Su.col + (size_t)sl * nm;
+    jb.brow = Su.brow + (size_t)sl * kNB * nm;
+    jb.spr = Su.spr + (size_t)sl * kNB * kNB;
+  }
 }
 
 void launch_factor3(const Setup3& Su, hipStream_t s) {
   const int ns = Su.nslabs, nm = Su.n_max;
-  const int tiles = (nm + 63) / 64;
   const size_t nn = (size_t)nm * nm;
   for (int t = 0; t < Su.m2; ++t) {
     hipLaunchKernelGGL(k3_coef, dim3((nm + 255) / 256, ns), dim3(256), 0, s, Su, t);
     hipLaunchKernelGGL(k3_schur, dim3(nblk(nn), ns), dim3(256), 0, s, Su, t);
-    for (int k0 = 0; k0 < nm; k0 += kNB) {
-      hipLaunchKernelGGL(k3_panel, dim3(ns), dim3(kPanelT), 0, s, Su, k0);
-      hipLaunchKernelGGL(k3_swap, dim3((nm + 255) / 256, ns), dim3(256), 0, s, Su, k0);
-      hipLaunchKernelGGL(k3_update, dim3(tiles * tiles, ns), dim3(256), 0, s, Su, k0, tiles);
-    }
-    hipLaunchKernelGGL(k3_colperm, dim3(ns), dim3(64), 0, s, Su);
+    launch_gauss_jordan(Su.jobs, ns, nm, 0, nm, Su.status, s);
     hipLaunchKernelGGL(k3_store, dim3(nblk(nn), ns), dim3(256), 0, s, Su, t);
   }
 }
@@ -651,6 +712,11 @@ hipError_t launch_stage3(const Stage3& st, hipStream_t s) {
   const size_t cnt = (size_t)st.G.m2 * st.n_max;
   const int m2 = st.G.m2;
   hipLaunchKernelGGL(k3s_prep, dim3(nblk(cnt), st.ntasks), dim3(256), 0, s, st);
+  if (st.nd) {
+    launch_nd_solve(st, *st.nd, *st.nd_lv, s);
+    hipLaunchKernelGGL(k3s_fin, dim3(nblk(cnt), st.ntasks), dim3(256), 0, s, st);
+    return hipGetLastError();
+  }
   const dim3 grd((st.n_max + kRowsPerBlock - 1) / kRowsPerBlock, st.ntasks);
   // pairs per lane: n_max (forward rows of 2 n_max entries), n_max / 2 (backward)
   const int npf = (st.n_max + 63) / 64, npb = (st.n_max + 127) / 128;

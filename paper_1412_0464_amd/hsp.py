@@ -19,6 +19,7 @@ _lib = None
 HSP_OK, HSP_EINVAL, HSP_ENOMEM, HSP_ESINGULAR, HSP_ENOCONV, HSP_EDEVICE = 0, -1, -2, -3, -4, -5
 SWEEP = {"x": 0, "ud": 1, "nx": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
+SLAB_FACTOR = {"auto": 0, "block": 1, "nd": 2}
 
 
 class HspError(RuntimeError):
@@ -37,14 +38,15 @@ class HspOptions(ctypes.Structure):
     _fields_ = [("fine_stencil", ctypes.c_int), ("two_grid", ctypes.c_int), ("w_dd", ctypes.c_int),
                 ("S_dd", ctypes.c_double), ("nu", ctypes.c_int), ("omega_jac", ctypes.c_double),
                 ("sweep", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
-                ("chunk", ctypes.c_int), ("krylov_fp32", ctypes.c_int), ("ncell", ctypes.c_int)]
+                ("chunk", ctypes.c_int), ("krylov_fp32", ctypes.c_int), ("ncell", ctypes.c_int),
+                ("slab_factor", ctypes.c_int)]
 
 
 class HspInfo(ctypes.Structure):
     _fields_ = [("n_fine", ctypes.c_int * 2), ("n_coarse", ctypes.c_int * 2), ("J", ctypes.c_int),
                 ("max_slab_layers", ctypes.c_int), ("precision", ctypes.c_int), ("two_grid", ctypes.c_int),
                 ("pivot_growth", ctypes.c_double), ("dim", ctypes.c_int), ("n_fine_z", ctypes.c_int),
-                ("n_coarse_z", ctypes.c_int)]
+                ("n_coarse_z", ctypes.c_int), ("slab_factor", ctypes.c_int)]
 
 
 EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", "hsp_apply_operator",
@@ -170,6 +172,8 @@ def make_options(**kw):
             v = SWEEP[v] if isinstance(v, str) else v
         if k == "precision":
             v = PRECISION[v] if isinstance(v, str) else v
+        if k == "slab_factor":
+            v = SLAB_FACTOR[v] if isinstance(v, str) else v
         if k in ("two_grid", "krylov_fp32"):
             v = int(bool(v))
         if k not in dict(HspOptions._fields_):
@@ -197,7 +201,7 @@ class Helmholtz:
             cells are sponge layers instead (S_outer = beta at the edge).
     Options follow hsp_options (fine_stencil, two_grid, w_dd, S_dd, nu,
     omega_jac, sweep 'x'/'ud'/'nx', precision 'fp64'/'mixed', restart, chunk,
-    krylov_fp32, ncell).  In 3-D the defaults are those of the paper's 3-D
+    krylov_fp32, ncell, slab_factor 'auto'/'block'/'nd').  In 3-D the defaults are those of the paper's 3-D
     experiments (Sec. 6.2): fine_stencil 7, w_dd 3, omega_jac 0.6, and the
     complex64 slab factors of precision 'mixed'.
     """
@@ -237,6 +241,7 @@ class Helmholtz:
         self.max_slab_layers = inf.max_slab_layers
         self.two_grid = bool(inf.two_grid)
         self.pivot_growth = inf.pivot_growth
+        self.slab_factor = {1: "block", 2: "nd"}.get(inf.slab_factor, "block")
         beta = (ctypes.c_int * (self.J + 1))()
         x0 = (ctypes.c_int * self.J)()
         x1 = (ctypes.c_int * self.J)()

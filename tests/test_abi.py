@@ -86,13 +86,29 @@ def test_workspace_size_3d():
     assert _ws3(fine_stencil=27) > _ws3()
 
 
+def test_nested_dissection_plans_and_sizes():
+    """The host plan of the nested dissection (its parent/child maps are
+    checked while it is built) for planes from 1 x 1 to 63 x 63 nodes; a
+    thin slab of a wide plane fits only the nested dissection; at the 3-D
+    benchmark size (127^3 + 8 PML, J = 16 coarse slabs) its workspace is
+    smaller than the block-tridiagonal one (fewer factor bytes)."""
+    for m in [(1, 1, 1), (5, 1, 7), (9, 2, 3), (12, 13, 11), (30, 31, 17), (16, 61, 61)]:
+        assert _ws3(n=m, pml=(1, 1, 1), J=1, w_dd=1, slab_factor="nd") > 0
+    assert _ws3(n=(40, 8, 300), J=1, slab_factor="nd") > 0
+    big = dict(n=(127, 127, 127), h=0.02, pml=(8, 8, 8), J=16, two_grid=True, w_dd=3)
+    assert _ws3(slab_factor="nd", **big) < 0.7 * _ws3(slab_factor="block", **big)
+    assert _ws3(slab_factor="auto", **big) == _ws3(slab_factor="nd", **big)
+
+
 @pytest.mark.parametrize("kw,msg", [
     (dict(precision="fp64"), "HSP_MIXED"),                 # 3-D factors are complex64
     (dict(fine_stencil=5), "7 or 27"),
     (dict(two_grid=True, n=(17, 8, 9)), "even"),
     (dict(J=9), "thinner than 3"),
-    (dict(n=(40, 8, 300), J=1), "exceed"),                 # slab planes beyond the panel kernel
+    (dict(n=(40, 8, 300), J=1, slab_factor="block"), "exceed"),  # slab planes beyond the panel kernel
+    (dict(n=(40, 300, 300), J=1, slab_factor="nd"), "exceed"),   # fronts beyond the panel kernel
     (dict(krylov_fp32=True), "krylov_fp32"),
+    (dict(slab_factor=3), "slab_factor"),
 ])
 def test_workspace_size_3d_rejects_invalid(kw, msg):
     with pytest.raises(hsp.HspError) as e:

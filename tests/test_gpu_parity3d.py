@@ -8,7 +8,10 @@ of 32 columns, several 64 x 64 update tiles with ragged edges, and (one case)
 more than 1024 rows per panel.  Tolerances: FP64 kernels 1e-12 relative;
 complex64 maps (slab factors from the FP32 matrix cores, sweeps, two-grid)
 2e-4 relative; solves to 1e-6 with iteration counts within +-1 of the
-oracle's FGMRES.
+oracle's FGMRES.  Both slab factorizations are covered: block tridiagonal
+along y with dense blocks, and the nested dissection of the slab planes
+(multifrontal fronts of up to a few hundred unknowns, children's Schur
+complements assembled into their parents).
 """
 import numpy as np
 import pytest
@@ -46,17 +49,21 @@ def _medium(n, w, seed=1412047):
     return np.pad(c, w, mode="edge")
 
 
-def _build(name, J=None, w_dd=2):
+SF = ["block", "nd"]
+
+
+def _build(name, J=None, w_dd=2, slab_factor="nd"):
     n, w, J0, fine, tg, sweep, ppw = CASES[name]
     J = J0 if J is None else J
     c = _medium(n, w)
     h = 0.05
     om = 2 * np.pi * 1.5 / (ppw * h)
-    print(f"[3d case {name} J={J} shape={c.shape}]", flush=True)
+    print(f"[3d case {name} J={J} shape={c.shape} slab_factor={slab_factor}]", flush=True)
     ref = Problem3D(c, om, h, w, J=J, w_dd=w_dd, fine=fine, two_grid=tg, sweep=sweep, omega_jac=0.6)
     from paper_1412_0464_amd import Helmholtz
     hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, J, fine_stencil=7 if fine == "fd7" else 27,
-                   two_grid=tg, sweep=sweep, w_dd=w_dd, omega_jac=0.6)
+                   two_grid=tg, sweep=sweep, w_dd=w_dd, omega_jac=0.6, slab_factor=slab_factor)
+    assert hs.slab_factor == slab_factor
     return c, ref, hs
 
 
@@ -115,9 +122,10 @@ def test_coarse_operator_and_transfers():
         hs.close()
 
 
+@pytest.mark.parametrize("sf", SF)
 @pytest.mark.parametrize("name", ["fd7_1lvl_x", "fe27_1lvl_x", "tg_x"])
-def test_slab_solves(name):
-    c, ref, hs = _build(name)
+def test_slab_solves(name, sf):
+    c, ref, hs = _build(name, slab_factor=sf)
     try:
         for j in range(hs.J):
             nl = hs.x1[j] - hs.x0[j] + 1
@@ -133,9 +141,11 @@ def test_slab_solves(name):
         hs.close()
 
 
-def test_single_slab_plane_of_more_than_1024_unknowns():
+@pytest.mark.parametrize("sf", SF)
+def test_single_slab_plane_of_more_than_1024_unknowns(sf):
     """J = 1: the sweep is the exact inverse; slab planes of 40 x 31 = 1240
-    unknowns (rows beyond 1024 of each panel live in LDS)."""
+    unknowns (block form: rows beyond 1024 of each panel live in LDS; nested
+    dissection: fronts of 40-layer separators)."""
     n, w = (34, 3, 25), 3
     c = _medium(n, w)
     h = 0.05
@@ -143,7 +153,7 @@ def test_single_slab_plane_of_more_than_1024_unknowns():
     print(f"[3d single slab, shape {c.shape}]", flush=True)
     ref = Problem3D(c, om, h, w, J=1, w_dd=2)
     from paper_1412_0464_amd import Helmholtz
-    hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, 1, w_dd=2)
+    hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, 1, w_dd=2, slab_factor=sf)
     try:
         assert hs.x1[0] - hs.x0[0] + 1 == 40 and hs.n_fine[2] == 31
         f = random_rhs(c.shape, 30)
@@ -154,9 +164,10 @@ def test_single_slab_plane_of_more_than_1024_unknowns():
         hs.close()
 
 
+@pytest.mark.parametrize("sf", SF)
 @pytest.mark.parametrize("name", list(CASES))
-def test_sweep(name):
-    c, ref, hs = _build(name)
+def test_sweep(name, sf):
+    c, ref, hs = _build(name, slab_factor=sf)
     try:
         f = random_rhs(hs.dd_shape, 40)
         u = hs.sweep(_t(f)).cpu().numpy().ravel()
@@ -167,9 +178,10 @@ def test_sweep(name):
         hs.close()
 
 
+@pytest.mark.parametrize("sf", SF)
 @pytest.mark.parametrize("name", list(CASES))
-def test_precond(name):
-    c, ref, hs = _build(name)
+def test_precond(name, sf):
+    c, ref, hs = _build(name, slab_factor=sf)
     try:
         r = random_rhs(c.shape, 50)
         z = hs.apply_precond(_t(r)).cpu().numpy().ravel()
@@ -178,9 +190,10 @@ def test_precond(name):
         hs.close()
 
 
+@pytest.mark.parametrize("sf", SF)
 @pytest.mark.parametrize("name", ["fd7_1lvl_x", "tg_x", "tg_ud"])
-def test_solve(name):
-    c, ref, hs = _build(name)
+def test_solve(name, sf):
+    c, ref, hs = _build(name, slab_factor=sf)
     try:
         f = point_source(c.shape, tuple(s // 2 for s in c.shape), 0.05)
         u, it, rr = hs.solve(hs.rhs(_t(f)), tol=1e-6, maxit=100)
@@ -204,4 +217,39 @@ def test_fp64_and_bad_stencil_rejected_in_3d():
     assert e.value.status == -1 and "HSP_MIXED" in str(e.value)
     with pytest.raises(HspError) as e:
         Helmholtz(torch.tensor(c, device=_dev()), 20.0, 0.05, 2, 1, fine_stencil=5)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("sf", SF)
+def test_singular_slab_gives_esingular_in_3d(sf):
+    """A separator block forced to zero (debug knob) reaches HSP_ESINGULAR
+    through the ABI for both factorizations."""
+    from paper_1412_0464_amd import Helmholtz, HspError, hsp
+    c = _medium((17, 8, 9), 3)
+    print(f"[3d failure path: singular block of slab 1, {sf}]", flush=True)
+    hsp.debug_set("singular_slab", 1)
+    try:
+        with pytest.raises(HspError) as e:
+            Helmholtz(torch.tensor(c, device=_dev()), 2 * np.pi * 1.5 / (8.0 * 0.05), 0.05, 3, 3, w_dd=2,
+                      slab_factor=sf)
+        assert e.value.status == hsp.HSP_ESINGULAR
+    finally:
+        hsp.debug_set("singular_slab", -1)
+
+
+def test_nested_dissection_fronts_span_levels():
+    """The nested dissection of a 9 x 11 plane has several levels, and its
+    pivot growth stays moderate on the two-grid case."""
+    c, ref, hs = _build("tg_x")
+    try:
+        assert hs.slab_factor == "nd" and 0 < hs.pivot_growth < 1e3
+    finally:
+        hs.close()
+
+
+def test_slab_factor_rejected_in_2d():
+    from paper_1412_0464_amd import Helmholtz, HspError
+    c = np.ones((20, 20))
+    with pytest.raises(HspError) as e:
+        Helmholtz(torch.tensor(c, device=_dev()), 20.0, 0.05, 3, 2, slab_factor="nd")
     assert e.value.status == -1
