@@ -331,10 +331,12 @@ def c4_medium(cfg, seed=1412047):
     return np.pad(smooth_medium_3d(n, n, n, seed, corr_len=10.0), w, mode="edge")
 
 
-def c4_run(steps, warmup, tol, profile=True):
+def c4_run(steps, warmup, tol, profile=True, slab_factor="nd"):
     """Setup (timed alone), then ``steps`` solves of a point source at the
     centre to ``tol``; optionally a profiled repeat with event pairs around
-    every kernel class."""
+    every kernel class.  ``slab_factor``: 'nd' (nested dissection of the
+    slab planes, the default) or 'block' (block tridiagonal along y);
+    ``steps`` = 0 stops after the setup."""
     import torch
     from paper_1412_0464_amd import Helmholtz
     from synth.media import point_source
@@ -345,10 +347,13 @@ def c4_run(steps, warmup, tol, profile=True):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hs = Helmholtz(ct, cfg["omega"], cfg["h"], cfg["w"], cfg["J"], two_grid=True, w_dd=cfg["w_dd"],
-                   omega_jac=cfg["omega_jac"], restart=60)
+                   omega_jac=cfg["omega_jac"], restart=60, slab_factor=slab_factor)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    print(f"[bench] c4 setup {setup_s:.3f} s, pivot growth {hs.pivot_growth:.3f}", file=sys.stderr, flush=True)
+    print(f"[bench] c4 ({slab_factor}) setup {setup_s:.3f} s, pivot growth {hs.pivot_growth:.3f}", file=sys.stderr,
+          flush=True)
+    if steps == 0:
+        return {"setup_s": setup_s, "slab_factor": slab_factor, "u": None, "hs": hs}
     f = point_source(c.shape, tuple(s // 2 for s in c.shape), cfg["h"])
     b = hs.rhs(torch.tensor(f, dtype=torch.complex128, device=dev))
     u = torch.empty_like(b)
@@ -365,7 +370,8 @@ def c4_run(steps, warmup, tol, profile=True):
     dof = cfg["n"] ** 3
     out = {"workload": cfg["workload"], "value": dof * its / dt, "unit": UNIT, "solve_s": dt / steps,
            "setup_s": setup_s, "iterations": it, "relres": rr, "dof_interior": dof, "unknowns": int(c.size),
-           "pivot_growth": hs.pivot_growth, "precision": "mixed (complex64 factors on FP32 MFMA, complex128 FGMRES)"}
+           "pivot_growth": hs.pivot_growth, "precision": "mixed (complex64 factors on FP32 MFMA, complex128 FGMRES)",
+           "slab_factor": slab_factor}
     if profile:
         hs.profile(True)
         for cls in CLASSES:
@@ -382,6 +388,18 @@ def c4_run(steps, warmup, tol, profile=True):
     out["u"] = u
     out["hs"] = hs
     return out
+
+
+def c4_report(args, slab_factor, setup_only=False):
+    r4 = c4_run(0 if setup_only else args.steps, args.warmup, args.tol, slab_factor=slab_factor)
+    r4.pop("u")
+    hs = r4.pop("hs")
+    hs.close()
+    if setup_only:
+        return r4
+    print(f"[bench] c4 ({slab_factor}): setup {r4['setup_s']:.2f} s, solve {r4['solve_s'] * 1e3:.1f} ms, "
+          f"{r4['iterations']} iterations, {r4['value']:.3e} dof*iter/s", file=sys.stderr, flush=True)
+    return r4
 
 
 def gpu_run(cfg, c, f, precision, steps, warmup, tol, profile=False):
@@ -529,6 +547,9 @@ def main():
     ap.add_argument("--c3-only", action="store_true",
                     help="time only the group workload (no config-2 runs, no CPU baseline)")
     ap.add_argument("--c4-only", action="store_true", help="time only the 3-D workload")
+    ap.add_argument("--c4-slab-factor", nargs="+", choices=("nd", "block"), default=["nd", "block"],
+                    help="3-D slab factorizations to time (nested dissection, block tridiagonal)")
+    ap.add_argument("--c4-setup-only", action="store_true", help="with --c4-only: stop after the setups")
     ap.add_argument("--c3-graph", choices=("both", "off", "on"), default="both",
                     help="group solves eager (off), with the preconditioner captured in a graph (on), or both")
     ap.add_argument("--tile", type=int, default=0, help="right-hand-side tile (0: tuned)")
@@ -550,12 +571,11 @@ def main():
 
     c3_graphs = {"both": (False, True), "off": (False,), "on": (True,)}[args.c3_graph]
     if args.c4_only:
-        r4 = c4_run(args.steps, args.warmup, args.tol)
-        r4.pop("u")
-        r4.pop("hs")
-        print(f"[bench] c4: setup {r4['setup_s']:.2f} s, solve {r4['solve_s'] * 1e3:.1f} ms, {r4['iterations']} "
-              f"iterations, {r4['value']:.3e} dof*iter/s", file=sys.stderr, flush=True)
-        print(json.dumps({"c4": r4}))
+        out = {}
+        for sf in args.c4_slab_factor:
+            r4 = c4_report(args, sf, args.c4_setup_only)
+            out["c4" if sf == "nd" else "c4_" + sf] = r4
+        print(json.dumps(out))
         return
     if args.c3_only:
         out = {}
@@ -675,12 +695,8 @@ def main():
         for graph in c3_graphs:
             out["c3_graph" if graph else "c3"] = c3_report(args, graph)
     if not args.no_c4:
-        r4 = c4_run(args.steps, args.warmup, args.tol)
-        r4.pop("u")
-        r4.pop("hs")
-        print(f"[bench] c4: setup {r4['setup_s']:.2f} s, solve {r4['solve_s'] * 1e3:.1f} ms, {r4['iterations']} "
-              f"iterations, {r4['value']:.3e} dof*iter/s", file=sys.stderr, flush=True)
-        out["c4"] = r4
+        for sf in args.c4_slab_factor:
+            out["c4" if sf == "nd" else "c4_" + sf] = c4_report(args, sf)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, c, fs[0], args.cpu_iters, args.tol)

@@ -248,9 +248,12 @@ struct NDGeom {       // one front of the plane (shared by all slabs)
 //   GN = [F11^-1 ; -F21 F11^-1]   (nf x s, row stride s + (s & 1)) and
 //   E  = F11^-1 F12               (s x b, row stride b + (b & 1)),
 // the offset of the front's update vector (b entries) in a task's scratch,
-// and (setup only) its dense front matrix.
+// the offset of its gather maps in NDSolve::maps (s + b + 2 nf ints: the
+// slab-layout positions of the separator and ring unknowns, then for every
+// front unknown the positions of the two children's update-vector entries
+// that add to it, -1 for none) and (setup only) its dense front matrix.
 struct NDFront {
-  size_t gn, e, u;
+  size_t gn, e, u, m;
   cf* F;
 };
 struct NDJob {
@@ -258,13 +261,12 @@ struct NDJob {
 };
 
 // Device view of the plan for the stage kernels.  Items are (front, first
-// row) pairs, four rows per workgroup: forward items cover the nf rows of
-// GN, backward items the s rows of E (fronts with a ring); the tables give
-// (offset, count) per slab and level.
+// row) pairs, a level-dependent number of rows per workgroup: forward items
+// cover the nf rows of GN, backward items the s rows of E (fronts with a
+// ring); the tables give (offset, count) per slab and level.
 struct NDSolve {
   const NDGeom* geom;
-  const int* pts;
-  const int* chmap;
+  const int* maps;
   const NDFront* fr;  // [slab][front]
   int nfronts, depth;
   const int2* items;
@@ -304,7 +306,9 @@ struct NDSetup {
   const int* chmap;
   const int* cmap;
   NDFront* fr;               // device [slab][front]
-  int nslabs, nfronts, m2, m3;
+  int nslabs, nfronts, m2, m3, n_max;
+  cf* coef;                  // [slab][m2 n][27]: coefficient rows of every slab
+  const size_t* coef_off;    // device [slab]: element offset into coef
   cf* factors;
   const NDJob* jobs;         // device, all levels
   GJob* gjobs;               // device, all levels
@@ -317,7 +321,13 @@ struct NDLevelHost {
   int first_job = 0, njobs = 0;  // into the job tables
   int s_max = 0, b_max = 0, nf_max = 0;
   int fwd_items = 0, bwd_items = 0;  // max over slabs (grid size)
+  int fwd_g = 64, fwd_np = 1;        // lanes per row and pairs per lane of the substitutions
+  int bwd_g = 64, bwd_np = 1;
+  int fwd_rows() const { return 4 * 64 / fwd_g; }  // rows per workgroup
+  int bwd_rows() const { return 4 * 64 / bwd_g; }
 };
+// Lanes per row and pairs of complex entries per lane for rows of n entries.
+void nd_row_shape(int n, int* g, int* np);
 void launch_factor_nd(const NDSetup& Su, const std::vector<NDLevelHost>& lv, hipStream_t s);
 
 // One SubdomSolve stage of the 3-D sweep: ntasks tasks, each a slab solve

@@ -50,11 +50,11 @@ struct D3Ctx {
   std::vector<d3::NDSizes> ndz;        // per slab
   std::vector<d3::NDLevelHost> ndlv;   // per level
   d3::NDSolve nds{};
-  size_t nd_njobs = 0, nd_nitems = 0, nd_u_stride = 0;
+  size_t nd_njobs = 0, nd_nitems = 0, nd_u_stride = 0, nd_nmaps = 0;
   size_t nd_buf[2] = {0, 0};           // complex64 elements of the two level buffers
   size_t nd_piv = 0, nd_brow = 0, nd_spr = 0;  // Gauss-Jordan scratch of the largest level
   size_t o_ndgeom = 0, o_ndpts = 0, o_ndlmap = 0, o_ndchmap = 0, o_ndcmap = 0, o_ndfr = 0, o_nditems = 0,
-         o_ndtab = 0, o_ndU = 0;
+         o_ndtab = 0, o_ndU = 0, o_ndmaps = 0;
   size_t nf() const { return (size_t)m[0] * m[1] * m[2]; }
   size_t nd() const { return (size_t)dm[0] * dm[1] * dm[2]; }
 };
@@ -96,9 +96,15 @@ hsp_status validate3(const hsp_grid* g, int J, const hsp_options* o) {
 }
 
 // Bytes of the setup scratch of the nested-dissection factorization.
+size_t nd_coef_elems(const D3Ctx& D, int J) {
+  size_t n = 0;
+  for (int j = 0; j < J; ++j) n += (size_t)D.nls[j] * D.dm[2] * D.dm[1] * 27;
+  return n;
+}
 size_t nd_setup_bytes(const D3Ctx& D, int J) {
-  return (D.nd_buf[0] + D.nd_buf[1] + D.nd_brow + D.nd_spr) * sizeof(cf) + 2 * D.nd_piv * sizeof(int) +
-         D.nd_njobs * (sizeof(d3::NDJob) + sizeof(d3::GJob)) + (size_t)J * 2 * sizeof(double) + 8 * 256;
+  return (D.nd_buf[0] + D.nd_buf[1] + D.nd_brow + D.nd_spr + nd_coef_elems(D, J)) * sizeof(cf) +
+         2 * D.nd_piv * sizeof(int) + D.nd_njobs * (sizeof(d3::NDJob) + sizeof(d3::GJob)) +
+         (size_t)J * (2 * sizeof(double) + sizeof(size_t)) + 10 * 256;
 }
 
 // The dissection, the per-slab sizes, the level table and the scratch sizes.
@@ -125,25 +131,33 @@ hsp_status plan_nd(D3Ctx& D, int J) {
   D.nd_njobs = 0;
   D.nd_buf[0] = D.nd_buf[1] = 0;
   D.nd_piv = D.nd_brow = D.nd_spr = 0;
+  D.nd_nmaps = 0;
   for (int L = 0; L < np.depth; ++L) {
     d3::NDLevelHost& l = D.ndlv[L];
     l.first_job = (int)D.nd_njobs;
     l.njobs = J * (int)np.levels[L].size();
     D.nd_njobs += l.njobs;
+    for (int j = 0; j < J; ++j)
+      for (int f : np.levels[L]) {
+        const d3::NDGeom& g = np.fronts[f];
+        l.s_max = std::max(l.s_max, g.ns * D.nls[j]);
+        l.b_max = std::max(l.b_max, g.nb * D.nls[j]);
+        l.nf_max = std::max(l.nf_max, (g.ns + g.nb) * D.nls[j]);
+      }
+    d3::nd_row_shape(l.s_max, &l.fwd_g, &l.fwd_np);
+    d3::nd_row_shape(l.b_max, &l.bwd_g, &l.bwd_np);
     size_t buf = 0, piv = 0, brow = 0;
     for (int j = 0; j < J; ++j) {
       int fi = 0, bi = 0;
       for (int f : np.levels[L]) {
         const d3::NDGeom& g = np.fronts[f];
         const int s = g.ns * D.nls[j], b = g.nb * D.nls[j], nf = s + b;
-        l.s_max = std::max(l.s_max, s);
-        l.b_max = std::max(l.b_max, b);
-        l.nf_max = std::max(l.nf_max, nf);
         buf += (size_t)nf * nf;
         piv += s;
         brow += (size_t)32 * nf;
-        fi += (nf + 3) / 4;
-        if (b > 0) bi += (s + 3) / 4;
+        fi += (nf + l.fwd_rows() - 1) / l.fwd_rows();
+        if (b > 0) bi += (s + l.bwd_rows() - 1) / l.bwd_rows();
+        D.nd_nmaps += (size_t)s + b + 2 * (size_t)nf;
       }
       l.fwd_items = std::max(l.fwd_items, fi);
       l.bwd_items = std::max(l.bwd_items, bi);
@@ -273,6 +287,7 @@ hsp_status plan3(const hsp_grid* g, int J, const hsp_options* o, D3Ctx& D, Plan&
     D.o_nditems = c.take(std::max<size_t>(D.nd_nitems, 1) * sizeof(int2));
     D.o_ndtab = c.take((size_t)J * np.depth * 4 * sizeof(int));
     D.o_ndU = c.take((size_t)P.maxtask * D.nd_u_stride * sizeof(cf));
+    D.o_ndmaps = c.take(D.nd_nmaps * sizeof(int));
   }
   D.o_status = c.take(64);
   D.o_growth = c.take((size_t)J * sizeof(double));
@@ -693,6 +708,8 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
     d3::NDJob* jobs_dev = reinterpret_cast<d3::NDJob*>(base + sc.take(D.nd_njobs * sizeof(d3::NDJob)));
     d3::GJob* gjobs_dev = reinterpret_cast<d3::GJob*>(base + sc.take(D.nd_njobs * sizeof(d3::GJob)));
     double* gmax = reinterpret_cast<double*>(base + sc.take((size_t)J * 2 * sizeof(double)));
+    cf* coefs = reinterpret_cast<cf*>(base + sc.take(nd_coef_elems(D, J) * sizeof(cf)));
+    size_t* coef_off = reinterpret_cast<size_t*>(base + sc.take((size_t)J * sizeof(size_t)));
     if (sc.off > nd_setup_bytes(D, J)) return cleanup(fail(HSP_EINVAL, "internal: nested-dissection scratch"));
     // per slab and front: factor and update offsets, front matrices
     std::vector<d3::NDFront> fr((size_t)J * nfr);
@@ -712,6 +729,50 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
         e.F = nullptr;
       }
     }
+    // gather maps: slab-layout positions of the separator and ring unknowns,
+    // the children's update-vector entries of every front unknown
+    std::vector<int> maps;
+    maps.reserve(D.nd_nmaps);
+    {
+      const int ldv = D.n_max + (D.n_max & 1), m3 = D.dm[2];
+      for (int j = 0; j < J; ++j) {
+        const int nl = D.nls[j];
+        for (int f = 0; f < nfr; ++f) {
+          const d3::NDGeom& g = np.fronts[f];
+          const int sv = g.ns * nl, bv = g.nb * nl, nf = sv + bv;
+          fr[(size_t)j * nfr + f].m = maps.size();
+          auto var = [&](int v, int& xl, int& Pt) {
+            if (v < sv) {
+              xl = v / g.ns;
+              Pt = v % g.ns;
+            } else {
+              xl = (v - sv) / g.nb;
+              Pt = g.ns + (v - sv) % g.nb;
+            }
+          };
+          for (int v = 0; v < nf; ++v) {
+            int xl, Pt;
+            var(v, xl, Pt);
+            const int p2 = np.pts[g.pt_off + Pt];
+            maps.push_back((p2 / m3) * ldv + xl * m3 + p2 % m3);
+          }
+          for (int c = 0; c < 2; ++c)
+            for (int v = 0; v < nf; ++v) {
+              int idx = -1;
+              const int ch = g.child[c];
+              if (ch >= 0) {
+                int xl, Pt;
+                var(v, xl, Pt);
+                const int qc = np.chmap[g.chmap_off[c] + Pt];
+                if (qc >= 0) idx = (int)(fr[(size_t)j * nfr + ch].u + (size_t)xl * np.fronts[ch].nb + qc);
+              }
+              maps.push_back(idx);
+            }
+        }
+      }
+    }
+    if (maps.size() != D.nd_nmaps) return cleanup(fail(HSP_EINVAL, "internal: nested-dissection maps"));
+    up(D.o_ndmaps, maps.data(), maps.size() * sizeof(int));
     if (ofac != D.n_fac) return cleanup(fail(HSP_EINVAL, "internal: nested-dissection factor size"));
     // jobs level by level (slab-major within a level); front matrices in the
     // buffer of the level's parity, Gauss-Jordan scratch reused per level
@@ -744,6 +805,13 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
     }
     up(D.o_ndfr, fr.data(), fr.size() * sizeof(d3::NDFront));
     CHK(hipMemcpyAsync(jobs_dev, jobs.data(), jobs.size() * sizeof(d3::NDJob), hipMemcpyHostToDevice, s));
+    std::vector<size_t> coff(J);
+    size_t o_coef = 0;
+    for (int j = 0; j < J; ++j) {
+      coff[j] = o_coef;
+      o_coef += (size_t)D.nls[j] * D.dm[2] * D.dm[1] * 27;
+    }
+    CHK(hipMemcpyAsync(coef_off, coff.data(), J * sizeof(size_t), hipMemcpyHostToDevice, s));
     CHK(hipMemcpyAsync(gjobs_dev, gjobs.data(), gjobs.size() * sizeof(d3::GJob), hipMemcpyHostToDevice, s));
     // substitution items: (front, first row) per slab and level, forward and backward
     std::vector<int2> items;
@@ -757,7 +825,7 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
         for (int f : np.levels[L]) {
           const d3::NDGeom& g = np.fronts[f];
           const int nf = (g.ns + g.nb) * D.nls[j];
-          for (int r0 = 0; r0 < nf; r0 += 4) items.push_back(make_int2(f, r0));
+          for (int r0 = 0; r0 < nf; r0 += D.ndlv[L].fwd_rows()) items.push_back(make_int2(f, r0));
         }
         ft[1] = (int)items.size() - ft[0];
         bt[0] = (int)items.size();
@@ -765,7 +833,7 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
           const d3::NDGeom& g = np.fronts[f];
           if (g.nb == 0) continue;
           const int sv = g.ns * D.nls[j];
-          for (int r0 = 0; r0 < sv; r0 += 4) items.push_back(make_int2(f, r0));
+          for (int r0 = 0; r0 < sv; r0 += D.ndlv[L].bwd_rows()) items.push_back(make_int2(f, r0));
         }
         bt[1] = (int)items.size() - bt[0];
       }
@@ -786,6 +854,9 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
     Su.nfronts = nfr;
     Su.m2 = D.dm[1];
     Su.m3 = D.dm[2];
+    Su.n_max = D.n_max;
+    Su.coef = coefs;
+    Su.coef_off = coef_off;
     Su.factors = D.factors;
     Su.jobs = jobs_dev;
     Su.gjobs = gjobs_dev;
@@ -805,8 +876,7 @@ hsp_status d3_setup(const double* c_dev, double omega, const hsp_grid* grid, int
     for (int j = 0; j < J; ++j) hg[j] = gm[2 * j] > 0 ? std::sqrt(gm[2 * j + 1] / gm[2 * j]) : 0.0;
     // device view for the stages
     D.nds.geom = Su.geom;
-    D.nds.pts = Su.pts;
-    D.nds.chmap = Su.chmap;
+    D.nds.maps = C->raw<int>(D.o_ndmaps);
     D.nds.fr = Su.fr;
     D.nds.nfronts = nfr;
     D.nds.depth = np.depth;

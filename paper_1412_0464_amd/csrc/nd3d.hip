@@ -20,9 +20,10 @@
 // forms v = its separator's right-hand side plus its children's update
 // vectors, z = F11^-1 v (kept in the solution vector) and its own update
 // vector u = v_ring - F21 F11^-1 v; backward, root to leaves,
-// x = z - F11^-1 F12 x_ring.  Both are dense matrix-vector products with
-// one wavefront per row, all fronts of a level (and all tasks of a stage) in
-// one launch.
+// x = z - F11^-1 F12 x_ring.  Both are dense matrix-vector products, a
+// group of lanes per row sized to the level's row length, all fronts of a
+// level (and all tasks of a stage) in one launch; the right-hand side and
+// solution entries are found through per-front gather maps built at setup.
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -199,10 +200,47 @@ __device__ __forceinline__ void atomic_max_pos(double* a, double v) {
 // ---- setup -----------------------------------------------------------------------
 constexpr int kAsmRows = 2;  // front rows per workgroup of the assembly (one per wavefront)
 
+// Block reduction of a non-negative value into *a (max).
+__device__ __forceinline__ void block_max_into(double v, double* a) {
+  __shared__ double sh[4];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) m = fmax(m, sh[w]);
+    if (m > 0) atomic_max_pos(a, m);
+  }
+}
+
+// The 27 coefficients of every slab row (slab layout: y-block, x_l m3 + z),
+// and the largest |entry| of the slab operator.
+__global__ void __launch_bounds__(256) kn_coef(NDSetup Su) {
+  const Slab3 sl = Su.slabs[blockIdx.y];
+  const int n = sl.n, m3 = Su.m3;
+  const size_t idx = blockIdx.x * 256ull + threadIdx.x;
+  double amax = 0;
+  if (idx < (size_t)n * Su.m2) {
+    const int y = (int)(idx / n), q = (int)(idx - (idx / n) * n);
+    const int xl = q / m3, z = q - (q / m3) * m3;
+    cd c[27];
+    coefs27(sl.op, xl + 1, y + 1, z + 1, c);
+    cf* o = Su.coef + Su.coef_off[blockIdx.y] + idx * 27;
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+      o[k] = cvt<float>(c[k]);
+      amax = fmax(amax, abs2(c[k]));
+    }
+  }
+  block_max_into(amax, Su.gmax + 2 * blockIdx.y);
+}
+
 // Front matrices of one level: each wavefront builds one row in LDS (zero,
 // the slab operator's entries that belong to the front, the children's
-// Schur complements in child order) and writes it out.
-__global__ void __launch_bounds__(64 * kAsmRows) kn_assemble(NDSetup Su, const NDJob* __restrict__ jobs) {
+// Schur complements in child order) and writes it out.  Dynamic LDS:
+// kAsmRows rows of the level's largest front.
+__global__ void __launch_bounds__(64 * kAsmRows) kn_assemble(NDSetup Su, const NDJob* __restrict__ jobs, int ldr) {
   const NDJob jb = jobs[blockIdx.y];
   const Slab3 sl = Su.slabs[jb.slab];
   const NDGeom g = Su.geom[jb.front];
@@ -211,25 +249,14 @@ __global__ void __launch_bounds__(64 * kAsmRows) kn_assemble(NDSetup Su, const N
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = blockIdx.x * kAsmRows + wv;
   const bool ok = r < nf;
-  __shared__ cf rowbuf[kAsmRows][kNDMaxFront];
-  __shared__ cf cofs[kAsmRows][27];
-  cf* row = rowbuf[wv];
+  extern __shared__ cf rowbuf[];
+  cf* row = rowbuf + (size_t)wv * ldr;
   for (int j = lane; j < nf; j += 64) row[j] = mk<float>(0, 0);
   int xl = 0, P = 0;
   if (ok) var_of(r, g.ns, g.nb, nl, xl, P);
   const int p2 = Su.pts[g.pt_off + (ok ? P : 0)];
   const int y = p2 / m3, z = p2 - (p2 / m3) * m3;
   const bool sep_row = ok && r < s;
-  double amax = 0;
-  if (ok && lane == 0) {
-    cd c[27];
-    coefs27(sl.op, xl + 1, y + 1, z + 1, c);
-#pragma unroll
-    for (int k = 0; k < 27; ++k) {
-      cofs[wv][k] = cvt<float>(c[k]);
-      if (sep_row) amax = fmax(amax, abs2(c[k]));
-    }
-  }
   __syncthreads();
   if (ok && lane < 27) {
     const int dx = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dz = lane % 3 - 1;
@@ -241,7 +268,8 @@ __global__ void __launch_bounds__(64 * kAsmRows) kn_assemble(NDSetup Su, const N
       // ring rows only those to the separator (the rest belongs to ancestors)
       if (Q >= 0 && (sep_row || Q < g.ns)) {
         const int v = var_idx(xx, Q, g.ns, g.nb, nl);
-        row[v] = row[v] + cofs[wv][lane];
+        const size_t ri = (size_t)y * sl.n + (size_t)xl * m3 + z;
+        row[v] = row[v] + Su.coef[Su.coef_off[jb.slab] + ri * 27 + lane];
       }
     }
   }
@@ -278,10 +306,7 @@ __global__ void __launch_bounds__(64 * kAsmRows) kn_assemble(NDSetup Su, const N
     }
   }
   for (int off = 32; off > 0; off >>= 1) fmaxv = fmax(fmaxv, __shfl_xor(fmaxv, off, 64));
-  if (lane == 0 && ok) {
-    if (amax > 0) atomic_max_pos(Su.gmax + 2 * jb.slab, amax);
-    if (fmaxv > 0) atomic_max_pos(Su.gmax + 2 * jb.slab + 1, fmaxv);
-  }
+  if (lane == 0 && ok && fmaxv > 0) atomic_max_pos(Su.gmax + 2 * jb.slab + 1, fmaxv);
 }
 
 // GN = [F11^-1 ; -F21 F11^-1] (columns un-permuted) and E = F11^-1 F12.
@@ -304,62 +329,52 @@ __global__ void __launch_bounds__(256) kn_store(NDSetup Su, const NDJob* __restr
 }
 
 // ---- substitutions -------------------------------------------------------------
-constexpr int kRows = 4;  // rows per workgroup (one per wavefront)
+// Each row of a factor block is taken by a group of G lanes (64 / G rows
+// per wavefront, four wavefronts per workgroup), every lane holding NP
+// pairs of complex entries (16 bytes each) of its row; all loads of the
+// rows are issued before the input vector is gathered into LDS.
 
-template <int NP>
-__device__ __forceinline__ void load_row(floatx4 (&a)[NP], const cf* row, int npair, int lane) {
-  const floatx4* w = reinterpret_cast<const floatx4*>(row) + lane;
+template <int NP, int G>
+__device__ __forceinline__ void load_rows(floatx4 (&a)[NP], const cf* row, int npair, int sub) {
+  const floatx4* w = reinterpret_cast<const floatx4*>(row) + sub;
 #pragma unroll
   for (int k = 0; k < NP; ++k)
-    a[k] = (lane + 64 * k < npair) ? __builtin_nontemporal_load(w + 64 * k) : floatx4{0.f, 0.f, 0.f, 0.f};
+    a[k] = (sub + G * k < npair) ? __builtin_nontemporal_load(w + G * k) : floatx4{0.f, 0.f, 0.f, 0.f};
 }
 
-template <int NP>
-__device__ __forceinline__ cf row_dot(const floatx4 (&a)[NP], const cf* vin, int npair, int lane) {
-  const floatx4* vv = reinterpret_cast<const floatx4*>(vin) + lane;
+template <int NP, int G>
+__device__ __forceinline__ cf group_dot(const floatx4 (&a)[NP], const cf* vin, int npair, int sub) {
+  const floatx4* vv = reinterpret_cast<const floatx4*>(vin) + sub;
   float ar = 0, ai = 0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    if (lane + 64 * k < npair) {
-      const floatx4 x = vv[64 * k];
+    if (sub + G * k < npair) {
+      const floatx4 x = vv[G * k];
       ar += a[k].x * x.x - a[k].y * x.y + a[k].z * x.z - a[k].w * x.w;
       ai += a[k].x * x.y + a[k].y * x.x + a[k].z * x.w + a[k].w * x.z;
     }
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
+  for (int off = G / 2; off > 0; off >>= 1) {
     ar += __shfl_xor(ar, off, 64);
     ai += __shfl_xor(ai, off, 64);
   }
   return mk<float>(ar, ai);
 }
 
-// Position of front point P, layer xl, in a task's slab-layout vector.
-__device__ __forceinline__ size_t slab_pos(const NDSolve& nd, const NDGeom& g, int xl, int P, int m3, int ldv) {
-  const int p2 = nd.pts[g.pt_off + P];
-  const int y = p2 / m3, z = p2 - (p2 / m3) * m3;
-  return (size_t)y * ldv + (size_t)xl * m3 + z;
-}
-
-// Sum of the children's update vectors at front point P, layer xl.
-__device__ __forceinline__ cf child_sum(const NDSolve& nd, const NDGeom& g, int slab, int xl, int P, const cf* U) {
-  cf v = mk<float>(0, 0);
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int ch = g.child[c];
-    if (ch < 0) continue;
-    const int qc = nd.chmap[g.chmap_off[c] + P];
-    if (qc < 0) continue;
-    const int nbc = nd.geom[ch].nb;
-    v = v + U[nd.fr[(size_t)slab * nd.nfronts + ch].u + (size_t)xl * nbc + qc];
-  }
-  return v;
+// children's update-vector entries that add to front unknown v
+__device__ __forceinline__ cf child_sum(const int* __restrict__ ch, int nf, int v, const cf* U) {
+  const int a = ch[v], b = ch[nf + v];
+  cf r = mk<float>(0, 0);
+  if (a >= 0) r = U[a];
+  if (b >= 0) r = r + U[b];
+  return r;
 }
 
 // Forward substitution of one level: rows of GN against v = [f_sep + the
 // children's updates]; separator rows give z (into ys), ring rows the
 // front's update vector.
-template <int NP>
+template <int NP, int G>
 __global__ void __launch_bounds__(256) kn_fwd(Stage3 st, NDSolve nd, int level) {
   const TaskDev tk = st.tasks[blockIdx.y];
   const int* tab = nd.fwd_tab + ((size_t)tk.slab * nd.depth + level) * 2;
@@ -368,42 +383,35 @@ __global__ void __launch_bounds__(256) kn_fwd(Stage3 st, NDSolve nd, int level) 
   const Slab3 sl = st.slabs[tk.slab];
   const NDGeom g = nd.geom[it.x];
   const NDFront fr = nd.fr[(size_t)tk.slab * nd.nfronts + it.x];
-  const int nl = sl.nl, m3 = st.G.m3, m2 = st.G.m2;
-  const int s = g.ns * nl, nf = (g.ns + g.nb) * nl;
+  const int nl = sl.nl, m2 = st.G.m2;
+  const int s = g.ns * nl, b = g.nb * nl, nf = s + b;
   const int ldv = st.n_max + (st.n_max & 1);
   const cf* fs = st.fs + (size_t)blockIdx.y * m2 * ldv;
   cf* ys = st.ys + (size_t)blockIdx.y * m2 * ldv;
   cf* U = nd.U + (size_t)blockIdx.y * nd.u_stride;
-  __shared__ __align__(16) cf vin[128 * NP];
+  const int* sep = nd.maps + fr.m;
+  const int* ch = sep + s + b;
+  __shared__ __align__(16) cf vin[2 * G * NP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int r = it.y + wv;
+  const int sub = lane % G;
+  const int r = it.y + wv * (64 / G) + lane / G;
   const bool ok = r < nf;
   const int npair = (s + 1) / 2;
   floatx4 a[NP];
-  load_row(a, st.factors + fr.gn + (size_t)(ok ? r : 0) * (s + (s & 1)), npair, lane);
-  for (int e = tid; e < 2 * npair; e += 256) {
-    cf v = mk<float>(0, 0);
-    if (e < s) {
-      int xl, P;
-      var_of(e, g.ns, g.nb, nl, xl, P);
-      v = fs[slab_pos(nd, g, xl, P, m3, ldv)] + child_sum(nd, g, tk.slab, xl, P, U);
-    }
-    vin[e] = v;
-  }
+  load_rows<NP, G>(a, st.factors + fr.gn + (size_t)(ok ? r : 0) * (s + (s & 1)), npair, sub);
+  for (int e = tid; e < 2 * npair; e += 256) vin[e] = e < s ? fs[sep[e]] + child_sum(ch, nf, e, U) : mk<float>(0, 0);
   __syncthreads();
-  const cf d = row_dot(a, vin, npair, lane);
-  if (lane == 0 && ok) {
-    int xl, P;
-    var_of(r, g.ns, g.nb, nl, xl, P);
+  const cf d = group_dot<NP, G>(a, vin, npair, sub);
+  if (sub == 0 && ok) {
     if (r < s)
-      ys[slab_pos(nd, g, xl, P, m3, ldv)] = d;
+      ys[sep[r]] = d;
     else
-      U[fr.u + (r - s)] = d + child_sum(nd, g, tk.slab, xl, P, U);
+      U[fr.u + (r - s)] = d + child_sum(ch, nf, r, U);
   }
 }
 
 // Backward substitution of one level: x_sep = z - E x_ring.
-template <int NP>
+template <int NP, int G>
 __global__ void __launch_bounds__(256) kn_bwd(Stage3 st, NDSolve nd, int level) {
   const TaskDev tk = st.tasks[blockIdx.y];
   const int* tab = nd.bwd_tab + ((size_t)tk.slab * nd.depth + level) * 2;
@@ -412,30 +420,25 @@ __global__ void __launch_bounds__(256) kn_bwd(Stage3 st, NDSolve nd, int level) 
   const Slab3 sl = st.slabs[tk.slab];
   const NDGeom g = nd.geom[it.x];
   const NDFront fr = nd.fr[(size_t)tk.slab * nd.nfronts + it.x];
-  const int nl = sl.nl, m3 = st.G.m3, m2 = st.G.m2;
+  const int nl = sl.nl, m2 = st.G.m2;
   const int s = g.ns * nl, b = g.nb * nl;
   const int ldv = st.n_max + (st.n_max & 1);
   cf* ys = st.ys + (size_t)blockIdx.y * m2 * ldv;
-  __shared__ __align__(16) cf xin[128 * NP];
+  const int* sep = nd.maps + fr.m;
+  const int* ring = sep + s;
+  __shared__ __align__(16) cf xin[2 * G * NP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int r = it.y + wv;
+  const int sub = lane % G;
+  const int r = it.y + wv * (64 / G) + lane / G;
   const bool ok = r < s;
   const int npair = (b + 1) / 2;
   floatx4 a[NP];
-  load_row(a, st.factors + fr.e + (size_t)(ok ? r : 0) * (b + (b & 1)), npair, lane);
-  for (int e = tid; e < 2 * npair; e += 256) {
-    cf v = mk<float>(0, 0);
-    if (e < b) {
-      const int xl = e / g.nb, q = e - xl * g.nb;
-      v = ys[slab_pos(nd, g, xl, g.ns + q, m3, ldv)];
-    }
-    xin[e] = v;
-  }
+  load_rows<NP, G>(a, st.factors + fr.e + (size_t)(ok ? r : 0) * (b + (b & 1)), npair, sub);
+  for (int e = tid; e < 2 * npair; e += 256) xin[e] = e < b ? ys[ring[e]] : mk<float>(0, 0);
   __syncthreads();
-  const cf d = row_dot(a, xin, npair, lane);
-  if (lane == 0 && ok) {
-    const int xl = r / g.ns, P = r - xl * g.ns;
-    cf* y = ys + slab_pos(nd, g, xl, P, m3, ldv);
+  const cf d = group_dot<NP, G>(a, xin, npair, sub);
+  if (sub == 0 && ok) {
+    cf* y = ys + sep[r];
     *y = *y - d;
   }
 }
@@ -443,60 +446,62 @@ __global__ void __launch_bounds__(256) kn_bwd(Stage3 st, NDSolve nd, int level) 
 }  // namespace
 
 void launch_factor_nd(const NDSetup& Su, const std::vector<NDLevelHost>& lv, hipStream_t s) {
+  hipLaunchKernelGGL(kn_coef, dim3(nblk((size_t)Su.n_max * Su.m2), Su.nslabs), dim3(256), 0, s, Su);
   for (int L = (int)lv.size() - 1; L >= 0; --L) {
     const NDLevelHost& l = lv[L];
     if (l.njobs < 1) continue;
     const NDJob* jobs = Su.jobs + l.first_job;
     const GJob* gj = Su.gjobs + l.first_job;
-    hipLaunchKernelGGL(kn_assemble, dim3((l.nf_max + kAsmRows - 1) / kAsmRows, l.njobs), dim3(64 * kAsmRows), 0, s,
-                       Su, jobs);
+    const int ldr = l.nf_max + (l.nf_max & 1);
+    hipLaunchKernelGGL(kn_assemble, dim3((l.nf_max + kAsmRows - 1) / kAsmRows, l.njobs), dim3(64 * kAsmRows),
+                       kAsmRows * ldr * sizeof(cf), s, Su, jobs, ldr);
     launch_gauss_jordan(gj, l.njobs, l.s_max, l.b_max, l.nf_max, Su.status, s);
     const size_t cnt = (size_t)l.nf_max * l.s_max + (size_t)l.s_max * l.b_max;
     hipLaunchKernelGGL(kn_store, dim3(nblk(cnt), l.njobs), dim3(256), 0, s, Su, jobs, gj);
   }
 }
 
+void nd_row_shape(int n, int* g, int* np) {
+  const int pairs = (n + 1) / 2;
+  static const int shapes[][3] = {{16, 16, 1}, {32, 16, 2}, {48, 16, 3}, {64, 32, 2},  {128, 32, 4},
+                                  {256, 64, 4}, {384, 64, 6}, {512, 64, 8}, {768, 64, 12}, {1024, 64, 16}};
+  for (const auto& sh : shapes)
+    if (pairs <= sh[0]) {
+      *g = sh[1];
+      *np = sh[2];
+      return;
+    }
+  *g = 64;
+  *np = 16;
+}
+
 void launch_nd_solve(const Stage3& st, const NDSolve& nd, const std::vector<NDLevelHost>& lv, hipStream_t s) {
   const int depth = (int)lv.size();
-#define ND_FWD(NP) hipLaunchKernelGGL((kn_fwd<NP>), grd, dim3(256), 0, s, st, nd, L)
-#define ND_BWD(NP) hipLaunchKernelGGL((kn_bwd<NP>), grd, dim3(256), 0, s, st, nd, L)
-  for (int L = depth - 1; L >= 0; --L) {
+  auto fwd = [&](int L) {
     const dim3 grd(std::max(lv[L].fwd_items, 1), st.ntasks);
-    const int np = (lv[L].s_max + 127) / 128;
-    if (np <= 1)
-      ND_FWD(1);
-    else if (np <= 2)
-      ND_FWD(2);
-    else if (np <= 4)
-      ND_FWD(4);
-    else if (np <= 6)
-      ND_FWD(6);
-    else if (np <= 8)
-      ND_FWD(8);
-    else
-      ND_FWD(12);
+#define ND_F(NP, G)                                                                 \
+  if (lv[L].fwd_g == G && lv[L].fwd_np == NP) {                                     \
+    hipLaunchKernelGGL((kn_fwd<NP, G>), grd, dim3(256), 0, s, st, nd, L);           \
+    return;                                                                         \
   }
-  for (int L = 0; L < depth; ++L) {
-    if (lv[L].bwd_items < 1) continue;
+    ND_F(1, 16) ND_F(2, 16) ND_F(3, 16) ND_F(2, 32) ND_F(4, 32) ND_F(4, 64) ND_F(6, 64) ND_F(8, 64) ND_F(12, 64)
+    ND_F(16, 64)
+#undef ND_F
+  };
+  auto bwd = [&](int L) {
     const dim3 grd(lv[L].bwd_items, st.ntasks);
-    const int np = (lv[L].b_max + 127) / 128;
-    if (np <= 1)
-      ND_BWD(1);
-    else if (np <= 2)
-      ND_BWD(2);
-    else if (np <= 4)
-      ND_BWD(4);
-    else if (np <= 6)
-      ND_BWD(6);
-    else if (np <= 8)
-      ND_BWD(8);
-    else if (np <= 12)
-      ND_BWD(12);
-    else
-      ND_BWD(16);
+#define ND_B(NP, G)                                                                 \
+  if (lv[L].bwd_g == G && lv[L].bwd_np == NP) {                                     \
+    hipLaunchKernelGGL((kn_bwd<NP, G>), grd, dim3(256), 0, s, st, nd, L);           \
+    return;                                                                         \
   }
-#undef ND_FWD
-#undef ND_BWD
+    ND_B(1, 16) ND_B(2, 16) ND_B(3, 16) ND_B(2, 32) ND_B(4, 32) ND_B(4, 64) ND_B(6, 64) ND_B(8, 64) ND_B(12, 64)
+    ND_B(16, 64)
+#undef ND_B
+  };
+  for (int L = depth - 1; L >= 0; --L) fwd(L);
+  for (int L = 0; L < depth; ++L)
+    if (lv[L].bwd_items > 0) bwd(L);
 }
 
 }  // namespace d3
