@@ -62,7 +62,7 @@ CLASSES = ("stage", "smooth", "coarse", "transfer", "krylov", "project", "update
 COPY_BYTES = 256 << 20
 
 # tangential blocks per chunk of the slab substitutions in the batched solves
-BATCH_CHUNK = 34
+AUTOTUNE = -1  # --chunk value that asks the autotuner for the chunk length and tile
 
 METRIC = "dof·iter/s and solve time to 1e-6 rel. residual: FP32-batched vs plain FP64"
 UNIT = "dof·iter/s"
@@ -201,6 +201,22 @@ def sources(cfg, shape, nsrc, seed=1412048):
         k = int(rng.integers(w + 1, shape[1] - w - 1))
         out.append(point_source(shape, (i, k), cfg["h"]))
     return out
+
+
+def autotune_batch(cfg, c, nsrc, precision):
+    """Chunk length and tile for the batched solves of this problem from the
+    library's autotuner (one setup and four timed tile choices per candidate
+    chunk length); not part of any timed region."""
+    import torch
+    from paper_1412_0464_amd import hsp
+    ct = torch.tensor(c, device=torch.device("cuda:0"))
+    t0 = time.perf_counter()
+    chunk, tile, ms, table = hsp.autotune(ct, cfg["omega"], cfg["h"], cfg["w"], cfg["J"], nsrc, restart=1,
+                                          S_outer=cfg.get("S_outer", 0.0), c_pml=cfg.get("c_pml", 0.0),
+                                          two_grid=cfg["two_grid"], precision=precision)
+    torch.cuda.synchronize()
+    return {"chunk": chunk, "tile": tile, "ms": ms, "s": time.perf_counter() - t0,
+            "candidates": [{"chunk": m, "tile": t, "ms": x} for m, t, x in table]}
 
 
 def gpu_run_batch(cfg, c, fs, precision, steps, warmup, tol, restart=40, profile=False, tile=0, **opts):
@@ -553,9 +569,10 @@ def main():
     ap.add_argument("--c3-graph", choices=("both", "off", "on"), default="both",
                     help="group solves eager (off), with the preconditioner captured in a graph (on), or both")
     ap.add_argument("--tile", type=int, default=0, help="right-hand-side tile (0: tuned)")
-    ap.add_argument("--chunk", type=int, default=BATCH_CHUNK,
+    ap.add_argument("--chunk", type=int, default=AUTOTUNE,
                     help="tangential blocks per chunk of the slab substitutions in the batched solves "
-                         "(0: about sqrt of the tangential nodes, the single-source choice)")
+                         "(-1: chosen with the tile by the library's autotuner, hsp_autotune; 0: about sqrt of "
+                         "the tangential nodes, the single-source choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a streaming kernel of known size (for counter scaling)")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -591,6 +608,14 @@ def main():
     print(f"[bench] {cfg['workload']}: {dof} interior dof, {c.size} unknowns, {len(fs)} sources",
           file=sys.stderr, flush=True)
 
+    tuned = None
+    if args.chunk == AUTOTUNE:
+        tuned = autotune_batch(cfg, c, len(fs), "mixed")
+        args.chunk = tuned["chunk"]
+        if not args.tile:
+            args.tile = tuned["tile"]
+        print(f"[bench] autotuner: chunk {tuned['chunk']}, tile {tuned['tile']} ({tuned['ms']:.2f} ms per batched "
+              f"preconditioner application; {tuned['s']:.1f} s)", file=sys.stderr, flush=True)
     if args.copy_calibration:
         copy_calibration()
     bat = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, profile=True, tile=args.tile,
@@ -611,6 +636,8 @@ def main():
                    "solve_s_per_source": bat["solve_s"] / len(fs), "precision": "mixed",
                    "rhs_tile": bat["tile"], "chunk": args.chunk},
     }
+    if tuned is not None:
+        out["config"]["autotune"] = tuned
     # rooflines from the event-timed classes of the profiled repeat:
     # algorithmic bytes per launch / average launch time.  The dominant kernel
     # class is the SubdomSolve stage (two dependent launches timed as one,

@@ -316,6 +316,27 @@ hsp_status hsp_apply_precond_batch(hsp_handle hd, int nrhs, const void* r_dev, v
 hsp_status hsp_apply_precond_batch_noalloc(hsp_handle hd, int nrhs, const void* r_dev, void* z_dev, int tile,
                                            size_t* scratch_bytes, void* stream);
 
+/* Autotuner of the batched solvers' evaluation order (the map computed does
+ * not depend on it): for every chunk length of the candidate list 16, 20,
+ * 24, 28, 34, 40, 48, 64 (those that give distinct chunk counts for the
+ * tangential length of the slabs) the problem is set up with that chunk
+ * length and one batched preconditioner application of nrhs right-hand
+ * sides is timed for every tile (hsp_tune_batch); the fastest (chunk, tile)
+ * is returned, and the caller sets its solver up with that chunk (the tile
+ * is passed to the batched calls).  2-D only.
+ *   ws / bws  device workspaces of at least the sizes
+ *             hsp_autotune_workspace_size gives (setup and batch workspaces,
+ *             the largest over the candidates); overwritten.
+ *   chunk_out, tile_out, ms_out  the choice and its time per application;
+ *   table (optional, 3 doubles per candidate chunk: chunk, best tile, ms)
+ *   and *ntable (entries written; at most 8).
+ * Errors: those of hsp_setup and hsp_tune_batch. */
+hsp_status hsp_autotune_workspace_size(const hsp_grid* grid, int J, const hsp_options* opt, int nrhs, int restart,
+                                       size_t* ws_bytes, size_t* bws_bytes);
+hsp_status hsp_autotune(const double* c_dev, double omega, const hsp_grid* grid, int J, const hsp_options* opt,
+                        int nrhs, int restart, void* ws_dev, size_t ws_bytes, void* bws_dev, size_t bws_bytes,
+                        int* chunk_out, int* tile_out, double* ms_out, double* table, int* ntable, void* stream);
+
 /* Times one batched preconditioner application for every tile and keeps the
  * fastest for batches of nrhs right-hand sides (used when tile = 0).  Writes
  * into the batch workspace (sized for nrhs, restart).  tile_out and ms_out

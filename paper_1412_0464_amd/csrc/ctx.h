@@ -181,6 +181,8 @@ namespace hsp {
 void prof_begin(hsp_ctx* C, int cls, hipStream_t s);
 void prof_end(hsp_ctx* C, int cls, hipStream_t s, double bytes);
 
+// Size plan of a 2-D setup workspace (validates the arguments).
+hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P);
 // Task list and stages of the sweep of Table 3 (X, UD or NX) from the
 // partition in C->P (beta, bt, x0, x1) and C->J, C->opt.sweep, C->opt.ncell.
 void build_schedule(hsp_ctx* C);

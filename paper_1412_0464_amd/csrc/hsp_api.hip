@@ -124,7 +124,7 @@ void coarse_map(int N, int w, std::vector<int>& ifp, std::vector<char>& ref) {
 
 }  // namespace hsp
 
-namespace {
+namespace hsp {
 
 hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   hsp_status st = validate(g, J, o);
@@ -294,7 +294,7 @@ hsp_status make_plan(const hsp_grid* g, int J, const hsp_options* o, Plan& P) {
   return HSP_OK;
 }
 
-}  // namespace
+}  // namespace hsp
 
 
 namespace hsp {

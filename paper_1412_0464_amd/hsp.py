@@ -55,7 +55,8 @@ EXPORTS = ["hsp_default_options", "hsp_workspace_size", "hsp_setup", "hsp_rhs", 
            "hsp_smooth", "hsp_sweep", "hsp_slab_solve", "hsp_profile_enable", "hsp_profile_read",
            "hsp_gradient_accumulate", "hsp_batch_workspace_size", "hsp_apply_precond_batch",
            "hsp_tune_batch", "hsp_solve_batch", "hsp_group_workspace_size", "hsp_apply_precond_group",
-           "hsp_solve_group", "hsp_debug_set", "hsp_apply_precond_batch_noalloc"]
+           "hsp_solve_group", "hsp_debug_set", "hsp_apply_precond_batch_noalloc", "hsp_autotune_workspace_size",
+           "hsp_autotune"]
 DEBUG_KNOBS = {"singular_slab": 0, "growth_limit": 1}
 GROUP_GRAPH = 1
 PROF_CLASSES = {"stage": 0, "smooth": 1, "coarse": 2, "transfer": 3, "krylov": 4, "project": 5, "update": 6}
@@ -107,6 +108,11 @@ def load():
                             I, I, I, I, P, S, ctypes.POINTER(I), ctypes.POINTER(D), P],
         "hsp_debug_set": [I, D],
         "hsp_apply_precond_batch_noalloc": [P, I, P, P, I, ctypes.POINTER(S), P],
+        "hsp_autotune_workspace_size": [ctypes.POINTER(HspGrid), I, ctypes.POINTER(HspOptions), I, I,
+                                        ctypes.POINTER(S), ctypes.POINTER(S)],
+        "hsp_autotune": [P, D, ctypes.POINTER(HspGrid), I, ctypes.POINTER(HspOptions), I, I, P, S, P, S,
+                         ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D),
+                         ctypes.POINTER(I), P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -116,6 +122,32 @@ def load():
     lib.hsp_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
+
+
+def autotune(c, omega, h, pml, J, nrhs, restart=40, S_outer=0.0, c_pml=0.0, sponge=False, **opts):
+    """Chunk length and right-hand-side tile of the batched solvers for this
+    problem and batch size (hsp_autotune).  Returns (chunk, tile, ms per
+    batched preconditioner application, [(chunk, tile, ms) per candidate])."""
+    lib = load()
+    if not (c.is_cuda and c.dtype == torch.float64 and c.is_contiguous() and c.dim() == 2):
+        raise ValueError("c must be a contiguous 2-D float64 CUDA tensor")
+    pml = (pml,) * 2 if isinstance(pml, int) else tuple(pml)
+    n = tuple(c.shape[a] - 2 * pml[a] for a in range(2))
+    g = make_grid(n, h, pml, S_outer, c_pml, sponge)
+    o = make_options(**opts)
+    wsb, bwsb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.hsp_autotune_workspace_size(ctypes.byref(g), int(J), ctypes.byref(o), int(nrhs), int(restart),
+                                           ctypes.byref(wsb), ctypes.byref(bwsb)))
+    ws = torch.empty(wsb.value, dtype=torch.uint8, device=c.device)
+    bws = torch.empty(bwsb.value, dtype=torch.uint8, device=c.device)
+    chunk, tile, ntab = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ms = ctypes.c_double()
+    tab = (ctypes.c_double * 24)()
+    _check(lib.hsp_autotune(_ptr(c), float(omega), ctypes.byref(g), int(J), ctypes.byref(o), int(nrhs), int(restart),
+                            _ptr(ws), wsb.value, _ptr(bws), bwsb.value, ctypes.byref(chunk), ctypes.byref(tile),
+                            ctypes.byref(ms), tab, ctypes.byref(ntab), _stream()))
+    table = [(int(tab[3 * i]), int(tab[3 * i + 1]), tab[3 * i + 2]) for i in range(ntab.value)]
+    return chunk.value, tile.value, ms.value, table
 
 
 def debug_set(knob, value):

@@ -115,3 +115,25 @@ def test_workspace_size_3d_rejects_invalid(kw, msg):
         _ws3(**kw)
     assert e.value.status == hsp.HSP_EINVAL
     assert msg in str(e.value)
+
+
+def test_autotune_workspace_sizes_without_device():
+    """The autotuner's workspace sizes are host logic: the largest setup and
+    batch workspaces over its candidate chunk lengths (restart 1 keeps the
+    batch workspace to the tuning itself); 3-D problems are refused."""
+    lib = hsp.load()
+    g = hsp.make_grid((255, 255), 0.04, (16, 16))
+    o = hsp.make_options(two_grid=True, precision="mixed")
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.hsp_autotune_workspace_size(ctypes.byref(g), 8, ctypes.byref(o), 64, 1, ctypes.byref(a),
+                                           ctypes.byref(b)) == hsp.HSP_OK
+    ws = ctypes.c_size_t()
+    for chunk in (16, 64):
+        oc = hsp.make_options(two_grid=True, precision="mixed", chunk=chunk)
+        assert lib.hsp_workspace_size(ctypes.byref(g), 8, ctypes.byref(oc), ctypes.byref(ws)) == hsp.HSP_OK
+        assert ws.value <= a.value
+    assert b.value > 0
+    g3 = hsp.make_grid((17, 8, 9), 0.05, (3, 3, 3))
+    o3 = hsp.make_options(fine_stencil=7, precision="mixed")
+    assert lib.hsp_autotune_workspace_size(ctypes.byref(g3), 3, ctypes.byref(o3), 4, 1, ctypes.byref(a),
+                                           ctypes.byref(b)) == hsp.HSP_EINVAL

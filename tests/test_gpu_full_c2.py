@@ -2,9 +2,10 @@
 
 The 2-D layered medium with 1023^2 interior nodes and 16 PML cells per side,
 8 points per wavelength, the two-grid sweeping preconditioner with J = 32
-coarse slabs, 64 point sources solved in one batch with a right-hand-side
-tile of 4 and 34 tangential blocks per chunk of the slab substitutions: the
-launch configuration bench.py times.  The oracle cannot run
+coarse slabs, 64 point sources solved in one batch with the chunk length of
+the slab substitutions and the right-hand-side tile that the library's
+autotuner picks for this batch: the launch configuration bench.py times
+(the tuner runs here the same way).  The oracle cannot run
 the whole batch in seconds, so the checks use outputs it computes one by one
 and properties that hold at any size:
 
@@ -48,6 +49,9 @@ def c2():
     fs = bench.sources(cfg, c.shape, 64)
     print(f"[full size c2] {cfg['workload']}, {c.shape}, 64 sources: oracle setup", flush=True)
     ref = Problem2D(c, cfg["omega"], cfg["h"], cfg["w"], J=cfg["J"], w_dd=4, two_grid=True)
+    tuned = bench.autotune_batch(cfg, c, 64, "mixed")
+    print(f"[full size c2] autotuner: chunk {tuned['chunk']}, tile {tuned['tile']}", flush=True)
+    cfg = dict(cfg, chunk=tuned["chunk"], tile=tuned["tile"])
     return cfg, c, fs, ref
 
 
@@ -75,12 +79,12 @@ def test_c2_fine_operator(c2):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
 def test_c2_batched_precond_sampled_columns(c2, precision, tol):
     cfg, c, fs, ref = c2
-    hs = _helmholtz(cfg, c, precision, chunk=bench.BATCH_CHUNK)
+    hs = _helmholtz(cfg, c, precision, chunk=cfg["chunk"])
     try:
         R = np.stack([random_rhs(c.shape, 1412100 + j) for j in range(64)])
-        print(f"[full size c2] batched preconditioner, {precision}, 64 columns, tile 4, chunk {bench.BATCH_CHUNK}",
-              flush=True)
-        Z = hs.apply_precond_batch(_t(R), tile=4).cpu().numpy()
+        print(f"[full size c2] batched preconditioner, {precision}, 64 columns, tile {cfg['tile']}, "
+              f"chunk {cfg['chunk']}", flush=True)
+        Z = hs.apply_precond_batch(_t(R), tile=cfg["tile"]).cpu().numpy()
         for j in SAMPLED:
             err = _relerr(Z[j], ref.precond(R[j].ravel()))
             print(f"[full size c2] {precision} column {j}: rel err {err:.2e}", flush=True)
@@ -91,11 +95,11 @@ def test_c2_batched_precond_sampled_columns(c2, precision, tol):
 
 def test_c2_batched_mixed_solve(c2):
     cfg, c, fs, ref = c2
-    hs = _helmholtz(cfg, c, "mixed", chunk=bench.BATCH_CHUNK)
+    hs = _helmholtz(cfg, c, "mixed", chunk=cfg["chunk"])
     try:
         B = torch.stack([hs.rhs(_t(f)) for f in fs])
-        print(f"[full size c2] batched mixed solve, 64 sources, tile 4, chunk {bench.BATCH_CHUNK}", flush=True)
-        U, its, rrs = hs.solve_batch(B, tol=1e-6, maxit=200, tile=4)
+        print(f"[full size c2] batched mixed solve, 64 sources, tile {cfg['tile']}, chunk {cfg['chunk']}", flush=True)
+        U, its, rrs = hs.solve_batch(B, tol=1e-6, maxit=200, tile=cfg["tile"])
         U = U.cpu().numpy()
     finally:
         hs.close()
