@@ -58,6 +58,7 @@ KERNEL_PATTERNS = {
     "update": r"k_bdcgs_update<double>",
     "matvec": r"k_stencil_multi<5, double, float, double, double>",
 }
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak
 CLASSES = ("stage", "smooth", "coarse", "transfer", "krylov", "project", "update")
 COPY_BYTES = 256 << 20
 
@@ -668,6 +669,22 @@ def main():
                                       recorded_traffic("update", bat["tile"], len(fs)))
     out["roofline_matvec"] = roofline("krylov", "FGMRES matvec k_stencil_multi<5> (batched 5-point operator)",
                                       recorded_traffic("matvec", bat["tile"], len(fs)))
+    # the same stage against the FP32 vector ALU by the method's flops: per
+    # slab solve and source, forward y_t = G_t (f_t - A_t y_{t-1}) and
+    # backward x_t = y_t - E_t x_{t+1} take 2 nl^2 + 3 nl complex multiply-adds
+    # (8 real flops each) per tangential node; an X-sweep solves every slab
+    # twice, and each FGMRES iteration of a source applies the preconditioner
+    # once (the chunked evaluation's extra fix-up products are not counted)
+    hs_b = bat["hs"]
+    n2c = hs_b.n_coarse[1] if hs_b.two_grid else hs_b.n_fine[1]
+    flops_app = sum(2.0 * n2c * 8.0 * (2.0 * nl * nl + 3.0 * nl)
+                    for nl in (x1 - x0 + 1 for x0, x1 in zip(hs_b.x0, hs_b.x1)))
+    st_ms, st_n, _ = cls["stage"]
+    achieved_tf = (bat["total_iters"] / args.steps) * flops_app / (st_ms * 1e-3 / args.steps) / 1e12
+    out["roofline_stage_flops"] = {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": achieved_tf / FP32_PEAK_TFLOPS, "traffic": None,
+                                   "kernel": "batched SubdomSolve stage (k_bstage_fwd + k_bstage_bwd), complex64",
+                                   "flop_per_application_per_source": flops_app}
     out["config"]["kernel_ms_per_solve"] = {k: v[0] / args.steps for k, v in cls.items()}
     out["config"]["profiled_solve_s"] = bat["profiled_solve_s"]
     samp = [0, len(fs) // 2, len(fs) - 1]

@@ -65,6 +65,24 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.complex128, device=torch.device("cuda:0"))
 
 
+def test_c2_nine_point_fine_operator_full_size(c2):
+    """The 9-point finite-element fine operator (Table (a) at the fine 1/G,
+    the literal reading of the configuration's stencil) at full size
+    against the oracle's assembly, on a random vector."""
+    cfg, c, fs, ref = c2
+    from paper_1412_0464_amd import Helmholtz
+    print("[full size c2] oracle 9-point fine operator", flush=True)
+    r9 = Problem2D(c, cfg["omega"], cfg["h"], cfg["w"], J=cfg["J"], w_dd=4, fine="fe9")
+    hs = Helmholtz(torch.tensor(c, device=torch.device("cuda:0")), cfg["omega"], cfg["h"], cfg["w"], cfg["J"],
+                   fine_stencil=9, precision="fp64")
+    try:
+        x = random_rhs(c.shape, 1412061)
+        y = hs.apply_operator(_t(x)).cpu().numpy().ravel()
+        assert _relerr(y, r9.matvec(x.ravel())) < 1e-12
+    finally:
+        hs.close()
+
+
 def test_c2_fine_operator(c2):
     cfg, c, fs, ref = c2
     hs = _helmholtz(cfg, c, "fp64")
