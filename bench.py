@@ -297,35 +297,62 @@ def c3_inputs(nsrc=64):
     return out
 
 
-def c3_run(steps, warmup, tol, nsrc=64, graph=False):
+_C3_TUNED = {}
+
+
+def c3_tune(nsrc=64):
+    """Chunk length per grid and the group's tile from the library's
+    autotuner (run once per process, outside the timed solves): each grid is
+    tuned for its own batch; the group takes the tile of the largest grid,
+    whose stages dominate the aligned launches."""
+    if nsrc in _C3_TUNED:
+        return _C3_TUNED[nsrc]
+    import torch
+    from paper_1412_0464_amd import hsp
+    dev = torch.device("cuda:0")
+    per = []
+    t0 = time.perf_counter()
+    for q in c3_inputs(nsrc):
+        chunk, tile, ms, _ = hsp.autotune(torch.tensor(q["c"], device=dev), q["omega"], q["h"], q["w"], q["J"], nsrc,
+                                          restart=1, two_grid=True, precision="mixed")
+        per.append({"n": q["n"], "chunk": chunk, "tile": tile, "ms": ms})
+    torch.cuda.synchronize()
+    _C3_TUNED[nsrc] = {"grids": per, "tile": per[-1]["tile"], "s": time.perf_counter() - t0}
+    return _C3_TUNED[nsrc]
+
+
+def c3_run(steps, warmup, tol, nsrc=64, graph=False, tuned=None):
     """All 4 x nsrc right-hand sides of c3_inputs solved to tol in one group
-    (every aligned sweep step is one launch pair over all grids)."""
+    (every aligned sweep step is one launch pair over all grids); with
+    ``tuned`` (c3_tune) the autotuner's chunk lengths and tile."""
     import torch
     from paper_1412_0464_amd import Group, Helmholtz
     dev = torch.device("cuda:0")
     probs, Bs, dofs = [], [], []
-    for q in c3_inputs(nsrc):
+    for k, q in enumerate(c3_inputs(nsrc)):
+        chunk = tuned["grids"][k]["chunk"] if tuned else 0
         hs = Helmholtz(torch.tensor(q["c"], device=dev), q["omega"], q["h"], q["w"], q["J"], two_grid=True,
-                       precision="mixed", restart=40)
+                       precision="mixed", restart=40, chunk=chunk)
         Bs.append(torch.stack([hs.rhs(torch.tensor(f, dtype=torch.complex128, device=dev)) for f in q["sources"]]))
         probs.append(hs)
         dofs.append(q["n"] * q["n"])
     w = 16
     grp = Group(probs, restart=40)
+    tile = tuned["tile"] if tuned else 0
     for _ in range(warmup):
-        grp.solve(Bs, tol=tol, maxit=200, graph=graph)
+        grp.solve(Bs, tol=tol, maxit=200, graph=graph, tile=tile)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     work = 0
     for _ in range(steps):
-        _, its, rrs = grp.solve(Bs, tol=tol, maxit=200, graph=graph)
+        _, its, rrs = grp.solve(Bs, tol=tol, maxit=200, graph=graph, tile=tile)
         work += sum(d * sum(it) for d, it in zip(dofs, its))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return {"value": work / dt, "unit": UNIT, "solve_s": dt / steps, "sources_per_grid": nsrc,
             "grids": [f"{n}^2 + {w} PML, ppw {ppw}, J={J}" for n, ppw, J in C3_GRIDS],
             "iterations": [[min(it), max(it)] for it in its], "relres_max": max(max(r) for r in rrs),
-            "graph": bool(graph)}
+            "graph": bool(graph), "autotune": tuned}
 
 
 def c4_config():
@@ -534,7 +561,8 @@ def oracle_check(cfg, c, fs, U, sampled):
 
 
 def c3_report(args, graph):
-    r3 = c3_run(max(1, args.steps - 1), 1, args.tol, nsrc=args.c3_sources, graph=graph)
+    tuned = c3_tune(args.c3_sources)
+    r3 = c3_run(max(1, args.steps - 1), 1, args.tol, nsrc=args.c3_sources, graph=graph, tuned=tuned)
     print(f"[bench] c3 group (graph={graph}): {r3['solve_s'] * 1e3:.1f} ms, {r3['value']:.3e} dof*iter/s",
           file=sys.stderr, flush=True)
     return r3

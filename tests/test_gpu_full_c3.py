@@ -1,7 +1,8 @@
 """Full-size checks of the batched multi-frequency workload (one group of
 four grids, 255^2 .. 1023^2 interior nodes + 16 PML cells, 8-12 points per
 wavelength, 64 point sources per grid, mixed precision) against the oracle,
-in the configuration bench.py times:
+in the configuration bench.py times (chunk lengths and tile from the
+library's autotuner, run here the same way):
 
 * every true residual of the group solve, recomputed with the oracle's
   FP64 operator of its grid, meets the tolerance 1e-6;
@@ -41,9 +42,13 @@ def c3():
     from paper_1412_0464_amd import Group, Helmholtz
     dev = torch.device("cuda:0")
     qs = bench.c3_inputs(64)
+    tuned = bench.c3_tune(64)
+    print(f"[full size c3] autotuner: {tuned['grids']}, group tile {tuned['tile']}", flush=True)
     probs = [Helmholtz(torch.tensor(q["c"], device=dev), q["omega"], q["h"], q["w"], q["J"], two_grid=True,
-                       precision="mixed", restart=40) for q in qs]
-    yield qs, probs, Group(probs, restart=40)
+                       precision="mixed", restart=40, chunk=t["chunk"]) for q, t in zip(qs, tuned["grids"])]
+    grp = Group(probs, restart=40)
+    grp.tile = tuned["tile"]
+    yield qs, probs, grp
     for p in probs:
         p.close()
 
@@ -61,7 +66,7 @@ def test_c3_group_solve_true_residuals_and_iterations(c3):
     Bs = [torch.stack([p.rhs(torch.tensor(f, dtype=torch.complex128, device=dev)) for f in q["sources"]])
           for p, q in zip(probs, qs)]
     print("[full size c3] group solve, 4 grids x 64 sources", flush=True)
-    Us, its, rrs = grp.solve(Bs, tol=1e-6, maxit=200)
+    Us, its, rrs = grp.solve(Bs, tol=1e-6, maxit=200, tile=grp.tile)
     for g, (q, U, it, rr) in enumerate(zip(qs, Us, its, rrs)):
         A, scale = _fine_matrix(q)
         U = U.cpu().numpy()
@@ -84,7 +89,7 @@ def test_c3_group_precond_sampled_columns(c3):
     Rs = [torch.tensor(np.stack([random_rhs(q["c"].shape, 1412200 + 101 * g + j) for j in range(4)]),
                        dtype=torch.complex128, device=dev) for g, q in enumerate(qs)]
     print("[full size c3] group preconditioner, 4 columns per grid", flush=True)
-    Zs = grp.apply_precond(Rs)
+    Zs = grp.apply_precond(Rs, tile=grp.tile)
     for g in range(2):
         q = qs[g]
         ref = Problem2D(q["c"], q["omega"], q["h"], q["w"], J=q["J"], w_dd=4, two_grid=True)
