@@ -253,3 +253,30 @@ def test_slab_factor_rejected_in_2d():
     with pytest.raises(HspError) as e:
         Helmholtz(torch.tensor(c, device=_dev()), 20.0, 0.05, 3, 2, slab_factor="nd")
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("sf", SF)
+@pytest.mark.parametrize("shape,pml", [((17, 8, 1), (3, 3, 0)), ((17, 1, 9), (3, 0, 3))])
+def test_degenerate_planes(shape, pml, sf):
+    """Slab planes one node thick in z (or y): the dissection of a line of
+    nodes (single-node separators) and block-tridiagonal blocks of n_l (or
+    a single block), against the oracle's slab solves, sweep and
+    preconditioner."""
+    c = np.pad(smooth_medium_3d(*shape, 1412047, corr_len=3.0), [(w, w) for w in pml], mode="edge")
+    h = 0.05
+    om = 2 * np.pi * 1.5 / (8.0 * h)
+    print(f"[3d degenerate plane {c.shape} pml {pml} {sf}]", flush=True)
+    ref = Problem3D(c, om, h, pml, J=3, w_dd=2)
+    from paper_1412_0464_amd import Helmholtz
+    hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, pml, 3, w_dd=2, slab_factor=sf)
+    try:
+        for j in range(hs.J):
+            nl = hs.x1[j] - hs.x0[j] + 1
+            b = random_rhs((nl,) + tuple(hs.dd_shape[1:]), 60 + j)
+            assert _relerr(hs.slab_solve(j, _t(b)).cpu().numpy().ravel(), ref.dd.lu[j].solve(b.ravel())) < TOL32
+        f = random_rhs(hs.dd_shape, 70)
+        assert _relerr(hs.sweep(_t(f)).cpu().numpy(), ref.dd.apply_x(f.ravel())) < TOL32
+        r = random_rhs(c.shape, 71)
+        assert _relerr(hs.apply_precond(_t(r)).cpu().numpy(), ref.precond(r.ravel())) < TOL32
+    finally:
+        hs.close()
