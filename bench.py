@@ -586,6 +586,8 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 3-D workload")
     ap.add_argument("--no-fp64-batched", action="store_true",
                     help="skip the plain FP64 batched run (same batch, restart, tile and chunk)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the batched runs with the NX-sweep and with sponge layers")
     ap.add_argument("--no-oracle-check", action="store_true",
                     help="skip the error of sampled solutions against the oracle's direct solve")
     ap.add_argument("--c3-sources", type=int, default=64)
@@ -739,6 +741,26 @@ def main():
                                "relres_max": max(bf["relres"]), "rhs_tile": bf["tile"], "chunk": args.chunk,
                                "speedup_mixed_over_fp64_same_batch": bf["solve_s"] / out["config"]["solve_s"]}
         del bf
+    if not args.no_variants:
+        # the same batch with the partial sweeps over two groups (SweepingPrecNX)
+        # and with the outer PML cells replaced by sponge layers (the two-grid
+        # method then coarsens every cell)
+        for key, label, extra in (("c2_nx", "NX-sweep, 2 groups", dict(sweep="nx", ncell=2)),
+                                  ("c2_sponge", "sponge layers (16 cells)", dict(sponge=True))):
+            bv = gpu_run_batch(cfg, c, fs, "mixed", args.steps, args.warmup, args.tol, tile=bat_tile,
+                               chunk=args.chunk, profile=True, **extra)
+            vits = bv["iters"]
+            ms_st, n_st, by_st = bv["classes"]["stage"]
+            print(f"[bench] batched mixed, {label}: solve {bv['solve_s'] * 1e3:.1f} ms, iterations "
+                  f"{min(vits)}..{max(vits)}, max relres {max(bv['relres']):.2e}", file=sys.stderr, flush=True)
+            out[key] = {"variant": label, "value": dof * bv["total_iters"] / bv["time_s"], "solve_s": bv["solve_s"],
+                        "setup_s": bv["setup_s"], "iterations_min": min(vits), "iterations_max": max(vits),
+                        "relres_max": max(bv["relres"]), "rhs_tile": bv["tile"], "chunk": args.chunk,
+                        "stage": {"avg_us": ms_st * 1e3 / max(n_st, 1),
+                                  "achieved_gbs": (by_st / max(n_st, 1)) / (ms_st * 1e-3 / max(n_st, 1)) / 1e9
+                                  if n_st else 0.0},
+                        "kernel_ms_per_solve": {k: v[0] / args.steps for k, v in bv["classes"].items()}}
+            del bv
     if not args.no_fp64:
         fp = gpu_run(cfg, c, fs[0], "fp64", args.steps, args.warmup, args.tol)
         print(f"[bench] plain fp64, one source: setup {fp['setup_s']:.3f} s, solve {fp['solve_s'] * 1e3:.2f} ms, "
