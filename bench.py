@@ -48,7 +48,10 @@ KERNEL_SOURCES = {
     "project": ["blas.hip", "internal.h", "common.h"],
     "update": ["blas.hip", "internal.h", "common.h"],
     "matvec": ["stencil.hip", "internal.h", "common.h"],
+    "nd_stage": ["nd3d.hip", "slab3d.hip", "d3.h", "internal.h", "common.h"],
 }
+# the 3-D nested-dissection stage's record (per stage of the 3-D workload)
+ND_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k3_nd_stage_factor_smooth127cubed.md")
 # kernel names in the counter files: the batched stage (two launches per
 # stage, for the tile in use) and the projection and update passes over the
 # complex128 Arnoldi basis
@@ -79,14 +82,14 @@ def sources_digest(kernel):
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, tile, nsrc, chunk=0):
+def recorded_traffic(kernel, tile, nsrc, chunk=0, path=None):
     """Measured HBM bytes per launch (per stage for "stage") from the counter
     record, or None when there is none for this kernel, tile, chunk length
     and batch size or the kernel's sources changed since it was taken (tile
     and chunk length matter for the stage only)."""
     import re
     try:
-        with open(TRAFFIC_RECORD) as fh:
+        with open(path or TRAFFIC_RECORD) as fh:
             txt = fh.read()
     except OSError:
         return None
@@ -429,6 +432,14 @@ def c4_run(steps, warmup, tol, profile=True, slab_factor="nd"):
         ms, n, by = cl["stage"]
         out["stage"] = {"launch_groups": n, "avg_us": ms * 1e3 / max(n, 1), "alg_bytes_per_stage": by / max(n, 1),
                         "achieved_gbs": (by / max(n, 1)) / (ms * 1e-3 / max(n, 1)) / 1e9 if n else 0.0}
+        ach = out["stage"]["achieved_gbs"]
+        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS,
+                           "traffic": recorded_traffic("nd_stage", 0, 1, 0, ND_TRAFFIC_RECORD)
+                           if slab_factor == "nd" else None,
+                           "kernel": "3-D SubdomSolve stage (" + ("kn_fwd / kn_bwd per dissection level"
+                                                                  if slab_factor == "nd" else "k3s_step per y-block")
+                                     + ", k3s_prep, k3s_fin)"}
     out["u"] = u
     out["hs"] = hs
     return out
