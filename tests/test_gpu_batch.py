@@ -331,3 +331,30 @@ def test_group_rejects_mixed_basis_precisions():
     _, _, h2 = _build("tg_ud", "mixed", krylov_fp32=True)
     with pytest.raises(HspError):
         Group([h1, h2], restart=40).workspace([1, 1])
+
+
+def test_autotuner_choice_and_its_preconditioner():
+    """hsp_autotune on a small two-grid problem: the chosen chunk length is
+    one of the candidates (distinct chunk counts), the tile one of 1, 2, 4,
+    8, every candidate was timed; the batched preconditioner set up with the
+    choice matches the oracle's columns (complex64 tolerance)."""
+    from paper_1412_0464_amd import hsp
+    n1, n2, w, J, fine, tg, sweep, ppw = CASES["tg_x_j5"]
+    c = extend_into_pml(layered_medium_2d(n1, n2, 1412046, n_layers=7, corr_len=6.0), w)
+    h = 0.02
+    om = 2 * np.pi * 1.5 / (ppw * h)
+    print("[autotuner on tg_x_j5, 6 right-hand sides]", flush=True)
+    chunk, tile, ms, table = hsp.autotune(torch.tensor(c, device=_dev()), om, h, w, J, 6, S_outer=5.0 * w,
+                                          two_grid=True, precision="mixed")
+    assert tile in (1, 2, 4, 8) and ms > 0
+    assert len(table) >= 2 and (chunk, tile) in [(m, t) for m, t, _ in table]
+    c_ref, ref, hs = _build("tg_x_j5", "mixed", chunk=chunk)
+    try:
+        ncoarse = hs.n_coarse[1]
+        assert len({(ncoarse + m - 1) // m for m, _, _ in table}) == len(table)
+        R = np.stack([random_rhs(c.shape, 300 + j) for j in range(6)])
+        Z = hs.apply_precond_batch(_t(R), tile=tile).cpu().numpy()
+        for j in (0, 5):
+            assert _relerr(Z[j], ref.precond(R[j].ravel())) < 2e-5
+    finally:
+        hs.close()
