@@ -32,8 +32,10 @@ namespace hsp {
 
 namespace {
 
+constexpr int kFactorThreads = 512;
+
 template <class T>
-__global__ void __launch_bounds__(256) k_factor(const SlabDev* __restrict__ slabs, int n2, cx<T>* factors,
+__global__ void __launch_bounds__(kFactorThreads) k_factor(const SlabDev* __restrict__ slabs, int n2, cx<T>* factors,
                                                 cd* setup, cd* scratchE, int* status, double* growth,
                                                 int dbg_singular) {
   extern __shared__ cd smem[];
@@ -646,8 +648,9 @@ void launch_factor(const SlabDev* slabs_dev, int nslabs, int nl_max, int n2, int
                    hipStream_t s) {
   // LDS: S, the row coefficients and one column; at least 2 x 256 doubles
   // for the growth reduction, which reuses S
-  const size_t shm = std::max(((size_t)nl_max * nl_max + 10 * (size_t)nl_max) * sizeof(cd), 512 * sizeof(double));
-  hipLaunchKernelGGL((k_factor<T>), dim3(nslabs), dim3(256), shm, s, slabs_dev, n2, factors, setup, scratchE, status,
+  const size_t shm = std::max(((size_t)nl_max * nl_max + 10 * (size_t)nl_max) * sizeof(cd),
+                              2 * (size_t)kFactorThreads * sizeof(double));
+  hipLaunchKernelGGL((k_factor<T>), dim3(nslabs), dim3(kFactorThreads), shm, s, slabs_dev, n2, factors, setup, scratchE, status,
                      growth, dbg_singular);
   hipLaunchKernelGGL((k_chunk_transfer<T>), dim3(P, nslabs), dim3(256), 0, s, slabs_dev, n2, m, factors,
                      (const cd*)setup, tmp);
