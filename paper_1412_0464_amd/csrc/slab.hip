@@ -32,7 +32,7 @@ namespace hsp {
 
 namespace {
 
-constexpr int kFactorThreads = 512;
+constexpr int kFactorThreads = 1024;
 
 template <class T>
 __global__ void __launch_bounds__(kFactorThreads) k_factor(const SlabDev* __restrict__ slabs, int n2, cx<T>* factors,
