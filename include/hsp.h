@@ -13,12 +13,16 @@
  * Mesh (Sec. 2.2): N = n + 1 + 2 w cells per axis (n interior nodes, w
  * outer-PML cells on each side), spacing h, unknowns at nodes 1..N-1.
  * Vectors are dense arrays over the unknown nodes with the x axis (the
- * sweep axis) slowest: index (i-1)*(N2-1) + (k-1) for node (i, k).
+ * sweep axis) slowest: index (i-1)*(N2-1) + (k-1) for node (i, k); in 3-D
+ * (hsp_grid.dim = 3, Sec. 6.2) index ((i-1)*(N2-1) + (j-1))*(N3-1) + (k-1)
+ * for node (i, j, k), z fastest.
  * Complex vectors are interleaved (re, im) pairs of double ("complex128").
  *
  * Memory and streams.  Every pointer named *_dev is a device pointer on the
  * current HIP device.  The caller owns all of them, including the workspace
- * passed to hsp_setup; the library never allocates device memory.  All work
+ * passed to hsp_setup; the library never allocates device memory (the
+ * allocation-free batched entry point uses a fixed device array of the
+ * library instead).  All work
  * is enqueued on the HIP stream passed in (NULL = the default stream); a call
  * blocks the host only where it must read a result (setup status, solve
  * iterations).  A handle may be used from one host thread at a time.
@@ -40,7 +44,8 @@ typedef enum {
   HSP_OK = 0,
   HSP_EINVAL = -1,     /* invalid argument: nothing was enqueued            */
   HSP_ENOMEM = -2,     /* workspace smaller than hsp_workspace_size        */
-  HSP_ESINGULAR = -3,  /* zero or non-finite pivot in a slab factorization */
+  HSP_ESINGULAR = -3,  /* zero or non-finite pivot in a slab factorization,
+                          or Schur-complement growth beyond the limit      */
   HSP_ENOCONV = -4,    /* maxit reached; the last iterate is returned      */
   HSP_EDEVICE = -5     /* a HIP runtime call failed                        */
 } hsp_status;
