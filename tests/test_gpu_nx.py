@@ -115,16 +115,17 @@ def test_nx_batched_and_grouped_mixed(tile):
         hs2.close()
 
 
-def test_nx_3d_sweep_and_precond():
+@pytest.mark.parametrize("sf", ["nd", "block"])
+def test_nx_3d_sweep_and_precond(sf):
     n, w, J = (33, 9, 11), 4, 5
     c = np.pad(smooth_medium_3d(*n, 1412047, corr_len=3.0), w, mode="edge")
     h = 0.05
     om = 2 * np.pi * 1.5 / (10.0 * h)
-    print(f"[nx 3d, shape {c.shape}]", flush=True)
+    print(f"[nx 3d, shape {c.shape}, slab_factor {sf}]", flush=True)
     ref = Problem3D(c, om, h, w, J=J, w_dd=2, two_grid=True, sweep="nx", ncell=2, omega_jac=0.6)
     from paper_1412_0464_amd import Helmholtz
     hs = Helmholtz(torch.tensor(c, device=_dev()), om, h, w, J, two_grid=True, sweep="nx", ncell=2, w_dd=2,
-                   omega_jac=0.6)
+                   omega_jac=0.6, slab_factor=sf)
     try:
         f = random_rhs(hs.dd_shape, 90)
         assert _relerr(hs.sweep(_t(f)).cpu().numpy(), ref.dd.apply_nx(f.ravel(), 2)) < 2e-4

@@ -158,3 +158,25 @@ def test_sponge_rejections():
         assert e.value.status == -1 and "sponge" in str(e.value)
     finally:
         hs.close()
+
+
+def test_sponge_batched_solve_mixed():
+    """Batched FGMRES with sponge layers: every source's true residual meets
+    the tolerance, and sampled sources take the oracle's iteration count
+    within +-1."""
+    c, ref, hs = _build("sp_tg_x", "mixed")
+    try:
+        fs = [point_source(c.shape, (c.shape[0] // 2 + 7 * j, c.shape[1] // 3 + 5 * j), 0.02) for j in range(4)]
+        B = torch.stack([hs.rhs(_t(f)) for f in fs])
+        U, its, rrs = hs.solve_batch(B, tol=1e-6, maxit=150, tile=2)
+        U = U.cpu().numpy()
+        for j, f in enumerate(fs):
+            b = ref.rhs(f)
+            rr = np.linalg.norm(b - ref.matvec(U[j].ravel())) / np.linalg.norm(b)
+            assert rr <= 1.001e-6, (j, rr)
+        for j in (0, 3):
+            _, ito, _, _ = ref.solve(fs[j], tol=1e-6, maxit=150)
+            print(f"[sponge batched solve: source {j} {its[j]} iterations, oracle {ito}]", flush=True)
+            assert abs(its[j] - ito) <= 1
+    finally:
+        hs.close()
