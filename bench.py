@@ -550,6 +550,95 @@ def cpu_baseline(cfg, c, f, iters, tol):
     return out
 
 
+def cpu_c3_sample(per_grid=1, seed=1412050):
+    """The oracle on a seeded subset of the multi-frequency workload:
+    ``per_grid`` of the 64 sources on each of the four grids (4 of the 256
+    systems by default), each grid's full FP64 setup and complete solves to
+    1e-6.  ``value`` is the subset's interior dof x iterations / solve time;
+    the whole group's oracle time is extrapolated as each grid's setup plus
+    64 times its mean solve time."""
+    from oracle.problem import Problem2D
+    rng = np.random.default_rng(seed)
+    work, solve_s, extra, grids = 0, 0.0, 0.0, []
+    c0 = time.process_time()
+    w0 = time.perf_counter()
+    for q in c3_inputs():
+        t0 = time.perf_counter()
+        P = Problem2D(q["c"], q["omega"], q["h"], q["w"], J=q["J"], w_dd=4, two_grid=True)
+        t1 = time.perf_counter()
+        picks = sorted(int(i) for i in rng.choice(len(q["sources"]), per_grid, replace=False))
+        its, ts = [], []
+        for i in picks:
+            s0 = time.perf_counter()
+            _, it, _, _ = P.solve(q["sources"][i], tol=1e-6, maxit=200)
+            ts.append(time.perf_counter() - s0)
+            its.append(it)
+        dof = q["n"] * q["n"]
+        work += dof * sum(its)
+        solve_s += sum(ts)
+        extra += (t1 - t0) + len(q["sources"]) * float(np.mean(ts))
+        grids.append({"n": q["n"], "setup_s": t1 - t0, "sources": picks, "iterations": its, "solve_s": ts})
+        del P
+    used = (time.process_time() - c0) / max(time.perf_counter() - w0, 1e-9)
+    return {"value": work / solve_s, "unit": UNIT, "cores": max(1, int(round(used))), "kind": "oracle",
+            "sample": f"{per_grid} seeded source{'s' if per_grid > 1 else ''} per grid ({4 * per_grid} of 256 systems): FP64 setup per grid and "
+                      f"complete solves to 1e-6; value = interior dof x iterations / solve time",
+            "extrapolated_group_s": extra, "grids": grids}
+
+
+def cpu_c4_sample():
+    """The oracle on a bounded part of the 3-D workload, whose full FP64
+    setup (16 SuperLU slab factorizations of about 69 k unknowns each) does
+    not fit a benchmark run: one middle slab of the 79^3 coarse level
+    assembled and factored, one solve with it, and the product with the
+    fine 7-point operator.  An X-sweep applies 2 J slab solves and the
+    two-grid cycle 2 nu + 2 fine products (smoothing, residual, FGMRES
+    product), which gives the extrapolated time per iteration; the setup is
+    extrapolated as J middle-slab factorizations (the two end slabs are
+    wider by their PML)."""
+    import scipy.sparse.linalg as spla
+    from oracle import discretization as D, dd as DD, problem3d as P3, twogrid as TG
+    cfg = c4_config()
+    c = c4_medium(cfg)
+    n, w, h, om, J = cfg["n"], cfg["w"], cfg["h"], cfg["omega"], cfg["J"]
+    N = n + 1 + 2 * w
+    cp = float(c.mean())
+    c0 = time.process_time()
+    w0 = time.perf_counter()
+    axes = [D.uniform_axis(N, h, w, 5.0 * w, cp) for _ in range(3)]
+    k2n = om ** 2 / c ** 2
+    A = P3.Level3D(*axes, om, "fd7", k2_nodes=k2n).matrix().tocsr()
+    cax, Ws = [], []
+    for a in axes:
+        ca, ifp, ref = TG.coarsen_axis(a, w)
+        cax.append(ca)
+        Ws.append(TG.cell_average_1d(ifp, ref, N))
+    lev = P3.Level3D(*cax, om, "fe27", k2_cells=P3.cell_average_3d(*Ws, P3.pad_nodes_edge_3d(k2n)))
+    beta = DD.partition(lev.n1, w, J)
+    j = J // 2
+    t0 = time.perf_counter()
+    As = lev.slab_level(beta, j, cfg["w_dd"], 5.0 * cfg["w_dd"], cp).matrix().tocsc()
+    t1 = time.perf_counter()
+    lu = spla.splu(As)
+    t2 = time.perf_counter()
+    rng = np.random.default_rng(1412051)
+    x = lu.solve(rng.standard_normal(As.shape[0]) + 1j * rng.standard_normal(As.shape[0]))
+    t3 = time.perf_counter()
+    v = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    y = A @ v
+    t4 = time.perf_counter()
+    del x, y
+    used = (time.process_time() - c0) / max(time.perf_counter() - w0, 1e-9)
+    nu = 3
+    per_iter = 2 * J * (t3 - t2) + (2 * nu + 2) * (t4 - t3)
+    return {"value": n ** 3 / per_iter, "unit": UNIT, "cores": max(1, int(round(used))), "kind": "oracle",
+            "sample": f"coarse slab {j} of {J} ({As.shape[0]} unknowns): assembly {t1 - t0:.1f} s, SuperLU "
+                      f"{t2 - t1:.1f} s, one solve {t3 - t2:.2f} s; fine 7-point product {t4 - t3:.3f} s; value = "
+                      f"interior dof / ({2 * J} slab solves + {2 * nu + 2} fine products), extrapolated",
+            "extrapolated_s_per_iter": per_iter, "extrapolated_setup_s": J * (t2 - t0),
+            "slab_unknowns": int(As.shape[0]), "slab_factor_nnz": int(lu.L.nnz + lu.U.nnz)}
+
+
 def oracle_check(cfg, c, fs, U, sampled):
     """Relative L2 error of sampled GPU solutions (batched, mixed precision)
     against the oracle's direct solution of the same FP64 system (sparse LU
@@ -593,6 +682,8 @@ def main():
                     help="skip the batched run with the Arnoldi basis in complex64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--no-cpu-samples", action="store_true",
+                    help="skip the oracle's timed samples of the multi-frequency and 3-D workloads")
     ap.add_argument("--no-c3", action="store_true", help="skip the batched multi-frequency group workload")
     ap.add_argument("--no-c4", action="store_true", help="skip the 3-D workload")
     ap.add_argument("--no-fp64-batched", action="store_true",
@@ -809,6 +900,12 @@ def main():
             print("[bench] sampled batched solutions against the oracle's direct solve ...", file=sys.stderr,
                   flush=True)
             out["cpu_baseline"]["oracle_check"] = oracle_check(cfg, c, fs, Ub, [0, len(fs) // 2, len(fs) - 1])
+        if not args.no_cpu_samples and "c3" in out:
+            print("[bench] oracle sample of the multi-frequency group ...", file=sys.stderr, flush=True)
+            out["c3"]["cpu_baseline"] = cpu_c3_sample()
+        if not args.no_cpu_samples and "c4" in out:
+            print("[bench] oracle sample of the 3-D workload ...", file=sys.stderr, flush=True)
+            out["c4"]["cpu_baseline"] = cpu_c4_sample()
     print(json.dumps(out))
 
 
