@@ -93,13 +93,14 @@ __device__ __forceinline__ cx<T> shfl_down1(cx<T> v, int width) {
 //   GD = true:   Z_k = Mat_r (B_k - Cpl_r Z_{k-1})
 // with Z_{-1} = 0, Mat_r the column-major nl x nl block at mat + r mstride
 // and Cpl_r the tridiagonal coupling (Cpl Z)[l] = sum_a cpl[r][a][l] Z[l+a-1].
-// B_k is read from, and Z_k written to, rows[(r RB + c) nl + l].  The matrix
+// B_k is read from, and Z_k written to, rows[((r - rbase) RB + c) nl + l]
+// (rows in global memory or a chunk's slice in LDS).  The matrix
 // slices (and B, couplings) of the next D steps are held in a register ring;
 // loads are unconditional from clamped addresses.  LDS: q [NB][RB] holds the
 // product input, ps [NG][RB][NB] the partial products.
-template <class T, int NB, int RB, int D, bool GD, int NC = NB>
+template <class T, int NB, int RB, int D, bool GD, int NC = NB, class R>
 __device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long mstride,
-                                       const GAS cx<T>* __restrict__ cpl, GAS cx<T>* rows, int first, int dir,
+                                       const GAS cx<T>* __restrict__ cpl, R rows, int rbase, int first, int dir,
                                        int count, int nl, T sigma, cx<T>* q, cx<T>* ps) {
   using LY = BLay<NB, RB, NC>;
   constexpr int NG = LY::NG, CW = LY::CW, RC = LY::RC, QR = LY::QR;
@@ -131,7 +132,7 @@ __device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long m
     _Pragma("unroll") for (int i = 0; i < RC; ++i) {                                             \
       const int c = g + NG * i;                                                                  \
       const int ccl = c < RB ? c : RB - 1;                                                       \
-      rb[d][i] = rows[((size_t)rbi * RB + ccl) * nl + lc];                                       \
+      rb[d][i] = rows[((size_t)(rbi - rbase) * RB + ccl) * nl + lc];                             \
     }                                                                                            \
     if constexpr (GD) {                                                                          \
       _Pragma("unroll") for (int a = 0; a < 3; ++a) ra[d][a] = cpl[((size_t)rbi * 3 + a) * nl + lc]; \
@@ -161,7 +162,7 @@ __device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long m
       else                                                                                       \
         zk = mk<T>(rb[d][i].re + sigma * s.re, rb[d][i].im + sigma * s.im);                      \
       zk = sel(act && c < RB, zk);                                                               \
-      if (act && c < RB) rows[((size_t)rk * RB + c) * nl + l] = zk;                              \
+      if (act && c < RB) rows[((size_t)(rk - rbase) * RB + c) * nl + l] = zk;                    \
       cx<T> qn = zk;                                                                             \
       if constexpr (GD) {                                                                        \
         const cx<T> zl = sel(l > 0, shfl_up1(zk, NB));                                           \
@@ -186,7 +187,7 @@ __device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long m
     const int c = g + NG * i;
     const int ccl = c < RB ? c : RB - 1;
     cx<T> v = mk<T>(0, 0);
-    if constexpr (GD) v = sel(act && c < RB, rows[((size_t)first * RB + ccl) * nl + lc]);
+    if constexpr (GD) v = sel(act && c < RB, rows[((size_t)(first - rbase) * RB + ccl) * nl + lc]);
     if (c < RB) q[l * RB + c] = v;
   }
 #pragma unroll
@@ -208,19 +209,19 @@ __device__ __forceinline__ void bchain(const GAS cx<T>* __restrict__ mat, long m
 #undef BCH_FETCH
 }
 
-// rows_t += Mat_t v for t in [s, e), v = LDS [nl][RB]; one (t, row) pair per
+// rows_{t - rbase} += Mat_t v for t in [s, e), v = LDS [nl][RB]; one (t, row) pair per
 // thread and all RB columns at once.  The row of Mat_t is fetched in blocks
 // of JB entries (unconditional loads from clamped addresses) so that each
 // block costs one memory round trip.
-template <class T, int RB>
-__device__ __forceinline__ void bfixup(const GAS cx<T>* __restrict__ mat, GAS cx<T>* rows, int s, int e, int nl,
+template <class T, int RB, class R>
+__device__ __forceinline__ void bfixup(const GAS cx<T>* __restrict__ mat, R rows, int rbase, int s, int e, int nl,
                                        const cx<T>* v) {
   constexpr int JB = sizeof(T) == 4 ? 32 : 16;
   const int cnt = e - s;
   for (int idx = threadIdx.x; idx < cnt * nl; idx += blockDim.x) {
     const int t = s + idx / nl, l = idx - (idx / nl) * nl;
     const GAS cx<T>* mb = mat + (size_t)t * nl * nl + l;
-    GAS cx<T>* o = rows + (size_t)t * RB * nl + l;
+    const R o = rows + (size_t)(t - rbase) * RB * nl + l;
     cx<T> acc[RB];
 #pragma unroll
     for (int c = 0; c < RB; ++c) acc[c] = o[(size_t)c * nl];
@@ -246,20 +247,20 @@ __device__ __forceinline__ void bfixup(const GAS cx<T>* __restrict__ mat, GAS cx
   }
 }
 
-// rows_t += Mat1_t v1 + Mat2_t v2 for t in [s, e): both fix-ups of a block
+// rows_{t - rbase} += Mat1_t v1 + Mat2_t v2 for t in [s, e): both fix-ups of a block
 // in one pass, the rows of the two matrices fetched together (one memory
 // round trip per block of JB entries of both).
-template <class T, int RB>
+template <class T, int RB, class R>
 __device__ __forceinline__ void bfixup2(const GAS cx<T>* __restrict__ m1, const cx<T>* v1,
-                                        const GAS cx<T>* __restrict__ m2, const cx<T>* v2, GAS cx<T>* rows, int s,
-                                        int e, int nl) {
+                                        const GAS cx<T>* __restrict__ m2, const cx<T>* v2, R rows, int rbase,
+                                        int s, int e, int nl) {
   constexpr int JB = sizeof(T) == 4 ? 32 : 16;
   const int cnt = e - s;
   for (int idx = threadIdx.x; idx < cnt * nl; idx += blockDim.x) {
     const int t = s + idx / nl, l = idx - (idx / nl) * nl;
     const GAS cx<T>* mb1 = m1 + (size_t)t * nl * nl + l;
     const GAS cx<T>* mb2 = m2 + (size_t)t * nl * nl + l;
-    GAS cx<T>* o = rows + (size_t)t * RB * nl + l;
+    const R o = rows + (size_t)(t - rbase) * RB * nl + l;
     cx<T> acc[RB];
 #pragma unroll
     for (int c = 0; c < RB; ++c) acc[c] = o[(size_t)c * nl];
@@ -388,7 +389,23 @@ struct IdxWalk {
   }
 };
 
-template <class T, int NB, int RB, int D, int NC>
+// Dynamic LDS of the stage kernels: with LY, the work item's chunk of the
+// slab scratch, [cnt][RB][nl], for the whole launch (the forward launch
+// writes it to y once at its end, the backward launch reads it once at its
+// start); without, both kernels work on y in global memory.
+extern __shared__ __align__(16) unsigned char bst_lds[];
+
+// The rows of a work item's chunk: y_t at yrows<LY>(..)[((t - base) RB + c) nl + l],
+// base = s in LDS, 0 in global memory.
+template <bool LY, class T>
+__device__ __forceinline__ auto yrows(GAS cx<T>* y) {
+  if constexpr (LY)
+    return reinterpret_cast<cx<T>*>(bst_lds);
+  else
+    return y;
+}
+
+template <class T, int NB, int RB, int D, int NC, bool LY>
 __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ segs, int nseg, int nitems) {
   __shared__ cx<T> q[BLay<NB, RB, NC>::QN * RB];
   __shared__ cx<T> ps[256 * RB];
@@ -411,6 +428,8 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
   const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
   const SlabFac<T> F(factors + sd.fac_off, n2, nl);
   GAS cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
+  const auto yr = yrows<LY, T>(y);
+  const int yb = LY ? s : 0;
   GAS cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
   const GAS cx<T>* src = tk.src ? g : f;
   // slab right-hand side of the chunk, t fastest (coalesced level reads);
@@ -435,13 +454,13 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
         const int glc = inside ? gl : tk.b;
         const cx<T> v = src[(size_t)(r0 + cc) * A.ld + (size_t)(glc - 1) * n2 + s + it.t];
         val[q] = sel(inside, v);
-        dst[q] = ((s + it.t) * RB + it.c) * nl + it.l;
+        dst[q] = ((s + it.t - yb) * RB + it.c) * nl + it.l;
         st[q] = it.c < RB && !trans_layer(gl);
         it.step();
       }
 #pragma unroll
       for (int q = 0; q < U; ++q)
-        if (st[q]) y[dst[q]] = val[q];
+        if (st[q]) yr[dst[q]] = val[q];
     }
   }
   // transmission layers from the precomputed coefficients: slot k < 2 is
@@ -479,38 +498,44 @@ __global__ void __launch_bounds__(256) k_bstage_fwd(const BSeg* __restrict__ seg
         }
         v = v + cvt<T>(acc);
       }
-      y[((size_t)t * RB + c) * nl + (gl - sd.x0)] = v;
+      yr[((size_t)(t - yb) * RB + c) * nl + (gl - sd.x0)] = v;
     }
   }
   __syncthreads();
   // chunk-local forward substitution y_t = G_t (f_t - A_t y_{t-1}) from zero
-  bchain<T, NB, RB, D, true, NC>(gp(F.G), (long)nl * nl, gp(F.A), y, s, 1, cnt, nl, T(1), q, ps);
+  bchain<T, NB, RB, D, true, NC>(gp(F.G), (long)nl * nl, gp(F.A), yr, yb, s, 1, cnt, nl, T(1), q, ps);
   GAS cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
-    tips[((size_t)w.p * RB + c) * nl + l] = y[((size_t)(e - 1) * RB + c) * nl + l];
+    tips[((size_t)w.p * RB + c) * nl + l] = yr[((size_t)(e - 1 - yb) * RB + c) * nl + l];
   }
   // chunk-local backward substitution x_t = y_t - E_t x_{t+1} on the local
   // forward values (bchain passes a barrier before its first write, so the
   // tips above are read before y is overwritten)
-  bchain<T, NB, RB, D, false, NC>(gp(F.E), (long)nl * nl, nullptr, y, e - 1, -1, cnt, nl, T(-1), q, ps);
+  bchain<T, NB, RB, D, false, NC>(gp(F.E), (long)nl * nl, nullptr, yr, yb, e - 1, -1, cnt, nl, T(-1), q, ps);
   for (int idx = threadIdx.x; idx < RB * nl; idx += 256) {
     const int c = idx / nl, l = idx - c * nl;
-    heads[((size_t)w.p * RB + c) * nl + l] = y[((size_t)s * RB + c) * nl + l];
+    heads[((size_t)w.p * RB + c) * nl + l] = yr[((size_t)(s - yb) * RB + c) * nl + l];
+  }
+  // the chunk's local solution to y for the backward launch (bchain ends on
+  // a barrier, so every row is in place)
+  if constexpr (LY) {
+    GAS cx<T>* yo = y + (size_t)s * RB * nl;
+    for (int idx = threadIdx.x; idx < cnt * RB * nl; idx += 256) yo[idx] = yr[idx];
   }
   if (P == 1) return;
   if (!last_arrival(counters + 2 * slot, P)) return;
   // true chunk-end values: tip_q = raw_q + Y_{e_q - 1} tip_{q-1}
   bchain<T, NB, RB, D, false, NC>(gp(F.Y) + (size_t)(m - 1) * nl * nl, (long)m * nl * nl, nullptr, tips, 0,
-                                  1, P - 1, nl, T(1), q, ps);
+                                  0, 1, P - 1, nl, T(1), q, ps);
   // chunk starts of the backward chains on the true forward values
   bheads_fix<T, RB>(gp(F.W), heads, tips, P, m, nl, ps, 256 * RB);
   // true chunk-start values: head_q = raw_q + X_{s_q} head_{q+1}
-  bchain<T, NB, RB, D, false, NC>(gp(F.X), (long)m * nl * nl, nullptr, heads, P - 1, -1, P - 1, nl, T(1), q,
-                                  ps);
+  bchain<T, NB, RB, D, false, NC>(gp(F.X), (long)m * nl * nl, nullptr, heads, 0, P - 1, -1, P - 1, nl, T(1),
+                                  q, ps);
 }
 
-template <class T, int NB, int RB>
+template <class T, int NB, int RB, bool LY>
 __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ segs, int nseg, int nitems) {
   __shared__ cx<T> hv[NB * RB], cv[NB * RB];
   BWork w;
@@ -530,8 +555,15 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ seg
   const int s = w.p * m, e = min(s + m, n2), cnt = e - s;
   const SlabFac<T> F(factors + sd.fac_off, n2, nl);
   GAS cx<T>* y = scratch + (size_t)slot * n2 * A.nl_max * RB;
+  const auto yr = yrows<LY, T>(y);
+  const int yb = LY ? s : 0;
   const GAS cx<T>* tips = red + (size_t)slot * 2 * P * A.nl_max * RB;
   const GAS cx<T>* heads = tips + (size_t)P * A.nl_max * RB;
+  if constexpr (LY) {
+    const GAS cx<T>* yi = y + (size_t)s * RB * nl;
+    for (int idx = threadIdx.x; idx < cnt * RB * nl; idx += 256) yr[idx] = yi[idx];
+    __syncthreads();
+  }
   // x_t += W_t c_{p-1} + X_t d_{p+1} (the true values at the neighbouring
   // chunk ends; absent at the first and last chunk)
   if (w.p > 0 || w.p < P - 1) {
@@ -542,11 +574,11 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ seg
     }
     __syncthreads();
     if (w.p > 0 && w.p < P - 1)
-      bfixup2<T, RB>(gp(F.W), cv, gp(F.X), hv, y, s, e, nl);
+      bfixup2<T, RB>(gp(F.W), cv, gp(F.X), hv, yr, yb, s, e, nl);
     else if (w.p > 0)
-      bfixup<T, RB>(gp(F.W), y, s, e, nl, cv);
+      bfixup<T, RB>(gp(F.W), yr, yb, s, e, nl, cv);
     else
-      bfixup<T, RB>(gp(F.X), y, s, e, nl, hv);
+      bfixup<T, RB>(gp(F.X), yr, yb, s, e, nl, hv);
     __syncthreads();
   }
   // u += J^T x over the task's layers, outgoing transmission layers; U
@@ -564,7 +596,7 @@ __global__ void __launch_bounds__(256) k_bstage_bwd(const BSeg* __restrict__ seg
       const int ll = it.l, t = s + it.t;
       const int gl = sd.x0 + ll;
       const int glc = (tk.at < gl && gl <= tk.bt) ? gl : tk.bt;
-      xv[q] = y[((size_t)t * RB + c) * nl + ll];
+      xv[q] = yr[((size_t)(t - yb) * RB + c) * nl + ll];
       uid[q] = (size_t)(r0 + c) * A.ld + (size_t)(glc - 1) * n2 + t;
       uv[q] = u[uid[q]];
       cq[q] = it.c;
@@ -635,14 +667,28 @@ void launch_trans_coef(const TaskDev* tasks, int ntasks, const SlabDev* slabs, c
   hipLaunchKernelGGL(k_trans_coef, dim3(blocks), dim3(256), 0, s, tasks, ntasks, slabs, G, out);
 }
 
+// LDS per workgroup of the stage kernels with the chunk scratch in LDS: at
+// most 64 KB (no launch attribute needed; two workgroups still share a CU)
+constexpr size_t kStageLdsCap = 64 << 10;
+
 template <class T>
-void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launch, int rb, hipStream_t s) {
+void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launch, int m_launch, int rb,
+                        hipStream_t s) {
   if (nseg < 1 || nitems < 1) return;
   const dim3 grd(8 * ((nitems + 7) / 8));
-#define BLAUNCH(NB, RB, D, NC)                                                                            \
-  do {                                                                                                    \
-    hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D, NC>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);  \
-    hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);         \
+#define BLAUNCH(NB, RB, D, NC)                                                                                 \
+  do {                                                                                                         \
+    const size_t ylds = (size_t)m_launch * RB * nl_launch * sizeof(cx<T>);                                     \
+    const size_t stat = (size_t)(BLay<NB, RB, NC>::QN * RB + 256 * RB) * sizeof(cx<T>);                        \
+    if (stat + ylds <= kStageLdsCap) {                                                                         \
+      hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D, NC, true>), grd, dim3(256), ylds, s, segs_dev, nseg,     \
+                         nitems);                                                                              \
+      hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB, true>), grd, dim3(256), ylds, s, segs_dev, nseg, nitems);   \
+    } else {                                                                                                   \
+      hipLaunchKernelGGL((k_bstage_fwd<T, NB, RB, D, NC, false>), grd, dim3(256), 0, s, segs_dev, nseg,       \
+                         nitems);                                                                              \
+      hipLaunchKernelGGL((k_bstage_bwd<T, NB, RB, false>), grd, dim3(256), 0, s, segs_dev, nseg, nitems);     \
+    }                                                                                                          \
   } while (0)
   constexpr int D32 = sizeof(T) == 4 ? 2 : 2;
   constexpr int D64 = sizeof(T) == 4 ? 2 : 1;
@@ -667,8 +713,8 @@ void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launc
 #undef BLAUNCH
 }
 
-template void launch_stage_group<double>(const BSeg*, int, int, int, int, hipStream_t);
-template void launch_stage_group<float>(const BSeg*, int, int, int, int, hipStream_t);
+template void launch_stage_group<double>(const BSeg*, int, int, int, int, int, hipStream_t);
+template void launch_stage_group<float>(const BSeg*, int, int, int, int, int, hipStream_t);
 
 #undef GAS
 #undef CAS

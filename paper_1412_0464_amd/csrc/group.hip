@@ -121,7 +121,7 @@ struct Group {
   char* ws = nullptr;
   BSeg* segs_dev = nullptr;
   struct Step {
-    int first = 0, nseg = 0, nitems = 0, nl = 0;
+    int first = 0, nseg = 0, nitems = 0, nl = 0, m = 0;
   };
   std::vector<Step> steps;
   std::vector<BSeg> segs_host;
@@ -236,6 +236,7 @@ hsp_status build_segments(Group& G, const std::vector<int>& nact, int rb, hipStr
       q.nbuf = P.nbuf;
       S.nitems += q.ntasks * q.P * q.ntiles;
       S.nl = std::max(S.nl, sg.nl);
+      S.m = std::max(S.m, P.chunk);
       G.segs_host.push_back(q);
       ++S.nseg;
     }
@@ -360,7 +361,7 @@ void run_precond_group(Group& G, const std::vector<int>& nact, const std::vector
       if (!sg.residual) bytes += sg.fac + (double)nact[p] * (sg.bytes - sg.fac);
     }
     prof_begin(C0, HSP_PROF_STAGE, s);
-    launch_stage_group<T>(G.segs_dev + S.first, S.nseg, S.nitems, S.nl, G.seg_key[0], s);
+    launch_stage_group<T>(G.segs_dev + S.first, S.nseg, S.nitems, S.nl, S.m, G.seg_key[0], s);
     prof_end(C0, HSP_PROF_STAGE, s, bytes * sizeof(cx<T>));
   }
   // back to the fine level

@@ -176,9 +176,10 @@ __host__ __device__ inline size_t trans_coef_elems(int n2) {
 void launch_trans_coef(const TaskDev* tasks, int ntasks, const SlabDev* slabs, const LevelDev& G, cd* out,
                        hipStream_t s);
 // segs_dev: nseg segments in device memory, nitems work items in total,
-// nl_launch the thickest slab, rb in {1, 2, 4, 8}.
+// nl_launch the thickest slab, m_launch the longest chunk, rb in {1, 2, 4, 8}.
 template <class T>
-void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launch, int rb, hipStream_t s);
+void launch_stage_group(const BSeg* segs_dev, int nseg, int nitems, int nl_launch, int m_launch, int rb,
+                        hipStream_t s);
 
 // ---- BLAS-1 and utilities (blas.hip) ---------------------------------------
 template <class To, class Ti>
