@@ -104,6 +104,15 @@ def test_committed_records_parse():
         assert f"traffic-record: kernel={kernel} " in txt
 
 
+def test_committed_records_match_sources():
+    """Every committed counter record was taken on the kernel sources as they
+    stand (a kernel change without new counters would report traffic null)."""
+    assert bench.recorded_traffic("stage", 4, 64, 34) is not None
+    for kernel in ("project", "update", "matvec"):
+        assert bench.recorded_traffic(kernel, 0, 64) is not None, kernel
+    assert bench.recorded_traffic("nd_stage", 0, 1, 0, bench.ND_TRAFFIC_RECORD) is not None
+
+
 def test_one_gpu_only():
     r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
