@@ -23,7 +23,9 @@
 //
 // Scratch per (task, tile) slot: y [n2][RB][nl] (right-hand side, then the
 // solution), chunk tips and heads [2][P][RB][nl], an arrival counter (of
-// two reserved).
+// two reserved).  Where a chunk's slice of y fits in 64 KB of LDS, each work
+// item keeps it there within a launch: y in global memory then only carries
+// the chunk-local solution from the forward to the backward launch.
 #include "internal.h"
 #include "sweep_dev.h"
 
